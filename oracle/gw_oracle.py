@@ -1,0 +1,230 @@
+"""Plain CPU FP64 oracle of the spinor Epsilon path.  TEST INFRASTRUCTURE ONLY.
+
+Slow and direct on purpose.  Each function states the passage of the paper
+(arXiv:2206.00808, "Fully relativistic GW/Bethe-Salpeter calculations in
+BerkeleyGW") it writes out.  Conventions (the readings are listed in the
+design notes):
+
+* Hartree energies; cutoffs on |k+G|^2 in bohr^-2 (Rydberg); orthorhombic
+  cell a = (a1, a2, a3); G = 2 pi g / a for integer g.
+* One k-point (k = 0, N_k = 1 unless a prefactor is passed): occupied (valence)
+  states at k+q, empty (conduction) states at k, as in the Adler-Wiser sum of
+  Sec. II.
+* Coefficients c[n][sigma][G] with sigma = up, down; the periodic part of a
+  spinor component on the grid is u(r_j) = sum_G c(G) exp(+2 pi i g.j / n).
+* M_vc(G) = sum_sigma <v,k+q,sigma| e^{i(q+G).r} |c,k,sigma>
+          = sum_sigma (1/N) sum_j conj(u_v(r_j)) u_c(r_j) exp(+2 pi i g.j / n).
+
+Function                 | pinned by (tests/test_oracle_pins.py)
+-------------------------|---------------------------------------------------
+wavefunction_on_box      | brute-force synthesis, unit-norm (Parseval)
+mtxel_fft                | convolution form, brute force, single plane wave
+mtxel_convolution        | brute force, single plane wave, orthonormality
+mtxel_bruteforce         | closed forms on single plane waves
+chi0                     | scipy ZHERK, Hermitian/NSD, Loewner, asymptote,
+                         | doubled collinear set (spinor = 2 x spinless)
+epsilon / epsilon_inverse| Sherman-Morrison closed form, eigenvalue bounds,
+                         | LU solve via scipy
+head_overlap             | convolution form at G = 0, orthonormality
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "box_offsets", "wavefunction_on_box", "mtxel_fft", "mtxel_convolution",
+    "mtxel_bruteforce", "chi0_weight", "chi0", "epsilon", "epsilon_inverse",
+    "head_overlap", "chi0_from_system", "rel_f", "alias_free",
+]
+
+
+def box_offsets(g, box):
+    """Box index of each integer G: g mod n along every axis."""
+    return np.mod(np.asarray(g, dtype=np.int64), np.asarray(box, dtype=np.int64))
+
+
+def alias_free(gv, gc, geps, box):
+    """True when no product component can alias onto an eps-sphere G.
+
+    The product conj(u_v) u_c holds Fourier components g_c - g_v; a component
+    folds onto -G of the eps sphere only if |g_c - g_v + G|_i >= n_i, which
+    cannot happen when n_i > max|g_v|_i + max|g_c|_i + max|G_eps|_i.
+    """
+    m = (np.abs(gv).max(0) + np.abs(gc).max(0) + np.abs(geps).max(0))
+    return bool(np.all(np.asarray(box) > m))
+
+
+def wavefunction_on_box(c, g, box):
+    """Periodic part of every spinor component on the real-space grid.
+
+    Sec. II (matrix elements via FFT): the spinor components phi_{nk,alpha}(r)
+    are brought to real space before their product is formed.
+    u_n^sigma(r_j) = sum_{G in sphere} c_n^sigma(G) exp(+2 pi i g.j/n), i.e.
+    N * numpy.fft.ifftn of the coefficients placed at g mod n.
+    c: [nb][ns][ng] complex128 -> [nb][ns][n1][n2][n3] complex128
+    """
+    c = np.asarray(c, dtype=np.complex128)
+    nb, ns, ng = c.shape
+    box = tuple(int(x) for x in box)
+    field = np.zeros((nb, ns) + box, dtype=np.complex128)
+    o = box_offsets(g, box)
+    field[:, :, o[:, 0], o[:, 1], o[:, 2]] = c
+    return np.fft.ifftn(field, axes=(2, 3, 4)) * float(np.prod(box))
+
+
+def mtxel_fft(cv, gv, cc, gc, geps, box):
+    """M_vc(G) by the route of Eq. (matrix_el): per spin component, the
+    inverse-transform of the real-space product, then the sum over spin.
+
+    Sec. II, Eq. (matrix_el) and the M_nn'(k,q,G) definition before it:
+    for each spin alpha, rho_alpha(r) = conj(phi_{v,k+q,alpha}(r)) phi_{c,k,alpha}(r)
+    is transformed with the exp(+i G.r)/N kernel and only then summed over
+    alpha.  Returns M[nv][nc][neps] complex128.
+    """
+    box = tuple(int(x) for x in box)
+    uv = wavefunction_on_box(cv, gv, box)
+    uc = wavefunction_on_box(cc, gc, box)
+    nv, ns = uv.shape[:2]
+    nc = uc.shape[0]
+    o = box_offsets(geps, box)
+    out = np.zeros((nv, nc, len(geps)), dtype=np.complex128)
+    for v in range(nv):
+        for c in range(nc):
+            acc = np.zeros(len(geps), dtype=np.complex128)
+            for s in range(ns):
+                rho = np.conj(uv[v, s]) * uc[c, s]
+                t = np.fft.ifftn(rho)
+                acc += t[o[:, 0], o[:, 1], o[:, 2]]
+            out[v, c] = acc
+    return out
+
+
+def _shift_index(gsrc_lookup, g_list, shift):
+    """Index in a sphere of each g - shift, or -1 if it lies outside."""
+    idx = np.empty(len(g_list), dtype=np.int64)
+    for i, g in enumerate(g_list):
+        idx[i] = gsrc_lookup.get((g[0] - shift[0], g[1] - shift[1], g[2] - shift[2]), -1)
+    return idx
+
+
+def mtxel_convolution(cv, gv, cc, gc, geps):
+    """M_vc(G) from its definition written in the plane-wave basis, no grid.
+
+    Sec. II, definition of M_nn'(k,q,G): with phi_{v,k+q} = sum c_v(G1)
+    e^{i(k+q+G1).r} and phi_{c,k} = sum c_c(G2) e^{i(k+G2).r}, the cell integral of
+    conj(phi_v) e^{i(q+G).r} phi_c keeps only G2 = G1 - G, so
+    M_vc(G) = sum_alpha sum_{G1} conj(c_v^alpha(G1)) c_c^alpha(G1 - G).
+    Returns M[nv][nc][neps].
+    """
+    cv = np.asarray(cv, dtype=np.complex128)
+    cc = np.asarray(cc, dtype=np.complex128)
+    nv, ns, ngv = cv.shape
+    nc = cc.shape[0]
+    lut = {tuple(g): i for i, g in enumerate(np.asarray(gc).tolist())}
+    gvl = np.asarray(gv).tolist()
+    out = np.zeros((nv, nc, len(geps)), dtype=np.complex128)
+    a = np.conj(cv).reshape(nv, ns * ngv)
+    for ig, G in enumerate(np.asarray(geps).tolist()):
+        idx = _shift_index(lut, gvl, G)
+        ok = idx >= 0
+        b = np.zeros((nc, ns, ngv), dtype=np.complex128)
+        b[:, :, ok] = cc[:, :, idx[ok]]
+        out[:, :, ig] = a @ b.reshape(nc, ns * ngv).T
+    return out
+
+
+def mtxel_bruteforce(cv, gv, cc, gc, geps, box):
+    """Explicit real-space sums, no FFT: for tiny grids only.
+
+    Synthesises u(r_j) = sum_G c(G) exp(2 pi i g.j/n) point by point and
+    projects M(G) = (1/N) sum_j sum_alpha conj(u_v) u_c exp(2 pi i g.j/n).
+    """
+    box = np.asarray(box, dtype=np.int64)
+    n_total = int(np.prod(box))
+    j = np.stack(np.meshgrid(*[np.arange(n) for n in box], indexing="ij"), -1).reshape(-1, 3)
+    frac = j / box  # r_j in units of the cell vectors
+
+    def synth(c, g):
+        ph = np.exp(2j * np.pi * (frac @ np.asarray(g, dtype=np.float64).T))  # [N, ng]
+        return np.einsum("rg,bsg->bsr", ph, np.asarray(c, dtype=np.complex128))
+
+    uv = synth(cv, gv)
+    uc = synth(cc, gc)
+    proj = np.exp(2j * np.pi * (frac @ np.asarray(geps, dtype=np.float64).T))  # [N, neps]
+    rho = np.einsum("vsr,csr->vcr", np.conj(uv), uc)
+    return np.einsum("vcr,rg->vcg", rho, proj) / n_total
+
+
+def chi0_weight(ev, ec, omega):
+    """Adler-Wiser energy factor on the imaginary axis, eta = 0.
+
+    Sec. II, polarizability P_GG'(q, w): the bracket
+    1/(e_v - e_c - w + i eta) + 1/(e_v - e_c + w + i eta) taken at w -> i*omega
+    and eta = 0; both terms are kept as written and summed.
+    Returns w[nfreq][nv*nc] (real: the imaginary parts cancel).
+    """
+    ev = np.asarray(ev, dtype=np.float64)
+    ec = np.asarray(ec, dtype=np.float64)
+    delta = (ev[:, None] - ec[None, :]).reshape(-1)
+    out = []
+    for om in np.atleast_1d(np.asarray(omega, dtype=np.float64)):
+        w = 1.0 / (delta - 1j * om) + 1.0 / (delta + 1j * om)
+        out.append(w.real)
+    return np.array(out)
+
+
+def chi0(mtxel, ev, ec, omega, prefactor=1.0):
+    """P_GG'(q, i omega) = (1/N_k) sum_{v,c} M*_vc(G) M_vc(G') [Adler-Wiser bracket].
+
+    Sec. II, the polarizability P_GG'(q, w) at imaginary frequency, one k-point.
+    mtxel: [nv][nc][neps].  Returns chi0[nfreq][neps][neps] complex128.
+    """
+    m = np.asarray(mtxel, dtype=np.complex128)
+    nv, nc, neps = m.shape
+    flat = m.reshape(nv * nc, neps)
+    w = chi0_weight(ev, ec, omega)
+    return np.stack([prefactor * ((np.conj(flat).T * wf[None, :]) @ flat) for wf in w])
+
+
+def epsilon(chi0_f, vcoul):
+    """eps_GG' = delta_GG' - v(q+G) P_GG'  (Sec. II, dielectric matrix)."""
+    c = np.asarray(chi0_f, dtype=np.complex128)
+    v = np.asarray(vcoul, dtype=np.float64)
+    n = c.shape[-1]
+    return np.eye(n, dtype=np.complex128) - v[:, None] * c
+
+
+def epsilon_inverse(chi0_all, vcoul):
+    """eps^-1 for every frequency by LAPACK getrf/getri (numpy.linalg.inv).
+
+    Sec. II defines W = eps^-1 v; the Performance section names the inversion
+    of the dielectric matrix as a large part of Epsilon's run time.
+    """
+    c = np.asarray(chi0_all, dtype=np.complex128)
+    return np.stack([np.linalg.inv(epsilon(cf, vcoul)) for cf in c])
+
+
+def head_overlap(cv, gv, cc, gc):
+    """M_vc(G=0) = sum_alpha sum_G conj(c_v^alpha(G)) c_c^alpha(G): the overlap of
+    the periodic parts, the G = 0 term of the M_nn' definition (Sec. II).
+    Returns [nv][nc] complex128.
+    """
+    return mtxel_convolution(cv, gv, cc, gc, np.zeros((1, 3), dtype=np.int32))[:, :, 0]
+
+
+def chi0_from_system(sysd, prefactor=1.0, nc=None, method="fft"):
+    """Convenience: M then chi0 for a generated system dict."""
+    cc = sysd["cc"] if nc is None else sysd["cc"][:nc]
+    ec = sysd["ec"] if nc is None else sysd["ec"][:nc]
+    if method == "fft":
+        m = mtxel_fft(sysd["cv"], sysd["gv"], cc, sysd["gc"], sysd["geps"], sysd["box"])
+    else:
+        m = mtxel_convolution(sysd["cv"], sysd["gv"], cc, sysd["gc"], sysd["geps"])
+    return m, chi0(m, sysd["ev"], ec, sysd["omega"], prefactor)
+
+
+def rel_f(x, ref):
+    """Relative Frobenius error ||x - ref||_F / ||ref||_F."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))

@@ -1,0 +1,276 @@
+"""Pins of the CPU oracle against closed forms, brute force and library routines.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped spin
+term, a wrong transform sign or normalisation, a transposed operand, a missing
+conjugate, a wrong energy denominator) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.linalg.blas
+
+import oracle
+import synth
+from synth.generate import SystemConfig, _random_spinors, g_sphere, vcoul
+
+
+def tiny_system(seed=7, q=(0.25, 0.0, -0.25), nv=3, nc=5, ns=2, box=(8, 9, 10),
+                cell=(5.0, 5.3, 5.7), ecut=8.0, ecut_eps=3.0):
+    rng = np.random.default_rng(seed)
+    gk = g_sphere(cell, (0, 0, 0), ecut)
+    gkq = g_sphere(cell, q, ecut)
+    geps = g_sphere(cell, q, ecut_eps)
+    cc = _random_spinors(rng, len(gk), nc, ns)
+    cv = _random_spinors(rng, len(gkq), nv, ns)
+    ev = np.sort(rng.uniform(-6, 0, nv)) / synth.EV_PER_HA
+    ec = np.sort(rng.uniform(1, 20, nc)) / synth.EV_PER_HA
+    return dict(cv=cv, gv=gkq, cc=cc, gc=gk, geps=geps, box=box, ev=ev, ec=ec,
+                vcoul=vcoul(cell, q, geps), cell=cell, q=q)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    s = tiny_system()
+    assert oracle.alias_free(s["gv"], s["gc"], s["geps"], s["box"])
+    return s
+
+
+def test_wavefunction_matches_explicit_synthesis(tiny):
+    s = tiny
+    u = oracle.wavefunction_on_box(s["cv"], s["gv"], s["box"])
+    box = np.array(s["box"])
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        j = rng.integers(0, box)
+        b, sp = rng.integers(0, s["cv"].shape[0]), rng.integers(0, 2)
+        val = np.sum(s["cv"][b, sp] * np.exp(2j * np.pi * (s["gv"] @ (j / box))))
+        assert abs(u[b, sp, j[0], j[1], j[2]] - val) < 1e-13
+
+
+def test_wavefunction_parseval(tiny):
+    # orthonormal spinors: (1/N) sum_r sum_sigma |u|^2 = 1 and cross terms vanish
+    u = oracle.wavefunction_on_box(tiny["cv"], tiny["gv"], tiny["box"])
+    n = np.prod(tiny["box"])
+    flat = u.reshape(u.shape[0], -1)
+    gram = np.conj(flat) @ flat.T / n
+    assert np.allclose(gram, np.eye(u.shape[0]), atol=1e-13)
+
+
+def test_mtxel_three_routes_agree(tiny):
+    s = tiny
+    m_fft = oracle.mtxel_fft(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"], s["box"])
+    m_conv = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    m_bf = oracle.mtxel_bruteforce(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"], s["box"])
+    assert oracle.rel_f(m_fft, m_conv) < 1e-13
+    assert oracle.rel_f(m_bf, m_conv) < 1e-12
+
+
+def test_aliasing_box_breaks_fft_route():
+    # a box at the alias limit must disagree with the grid-free definition
+    s = tiny_system(box=(5, 5, 5))
+    assert not oracle.alias_free(s["gv"], s["gc"], s["geps"], s["box"])
+    m_fft = oracle.mtxel_fft(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"], s["box"])
+    m_conv = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    assert oracle.rel_f(m_fft, m_conv) > 1e-3
+
+
+@pytest.mark.parametrize("sa,sb", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_single_plane_wave_pair_gives_delta(tiny, sa, sb):
+    s = tiny
+    gv, gc, geps = s["gv"], s["gc"], s["geps"]
+    ia, ib = 5, 3
+    cv = np.zeros((1, 2, len(gv)), complex)
+    cc = np.zeros((1, 2, len(gc)), complex)
+    cv[0, sa, ia] = 1.0
+    cc[0, sb, ib] = 1.0
+    want = np.zeros(len(geps), complex)
+    if sa == sb:
+        d = gv[ia] - gc[ib]
+        hit = np.where((geps == d).all(axis=1))[0]
+        want[hit] = 1.0
+    for m in (oracle.mtxel_fft(cv, gv, cc, gc, geps, s["box"])[0, 0],
+              oracle.mtxel_convolution(cv, gv, cc, gc, geps)[0, 0],
+              oracle.mtxel_bruteforce(cv, gv, cc, gc, geps, s["box"])[0, 0]):
+        assert np.abs(m - want).max() < 1e-13
+
+
+def test_head_vanishes_for_orthonormal_states_at_q0():
+    # q = 0: valence and conduction from one orthonormal set -> M_vc(G=0) = 0
+    rng = np.random.default_rng(3)
+    cell = (5.0, 5.3, 5.7)
+    gk = g_sphere(cell, (0, 0, 0), 8.0)
+    geps = g_sphere(cell, (0, 0, 0), 3.0)
+    joint = _random_spinors(rng, len(gk), 9, 2)
+    cv, cc = joint[:3], joint[3:]
+    m = oracle.mtxel_fft(cv, gk, cc, gk, geps, (8, 9, 10))
+    i0 = np.where((geps == 0).all(axis=1))[0][0]
+    assert np.abs(m[:, :, i0]).max() < 1e-14
+    # and the diagonal overlap of a state with itself is 1
+    h = oracle.head_overlap(joint, gk, joint, gk)
+    assert np.allclose(h, np.eye(9), atol=1e-14)
+
+
+def test_zero_down_component_is_spinless(tiny):
+    s = tiny
+    cv, cc = s["cv"].copy(), s["cc"].copy()
+    cv[:, 1] = 0.0
+    cc[:, 1] = 0.0
+    m2 = oracle.mtxel_fft(cv, s["gv"], cc, s["gc"], s["geps"], s["box"])
+    m1 = oracle.mtxel_fft(cv[:, :1], s["gv"], cc[:, :1], s["gc"], s["geps"], s["box"])
+    assert np.abs(m2 - m1).max() < 1e-15
+
+
+def test_doubled_collinear_set_doubles_chi0(tiny):
+    # Sec. II: the spinor P has the spinless form with spin traced and both
+    # band counts doubled.  Spinor set {(phi,0),(0,phi)} => chi0 = 2 chi0_spinless.
+    s = tiny
+    phi_v, phi_c = s["cv"][:, :1], s["cc"][:, :1]
+    m1 = oracle.mtxel_fft(phi_v, s["gv"], phi_c, s["gc"], s["geps"], s["box"])
+    x1 = oracle.chi0(m1, s["ev"], s["ec"], [0.0, 1.5])
+
+    def doubled(phi):
+        nb, _, ng = phi.shape
+        out = np.zeros((2 * nb, 2, ng), complex)
+        out[:nb, 0] = phi[:, 0]
+        out[nb:, 1] = phi[:, 0]
+        return out
+
+    m2 = oracle.mtxel_fft(doubled(phi_v), s["gv"], doubled(phi_c), s["gc"], s["geps"], s["box"])
+    x2 = oracle.chi0(m2, np.tile(s["ev"], 2), np.tile(s["ec"], 2), [0.0, 1.5])
+    assert oracle.rel_f(x2, 2 * x1) < 1e-14
+
+
+def test_completeness_sum_rule():
+    # sum over a complete basis at k of M*_vn(G) M_vn(G') equals
+    # sum_sigma sum_{a in S_k} c_v(a+G) conj(c_v(a+G')), from the M definition
+    rng = np.random.default_rng(11)
+    cell, q = (5.0, 5.3, 5.7), (0.25, 0.0, 0.0)
+    gk = g_sphere(cell, (0, 0, 0), 6.0)
+    gkq = g_sphere(cell, q, 6.0)
+    geps = g_sphere(cell, q, 2.5)
+    full = _random_spinors(rng, len(gk), 2 * len(gk), 2)   # unitary basis at k
+    cv = _random_spinors(rng, len(gkq), 2, 2)
+    m = oracle.mtxel_fft(cv, gkq, full, gk, geps, (12, 12, 12))
+    lhs = np.einsum("vng,vnh->vgh", np.conj(m), m)
+    lutv = {tuple(g): i for i, g in enumerate(gkq.tolist())}
+    rhs = np.zeros_like(lhs)
+    for v in range(cv.shape[0]):
+        for ig, G in enumerate(geps.tolist()):
+            for jg, H in enumerate(geps.tolist()):
+                acc = 0j
+                for a in gk.tolist():
+                    i1 = lutv.get((a[0] + G[0], a[1] + G[1], a[2] + G[2]))
+                    i2 = lutv.get((a[0] + H[0], a[1] + H[1], a[2] + H[2]))
+                    if i1 is not None and i2 is not None:
+                        acc += np.sum(cv[v, :, i1] * np.conj(cv[v, :, i2]))
+                rhs[v, ig, jg] = acc
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+def test_weight_closed_form():
+    ev = np.array([-0.2, -0.05])
+    ec = np.array([0.1, 0.3, 0.7])
+    om = np.array([0.0, 0.4])
+    w = oracle.chi0_weight(ev, ec, om)
+    d = (ev[:, None] - ec[None, :]).ravel()
+    for f, o in enumerate(om):
+        assert np.allclose(w[f], 2 * d / (d * d + o * o), rtol=1e-15, atol=0)
+    assert np.all(w < 0)
+
+
+def test_chi0_matches_zherk_and_is_hermitian_nsd(tiny):
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    om = [0.0, 0.2, 1.0, 5.0]
+    x = oracle.chi0(m, s["ev"], s["ec"], om, prefactor=0.5)
+    flat = m.reshape(-1, m.shape[-1])
+    d = (s["ev"][:, None] - s["ec"][None, :]).ravel()
+    for f, o in enumerate(om):
+        a = np.sqrt(-2 * d / (d * d + o * o))[:, None] * flat
+        up = scipy.linalg.blas.zherk(-0.5, a, trans=2)       # -0.5 * a^H a, upper
+        ref = np.triu(up) + np.triu(up, 1).conj().T
+        assert oracle.rel_f(x[f], ref) < 1e-14
+        assert np.abs(x[f] - x[f].conj().T).max() < 1e-15 * np.abs(x[f]).max()
+        assert np.linalg.eigvalsh(x[f]).max() < 1e-14 * np.abs(x[f]).max()
+    # Loewner monotone in omega: chi0(i w2) - chi0(i w1) is PSD for w2 > w1
+    for f in range(len(om) - 1):
+        assert np.linalg.eigvalsh(x[f + 1] - x[f]).min() > -1e-14 * np.abs(x[f]).max()
+
+
+def test_chi0_large_omega_asymptote(tiny):
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    big = 1e4
+    x = oracle.chi0(m, s["ev"], s["ec"], [big])[0] * big * big
+    flat = m.reshape(-1, m.shape[-1])
+    d = (s["ev"][:, None] - s["ec"][None, :]).ravel()
+    lim = (np.conj(flat).T * (2 * d)[None, :]) @ flat
+    assert oracle.rel_f(x, lim) < 1e-6
+
+
+def test_chi0_chunked_accumulation(tiny):
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    om = [0.0, 0.7]
+    full = oracle.chi0(m, s["ev"], s["ec"], om)
+    part = oracle.chi0(m[:, :2], s["ev"], s["ec"][:2], om) + oracle.chi0(m[:, 2:], s["ev"], s["ec"][2:], om)
+    assert oracle.rel_f(part, full) < 1e-15
+
+
+def test_epsinv_sherman_morrison_single_pair(tiny):
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"][:1], s["gv"], s["cc"][:1], s["gc"], s["geps"])
+    om = [0.0, 0.3]
+    x = oracle.chi0(m, s["ev"][:1], s["ec"][:1], om)
+    einv = oracle.epsilon_inverse(x, s["vcoul"])
+    mv = m[0, 0]
+    d = s["ev"][0] - s["ec"][0]
+    for f, o in enumerate(om):
+        w = 2 * d / (d * d + o * o)
+        u = w * s["vcoul"] * np.conj(mv)
+        ref = np.eye(len(mv)) + np.outer(u, mv) / (1 - mv @ u)
+        assert oracle.rel_f(einv[f], ref) < 1e-13
+
+
+def test_eps_spectrum_bounds_and_lu_solve():
+    s = synth.build_system(synth.CONFIGS["C1"])
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(m, s["ev"], s["ec"], [0.0, 1.0])
+    einv = oracle.epsilon_inverse(x, s["vcoul"])
+    vh = np.sqrt(s["vcoul"])
+    for f in range(2):
+        eps = oracle.epsilon(x[f], s["vcoul"])
+        # eps is similar to I - V^1/2 chi0 V^1/2 (Hermitian, >= 1)
+        ev_eps = np.linalg.eigvals(eps)
+        assert np.abs(ev_eps.imag).max() < 1e-10
+        assert ev_eps.real.min() > 1 - 1e-12
+        sym = np.eye(len(vh)) - vh[:, None] * x[f] * vh[None, :]
+        lam = np.linalg.eigvalsh(sym)
+        assert lam.min() > 1 - 1e-12
+        inv_ev = np.linalg.eigvals(einv[f])
+        assert inv_ev.real.min() > 0 and inv_ev.real.max() < 1 + 1e-12
+        lu = scipy.linalg.lu_factor(eps)
+        ref = scipy.linalg.lu_solve(lu, np.eye(len(vh)))
+        assert oracle.rel_f(einv[f], ref) < 1e-13
+
+
+def test_generator_is_deterministic():
+    a = synth.build_system(synth.CONFIGS["C1"])
+    b = synth.build_system(synth.CONFIGS["C1"])
+    for k in ("cv", "cc", "gv", "gc", "geps", "ev", "ec", "vcoul"):
+        assert np.array_equal(a[k], b[k])
+    assert a["geps"].shape[0] == 59
+    assert a["gc"].shape[0] == 395 and a["gv"].shape[0] == 399
+    # orthonormal stacked spinors
+    flat = a["cc"].reshape(a["cc"].shape[0], -1)
+    assert np.allclose(np.conj(flat) @ flat.T, np.eye(flat.shape[0]), atol=1e-13)
+
+
+def test_q0_head_construction_scales_with_q():
+    s = synth.build_system(synth.CONFIGS["T1Q0"])
+    h = oracle.head_overlap(s["cv"], s["gv"], s["cc"], s["gc"])
+    qn = np.linalg.norm(s["qg"][s["head_index"]])
+    assert s["head_index"] >= 0
+    assert np.abs(h).max() < 20 * qn and np.abs(h).max() > 1e-3 * qn
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    assert np.allclose(m[:, :, s["head_index"]], h, atol=1e-15)
