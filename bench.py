@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the spinor chi0 / eps^-1 hot path on one MI355X.
+
+One step = one pass of the whole path over one q-point of the Si-like
+workload (FFT box 48^3, ~2,000 G per spinor component, N_v = 16, N_c = 800,
+eps sphere 1,000 G, static + 8 imaginary frequencies), inputs resident in HBM:
+  band transforms -> pair products + pruned transforms (M) -> chi0 contraction
+  -> eps build + LU inverse.
+The FP64 path is the headline; the mixed path (float transforms, split-BF16
+contraction, FP64 eps^-1) runs the same step and reports its eps^-1 relative
+error against the FP64 path.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("chi0 TFLOP/s + (v,c) pairs/s, mixed vs FP64 path at stated "
+          "ε⁻¹ rel error")
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def fft_stage_bytes(d, elem):
+    """Algorithmic HBM bytes of the FFT stage (band + pair transforms) per q."""
+    nbox = int(np.prod(d["box"]))
+    nv, nc, neps = d["nv"], d["nc"], d["neps"]
+    ngv, ngc = d["gv"].shape[0], d["gc"].shape[0]
+    ns = d["nspinor"]
+    band = elem * (ns * (nv * ngv + nc * ngc) + ns * (nv + nc) * nbox)
+    pair = nv * nc * elem * (ns * nbox + neps)
+    return band, pair
+
+
+def kernel_bytes(name, d, elem, launches):
+    """Algorithmic bytes of one named kernel summed over its launches in one step."""
+    nbox = int(np.prod(d["box"]))
+    nv, nc, neps, ns = d["nv"], d["nc"], d["neps"], d["nspinor"]
+    P = nv * nc
+    if name == "pair_plane":   # the c-band's spin planes per pair (valence reused on chip)
+        return P * ns * nbox * elem
+    if name == "pair_xpass":   # the eps-sphere output per pair
+        return P * neps * elem
+    if name == "band_xpass":
+        return ns * (nv * d["gv"].shape[0] + nc * d["gc"].shape[0]) * elem
+    if name == "band_plane":
+        return ns * (nv + nc) * nbox * elem
+    return None
+
+
+def chi0_flops(d):
+    return 4.0 * d["neps"] ** 2 * d["nv"] * d["nc"] * len(d["omega"])
+
+
+def time_path(ctx, P, pipeline, d, out, prec, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        pipeline.run_path(ctx, d, out, prec=prec)
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        pipeline.run_path(ctx, d, out, prec=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    table = ctx.profile_table()
+    ctx.profile(False)
+    return ms, wall, table
+
+
+def cpu_baseline(sysd, seconds):
+    """The oracle on a bounded sample of the same workload, scaled to pairs/s."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    nv, nc = sysd["cv"].shape[0], sysd["cc"].shape[0]
+    # pairs: valence band 0 against growing blocks of conduction bands
+    t0 = time.perf_counter()
+    done = 0
+    cb = 8
+    v = 0
+    c0 = 0
+    while time.perf_counter() - t0 < seconds and done < nv * nc:
+        cs = slice(c0, min(nc, c0 + cb))
+        m = oracle.mtxel_fft(sysd["cv"][v:v + 1], sysd["gv"], sysd["cc"][cs], sysd["gc"],
+                             sysd["geps"], sysd["box"])
+        oracle.chi0(m, sysd["ev"][v:v + 1], sysd["ec"][cs], sysd["omega"])
+        done += cs.stop - cs.start
+        c0 = cs.stop
+        if c0 >= nc:
+            c0, v = 0, v + 1
+    t_pairs = time.perf_counter() - t0
+    per_pair = t_pairs / done
+    # eps^-1 once per step at full size (chi0 taken as a Hermitian NSD stand-in)
+    neps = sysd["geps"].shape[0]
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((neps, 64)) + 1j * rng.standard_normal((neps, 64))
+    chi = -(a @ a.conj().T) / 64.0 * 1e-3
+    t1 = time.perf_counter()
+    oracle.epsilon_inverse(np.stack([chi] * len(sysd["omega"])), sysd["vcoul"])
+    t_inv = time.perf_counter() - t1
+    P = nv * nc
+    step = per_pair * P + t_inv
+    return {
+        "value": P / step, "unit": "(v,c) pairs/s", "cores": int(blas_threads), "kind": "oracle",
+        "sample": (f"oracle FFT route + chi0 on {done} of {P} pairs ({t_pairs:.1f} s, numpy FFT "
+                   f"single-threaded, BLAS {blas_threads} threads) plus eps^-1 of all "
+                   f"{len(sysd['omega'])} frequencies at N_eps={neps} ({t_inv:.2f} s); "
+                   f"projected full step {step:.1f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    import paper_2206_00808_amd as P
+    from paper_2206_00808_amd import pipeline
+
+    cfg = synth.CONFIGS[args.config]
+    sysd = synth.build_system(cfg)
+    ctx = P.Context(0)
+
+    # ---------------- FP64 path
+    d64 = pipeline.upload(sysd, dtype="c128")
+    o64 = pipeline.alloc_outputs(d64)
+    ms64, wall64, tab64 = time_path(ctx, P, pipeline, d64, o64, P.GW_PREC_FP64, args.steps,
+                                    args.warmup)
+    pairs = d64["nv"] * d64["nc"]
+    flops = chi0_flops(d64)
+    kt64 = {k: (n / args.steps, t / args.steps) for k, (n, t) in tab64.items()}
+    chi_ms64 = kt64.get("chi0_fp64", (0, float("nan")))[1]
+    result = {
+        "metric": METRIC,
+        "value": pairs / (ms64 * 1e-3),
+        "unit": "(v,c) pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: Si-like spinor chi0+eps^-1, box {cfg.box}, "
+                               f"N_G {sysd['gv'].shape[0]}/{sysd['gc'].shape[0]}, "
+                               f"N_v {cfg.nv}, N_c {cfg.nc}, N_eps {d64['neps']}, "
+                               f"{len(cfg.omega_ev)} frequencies",
+                   "global_batch": 1, "pairs": pairs, "parallelism": "single GPU"},
+        "chi0_tflops": flops / (chi_ms64 * 1e-3) / 1e12,
+        "chi0_tflops_whole_step": flops / (ms64 * 1e-3) / 1e12,
+        "stage_ms": {k: round(v[1], 4) for k, v in sorted(kt64.items())},
+        "wall_ms_per_step": wall64 * 1e3 / args.steps,
+    }
+    # dominant kernel roofline
+    dom = max(kt64.items(), key=lambda kv: kv[1][1])
+    dname, (dl, dms) = dom
+    if dname in ("chi0_fp64",):
+        ach = flops / (dms * 1e-3) / 1e12
+        roof = {"kernel": dname, "bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None}
+    else:
+        nb = kernel_bytes(dname, d64, 16, dl)
+        if nb is None:
+            roof = {"kernel": dname, "bound": "unknown", "achieved": None, "peak": None,
+                    "unit": None, "frac": None, "traffic": None}
+        else:
+            ach = nb / (dms * 1e-3) / 1e9
+            roof = {"kernel": dname, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "launches_per_step": dl, "avg_launch_ms": dms / dl}
+    result["roofline"] = roof
+    bb, pb = fft_stage_bytes(d64, 16)
+    fft_ms = sum(kt64.get(k, (0, 0))[1] for k in ("band_xpass", "band_plane", "pair_plane",
+                                                  "pair_xpass"))
+    result["fft_stage"] = {"algorithmic_GB": (bb + pb) / 1e9, "ms": fft_ms,
+                           "GB_per_s": (bb + pb) / (fft_ms * 1e-3) / 1e9}
+    epsinv64 = o64["epsinv"]
+
+    # ---------------- mixed path
+    if not args.no_mixed:
+        d32 = pipeline.upload(sysd, dtype="c64")
+        o32 = pipeline.alloc_outputs(d32)
+        ms32, wall32, tab32 = time_path(ctx, P, pipeline, d32, o32, P.GW_PREC_SPLITBF16,
+                                        args.steps, args.warmup)
+        kt32 = {k: (n / args.steps, t / args.steps) for k, (n, t) in tab32.items()}
+        chi_ms32 = kt32.get("chi0_bf16x3", (0, float("nan")))[1]
+        diff = (o32["epsinv"] - epsinv64).reshape(len(cfg.omega_ev), -1)
+        ref = epsinv64.reshape(len(cfg.omega_ev), -1)
+        err_inv = float((torch.linalg.vector_norm(diff, dim=1) /
+                         torch.linalg.vector_norm(ref, dim=1)).max())
+        cd = (o32["chi0"] - o64["chi0"]).reshape(len(cfg.omega_ev), -1)
+        cr = o64["chi0"].reshape(len(cfg.omega_ev), -1)
+        err_chi = float((torch.linalg.vector_norm(cd, dim=1) /
+                         torch.linalg.vector_norm(cr, dim=1)).max())
+        result["mixed"] = {
+            "pairs_per_s": pairs / (ms32 * 1e-3), "ms_per_step": ms32,
+            "chi0_tflops": flops / (chi_ms32 * 1e-3) / 1e12,
+            "chi0_frac_of_bf16_peak_x3": 3 * flops / (chi_ms32 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+            "epsinv_rel_err_vs_fp64": err_inv, "chi0_rel_err_vs_fp64": err_chi,
+            "dtype": "c64 transforms, split-bf16x3 contraction, f64 eps^-1",
+            "stage_ms": {k: round(v[1], 4) for k, v in sorted(kt32.items())},
+        }
+        del d32, o32
+    ctx.close()
+
+    # ---------------- CPU oracle baseline
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(sysd, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * gw.h -- C ABI of libgwspinor: the Epsilon-stage hot path of fully
+ * relativistic (two-component spinor) GW on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Sec. II of arXiv:2206.00808 ("Spinor Wavefunctions in
+ * Many-Body Perturbation Theory"):
+ *   M_vc(q+G)   = sum_alpha <v,k+q,alpha| e^{i(q+G).r} |c,k,alpha>
+ *                 computed by transforming the spin-summed real-space product
+ *                 (the matrix-element definition and Eq. (matrix_el));
+ *   chi0_GG'    = (1/N_k) sum_{v,c} M*_vc(G) M_vc(G') [Adler-Wiser bracket]
+ *                 on the imaginary axis w = i*omega, eta = 0
+ *                 (the polarizability P_GG'(q,w));
+ *   eps_GG'     = delta_GG' - v(q+G) chi0_GG'  and its inverse
+ *                 (the dielectric-matrix definition; the Performance section
+ *                 names the inversion as a large share of Epsilon's time).
+ *
+ * Conventions shared by every entry point
+ *   - Energies in Hartree.  G vectors are integer triples g (the Cartesian
+ *     vector is 2*pi*(g + k)/a on an orthorhombic cell; the library never needs a).
+ *   - Complex numbers are interleaved (re, im).  GW_C128 = two doubles,
+ *     GW_C64 = two floats.  All arrays are row-major, last index fastest.
+ *   - "(device)" pointers are HIP device memory owned by the caller; the
+ *     library never frees or retains them past the call.  "(host)" pointers are
+ *     read during the call only.
+ *   - Every call is enqueued on the context's HIP stream and is asynchronous
+ *     with respect to the host unless stated otherwise.
+ *   - Arguments are validated on the host before anything is enqueued; on an
+ *     error status no output has been touched.  gw_last_error() returns a
+ *     per-context message describing the last non-OK status.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Contexts allocate their own device workspace (grown on demand, freed by
+ *     gw_ctx_destroy).  Calls overlapping on one context race on it.
+ */
+#ifndef GW_SPINOR_H
+#define GW_SPINOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GW_OK = 0,
+  GW_EINVAL = -1,        /* bad argument (size, null pointer, enum value) */
+  GW_ENOMEM = -2,        /* device workspace allocation failed */
+  GW_EDEVICE = -3,       /* no usable HIP device, or a HIP runtime error */
+  GW_EALIAS = -4,        /* FFT box too small: the pair product aliases onto an eps G */
+  GW_ESINGULAR = -5,     /* a zero pivot in the LU factorisation of eps */
+  GW_ENOTTRAINED = -6,   /* closure inference requested from an untrained network */
+  GW_EUNSUPPORTED = -7,  /* valid request this build does not implement */
+  GW_EFALLBACK = 1       /* not an error: the closure fell back to the full band sum */
+} gw_status;
+
+typedef enum { GW_C128 = 0, GW_C64 = 1 } gw_dtype;
+
+/* Contraction precision for chi0 (gw_chi0_accumulate):
+ *   GW_PREC_FP64      complex double products, double accumulation;
+ *   GW_PREC_SPLITBF16 each float component x is split into hi = bf16(x) and
+ *                     lo = bf16(x - hi) (round to nearest even); every real
+ *                     product is hi*hi + hi*lo + lo*hi on BF16 matrix cores with
+ *                     float accumulation inside a K-chunk, chunks summed in double.
+ *                     Requires GW_C64 matrix elements.                            */
+typedef enum { GW_PREC_FP64 = 0, GW_PREC_SPLITBF16 = 1 } gw_prec;
+
+typedef struct gw_ctx gw_ctx;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (may be
+ * NULL = the null stream).  Returns GW_EDEVICE when no device is usable. */
+gw_status gw_ctx_create(gw_ctx** ctx, int device, void* hip_stream);
+gw_status gw_ctx_destroy(gw_ctx* ctx);
+/* Change the stream later calls are enqueued on. */
+gw_status gw_ctx_set_stream(gw_ctx* ctx, void* hip_stream);
+/* Message for the last non-OK status on this context ("" if none).  The string
+ * is owned by the context and valid until its next call. */
+const char* gw_last_error(const gw_ctx* ctx);
+/* Static name of a status code. */
+const char* gw_status_string(gw_status s);
+
+/* Per-kernel timing.  When enabled, every kernel the library launches is
+ * bracketed by HIP events on the context stream; gw_ctx_profile_entry
+ * synchronises the stream and reports, per kernel name, the launch count and
+ * the summed event time in milliseconds.  Disabled by default. */
+gw_status gw_ctx_profile(gw_ctx* ctx, int enable);
+gw_status gw_ctx_profile_reset(gw_ctx* ctx);
+int gw_ctx_profile_count(gw_ctx* ctx);
+gw_status gw_ctx_profile_entry(gw_ctx* ctx, int i, const char** name, int* launches,
+                               double* total_ms);
+
+/*
+ * gw_mtxel_spinor -- plane-wave matrix elements of a spinor band pair
+ * (Sec. II, definition of M_nn'(k,q,G) and Eq. (matrix_el)).
+ *
+ * For every valence band v at k+q and conduction band c at k:
+ *   u_n^s(r_j) = sum_{G in sphere} c_n^s(G) exp(+2 pi i g.j/n)          (band to grid)
+ *   rho_vc(r)  = sum_{s=1..nspinor} conj(u_v^s(r)) u_c^s(r)            (spin-summed product)
+ *   M_vc(G)    = (1/N) sum_j rho_vc(r_j) exp(+2 pi i g.j/n),  G in geps (pruned transform)
+ * The spin sum is taken before the transform; by linearity this equals the
+ * paper's per-spin transforms followed by the spin sum.
+ *
+ *   box        (host) int[3] FFT grid n1 x n2 x n3; each n_i must factor into 2, 3, 5.
+ *   nspinor    1 (spinless) or 2 (spinor).
+ *   nv, ngv    valence band count and wavefunction-sphere size at k+q.
+ *   gv         (host) int32[ngv][3] G vectors of the k+q sphere.
+ *   cv         (device) complex[nv][nspinor][ngv] coefficients, dtype `dtype`.
+ *   nc, ngc, gc, cc   the same for the conduction bands at k.
+ *   neps       size of the dielectric sphere;  geps (host) int32[neps][3].
+ *   dtype      GW_C128 (double transforms) or GW_C64 (float transforms).
+ *   mtxel      (device) out complex[nv][nc][neps], dtype `dtype`; pair p = v*nc + c.
+ *   head_index index of G = 0 in geps for the small-q head, or -1.
+ *   mhead      (device) out complex double[nv*nc]: M_vc(G=0) by the direct
+ *              double-precision overlap sum_s sum_G conj(c_v^s(G)) c_c^s(G); NULL to skip.
+ * Errors: GW_EINVAL (sizes, a G vector outside the box, duplicate G), GW_EALIAS
+ * when some n_i <= max|gv_i| + max|gc_i| + max|geps_i|, GW_ENOMEM.
+ */
+gw_status gw_mtxel_spinor(gw_ctx* ctx, const int box[3], int nspinor,
+                          int nv, int ngv, const int32_t* gv, const void* cv,
+                          int nc, int ngc, const int32_t* gc, const void* cc,
+                          int neps, const int32_t* geps, gw_dtype dtype,
+                          void* mtxel, int head_index, double* mhead);
+
+/*
+ * gw_chi0_accumulate -- chi0_f[G][G'] += prefactor * sum_p w_p(omega_f) conj(M_p(G)) M_p(G')
+ * (Sec. II, the Adler-Wiser polarizability at imaginary frequency, eta = 0):
+ *   w_p(omega) = 1/(D_p - i omega) + 1/(D_p + i omega) = 2 D_p / (D_p^2 + omega^2),
+ *   D_p = ev[v] - ec[c],  p = v*nc + c.
+ *
+ *   mtxel      (device) complex[nv*nc][neps] of dtype `dtype` (as written by gw_mtxel_spinor).
+ *   ev, ec     (device) double[nv], double[nc].
+ *   nfreq      number of frequencies; omega (host) double[nfreq], each >= 0 (0 = static).
+ *   prefactor  1/N_k.
+ *   prec       GW_PREC_FP64 (any dtype; c64 inputs are widened) or GW_PREC_SPLITBF16 (c64 only).
+ *   mhead      (device) complex double[nv*nc] FP64 head elements or NULL; when given
+ *              together with head_index >= 0, row and column head_index of chi0
+ *              are accumulated in double from mhead (head) and mhead x mtxel (wings).
+ *   chi0       (device) in/out complex double[nfreq][neps][neps]; the update is added.
+ * chi0's update is Hermitian; only upper tiles are computed and mirrored.
+ */
+gw_status gw_chi0_accumulate(gw_ctx* ctx, int nv, int nc, int neps,
+                             const void* mtxel, gw_dtype dtype,
+                             const double* ev, const double* ec,
+                             int nfreq, const double* omega, double prefactor,
+                             gw_prec prec, const double* mhead, int head_index,
+                             double* chi0);
+
+/*
+ * gw_epsinv -- eps_f = I - diag(vcoul) chi0_f, then eps_f^-1 by LU factorisation
+ * with partial pivoting (row interchanges, largest |re|+|im| in the column,
+ * lowest index on ties) followed by forward and back substitution on the
+ * permuted identity, all in double (Sec. II, dielectric matrix and W = eps^-1 v).
+ *
+ *   chi0    (device) complex double[nfreq][neps][neps].
+ *   vcoul   (device) double[neps], v(q+G) = 4 pi / (Omega |q+G|^2).
+ *   epsinv  (device) out complex double[nfreq][neps][neps]; may not alias chi0.
+ * Synchronises the context stream to read the singular flag: GW_ESINGULAR if
+ * any pivot of any frequency was exactly zero (epsinv then holds non-finite values).
+ */
+gw_status gw_epsinv(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
+                    const double* vcoul, double* epsinv);
+
+/* ------------------------------------------------------------------------ */
+/* Learned closure of the truncated conduction-band sum.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct gw_mlp gw_mlp;
+
+typedef enum {
+  GW_CLOSURE_INFER = 0,         /* chi0_out = chi0_trunc + Hermitised network remainder */
+  GW_CLOSURE_TRAIN_STEP = 1,    /* one Adam step on the MSE to (chi0_full - chi0_trunc) */
+  GW_CLOSURE_FULL_FALLBACK = 2  /* chi0_out = chi0_full (the full band sum) */
+} gw_closure_mode;
+
+/* Network: nin -> depth hidden layers of `width` (SiLU) -> nout, weights
+ * initialised from `seed`.  bf16 matrix-core products, float master weights. */
+gw_status gw_mlp_create(gw_ctx* ctx, gw_mlp** net, int nin, int width, int depth,
+                        int nout, uint64_t seed);
+gw_status gw_mlp_destroy(gw_mlp* net);
+/* Serialise float master weights and Adam state to a host buffer.  Call with
+ * host_buf = NULL to query *nbytes. */
+gw_status gw_mlp_save(const gw_mlp* net, void* host_buf, size_t* nbytes);
+gw_status gw_mlp_load(gw_mlp* net, const void* host_buf, size_t nbytes);
+
+/*
+ * gw_chi0_closure -- predict the remainder chi0_full - chi0_trunc of one
+ * (q, omega = 0) matrix from per-(G,G') features (G <= G' only):
+ *   |q+G|, |q+G'|, (q+G).(q+G')... see the design notes for the exact list:
+ *   |q+G|, |q+G'|, G.G' (Cartesian), Re chi0_trunc, Im chi0_trunc, gap, emax.
+ *   qG          (device) double[neps][3] Cartesian q+G.
+ *   chi0_trunc  (device) complex double[neps][neps].
+ *   chi0_full   (device) complex double[neps][neps]: training target
+ *               (TRAIN_STEP) or the fallback value (FULL_FALLBACK / fallback check).
+ *   lr          Adam learning rate (TRAIN_STEP).
+ *   loss        (host) out float: the MSE before the step, or NULL.
+ *   chi0_out    (device) out complex double[neps][neps] (INFER, FULL_FALLBACK).
+ * In INFER mode, if the corrected matrix is not negative semidefinite (a
+ * double-precision Cholesky of -chi0_out fails) and chi0_full is given, the
+ * full sum is written instead and GW_EFALLBACK is returned.
+ */
+gw_status gw_chi0_closure(gw_ctx* ctx, gw_mlp* net, int mode, int neps,
+                          const double* qG, const double* chi0_trunc, double gap,
+                          double emax, const double* chi0_full, float lr, float* loss,
+                          double* chi0_out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched many-q plan: one captured graph over every q.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct gw_plan gw_plan;
+
+/* Per-q description (host struct; the pointers it holds are device pointers
+ * except gv/gc/geps, which are host). */
+typedef struct {
+  int nv, ngv;  const int32_t* gv;  const void* cv;    /* valence at k+q */
+  int nc, ngc;  const int32_t* gc;  const void* cc;    /* conduction at k */
+  int neps;     const int32_t* geps;
+  const double* ev;  const double* ec;                 /* (device) energies */
+  const double* vcoul;                                 /* (device) v(q+G) */
+  int head_index;                                      /* G = 0 index or -1 */
+  double* chi0;                                        /* (device) out [nfreq][neps][neps] */
+  double* epsinv;                                      /* (device) out [nfreq][neps][neps] */
+} gw_q_desc;
+
+/* All q share box, nspinor, dtype, precision and frequencies. */
+gw_status gw_plan_create(gw_ctx* ctx, gw_plan** plan, const int box[3], int nspinor,
+                         gw_dtype dtype, gw_prec prec, int nfreq, const double* omega,
+                         double prefactor, int nq, const gw_q_desc* q);
+/* Autotune tile shapes (timed trial launches) and capture every stage of every
+ * q into one HIP graph.  Allocates all workspace. */
+gw_status gw_plan_compile(gw_plan* plan);
+/* Replay the graph on the context stream; synchronises and reports
+ * GW_ESINGULAR if any q's eps had a zero pivot. */
+gw_status gw_plan_launch(gw_plan* plan);
+gw_status gw_plan_destroy(gw_plan* plan);
+/* Autotuner result for the plan as a short text (valid until the plan is destroyed). */
+const char* gw_plan_describe(const gw_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GW_SPINOR_H */

@@ -1,0 +1,218 @@
+"""ctypes binding of libgwspinor (include/gw.h): argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and passes
+torch device tensors by pointer; all computation happens in the library's HIP
+kernels.  The library must be built (``paper_2206_00808_amd.build.build()``);
+importing this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libgwspinor.so")
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE = 0, -1, -2, -3
+GW_EALIAS, GW_ESINGULAR, GW_ENOTTRAINED, GW_EUNSUPPORTED, GW_EFALLBACK = -4, -5, -6, -7, 1
+GW_C128, GW_C64 = 0, 1
+GW_PREC_FP64, GW_PREC_SPLITBF16 = 0, 1
+GW_CLOSURE_INFER, GW_CLOSURE_TRAIN_STEP, GW_CLOSURE_FULL_FALLBACK = 0, 1, 2
+
+EXPORTED = [
+    "gw_ctx_create", "gw_ctx_destroy", "gw_ctx_set_stream", "gw_last_error", "gw_status_string",
+    "gw_ctx_profile", "gw_ctx_profile_reset", "gw_ctx_profile_count", "gw_ctx_profile_entry",
+    "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv",
+    "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
+    "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
+]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2206_00808_amd.build.build() "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ct.CDLL(LIB_PATH)
+
+_vp, _i, _d, _u64 = ct.c_void_p, ct.c_int, ct.c_double, ct.c_uint64
+_ip = ct.POINTER(ct.c_int)
+
+
+class QDesc(ct.Structure):
+    _fields_ = [
+        ("nv", _i), ("ngv", _i), ("gv", _vp), ("cv", _vp),
+        ("nc", _i), ("ngc", _i), ("gc", _vp), ("cc", _vp),
+        ("neps", _i), ("geps", _vp),
+        ("ev", _vp), ("ec", _vp), ("vcoul", _vp),
+        ("head_index", _i), ("chi0", _vp), ("epsinv", _vp),
+    ]
+
+
+_SIG = {
+    "gw_ctx_create": (_i, [ct.POINTER(_vp), _i, _vp]),
+    "gw_ctx_destroy": (_i, [_vp]),
+    "gw_ctx_set_stream": (_i, [_vp, _vp]),
+    "gw_last_error": (ct.c_char_p, [_vp]),
+    "gw_status_string": (ct.c_char_p, [_i]),
+    "gw_ctx_profile": (_i, [_vp, _i]),
+    "gw_ctx_profile_reset": (_i, [_vp]),
+    "gw_ctx_profile_count": (_i, [_vp]),
+    "gw_ctx_profile_entry": (_i, [_vp, _i, ct.POINTER(ct.c_char_p), _ip, ct.POINTER(_d)]),
+    "gw_mtxel_spinor": (_i, [_vp, _ip, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp, _i, _vp, _i,
+                             _vp, _i, _vp]),
+    "gw_chi0_accumulate": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _i, _vp, _i,
+                                _vp]),
+    "gw_epsinv": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_mlp_create": (_i, [_vp, ct.POINTER(_vp), _i, _i, _i, _i, _u64]),
+    "gw_mlp_destroy": (_i, [_vp]),
+    "gw_mlp_save": (_i, [_vp, _vp, ct.POINTER(ct.c_size_t)]),
+    "gw_mlp_load": (_i, [_vp, _vp, ct.c_size_t]),
+    "gw_chi0_closure": (_i, [_vp, _vp, _i, _i, _vp, _vp, _d, _d, _vp, ct.c_float,
+                             ct.POINTER(ct.c_float), _vp]),
+    "gw_plan_create": (_i, [_vp, ct.POINTER(_vp), _ip, _i, _i, _i, _i, _vp, _d, _i,
+                            ct.POINTER(QDesc)]),
+    "gw_plan_compile": (_i, [_vp]),
+    "gw_plan_launch": (_i, [_vp]),
+    "gw_plan_destroy": (_i, [_vp]),
+    "gw_plan_describe": (ct.c_char_p, [_vp]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class GwError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+def status_string(s):
+    return _lib.gw_status_string(int(s)).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _host_i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a
+
+
+def _check(ctx, status, ok=(GW_OK,)):
+    if status not in ok:
+        raise GwError(status, _lib.gw_last_error(ctx.handle).decode() if ctx else "")
+    return status
+
+
+class Context:
+    """Owns a gw_ctx on one HIP device; calls run on torch's current stream."""
+
+    def __init__(self, device=0):
+        h = _vp()
+        s = _lib.gw_ctx_create(ct.byref(h), int(device), None)
+        if s != GW_OK:
+            raise GwError(s, "gw_ctx_create failed (no usable HIP device?)")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_stream(self):
+        import torch
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.gw_ctx_set_stream(self.handle, ct.c_void_p(st))
+
+    # profiling -------------------------------------------------------------
+    def profile(self, enable=True):
+        _check(self, _lib.gw_ctx_profile(self.handle, 1 if enable else 0))
+
+    def profile_reset(self):
+        _check(self, _lib.gw_ctx_profile_reset(self.handle))
+
+    def profile_table(self):
+        out = {}
+        n = _lib.gw_ctx_profile_count(self.handle)
+        for i in range(n):
+            name = ct.c_char_p()
+            launches = ct.c_int()
+            ms = ct.c_double()
+            _check(self, _lib.gw_ctx_profile_entry(self.handle, i, ct.byref(name),
+                                                   ct.byref(launches), ct.byref(ms)))
+            out[name.value.decode()] = (launches.value, ms.value)
+        return out
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return GW_C128
+    if t.dtype == torch.complex64:
+        return GW_C64
+    raise TypeError(f"complex128 or complex64 expected, got {t.dtype}")
+
+
+def gw_mtxel_spinor(ctx, box, nspinor, gv, cv, gc, cc, geps, mtxel, head_index=-1, mhead=None):
+    """M[v][c][G] on the eps sphere (see include/gw.h).  gv/gc/geps: host int arrays [n][3];
+    cv [nv][nspinor][ngv], cc [nc][nspinor][ngc], mtxel [nv][nc][neps]: device tensors."""
+    ctx.sync_stream()
+    box_a = (ct.c_int * 3)(*[int(x) for x in box])
+    gv, gc, geps = _host_i32(gv), _host_i32(gc), _host_i32(geps)
+    nv, nc, neps = cv.shape[0], cc.shape[0], geps.shape[0]
+    for t in (cv, cc, mtxel):
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+    dt = _dtype_code(cv)
+    if _dtype_code(cc) != dt or _dtype_code(mtxel) != dt:
+        raise TypeError("cv, cc and mtxel must share one complex dtype")
+    if tuple(mtxel.shape) != (nv, nc, neps):
+        raise ValueError(f"mtxel shape {tuple(mtxel.shape)} != {(nv, nc, neps)}")
+    if cv.shape[1] != nspinor or cc.shape[1] != nspinor:
+        raise ValueError("spinor dimension mismatch")
+    if cv.shape[2] != gv.shape[0] or cc.shape[2] != gc.shape[0]:
+        raise ValueError("sphere size mismatch")
+    s = _lib.gw_mtxel_spinor(ctx.handle, ct.cast(box_a, _ip), int(nspinor), nv, gv.shape[0],
+                             gv.ctypes.data, _ptr(cv), nc, gc.shape[0], gc.ctypes.data, _ptr(cc),
+                             neps, geps.ctypes.data, dt, _ptr(mtxel), int(head_index),
+                             _ptr(mhead))
+    return _check(ctx, s)
+
+
+def gw_chi0_accumulate(ctx, nv, nc, neps, mtxel, ev, ec, omega, prefactor, prec, chi0,
+                       mhead=None, head_index=-1):
+    """chi0[f] += prefactor * sum_p w_p(omega_f) conj(M_p) M_p^T (see include/gw.h)."""
+    ctx.sync_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    dt = _dtype_code(mtxel)
+    s = _lib.gw_chi0_accumulate(ctx.handle, int(nv), int(nc), int(neps), _ptr(mtxel), dt,
+                                _ptr(ev), _ptr(ec), len(om), om.ctypes.data, float(prefactor),
+                                int(prec), _ptr(mhead), int(head_index), _ptr(chi0))
+    return _check(ctx, s)
+
+
+def gw_epsinv(ctx, neps, nfreq, chi0, vcoul, epsinv):
+    """epsinv[f] = (I - diag(vcoul) chi0[f])^-1 (see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_epsinv(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul), _ptr(epsinv))
+    return _check(ctx, s)
+
+
+def raw():
+    """The loaded ctypes library (for tests of the exported symbol table)."""
+    return _lib

@@ -1,0 +1,404 @@
+// C ABI of libgwspinor: argument validation, device tables, workspace,
+// per-kernel event timing, and the entry points declared in include/gw.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <set>
+#include <tuple>
+
+#include "common.h"
+
+namespace gw {
+
+gw_status fail(gw_ctx* c, gw_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what) {
+  const gw_status s = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? GW_ENOMEM
+                                                                                  : GW_EDEVICE;
+  return fail(c, s, "%s: %s", what, hipGetErrorString(e));
+}
+
+gw_status ws_begin(gw_ctx* c, size_t total) {
+  total = align_up(total + 256);
+  if (total > c->ws_cap) {
+    if (c->ws) {
+      hipError_t e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      (void)hipFree(c->ws);
+      c->ws = nullptr;
+      c->ws_cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) return fail(c, GW_ENOMEM, "workspace of %zu bytes: %s", total,
+                                     hipGetErrorString(e));
+    c->ws = static_cast<char*>(p);
+    c->ws_cap = total;
+  }
+  c->ws_used = 0;
+  return GW_OK;
+}
+
+void* ws_take(gw_ctx* c, size_t bytes) {
+  void* p = c->ws + c->ws_used;
+  c->ws_used += align_up(bytes);
+  return p;
+}
+
+static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], SphereMap** out) {
+  char key[96];
+  const uint64_t h = fnv1a(g, (size_t)n * 3 * sizeof(int32_t));
+  snprintf(key, sizeof key, "%d:%d:%d:%d:%016llx", box[0], box[1], box[2], n,
+           (unsigned long long)h);
+  auto it = c->spheres.find(key);
+  if (it != c->spheres.end()) { *out = &it->second; return GW_OK; }
+  SphereMap sm;
+  sm.n = n;
+  for (int a = 0; a < 3; ++a) sm.gmax[a] = 0;
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) sm.gmax[a] = std::max(sm.gmax[a], std::abs(g[3 * i + a]));
+  for (int a = 0; a < 3; ++a) {
+    sm.ext[a] = 2 * sm.gmax[a] + 1;
+    if (sm.ext[a] > box[a])
+      return fail(c, GW_EINVAL, "G vectors span %d points along axis %d but the box has %d",
+                  sm.ext[a], a, box[a]);
+  }
+  const size_t ncube = (size_t)sm.ext[0] * sm.ext[1] * sm.ext[2];
+  std::vector<int> cube(ncube, -1);
+  for (int i = 0; i < n; ++i) {
+    const size_t idx = ((size_t)(g[3 * i] + sm.gmax[0]) * sm.ext[1] + (g[3 * i + 1] + sm.gmax[1])) *
+                           sm.ext[2] + (g[3 * i + 2] + sm.gmax[2]);
+    if (cube[idx] >= 0) return fail(c, GW_EINVAL, "duplicate G vector at index %d", i);
+    cube[idx] = i;
+  }
+  GW_HIP(c, hipMalloc(&sm.d_cube, ncube * sizeof(int)));
+  GW_HIP(c, hipMemcpy(sm.d_cube, cube.data(), ncube * sizeof(int), hipMemcpyHostToDevice));
+  auto res = c->spheres.emplace(key, sm);
+  *out = &res.first->second;
+  return GW_OK;
+}
+
+ProfScope::ProfScope(gw_ctx* cc, const char* nm) : c(cc), name(nm) {
+  if (!c->profiling) return;
+  auto get = [&]() {
+    hipEvent_t e;
+    if (!c->ev_pool.empty()) { e = c->ev_pool.back(); c->ev_pool.pop_back(); }
+    else (void)hipEventCreate(&e);
+    return e;
+  };
+  a = get();
+  b = get();
+  (void)hipEventRecord(a, c->stream);
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  (void)hipEventRecord(b, c->stream);
+  c->prof_pending.push_back(ProfRec{name, a, b});
+}
+
+static void prof_collect(gw_ctx* c) {
+  if (c->prof_pending.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof_pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    auto it = c->prof.find(r.name);
+    if (it == c->prof.end()) {
+      c->prof_names.push_back(r.name);
+      it = c->prof.emplace(r.name, ProfAcc{}).first;
+    }
+    it->second.launches += 1;
+    it->second.ms += ms;
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+}
+
+static bool factorable(int n) {
+  if (n <= 0) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+static bool g_ok(const int32_t* g, int n) { return n == 0 || g != nullptr; }
+
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" {
+
+const char* gw_status_string(gw_status s) {
+  switch (s) {
+    case GW_OK: return "GW_OK";
+    case GW_EINVAL: return "GW_EINVAL";
+    case GW_ENOMEM: return "GW_ENOMEM";
+    case GW_EDEVICE: return "GW_EDEVICE";
+    case GW_EALIAS: return "GW_EALIAS";
+    case GW_ESINGULAR: return "GW_ESINGULAR";
+    case GW_ENOTTRAINED: return "GW_ENOTTRAINED";
+    case GW_EUNSUPPORTED: return "GW_EUNSUPPORTED";
+    case GW_EFALLBACK: return "GW_EFALLBACK";
+  }
+  return "GW_UNKNOWN";
+}
+
+gw_status gw_ctx_create(gw_ctx** out, int device, void* stream) {
+  if (!out) return GW_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GW_EDEVICE;
+  if (device < 0 || device >= ndev) return GW_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return GW_EDEVICE;
+  gw_ctx* c = new gw_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipMalloc(&c->d_flag, 64) != hipSuccess) { delete c; return GW_ENOMEM; }
+  if (hipMemset(c->d_flag, 0, 64) != hipSuccess) { (void)hipFree(c->d_flag); delete c; return GW_EDEVICE; }
+  *out = c;
+  return GW_OK;
+}
+
+gw_status gw_ctx_destroy(gw_ctx* c) {
+  if (!c) return GW_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->spheres) (void)hipFree(kv.second.d_cube);
+  for (auto& kv : c->twiddles) (void)hipFree(kv.second);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->d_flag) (void)hipFree(c->d_flag);
+  delete c;
+  return GW_OK;
+}
+
+gw_status gw_ctx_set_stream(gw_ctx* c, void* stream) {
+  if (!c) return GW_EINVAL;
+  c->stream = static_cast<hipStream_t>(stream);
+  return GW_OK;
+}
+
+const char* gw_last_error(const gw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+gw_status gw_ctx_profile(gw_ctx* c, int enable) {
+  if (!c) return GW_EINVAL;
+  c->profiling = enable != 0;
+  return GW_OK;
+}
+
+gw_status gw_ctx_profile_reset(gw_ctx* c) {
+  if (!c) return GW_EINVAL;
+  prof_collect(c);
+  c->prof.clear();
+  c->prof_names.clear();
+  return GW_OK;
+}
+
+int gw_ctx_profile_count(gw_ctx* c) {
+  if (!c) return 0;
+  prof_collect(c);
+  return (int)c->prof_names.size();
+}
+
+gw_status gw_ctx_profile_entry(gw_ctx* c, int i, const char** name, int* launches,
+                               double* total_ms) {
+  if (!c) return GW_EINVAL;
+  prof_collect(c);
+  if (i < 0 || i >= (int)c->prof_names.size()) return fail(c, GW_EINVAL, "profile index %d", i);
+  const auto& nm = c->prof_names[i];
+  const auto& acc = c->prof[nm];
+  if (name) *name = nm.c_str();
+  if (launches) *launches = acc.launches;
+  if (total_ms) *total_ms = acc.ms;
+  return GW_OK;
+}
+
+gw_status gw_mtxel_spinor(gw_ctx* c, const int box[3], int nspinor, int nv, int ngv,
+                          const int32_t* gv, const void* cv, int nc, int ngc, const int32_t* gc,
+                          const void* cc, int neps, const int32_t* geps, gw_dtype dtype,
+                          void* mtxel, int head_index, double* mhead) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (!box) return fail(c, GW_EINVAL, "box is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!factorable(box[a]))
+      return fail(c, GW_EINVAL, "box[%d] = %d must be a positive product of 2, 3 and 5", a, box[a]);
+  if (box[0] > 4096 || box[1] > 4096 || box[2] > 4096)
+    return fail(c, GW_EINVAL, "box dimension above 4096");
+  if (nspinor != 1 && nspinor != 2) return fail(c, GW_EINVAL, "nspinor must be 1 or 2");
+  if (nv < 0 || nc < 0 || neps < 0 || ngv < 0 || ngc < 0)
+    return fail(c, GW_EINVAL, "negative size");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (nv == 0 || nc == 0 || neps == 0) return GW_OK;
+  if (ngv == 0 || ngc == 0) return fail(c, GW_EINVAL, "empty wavefunction sphere");
+  if (!g_ok(gv, ngv) || !g_ok(gc, ngc) || !g_ok(geps, neps) || !cv || !cc || !mtxel)
+    return fail(c, GW_EINVAL, "NULL array argument");
+  if (head_index >= neps) return fail(c, GW_EINVAL, "head_index %d >= neps %d", head_index, neps);
+  if (head_index >= 0 &&
+      (geps[3 * head_index] != 0 || geps[3 * head_index + 1] != 0 || geps[3 * head_index + 2] != 0))
+    return fail(c, GW_EINVAL, "geps[head_index] is not G = 0");
+  if ((long long)nv * nc > (1LL << 31) / 2) return fail(c, GW_EINVAL, "too many pairs");
+  (void)hipSetDevice(c->device);
+
+  SphereMap *sv, *sc, *se;
+  gw_status st;
+  if ((st = sphere_map(c, gv, ngv, box, &sv)) != GW_OK) return st;
+  if ((st = sphere_map(c, gc, ngc, box, &sc)) != GW_OK) return st;
+  if ((st = sphere_map(c, geps, neps, box, &se)) != GW_OK) return st;
+  for (int a = 0; a < 3; ++a)
+    if (box[a] <= sv->gmax[a] + sc->gmax[a] + se->gmax[a])
+      return fail(c, GW_EALIAS,
+                  "box[%d] = %d <= %d + %d + %d: the pair product would alias onto an eps G", a,
+                  box[a], sv->gmax[a], sc->gmax[a], se->gmax[a]);
+
+  const size_t elem = dtype == GW_C128 ? 16 : 8;
+  const size_t nbox = (size_t)box[0] * box[1] * box[2];
+  const size_t uv_bytes = (size_t)nv * nspinor * nbox * elem;
+  const size_t uc_bytes = (size_t)nc * nspinor * nbox * elem;
+  // band scratch: a chunk of band-spins of the compact x-pass output
+  const size_t band_per = band_scratch_bytes(box, sv, 1, elem) > band_scratch_bytes(box, sc, 1, elem)
+                              ? band_scratch_bytes(box, sv, 1, elem)
+                              : band_scratch_bytes(box, sc, 1, elem);
+  const int nbs_max = std::max(nv, nc) * nspinor;
+  const int band_chunk = (int)std::max<size_t>(1, std::min<size_t>(nbs_max, (512ull << 20) / band_per));
+  const size_t band_bytes = band_per * band_chunk;
+  // pair scratch: all valence bands times a tile of conduction bands
+  const size_t pair_per = pair_scratch_bytes(box, se, 1, elem);
+  size_t pair_budget = 1ull << 30;
+  int max_pairs = (int)std::max<size_t>(1, pair_budget / pair_per);
+  if (max_pairs > 65535) max_pairs = 65535;
+  int vt = std::min(nv, max_pairs);
+  int ct = std::max(1, std::min(nc, max_pairs / vt));
+  const size_t pair_bytes = pair_per * (size_t)vt * ct;
+  // head match list
+  std::vector<int> match;
+  if (mhead) {
+    std::map<std::tuple<int, int, int>, int> lut;
+    for (int i = 0; i < ngc; ++i) lut[std::make_tuple(gc[3 * i], gc[3 * i + 1], gc[3 * i + 2])] = i;
+    for (int i = 0; i < ngv; ++i) {
+      auto it = lut.find(std::make_tuple(gv[3 * i], gv[3 * i + 1], gv[3 * i + 2]));
+      if (it != lut.end()) { match.push_back(i); match.push_back(it->second); }
+    }
+  }
+  const size_t match_bytes = match.size() * sizeof(int) + 16;
+  st = ws_begin(c, align_up(uv_bytes) + align_up(uc_bytes) + align_up(band_bytes) +
+                       align_up(pair_bytes) + align_up(match_bytes));
+  if (st != GW_OK) return st;
+  void* uv = ws_take(c, uv_bytes);
+  void* uc = ws_take(c, uc_bytes);
+  void* bscr = ws_take(c, band_bytes);
+  void* pscr = ws_take(c, pair_bytes);
+  int* dmatch = static_cast<int*>(ws_take(c, match_bytes));
+
+  if (dtype == GW_C128) {
+    if ((st = band_to_grid<double>(c, box, nv * nspinor, ngv, cv, sv, uv, bscr, band_bytes)) != GW_OK) return st;
+    if ((st = band_to_grid<double>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes)) != GW_OK) return st;
+  } else {
+    if ((st = band_to_grid<float>(c, box, nv * nspinor, ngv, cv, sv, uv, bscr, band_bytes)) != GW_OK) return st;
+    if ((st = band_to_grid<float>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes)) != GW_OK) return st;
+  }
+  for (int v0 = 0; v0 < nv; v0 += vt) {
+    const int nvt = std::min(vt, nv - v0);
+    for (int c0 = 0; c0 < nc; c0 += ct) {
+      const int nct = std::min(ct, nc - c0);
+      if (dtype == GW_C128)
+        st = pair_to_eps<double>(c, box, nspinor, uv, uc, v0, nvt, c0, nct, nc, se, mtxel, pscr);
+      else
+        st = pair_to_eps<float>(c, box, nspinor, uv, uc, v0, nvt, c0, nct, nc, se, mtxel, pscr);
+      if (st != GW_OK) return st;
+    }
+  }
+  if (mhead) {
+    const int nm = (int)match.size() / 2;
+    if (nm > 0) {
+      GW_HIP(c, hipMemcpyAsync(dmatch, match.data(), match.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream));
+      if ((st = head_overlap(c, dtype, nspinor, nv, ngv, cv, nc, ngc, cc, dmatch, nm, mhead)) != GW_OK)
+        return st;
+    } else {
+      GW_HIP(c, hipMemsetAsync(mhead, 0, (size_t)nv * nc * 16, c->stream));
+    }
+    // the pageable copy above must complete before the host vector dies
+    GW_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return GW_OK;
+}
+
+gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mtxel,
+                             gw_dtype dtype, const double* ev, const double* ec, int nfreq,
+                             const double* omega, double prefactor, gw_prec prec,
+                             const double* mhead, int head_index, double* chi0) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (nv < 0 || nc < 0 || neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (prec != GW_PREC_FP64 && prec != GW_PREC_SPLITBF16) return fail(c, GW_EINVAL, "unknown precision");
+  if (prec == GW_PREC_SPLITBF16 && dtype != GW_C64)
+    return fail(c, GW_EINVAL, "split-BF16 contraction needs GW_C64 matrix elements");
+  if (nv == 0 || nc == 0 || neps == 0 || nfreq == 0) return GW_OK;
+  if (!mtxel || !ev || !ec || !omega || !chi0) return fail(c, GW_EINVAL, "NULL array argument");
+  if (!std::isfinite(prefactor)) return fail(c, GW_EINVAL, "non-finite prefactor");
+  for (int f = 0; f < nfreq; ++f)
+    if (!(omega[f] >= 0.0) || !std::isfinite(omega[f]))
+      return fail(c, GW_EINVAL, "omega[%d] must be finite and >= 0", f);
+  if (head_index >= neps) return fail(c, GW_EINVAL, "head_index >= neps");
+  if ((long long)neps * neps > (1LL << 40)) return fail(c, GW_EINVAL, "neps too large");
+  (void)hipSetDevice(c->device);
+  const int P = nv * nc;
+  const bool use_head = mhead != nullptr && head_index >= 0;
+  gw_status st = ws_begin(c, align_up((size_t)nfreq * 8) + align_up((size_t)nfreq * P * 8));
+  if (st != GW_OK) return st;
+  double* d_om = static_cast<double*>(ws_take(c, (size_t)nfreq * 8));
+  double* wts = static_cast<double*>(ws_take(c, (size_t)nfreq * P * 8));
+  GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
+  if ((st = chi0_weights(c, nv, nc, ev, ec, nfreq, d_om, prefactor, wts)) != GW_OK) return st;
+  const int skip = use_head ? head_index : -1;
+  if (prec == GW_PREC_FP64)
+    st = chi0_fp64(c, P, neps, mtxel, dtype, nfreq, wts, skip, chi0);
+  else
+    st = chi0_splitbf16(c, P, neps, mtxel, nfreq, wts, skip, chi0);
+  if (st != GW_OK) return st;
+  if (use_head) {
+    if ((st = chi0_wings(c, P, neps, mtxel, dtype, mhead, head_index, nfreq, wts, chi0)) != GW_OK)
+      return st;
+  }
+  // omega was copied from pageable host memory: finish before returning
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  return GW_OK;
+}
+
+gw_status gw_epsinv(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
+                    double* epsinv) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (neps == 0 || nfreq == 0) return GW_OK;
+  if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
+  if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv may not alias chi0");
+  if (neps > 16384) return fail(c, GW_EINVAL, "neps above 16384");
+  if (nfreq > 65535) return fail(c, GW_EINVAL, "nfreq above 65535");
+  (void)hipSetDevice(c->device);
+  return epsinv_run(c, neps, nfreq, chi0, vcoul, epsinv);
+}
+
+}  // extern "C"

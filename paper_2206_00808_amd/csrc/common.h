@@ -1,0 +1,161 @@
+// Internal definitions shared by the libgwspinor translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gw.h"
+
+namespace gw {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cpx { T x, y; };
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mk(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> scal(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// multiply by +i
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return mk(-a.y, a.x); }
+
+// ---------------------------------------------------------------- FFT plan
+// Length n = product of radices (each 2, 3, 4 or 5), executed as Stockham passes.
+struct FftPlan {
+  int n;
+  int npass;
+  int radix[12];
+};
+FftPlan make_fft_plan(int n);  // n must factor into 2, 3, 5
+
+// ---------------------------------------------------------------- geometry
+// A G-sphere placed in a box: compact cube [2gx+1][2gy+1][2gz+1] -> sphere index or -1.
+struct SphereMap {
+  int gmax[3];
+  int ext[3];            // 2*gmax+1
+  int* d_cube = nullptr; // device int32[ext0*ext1*ext2]
+  int n = 0;             // sphere size
+};
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+struct ProfAcc {
+  int launches = 0;
+  double ms = 0.0;
+};
+
+}  // namespace gw
+
+struct gw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // growable workspace (bump sub-allocation per call)
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  size_t ws_used = 0;
+  // cached device tables
+  std::map<std::string, gw::SphereMap> spheres;
+  std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
+  int* d_flag = nullptr;                          // device status flags
+  // profiling
+  bool profiling = false;
+  std::vector<gw::ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  std::map<std::string, gw::ProfAcc> prof;
+  std::vector<std::string> prof_names;
+};
+
+namespace gw {
+
+gw_status fail(gw_ctx* c, gw_status s, const char* fmt, ...);
+gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what);
+
+// Workspace: reset at the start of a call, then carve aligned pieces.
+gw_status ws_begin(gw_ctx* c, size_t total_bytes);
+void* ws_take(gw_ctx* c, size_t bytes);
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Device tables.
+gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], SphereMap** out);
+gw_status twiddle_table(gw_ctx* c, int n, bool dbl, const void** out);
+
+// Profiling scope around a launch.
+struct ProfScope {
+  gw_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(gw_ctx* cc, const char* nm);
+  ~ProfScope();
+};
+
+#define GW_CHECK_LAUNCH(ctx, what)                                   \
+  do {                                                               \
+    hipError_t _e = hipGetLastError();                               \
+    if (_e != hipSuccess) return ::gw::hip_fail((ctx), _e, (what));  \
+  } while (0)
+
+#define GW_HIP(ctx, call)                                            \
+  do {                                                               \
+    hipError_t _e = (call);                                          \
+    if (_e != hipSuccess) return ::gw::hip_fail((ctx), _e, #call);   \
+  } while (0)
+
+// ---- launchers implemented in the kernel translation units ----
+// FFT stage (fft.hip)
+template <typename T>
+gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                       const SphereMap* sm, void* u_out, void* scratch, size_t scratch_bytes);
+template <typename T>
+gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, const void* uc,
+                      int v0, int nvt, int c0, int nct, int nc_total, const SphereMap* em,
+                      void* mtxel, void* scratch);
+size_t band_scratch_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
+size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem);
+
+// Head overlap (head.hip)
+gw_status head_overlap(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int ngv, const void* cv,
+                       int nc, int ngc, const void* cc, const int* d_match, int nmatch,
+                       double* mhead);
+gw_status chi0_wings(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt,
+                     const double* mhead, int head, int nfreq, const double* wts, double* chi0);
+
+// chi0 contraction (gemm.hip)
+gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double* ec, int nfreq,
+                       const double* d_omega, double pref, double* wts);
+gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
+                    const double* wts, int skip_head, double* chi0);
+gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
+                         const double* wts, int skip_head, double* chi0);
+// generic batched C[i][j] += alpha * sum_k A[i][k] B[k][j] (complex double, row-major)
+gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, int lda,
+                   long long sA, const double* B, int ldb, long long sB, double* C, int ldc,
+                   long long sC, int batch);
+
+// eps and its inverse (lu.hip)
+gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
+                     double* epsinv);
+
+}  // namespace gw

@@ -1,0 +1,429 @@
+// FFT stage of the spinor matrix elements (Sec. II, Eq. (matrix_el)).
+//
+//   band_to_grid : sphere coefficients -> periodic spinor components on the grid
+//                  u(r_j) = sum_G c(G) exp(+2 pi i g.j/n)            (input-pruned 3D FFT)
+//   pair_to_eps  : rho_vc = sum_s conj(u_v^s) u_c^s, then
+//                  M_vc(G) = (1/N) sum_j rho_vc(r_j) exp(+2 pi i g.j/n)  on the eps sphere
+//                  (output-pruned 3D FFT; the spin sum is fused into the product)
+//
+// Layout: u[band][spin][x][y][z] (z fastest).  Each 3D transform is split into
+// an x-pass over pencils of the compact (y,z) cube and a plane pass that does
+// the y and z transforms of one x-plane inside LDS, so a plane crosses HBM once.
+// Pruning keeps only the |g_i| <= gmax_i rows/columns of the transforms whose
+// input (band) or output (pair) is confined to a sphere.
+#include "common.h"
+
+#include <cmath>
+
+namespace gw {
+
+// ---------------------------------------------------------------- host tables
+FftPlan make_fft_plan(int n) {
+  FftPlan p{};
+  p.n = n;
+  p.npass = 0;
+  int m = n;
+  while (m % 4 == 0) { p.radix[p.npass++] = 4; m /= 4; }
+  while (m % 2 == 0) { p.radix[p.npass++] = 2; m /= 2; }
+  while (m % 3 == 0) { p.radix[p.npass++] = 3; m /= 3; }
+  while (m % 5 == 0) { p.radix[p.npass++] = 5; m /= 5; }
+  if (m != 1) p.npass = -1;
+  return p;
+}
+
+// exp(+2 pi i m / n) in double with the argument reduced to [0, pi/4] by exact
+// integer quadrant/octant folding, so every entry is within ~1 ulp.
+static void unit_root(int m, int n, double* c, double* s) {
+  m %= n;
+  if (m < 0) m += n;
+  long long q = (4LL * m) / n;            // quadrant
+  long long rem = 4LL * m - q * n;        // angle within quadrant = (pi/2) rem / n
+  double cc, ss;
+  if (2 * rem <= n) {
+    double a = (M_PI / 2.0) * (double)rem / (double)n;
+    cc = std::cos(a); ss = std::sin(a);
+  } else {
+    double a = (M_PI / 2.0) * (double)(n - rem) / (double)n;
+    cc = std::sin(a); ss = std::cos(a);
+  }
+  switch (q) {
+    case 0: *c = cc; *s = ss; break;
+    case 1: *c = -ss; *s = cc; break;
+    case 2: *c = -cc; *s = -ss; break;
+    default: *c = ss; *s = -cc; break;
+  }
+}
+
+gw_status twiddle_table(gw_ctx* c, int n, bool dbl, const void** out) {
+  auto key = std::make_pair(n, dbl ? 1 : 0);
+  auto it = c->twiddles.find(key);
+  if (it != c->twiddles.end()) { *out = it->second; return GW_OK; }
+  std::vector<double> h(2 * (size_t)n);
+  for (int m = 0; m < n; ++m) unit_root(m, n, &h[2 * m], &h[2 * m + 1]);
+  void* d = nullptr;
+  size_t bytes = (size_t)n * (dbl ? 16 : 8);
+  GW_HIP(c, hipMalloc(&d, bytes));
+  if (dbl) {
+    GW_HIP(c, hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(2 * (size_t)n);
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)h[i];
+    GW_HIP(c, hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice));
+  }
+  c->twiddles[key] = d;
+  *out = d;
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------- radix kernels
+// y_k = sum_j a_j exp(+2 pi i j k / R)
+template <typename T>
+__device__ __forceinline__ void dft(int R, cpx<T>* a) {
+  if (R == 4) {
+    cpx<T> t0 = a[0] + a[2], t1 = a[0] - a[2];
+    cpx<T> t2 = a[1] + a[3], t3 = mul_i(a[1] - a[3]);
+    a[0] = t0 + t2; a[2] = t0 - t2;
+    a[1] = t1 + t3; a[3] = t1 - t3;
+  } else if (R == 2) {
+    cpx<T> t = a[0];
+    a[0] = t + a[1]; a[1] = t - a[1];
+  } else if (R == 3) {
+    const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
+    cpx<T> t1 = a[1] + a[2];
+    cpx<T> t2 = a[0] - scal(t1, (T)0.5);
+    cpx<T> t3 = scal(mul_i(a[1] - a[2]), h);
+    a[0] = a[0] + t1;
+    a[1] = t2 + t3;
+    a[2] = t2 - t3;
+  } else {  // R == 5
+    const T c1 = (T)0.30901699437494742410, s1 = (T)0.95105651629515357212;   // 2 pi / 5
+    const T c2 = (T)-0.80901699437494742410, s2 = (T)0.58778525229247312917;  // 4 pi / 5
+    cpx<T> t1 = a[1] + a[4], t2 = a[2] + a[3];
+    cpx<T> t3 = a[1] - a[4], t4 = a[2] - a[3];
+    cpx<T> b1 = a[0] + scal(t1, c1) + scal(t2, c2);
+    cpx<T> b2 = a[0] + scal(t1, c2) + scal(t2, c1);
+    cpx<T> d1 = mul_i(scal(t3, s1) + scal(t4, s2));
+    cpx<T> d2 = mul_i(scal(t3, s2) - scal(t4, s1));
+    a[0] = a[0] + t1 + t2;
+    a[1] = b1 + d1; a[4] = b1 - d1;
+    a[2] = b2 + d2; a[3] = b2 - d2;
+  }
+}
+
+// Batched in-LDS transform y_k = sum_j x_j exp(+2 pi i jk/n) of `npen` pencils;
+// element i of pencil b lives at buf[off(b) + i*es].  Stockham passes; each
+// pass reads every butterfly of a group of whole pencils into registers before
+// writing, so it runs in place.  Ends with a barrier.
+template <typename T, int MAXB, typename Off>
+__device__ void lds_fft(cpx<T>* buf, int npen, int es, Off off, const FftPlan& pl,
+                        const cpx<T>* __restrict__ tw) {
+  const int n = pl.n;
+  const int nt = blockDim.x;
+  int Ns = 1;
+  for (int s = 0; s < pl.npass; ++s) {
+    const int R = pl.radix[s];
+    const int nq = n / R;
+    const int tws = n / (Ns * R);
+    int gp = (nt * MAXB) / nq;
+    if (gp < 1) gp = 1;
+    for (int p0 = 0; p0 < npen; p0 += gp) {
+      const int pend = min(npen, p0 + gp);
+      const int tbeg = p0 * nq, tend = pend * nq;
+      cpx<T> v[MAXB][5];
+#pragma unroll
+      for (int u = 0; u < MAXB; ++u) {
+        const int t = tbeg + u * nt + (int)threadIdx.x;
+        if (t < tend) {
+          const int b = t / nq, j = t - b * nq;
+          const int o = off(b);
+          const int k = j % Ns;
+          for (int r = 0; r < R; ++r) {
+            cpx<T> a = buf[o + (j + r * nq) * es];
+            if (r != 0 && k != 0) a = cmul(a, tw[r * k * tws]);
+            v[u][r] = a;
+          }
+          dft<T>(R, v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < MAXB; ++u) {
+        const int t = tbeg + u * nt + (int)threadIdx.x;
+        if (t < tend) {
+          const int b = t / nq, j = t - b * nq;
+          const int o = off(b);
+          const int k = j % Ns;
+          const int d = (j / Ns) * Ns * R + k;
+          for (int r = 0; r < R; ++r) buf[o + (d + r * Ns) * es] = v[u][r];
+        }
+      }
+      __syncthreads();
+    }
+    Ns *= R;
+  }
+}
+
+constexpr int kThreads = 256;
+constexpr int kMaxB = 4;
+
+__device__ __forceinline__ int wrap(int g, int n) { return g < 0 ? g + n : g; }
+
+// ---------------------------------------------------------------- band transforms
+// x-pass from the sphere: for each compact column (jy,jz) gather the |gx|<=gmax
+// coefficients, transform along x, write T1[bs][x][col].
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_band_x(
+    const cpx<T>* __restrict__ coef, int ng, const int* __restrict__ cube, int ex, int ey,
+    int ez, int gx, int n1, int ncol, int CH, FftPlan pl, const cpx<T>* __restrict__ tw,
+    cpx<T>* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int bs = blockIdx.y;
+  const int col0 = blockIdx.x * CH;
+  const int nch = min(CH, ncol - col0);
+  const cpx<T>* cf = coef + (size_t)bs * ng;
+  for (int i = threadIdx.x; i < n1 * CH; i += blockDim.x) lds[i] = mk<T>(0, 0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ex * nch; i += blockDim.x) {
+    const int jx = i / nch, cl = i - jx * nch;
+    const int col = col0 + cl;
+    const int jy = col / ez, jz = col - jy * ez;
+    const int idx = cube[(jx * ey + jy) * ez + jz];
+    if (idx >= 0) lds[wrap(jx - gx, n1) * CH + cl] = cf[idx];
+  }
+  __syncthreads();
+  lds_fft<T, kMaxB>(lds, nch, CH, [](int b) { return b; }, pl, tw);
+  cpx<T>* o = out + (size_t)bs * n1 * ncol;
+  for (int i = threadIdx.x; i < n1 * nch; i += blockDim.x) {
+    const int x = i / nch, cl = i - x * nch;
+    o[(size_t)x * ncol + col0 + cl] = lds[x * CH + cl];
+  }
+}
+
+// plane pass: expand the compact (y,z) plane of one x, transform along y on the
+// occupied z columns, then along z on every row; write the full plane.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_band_plane(
+    const cpx<T>* __restrict__ t1, int ey, int ez, int gy, int gz, int n1, int n2, int n3,
+    int P, FftPlan ply, FftPlan plz, const cpx<T>* __restrict__ twy,
+    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ u) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int x = blockIdx.x, bs = blockIdx.y;
+  const int ncol = ey * ez;
+  for (int i = threadIdx.x; i < n2 * P; i += blockDim.x) pl[i] = mk<T>(0, 0);
+  __syncthreads();
+  const cpx<T>* src = t1 + ((size_t)bs * n1 + x) * ncol;
+  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
+    const int jy = i / ez, jz = i - jy * ez;
+    pl[wrap(jy - gy, n2) * P + wrap(jz - gz, n3)] = src[i];
+  }
+  __syncthreads();
+  lds_fft<T, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
+  lds_fft<T, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
+  cpx<T>* dst = u + ((size_t)bs * n1 + x) * (size_t)n2 * n3;
+  for (int i = threadIdx.x; i < n2 * n3; i += blockDim.x) {
+    const int y = i / n3, z = i - y * n3;
+    dst[i] = pl[y * P + z];
+  }
+}
+
+// ---------------------------------------------------------------- pair transforms
+// plane pass: spin-summed product of one x-plane, z transform (keep |gz|<=gmax),
+// y transform of the kept columns (keep |gy|<=gmax), write T2[pair][x][jy][jz].
+template <typename T, int NS>
+__global__ void __launch_bounds__(kThreads) k_pair_plane(
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
+    int n1, int n2, int n3, int P, int ey, int ez, int gy, int gz, FftPlan ply, FftPlan plz,
+    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int x = blockIdx.x, pr = blockIdx.y;
+  const int v = v0 + pr % nvt, c = c0 + pr / nvt;
+  const size_t nb = (size_t)n1 * n2 * n3, np = (size_t)n2 * n3;
+  const cpx<T>* pv = uv + (size_t)v * NS * nb + (size_t)x * np;
+  const cpx<T>* pc = uc + (size_t)c * NS * nb + (size_t)x * np;
+  for (int i = threadIdx.x; i < (int)np; i += blockDim.x) {
+    cpx<T> acc = cmulc(pv[i], pc[i]);
+    if (NS == 2) acc = acc + cmulc(pv[nb + i], pc[nb + i]);
+    const int y = i / n3, z = i - y * n3;
+    pl[y * P + z] = acc;
+  }
+  __syncthreads();
+  lds_fft<T, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
+  lds_fft<T, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
+  const int ncol = ey * ez;
+  cpx<T>* dst = t2 + ((size_t)pr * n1 + x) * ncol;
+  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
+    const int jy = i / ez, jz = i - jy * ez;
+    dst[i] = pl[wrap(jy - gy, n2) * P + wrap(jz - gz, n3)];
+  }
+}
+
+// x-pass + eps gather: transform the kept (jy,jz) columns along x, keep the
+// |gx|<=gmax outputs that lie on the eps sphere, scale by 1/N.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_pair_x(
+    const cpx<T>* __restrict__ t2, int n1, int ncol, int CH, int ex, int ey, int ez, int gx,
+    const int* __restrict__ emap, FftPlan plx, const cpx<T>* __restrict__ twx, T invN, int v0,
+    int nvt, int c0, int nct_total, int neps, cpx<T>* __restrict__ M) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int col0 = blockIdx.x * CH, pr = blockIdx.y;
+  const int nch = min(CH, ncol - col0);
+  const cpx<T>* src = t2 + (size_t)pr * n1 * ncol;
+  for (int i = threadIdx.x; i < n1 * nch; i += blockDim.x) {
+    const int x = i / nch, cl = i - x * nch;
+    lds[x * CH + cl] = src[(size_t)x * ncol + col0 + cl];
+  }
+  __syncthreads();
+  lds_fft<T, kMaxB>(lds, nch, CH, [](int b) { return b; }, plx, twx);
+  const int v = v0 + pr % nvt, c = c0 + pr / nvt;
+  cpx<T>* dst = M + ((size_t)v * nct_total + c) * neps;
+  for (int i = threadIdx.x; i < ex * nch; i += blockDim.x) {
+    const int jx = i / nch, cl = i - jx * nch;
+    const int col = col0 + cl;
+    const int jy = col / ez, jz = col - jy * ez;
+    const int idx = emap[(jx * ey + jy) * ez + jz];
+    if (idx >= 0) dst[idx] = scal(lds[wrap(jx - gx, n1) * CH + cl], invN);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static int plane_pitch(int n3) { return (n3 % 2 == 0) ? n3 + 1 : n3; }
+
+template <typename T>
+static int col_chunk(int n1) {
+  // keep the x-pass tile (n1 x CH) at <= 48 KiB
+  int ch = (48 * 1024) / (n1 * (int)sizeof(cpx<T>));
+  if (ch > 128) ch = 128;
+  if (ch < 1) ch = 1;
+  return ch;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t band_scratch_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem) {
+  return (size_t)nbs * box[0] * sm->ext[1] * sm->ext[2] * elem;
+}
+
+size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem) {
+  return (size_t)npairs * box[0] * em->ext[1] * em->ext[2] * elem;
+}
+
+template <typename T>
+gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                       const SphereMap* sm, void* u_out, void* scratch, size_t scratch_bytes) {
+  const int n1 = box[0], n2 = box[1], n3 = box[2];
+  FftPlan px = make_fft_plan(n1), py = make_fft_plan(n2), pz = make_fft_plan(n3);
+  const void *twx, *twy, *twz;
+  const bool dbl = sizeof(T) == 8;
+  gw_status st;
+  if ((st = twiddle_table(c, n1, dbl, &twx)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n2, dbl, &twy)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n3, dbl, &twz)) != GW_OK) return st;
+  const int ncol = sm->ext[1] * sm->ext[2];
+  const size_t per = (size_t)n1 * ncol * sizeof(cpx<T>);
+  int chunk = (int)(scratch_bytes / per);
+  if (chunk < 1) return fail(c, GW_ENOMEM, "band scratch too small");
+  if (chunk > 65535) chunk = 65535;
+  const int CH = col_chunk<T>(n1);
+  const size_t lds_x = (size_t)n1 * CH * sizeof(cpx<T>);
+  const int P = plane_pitch(n3);
+  const size_t lds_p = (size_t)n2 * P * sizeof(cpx<T>);
+  GW_HIP(c, allow_lds(k_band_x<T>, lds_x));
+  GW_HIP(c, allow_lds(k_band_plane<T>, lds_p));
+  const cpx<T>* cf = static_cast<const cpx<T>*>(coef);
+  cpx<T>* u = static_cast<cpx<T>*>(u_out);
+  cpx<T>* t1 = static_cast<cpx<T>*>(scratch);
+  for (int b0 = 0; b0 < nbs; b0 += chunk) {
+    const int nb = std::min(chunk, nbs - b0);
+    {
+      ProfScope ps(c, "band_xpass");
+      dim3 g((ncol + CH - 1) / CH, nb);
+      hipLaunchKernelGGL(k_band_x<T>, g, dim3(kThreads), lds_x, c->stream, cf + (size_t)b0 * ng,
+                         ng, sm->d_cube, sm->ext[0], sm->ext[1], sm->ext[2], sm->gmax[0], n1,
+                         ncol, CH, px, static_cast<const cpx<T>*>(twx), t1);
+      GW_CHECK_LAUNCH(c, "k_band_x");
+    }
+    {
+      ProfScope ps(c, "band_plane");
+      dim3 g(n1, nb);
+      hipLaunchKernelGGL(k_band_plane<T>, g, dim3(kThreads), lds_p, c->stream, t1, sm->ext[1],
+                         sm->ext[2], sm->gmax[1], sm->gmax[2], n1, n2, n3, P, py, pz,
+                         static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz),
+                         u + (size_t)b0 * n1 * n2 * n3);
+      GW_CHECK_LAUNCH(c, "k_band_plane");
+    }
+  }
+  return GW_OK;
+}
+
+template <typename T>
+gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, const void* uc,
+                      int v0, int nvt, int c0, int nct, int nc_total, const SphereMap* em,
+                      void* mtxel, void* scratch) {
+  const int n1 = box[0], n2 = box[1], n3 = box[2];
+  FftPlan px = make_fft_plan(n1), py = make_fft_plan(n2), pz = make_fft_plan(n3);
+  const void *twx, *twy, *twz;
+  const bool dbl = sizeof(T) == 8;
+  gw_status st;
+  if ((st = twiddle_table(c, n1, dbl, &twx)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n2, dbl, &twy)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n3, dbl, &twz)) != GW_OK) return st;
+  const int npairs = nvt * nct;
+  const int P = plane_pitch(n3);
+  const size_t lds_p = (size_t)n2 * P * sizeof(cpx<T>);
+  const int ncol = em->ext[1] * em->ext[2];
+  const int CH = col_chunk<T>(n1);
+  const size_t lds_x = (size_t)n1 * CH * sizeof(cpx<T>);
+  cpx<T>* t2 = static_cast<cpx<T>*>(scratch);
+  if (nspinor == 2) {
+    GW_HIP(c, allow_lds(k_pair_plane<T, 2>, lds_p));
+  } else {
+    GW_HIP(c, allow_lds(k_pair_plane<T, 1>, lds_p));
+  }
+  GW_HIP(c, allow_lds(k_pair_x<T>, lds_x));
+  {
+    ProfScope ps(c, "pair_plane");
+    dim3 g(n1, npairs);
+    if (nspinor == 2)
+      hipLaunchKernelGGL((k_pair_plane<T, 2>), g, dim3(kThreads), lds_p, c->stream,
+                         static_cast<const cpx<T>*>(uv), static_cast<const cpx<T>*>(uc), v0, nvt,
+                         c0, n1, n2, n3, P, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2], py,
+                         pz, static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2);
+    else
+      hipLaunchKernelGGL((k_pair_plane<T, 1>), g, dim3(kThreads), lds_p, c->stream,
+                         static_cast<const cpx<T>*>(uv), static_cast<const cpx<T>*>(uc), v0, nvt,
+                         c0, n1, n2, n3, P, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2], py,
+                         pz, static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2);
+    GW_CHECK_LAUNCH(c, "k_pair_plane");
+  }
+  {
+    ProfScope ps(c, "pair_xpass");
+    dim3 g((ncol + CH - 1) / CH, npairs);
+    const T invN = (T)(1.0 / ((double)n1 * n2 * n3));
+    hipLaunchKernelGGL(k_pair_x<T>, g, dim3(kThreads), lds_x, c->stream, t2, n1, ncol, CH,
+                       em->ext[0], em->ext[1], em->ext[2], em->gmax[0], em->d_cube, px,
+                       static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,
+                       static_cast<cpx<T>*>(mtxel));
+    GW_CHECK_LAUNCH(c, "k_pair_x");
+  }
+  return GW_OK;
+}
+
+template gw_status band_to_grid<double>(gw_ctx*, const int*, int, int, const void*,
+                                        const SphereMap*, void*, void*, size_t);
+template gw_status band_to_grid<float>(gw_ctx*, const int*, int, int, const void*,
+                                       const SphereMap*, void*, void*, size_t);
+template gw_status pair_to_eps<double>(gw_ctx*, const int*, int, const void*, const void*, int,
+                                       int, int, int, int, const SphereMap*, void*, void*);
+template gw_status pair_to_eps<float>(gw_ctx*, const int*, int, const void*, const void*, int,
+                                      int, int, int, int, const SphereMap*, void*, void*);
+
+}  // namespace gw

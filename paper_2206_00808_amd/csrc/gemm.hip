@@ -1,0 +1,415 @@
+// chi0 band-pair contraction on the matrix cores (Sec. II, Adler-Wiser
+// polarizability at imaginary frequency):
+//   chi0_f[i][j] += sum_p conj(M[p][i]) * w_f(p) * M[p][j],
+//   w_f(p) = prefactor * (1/(D_p - i w_f) + 1/(D_p + i w_f)),  D_p = e_v - e_c.
+// The update is Hermitian, so only tiles ti <= tj are computed; an
+// off-diagonal tile is added at (ti,tj) and its conjugate transpose at (tj,ti).
+//
+// FP64 path: v_mfma_f64_16x16x4_f64, complex via four real products.
+// Split-BF16 path: each float x = hi + lo with hi = bf16_rn(x), lo = bf16_rn(x - hi);
+// real products use hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with
+// float accumulation over K-chunks that are flushed into double registers.
+#include "common.h"
+
+namespace gw {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- weights
+__global__ void k_weights(const double* __restrict__ ev, const double* __restrict__ ec, int nv,
+                          int nc, const double* __restrict__ om, int nfreq, double pref,
+                          double* __restrict__ w) {
+  const int P = nv * nc;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (p >= P || f >= nfreq) return;
+  const double d = ev[p / nc] - ec[p % nc];
+  const double o = om[f];
+  // 1/(d - i o) + 1/(d + i o) = 2 d / (d^2 + o^2)
+  w[(size_t)f * P + p] = pref * (2.0 * d / (d * d + o * o));
+}
+
+gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double* ec, int nfreq,
+                       const double* d_omega, double pref, double* wts) {
+  const int P = nv * nc;
+  ProfScope ps(c, "chi0_weights");
+  hipLaunchKernelGGL(k_weights, dim3((P + 255) / 256, nfreq), dim3(256), 0, c->stream, ev, ec, nv,
+                     nc, d_omega, nfreq, pref, wts);
+  GW_CHECK_LAUNCH(c, "k_weights");
+  return GW_OK;
+}
+
+// upper-triangle tile index -> (ti, tj), ti <= tj, row-major over the triangle
+__device__ __forceinline__ void tri_tile(int idx, int nt, int* ti, int* tj) {
+  int r = 0, start = 0;
+  while (start + (nt - r) <= idx) { start += nt - r; ++r; }
+  *ti = r;
+  *tj = r + (idx - start);
+}
+
+// ---------------------------------------------------------------- FP64 chi0
+constexpr int TM = 64;   // tile edge (complex elements)
+constexpr int KT = 16;   // K step (pairs)
+constexpr int LP = TM + 1;  // LDS pitch
+
+template <typename Tin>
+__device__ __forceinline__ cpx<double> load_widen(const cpx<Tin>* p) {
+  cpx<Tin> v = *p;
+  return mk<double>((double)v.x, (double)v.y);
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P, int neps,
+                                                  const double* __restrict__ wts,
+                                                  cpx<double>* __restrict__ chi, int nt,
+                                                  int skip_head) {
+  __shared__ cpx<double> As[KT][LP];
+  __shared__ cpx<double> Bs[KT][LP];
+  int ti, tj;
+  tri_tile(blockIdx.x, nt, &ti, &tj);
+  const int f = blockIdx.y;
+  const double* w = wts + (size_t)f * P;
+  const int i0 = ti * TM, j0 = tj * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (d4){0, 0, 0, 0};
+      ci[a][b] = (d4){0, 0, 0, 0};
+    }
+  for (int p0 = 0; p0 < P; p0 += KT) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < (KT * TM) / 256; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx / TM, ii = idx % TM;
+      const int p = p0 + kk;
+      cpx<double> a = mk<double>(0, 0), b = mk<double>(0, 0);
+      if (p < P) {
+        if (i0 + ii < neps) a = load_widen(M + (size_t)p * neps + i0 + ii);
+        if (j0 + ii < neps) b = scal(load_widen(M + (size_t)p * neps + j0 + ii), w[p]);
+      }
+      As[kk][ii] = a;
+      Bs[kk][ii] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KT / 4; ++s) {
+      const int kk = s * 4 + lk;
+      cpx<double> av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc * 32 + b * 16 + l16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+        }
+    }
+  }
+  cpx<double>* C = chi + (size_t)f * neps * neps;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + lk * 4 + r;
+        const int j = j0 + wc * 32 + b * 16 + l16;
+        if (i >= neps || j >= neps) continue;
+        if (skip_head >= 0 && (i == skip_head || j == skip_head)) continue;
+        const double re = cr[a][b][r], im = ci[a][b][r];
+        cpx<double>* d = C + (size_t)i * neps + j;
+        *d = mk(d->x + re, d->y + im);
+        if (ti != tj) {
+          cpx<double>* m = C + (size_t)j * neps + i;
+          *m = mk(m->x + re, m->y - im);
+        }
+      }
+}
+
+gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
+                    const double* wts, int skip_head, double* chi0) {
+  const int nt = (neps + TM - 1) / TM;
+  const int ntri = nt * (nt + 1) / 2;
+  ProfScope ps(c, "chi0_fp64");
+  if (dt == GW_C128)
+    hipLaunchKernelGGL(k_chi0_f64<double>, dim3(ntri, nfreq), dim3(256), 0, c->stream,
+                       static_cast<const cpx<double>*>(mtxel), P, neps, wts,
+                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
+  else
+    hipLaunchKernelGGL(k_chi0_f64<float>, dim3(ntri, nfreq), dim3(256), 0, c->stream,
+                       static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
+  GW_CHECK_LAUNCH(c, "k_chi0_f64");
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------- generic ZGEMM
+// C[i][j] += alpha * sum_k A[i][k] B[k][j], complex double, row-major, batched on z.
+__global__ void __launch_bounds__(256) k_zgemm_nn(int m, int n, int kdim, double alpha,
+                                                  const cpx<double>* __restrict__ A, int lda,
+                                                  long long sA, const cpx<double>* __restrict__ B,
+                                                  int ldb, long long sB, cpx<double>* __restrict__ C,
+                                                  int ldc, long long sC) {
+  __shared__ cpx<double> As[KT][LP];
+  __shared__ cpx<double> Bs[KT][LP];
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TM;
+  A += (size_t)blockIdx.z * sA;
+  B += (size_t)blockIdx.z * sB;
+  C += (size_t)blockIdx.z * sC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (d4){0, 0, 0, 0};
+      ci[a][b] = (d4){0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < kdim; k0 += KT) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < (KT * TM) / 256; ++e) {
+      const int idx = tid + e * 256;
+      // A tile: TM rows x KT columns, k fastest for coalescing
+      const int ai = idx / KT, ak = idx % KT;
+      cpx<double> a = mk<double>(0, 0);
+      if (i0 + ai < m && k0 + ak < kdim) a = A[(size_t)(i0 + ai) * lda + k0 + ak];
+      As[ak][ai] = a;
+      const int bk = idx / TM, bj = idx % TM;
+      cpx<double> b = mk<double>(0, 0);
+      if (k0 + bk < kdim && j0 + bj < n) b = B[(size_t)(k0 + bk) * ldb + j0 + bj];
+      Bs[bk][bj] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KT / 4; ++s) {
+      const int kk = s * 4 + lk;
+      cpx<double> av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc * 32 + b * 16 + l16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          // a * b = (ar br - ai bi) + i (ar bi + ai br)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + lk * 4 + r;
+        const int j = j0 + wc * 32 + b * 16 + l16;
+        if (i >= m || j >= n) continue;
+        cpx<double>* d = C + (size_t)i * ldc + j;
+        *d = mk(d->x + alpha * cr[a][b][r], d->y + alpha * ci[a][b][r]);
+      }
+}
+
+gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, int lda,
+                   long long sA, const double* B, int ldb, long long sB, double* C, int ldc,
+                   long long sC, int batch) {
+  if (m <= 0 || n <= 0 || k <= 0) return GW_OK;
+  ProfScope ps(c, "zgemm_update");
+  dim3 g((n + TM - 1) / TM, (m + TM - 1) / TM, batch);
+  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha,
+                     reinterpret_cast<const cpx<double>*>(A), lda, sA,
+                     reinterpret_cast<const cpx<double>*>(B), ldb, sB,
+                     reinterpret_cast<cpx<double>*>(C), ldc, sC);
+  GW_CHECK_LAUNCH(c, "k_zgemm_nn");
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------- split-BF16 chi0
+// bf16 round-to-nearest-even from the IEEE-754 binary32 bit pattern (finite inputs).
+__device__ __forceinline__ unsigned short bf16_rn_bits(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+constexpr int BK = 32;          // K step (pairs) = one 16x16x32 MFMA
+constexpr int BKP = BK + 8;     // LDS pitch in bf16 (16-byte aligned rows)
+constexpr int KFLUSH = 512;     // pairs accumulated in float before the double flush
+
+// LDS arrays [4 parts: re_hi, re_lo, im_hi, im_lo][TM rows][BKP]
+__global__ void __launch_bounds__(256) k_chi0_bf16x3(const cpx<float>* __restrict__ M, int P,
+                                                     int neps, const double* __restrict__ wts,
+                                                     cpx<double>* __restrict__ chi, int nt,
+                                                     int skip_head) {
+  __shared__ __align__(16) unsigned short As[4][TM][BKP];
+  __shared__ __align__(16) unsigned short Bs[4][TM][BKP];
+  int ti, tj;
+  tri_tile(blockIdx.x, nt, &ti, &tj);
+  const int f = blockIdx.y;
+  const double* w = wts + (size_t)f * P;
+  const int i0 = ti * TM, j0 = tj * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double dr[2][2][4], di[2][2][4];
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
+    }
+  int since_flush = 0;
+  for (int p0 = 0; p0 < P; p0 += BK) {
+    __syncthreads();
+    // stage: BK pairs x TM columns of A (=M) and B (=w*M), split into hi/lo
+#pragma unroll
+    for (int e = 0; e < (BK * TM) / 256; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx / TM, ii = idx % TM;
+      const int p = p0 + kk;
+      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+      if (p < P) {
+        if (i0 + ii < neps) {
+          cpx<float> v = M[(size_t)p * neps + i0 + ii];
+          ar = v.x; ai = v.y;
+        }
+        if (j0 + ii < neps) {
+          cpx<float> v = M[(size_t)p * neps + j0 + ii];
+          const float wf = (float)w[p];
+          br = v.x * wf; bi = v.y * wf;
+        }
+      }
+      unsigned short h;
+      h = bf16_rn_bits(ar); As[0][ii][kk] = h; As[1][ii][kk] = bf16_rn_bits(ar - bf16_to_f(h));
+      h = bf16_rn_bits(ai); As[2][ii][kk] = h; As[3][ii][kk] = bf16_rn_bits(ai - bf16_to_f(h));
+      h = bf16_rn_bits(br); Bs[0][ii][kk] = h; Bs[1][ii][kk] = bf16_rn_bits(br - bf16_to_f(h));
+      h = bf16_rn_bits(bi); Bs[2][ii][kk] = h; Bs[3][ii][kk] = bf16_rn_bits(bi - bf16_to_f(h));
+    }
+    __syncthreads();
+    bf8 a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[x][q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + x * 16 + l16][lk * 8]);
+        b[x][q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + x * 16 + l16][lk * 8]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        // Re: ar*br + ai*bi ; Im: ar*bi - ai*br ; each as hi*hi + hi*lo + lo*hi
+        f4 r = cr[x][y], im = ci[x][y];
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][1], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][1], b[y][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][3], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][3], b[y][2], r, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][2], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][3], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][1], b[y][2], im, 0, 0, 0);
+        cr[x][y] = r;
+        ci[x][y] = im;
+      }
+    // the -ai*br term: negate by accumulating into a separate register set would
+    // cost registers; subtract through a negated copy of the A operands instead.
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 2; q < 4; ++q) {
+        // flip the sign bit of every bf16 lane
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 t = __builtin_bit_cast(us8, a[x][q]);
+        t ^= (us8)(0x8000);
+        a[x][q] = __builtin_bit_cast(bf8, t);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        f4 im = ci[x][y];
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][0], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][1], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][3], b[y][0], im, 0, 0, 0);
+        ci[x][y] = im;
+      }
+    since_flush += BK;
+    if (since_flush >= KFLUSH || p0 + BK >= P) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dr[x][y][r] += (double)cr[x][y][r];
+            di[x][y][r] += (double)ci[x][y][r];
+          }
+          cr[x][y] = (f4){0, 0, 0, 0};
+          ci[x][y] = (f4){0, 0, 0, 0};
+        }
+      since_flush = 0;
+    }
+  }
+  cpx<double>* C = chi + (size_t)f * neps * neps;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + x * 16 + lk * 4 + r;
+        const int j = j0 + wc * 32 + y * 16 + l16;
+        if (i >= neps || j >= neps) continue;
+        if (skip_head >= 0 && (i == skip_head || j == skip_head)) continue;
+        const double re = dr[x][y][r], im = di[x][y][r];
+        cpx<double>* d = C + (size_t)i * neps + j;
+        *d = mk(d->x + re, d->y + im);
+        if (ti != tj) {
+          cpx<double>* m = C + (size_t)j * neps + i;
+          *m = mk(m->x + re, m->y - im);
+        }
+      }
+}
+
+gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
+                         const double* wts, int skip_head, double* chi0) {
+  const int nt = (neps + TM - 1) / TM;
+  const int ntri = nt * (nt + 1) / 2;
+  ProfScope ps(c, "chi0_bf16x3");
+  hipLaunchKernelGGL(k_chi0_bf16x3, dim3(ntri, nfreq), dim3(256), 0, c->stream,
+                     static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+                     reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
+  GW_CHECK_LAUNCH(c, "k_chi0_bf16x3");
+  return GW_OK;
+}
+
+}  // namespace gw

@@ -1,0 +1,282 @@
+// eps = I - diag(v) chi0 and its inverse in double (Sec. II, dielectric matrix;
+// the Performance section names this inversion as a large part of Epsilon).
+//
+// Right-looking blocked LU with partial pivoting (PA = LU), every frequency
+// in the same launches (grid.z / grid.y = frequency):
+//   panel  : one 1024-thread workgroup factors the N x nb column panel
+//            (pivot = largest |re|+|im|, lowest row on ties)
+//   laswp  : the panel's row interchanges applied to the other columns
+//   trsm   : U12 = L11^-1 A12
+//   update : A22 -= L21 U12 on the FP64 matrix cores
+// then eps^-1 = U^-1 L^-1 P by blocked forward/back substitution on P*I.
+#include "common.h"
+
+namespace gw {
+
+constexpr int NB = 32;  // block width of the factorisation and the substitutions
+
+__global__ void k_eps_build(const cpx<double>* __restrict__ chi, const double* __restrict__ v,
+                            cpx<double>* __restrict__ A, int N) {
+  const size_t nn = (size_t)N * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const size_t off = (size_t)blockIdx.y * nn + idx;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  const cpx<double> x = chi[off];
+  A[off] = mk((i == j ? 1.0 : 0.0) - v[i] * x.x, -v[i] * x.y);
+}
+
+__global__ void __launch_bounds__(1024) k_lu_panel(cpx<double>* __restrict__ A, int N, int k,
+                                                   int nbk, int* __restrict__ ipiv,
+                                                   int* __restrict__ flag) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ cpx<double> prow[NB];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  A += (size_t)blockIdx.x * N * N;
+  ipiv += (size_t)blockIdx.x * N;
+  for (int jj = 0; jj < nbk; ++jj) {
+    const int j = k + jj;
+    double best = -1.0;
+    int bi = N;
+    for (int i = j + tid; i < N; i += nt) {
+      const cpx<double> a = A[(size_t)i * N + j];
+      const double m = fabs(a.x) + fabs(a.y);
+      if (m > best) { best = m; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = sv[tid + s];
+        const int oi = si[tid + s];
+        if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const double pm = sv[0];
+    const int p = (si[0] < N) ? si[0] : j;  // no finite candidate: keep the diagonal
+    if (tid == 0) {
+      ipiv[j] = p;
+      if (!(pm > 0.0)) flag[0] = 1;
+    }
+    if (p != j) {
+      for (int c = tid; c < nbk; c += nt) {
+        const cpx<double> t = A[(size_t)j * N + k + c];
+        A[(size_t)j * N + k + c] = A[(size_t)p * N + k + c];
+        A[(size_t)p * N + k + c] = t;
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < nbk; c += nt) prow[c] = A[(size_t)j * N + k + c];
+    __syncthreads();
+    if (pm > 0.0) {
+      const cpx<double> piv = prow[jj];
+      const double den = piv.x * piv.x + piv.y * piv.y;
+      const cpx<double> inv = mk(piv.x / den, -piv.y / den);
+      for (int i = j + 1 + tid; i < N; i += nt) {
+        cpx<double>* row = A + (size_t)i * N + k;
+        const cpx<double> l = cmul(row[jj], inv);
+        row[jj] = l;
+        for (int c = jj + 1; c < nbk; ++c) row[c] = row[c] - cmul(l, prow[c]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_lu_laswp(cpx<double>* __restrict__ A, int N, int k, int nbk,
+                           const int* __restrict__ ipiv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N || (c >= k && c < k + nbk)) return;
+  A += (size_t)blockIdx.y * N * N;
+  ipiv += (size_t)blockIdx.y * N;
+  for (int s = k; s < k + nbk; ++s) {
+    const int p = ipiv[s];
+    if (p != s) {
+      const cpx<double> t = A[(size_t)s * N + c];
+      A[(size_t)s * N + c] = A[(size_t)p * N + c];
+      A[(size_t)p * N + c] = t;
+    }
+  }
+}
+
+// Solve T X = B in place on rows kb..kb+nbk of X for columns c0..c0+ncols, where
+// T is the nbk x nbk diagonal block of the LU factors: unit lower (UPPER=false)
+// or non-unit upper (UPPER=true).  One thread per right-hand-side column.
+template <bool UPPER>
+__global__ void __launch_bounds__(256) k_trsm_block(const cpx<double>* __restrict__ LU, int N,
+                                                   int kb, int nbk, cpx<double>* __restrict__ X,
+                                                   int c0, int ncols) {
+  __shared__ cpx<double> T[NB][NB + 1];
+  __shared__ cpx<double> dinv[NB];
+  LU += (size_t)blockIdx.y * N * N;
+  X += (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < nbk * nbk; e += blockDim.x) {
+    const int r = e / nbk, cc = e % nbk;
+    T[r][cc] = LU[(size_t)(kb + r) * N + kb + cc];
+  }
+  __syncthreads();
+  if (UPPER && threadIdx.x < nbk) {
+    const cpx<double> d = T[threadIdx.x][threadIdx.x];
+    const double den = d.x * d.x + d.y * d.y;
+    dinv[threadIdx.x] = mk(d.x / den, -d.y / den);
+  }
+  __syncthreads();
+  const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cidx >= ncols) return;
+  const int col = c0 + cidx;
+  cpx<double> x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    x[i] = (i < nbk) ? X[(size_t)(kb + i) * N + col] : mk<double>(0, 0);
+  if (!UPPER) {
+#pragma unroll
+    for (int i = 1; i < NB; ++i) {
+      if (i < nbk) {
+        cpx<double> s = x[i];
+#pragma unroll
+        for (int t = 0; t < i; ++t) s = s - cmul(T[i][t], x[t]);
+        x[i] = s;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+      if (i < nbk) {
+        cpx<double> s = x[i];
+#pragma unroll
+        for (int t = i + 1; t < NB; ++t)
+          if (t < nbk) s = s - cmul(T[i][t], x[t]);
+        x[i] = cmul(s, dinv[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < nbk) X[(size_t)(kb + i) * N + col] = x[i];
+}
+
+// Row s of P*I is e_perm[s], perm = identity after the interchanges s <-> ipiv[s].
+__global__ void __launch_bounds__(256) k_perm_identity(const int* __restrict__ ipiv, int N,
+                                                       int* __restrict__ perm,
+                                                       cpx<double>* __restrict__ Y) {
+  extern __shared__ int sp[];
+  const int f = blockIdx.x;
+  ipiv += (size_t)f * N;
+  perm += (size_t)f * N;
+  Y += (size_t)f * N * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sp[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < N; ++s) {
+      const int p = ipiv[s];
+      const int t = sp[s];
+      sp[s] = sp[p];
+      sp[p] = t;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) perm[i] = sp[i];
+  for (size_t e = threadIdx.x; e < (size_t)N * N; e += blockDim.x) {
+    const int s = (int)(e / N), j = (int)(e % N);
+    Y[e] = mk(j == sp[s] ? 1.0 : 0.0, 0.0);
+  }
+}
+
+gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
+                     double* epsinv) {
+  const size_t nn = (size_t)N * N;
+  const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up((size_t)nfreq * N * 4);
+  gw_status st = ws_begin(c, bytes);
+  if (st != GW_OK) return st;
+  cpx<double>* LU = static_cast<cpx<double>*>(ws_take(c, nfreq * nn * 16));
+  int* ipiv = static_cast<int*>(ws_take(c, (size_t)nfreq * N * 4));
+  int* perm = static_cast<int*>(ws_take(c, (size_t)nfreq * N * 4));
+  cpx<double>* Y = reinterpret_cast<cpx<double>*>(epsinv);
+  GW_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  {
+    ProfScope ps(c, "eps_build");
+    hipLaunchKernelGGL(k_eps_build, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, reinterpret_cast<const cpx<double>*>(chi0), vcoul, LU, N);
+    GW_CHECK_LAUNCH(c, "k_eps_build");
+  }
+  const long long s2 = (long long)nn * 2;  // batch stride in doubles
+  double* LUd = reinterpret_cast<double*>(LU);
+  for (int k = 0; k < N; k += NB) {
+    const int nbk = std::min(NB, N - k);
+    {
+      ProfScope ps(c, "lu_panel");
+      hipLaunchKernelGGL(k_lu_panel, dim3(nfreq), dim3(1024), 0, c->stream, LU, N, k, nbk, ipiv,
+                         c->d_flag);
+      GW_CHECK_LAUNCH(c, "k_lu_panel");
+    }
+    {
+      ProfScope ps(c, "lu_laswp");
+      hipLaunchKernelGGL(k_lu_laswp, dim3((N + 255) / 256, nfreq), dim3(256), 0, c->stream, LU,
+                         N, k, nbk, ipiv);
+      GW_CHECK_LAUNCH(c, "k_lu_laswp");
+    }
+    const int rest = N - k - nbk;
+    if (rest > 0) {
+      {
+        ProfScope ps(c, "lu_trsm");
+        hipLaunchKernelGGL(k_trsm_block<false>, dim3((rest + 255) / 256, nfreq), dim3(256), 0,
+                           c->stream, LU, N, k, nbk, LU, k + nbk, rest);
+        GW_CHECK_LAUNCH(c, "k_trsm_block");
+      }
+      st = zgemm_nn(c, rest, rest, nbk, -1.0, LUd + 2 * ((size_t)(k + nbk) * N + k), N, s2,
+                    LUd + 2 * ((size_t)k * N + k + nbk), N, s2,
+                    LUd + 2 * ((size_t)(k + nbk) * N + k + nbk), N, s2, nfreq);
+      if (st != GW_OK) return st;
+    }
+  }
+  {
+    ProfScope ps(c, "inv_perm");
+    hipLaunchKernelGGL(k_perm_identity, dim3(nfreq), dim3(256), (size_t)N * 4, c->stream, ipiv,
+                       N, perm, Y);
+    GW_CHECK_LAUNCH(c, "k_perm_identity");
+  }
+  // forward: L Y = P I
+  for (int kb = 0; kb < N; kb += NB) {
+    const int nbk = std::min(NB, N - kb);
+    {
+      ProfScope ps(c, "inv_trsm_lower");
+      hipLaunchKernelGGL(k_trsm_block<false>, dim3((N + 255) / 256, nfreq), dim3(256), 0,
+                         c->stream, LU, N, kb, nbk, Y, 0, N);
+      GW_CHECK_LAUNCH(c, "k_trsm_block");
+    }
+    const int below = N - kb - nbk;
+    if (below > 0) {
+      st = zgemm_nn(c, below, N, nbk, -1.0, LUd + 2 * ((size_t)(kb + nbk) * N + kb), N, s2,
+                    epsinv + 2 * ((size_t)kb * N), N, s2, epsinv + 2 * ((size_t)(kb + nbk) * N),
+                    N, s2, nfreq);
+      if (st != GW_OK) return st;
+    }
+  }
+  // back: U X = Y
+  const int nblk = (N + NB - 1) / NB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int kb = b * NB;
+    const int nbk = std::min(NB, N - kb);
+    {
+      ProfScope ps(c, "inv_trsm_upper");
+      hipLaunchKernelGGL(k_trsm_block<true>, dim3((N + 255) / 256, nfreq), dim3(256), 0,
+                         c->stream, LU, N, kb, nbk, Y, 0, N);
+      GW_CHECK_LAUNCH(c, "k_trsm_block");
+    }
+    if (kb > 0) {
+      st = zgemm_nn(c, kb, N, nbk, -1.0, LUd + 2 * ((size_t)kb), N, s2,
+                    epsinv + 2 * ((size_t)kb * N), N, s2, epsinv, N, s2, nfreq);
+      if (st != GW_OK) return st;
+    }
+  }
+  int flag = 0;
+  GW_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  if (flag) return fail(c, GW_ESINGULAR, "eps has a zero pivot (singular dielectric matrix)");
+  return GW_OK;
+}
+
+}  // namespace gw

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Small systems are compared element by element; the full-size workloads are
+checked on outputs the oracle can compute one by one (sampled pairs, sampled
+(G, G') blocks) and on properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2206_00808_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+def _sys(name):
+    return synth.build_system(synth.CONFIGS[name])
+
+
+def _run(P, ctx, s, dtype="c128", prec=None, with_head=False, nc=None):
+    from paper_2206_00808_amd import pipeline
+    prec = P.GW_PREC_FP64 if prec is None else prec
+    d = pipeline.upload(s, dtype=dtype, nc=nc)
+    out = pipeline.alloc_outputs(d, with_head=with_head)
+    pipeline.run_path(ctx, d, out, prec=prec)
+    torch.cuda.synchronize()
+    return d, {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def _max_rel(x, ref):
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+# ----------------------------------------------------------------- matrix elements
+@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+def test_mtxel_fp64_matches_definition(P, ctx, name):
+    s = _sys(name)
+    _, out = _run(P, ctx, s)
+    ref = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    assert _max_rel(out["mtxel"], ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["C1", "T2"])
+def test_mtxel_fp32_matches_definition(P, ctx, name):
+    s = _sys(name)
+    _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
+    ref = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    assert _max_rel(out["mtxel"], ref) < 2e-6
+
+
+def test_single_plane_wave_pairs_give_deltas(P, ctx):
+    s = _sys("T2")
+    gv, gc, geps = s["gv"], s["gc"], s["geps"]
+    cv = np.zeros((2, 2, len(gv)), complex)
+    cc = np.zeros((3, 2, len(gc)), complex)
+    cv[0, 0, 4] = 1.0
+    cv[1, 1, 9] = 1.0
+    cc[0, 0, 2] = 1.0
+    cc[1, 1, 2] = 1.0
+    cc[2, 0, 7] = 1.0
+    t = dict(s, cv=cv, cc=cc, ev=s["ev"][:2], ec=s["ec"][:3])
+    _, out = _run(P, ctx, t)
+    want = np.zeros((2, 3, len(geps)), complex)
+    for v, (sv, iv) in enumerate([(0, 4), (1, 9)]):
+        for c, (sc, ic) in enumerate([(0, 2), (1, 2), (0, 7)]):
+            if sv == sc:
+                hit = np.where((geps == gv[iv] - gc[ic]).all(axis=1))[0]
+                want[v, c, hit] = 1.0
+    assert np.abs(out["mtxel"] - want).max() < 1e-14
+
+
+def test_zero_down_equals_spinless(P, ctx):
+    s = _sys("T1")
+    z = dict(s, cv=s["cv"].copy(), cc=s["cc"].copy())
+    z["cv"][:, 1] = 0
+    z["cc"][:, 1] = 0
+    one = dict(s, cv=np.ascontiguousarray(s["cv"][:, :1]), cc=np.ascontiguousarray(s["cc"][:, :1]))
+    _, o2 = _run(P, ctx, z)
+    _, o1 = _run(P, ctx, one)
+    assert np.abs(o2["mtxel"] - o1["mtxel"]).max() < 1e-15
+    assert np.abs(o2["chi0"] - o1["chi0"]).max() <= 1e-14 * np.abs(o1["chi0"]).max()
+
+
+def test_orthonormal_head_vanishes_at_q0(P, ctx):
+    s = _sys("T1Q0")
+    # replace the q0 valence by states of the same orthonormal set as the conduction
+    rng = np.random.default_rng(5)
+    from synth.generate import _random_spinors, g_sphere
+    cell = tuple(s["cell"])
+    gk = s["gc"]
+    geps = g_sphere(cell, (0, 0, 0), 3.367)
+    joint = _random_spinors(rng, len(gk), 10, 2)
+    t = dict(s, cv=joint[:3], gv=gk, cc=joint[3:], geps=geps, ev=s["ev"][:3], ec=s["ec"][:7],
+             vcoul=np.ones(len(geps)), head_index=-1)
+    _, out = _run(P, ctx, t)
+    i0 = np.where((geps == 0).all(axis=1))[0][0]
+    assert np.abs(out["mtxel"][:, :, i0]).max() < 1e-14
+
+
+# ----------------------------------------------------------------- chi0 and eps^-1, FP64
+@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+def test_chi0_and_epsinv_fp64(P, ctx, name):
+    s = _sys(name)
+    _, out = _run(P, ctx, s)
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(m, s["ev"], s["ec"], s["omega"])
+    e = oracle.epsilon_inverse(x, s["vcoul"])
+    for f in range(len(s["omega"])):
+        assert oracle.rel_f(out["chi0"][f], x[f]) < 1e-10
+        assert oracle.rel_f(out["epsinv"][f], e[f]) < 1e-10
+    # Hermitian by construction (mirrored tiles)
+    c = out["chi0"]
+    assert np.abs(c - np.conj(np.transpose(c, (0, 2, 1)))).max() <= 1e-15 * np.abs(c).max()
+
+
+def test_chi0_accumulates_in_chunks(P, ctx):
+    from paper_2206_00808_amd import pipeline
+    s = _sys("T1")
+    d = pipeline.upload(s)
+    out = pipeline.alloc_outputs(d)
+    pipeline.run_path(ctx, d, out, stages=("mtxel", "chi0"))
+    full = out["chi0"].clone()
+    m = out["mtxel"]
+    acc = torch.zeros_like(full)
+    half = d["nc"] // 2
+    for lo, hi in ((0, half), (half, d["nc"])):
+        part = m[:, lo:hi].contiguous()
+        P.gw_chi0_accumulate(ctx, d["nv"], hi - lo, d["neps"], part, d["ev"], d["ec"][lo:hi].contiguous(),
+                             d["omega"], 1.0, P.GW_PREC_FP64, acc)
+    torch.cuda.synchronize()
+    assert oracle.rel_f(acc.cpu().numpy(), full.cpu().numpy()) < 1e-14
+
+
+# ----------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+def test_mixed_path_within_1e4(P, ctx, name):
+    s = _sys(name)
+    _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(m, s["ev"], s["ec"], s["omega"])
+    e = oracle.epsilon_inverse(x, s["vcoul"])
+    for f in range(len(s["omega"])):
+        assert oracle.rel_f(out["chi0"][f], x[f]) < 1e-4
+        assert oracle.rel_f(out["epsinv"][f], e[f]) < 1e-4
+
+
+def test_mixed_head_wings_in_fp64(P, ctx):
+    s = _sys("T1Q0")
+    h = s["head_index"]
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(m, s["ev"], s["ec"], s["omega"])
+    e = oracle.epsilon_inverse(x, s["vcoul"])
+    _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16, with_head=True)
+    mh = oracle.head_overlap(s["cv"], s["gv"], s["cc"], s["gc"]).reshape(-1)
+    assert _max_rel(out["mhead"], mh) < 1e-6   # from float coefficients, summed in double
+    for f in range(len(s["omega"])):
+        assert abs(out["chi0"][f][h, h] - x[f][h, h]) / abs(x[f][h, h]) < 1e-5
+        assert oracle.rel_f(out["epsinv"][f], e[f]) < 1e-4
+    # FP64 path with the FP64 head: identical math, tight bound
+    _, o64 = _run(P, ctx, s, with_head=True)
+    for f in range(len(s["omega"])):
+        assert oracle.rel_f(o64["chi0"][f], x[f]) < 1e-10
+        assert oracle.rel_f(o64["epsinv"][f], e[f]) < 1e-10
+
+
+# ----------------------------------------------------------------- error paths
+def test_alias_box_rejected(P, ctx):
+    s = _sys("C1")
+    from paper_2206_00808_amd import pipeline
+    d = pipeline.upload(s)
+    out = pipeline.alloc_outputs(d)
+    before = out["mtxel"].clone()
+    with pytest.raises(P.GwError) as ei:
+        P.gw_mtxel_spinor(ctx, (12, 12, 12), 2, d["gv"], d["cv"], d["gc"], d["cc"], d["geps"],
+                          out["mtxel"])
+    assert ei.value.status == P.GW_EALIAS
+    torch.cuda.synchronize()
+    assert torch.equal(before, out["mtxel"])
+    with pytest.raises(P.GwError) as ei:
+        P.gw_mtxel_spinor(ctx, (16, 16, 7), 2, d["gv"], d["cv"], d["gc"], d["cc"], d["geps"],
+                          out["mtxel"])
+    assert ei.value.status == P.GW_EINVAL
+
+
+def test_singular_eps_reported(P, ctx):
+    n = 70
+    chi = torch.eye(n, dtype=torch.complex128, device="cuda").reshape(1, n, n).contiguous()
+    v = torch.ones(n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(chi)
+    with pytest.raises(P.GwError) as ei:
+        P.gw_epsinv(ctx, n, 1, chi, v, out)
+    assert ei.value.status == P.GW_ESINGULAR
+    # the flag is cleared for the next call
+    chi2 = torch.zeros_like(chi)
+    P.gw_epsinv(ctx, n, 1, chi2, v, out)
+    torch.cuda.synchronize()
+    assert torch.allclose(out[0], torch.eye(n, dtype=torch.complex128, device="cuda"))
+
+
+def test_empty_inputs_are_noops(P, ctx):
+    chi = torch.zeros((1, 5, 5), dtype=torch.complex128, device="cuda")
+    m = torch.zeros((0, 3, 5), dtype=torch.complex128, device="cuda")
+    ev = torch.zeros(0, dtype=torch.float64, device="cuda")
+    ec = torch.zeros(3, dtype=torch.float64, device="cuda")
+    P.gw_chi0_accumulate(ctx, 0, 3, 5, m, ev, ec, [0.0], 1.0, P.GW_PREC_FP64, chi)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(chi) == 0
+
+
+# ----------------------------------------------------------------- full-size workloads
+def _sampled_checks(P, ctx, name, dtype, prec, tol_m, tol_chi, tol_inv, seed=0):
+    s = _sys(name)
+    d, out = None, None
+    from paper_2206_00808_amd import pipeline
+    d = pipeline.upload(s, dtype=dtype)
+    o = pipeline.alloc_outputs(d)
+    pipeline.run_path(ctx, d, o, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    nv, nc, neps = d["nv"], d["nc"], d["neps"]
+    # sampled pairs, all G
+    for _ in range(6):
+        v, c = int(rng.integers(nv)), int(rng.integers(nc))
+        ref = oracle.mtxel_convolution(s["cv"][v:v + 1], s["gv"], s["cc"][c:c + 1], s["gc"],
+                                       s["geps"])[0, 0]
+        got = o["mtxel"][v, c].cpu().numpy()
+        assert np.abs(got - ref).max() / np.abs(ref).max() < tol_m
+    # sampled (G, G') block over every pair
+    sel = np.sort(rng.choice(neps, size=6, replace=False))
+    sel[0] = 0
+    msel = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"][sel])
+    xref = oracle.chi0(msel, s["ev"], s["ec"], s["omega"])
+    got = o["chi0"].cpu().numpy()[:, sel][:, :, sel]
+    for f in range(len(s["omega"])):
+        assert oracle.rel_f(got[f], xref[f]) < tol_chi
+    # eps^-1 against the property eps(chi0) eps^-1 = I
+    x = o["chi0"].cpu().numpy()
+    einv = o["epsinv"].cpu().numpy()
+    for f in range(len(s["omega"])):
+        eps = np.eye(neps) - s["vcoul"][:, None] * x[f]
+        r = eps @ einv[f] - np.eye(neps)
+        assert np.linalg.norm(r) / np.sqrt(neps) < tol_inv
+
+
+@pytest.mark.slow
+def test_c2_full_size_fp64(P, ctx):
+    _sampled_checks(P, ctx, "C2", "c128", P.GW_PREC_FP64, 1e-12, 1e-10, 1e-10)
+
+
+@pytest.mark.slow
+def test_c3_full_size_mixed(P, ctx):
+    _sampled_checks(P, ctx, "C3", "c64", P.GW_PREC_SPLITBF16, 2e-6, 1e-4, 1e-6)
