@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) k_chi0_f64(const cpx<Tin>* __restrict__ M
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 32 + a * 16 + lk * 4 + r;
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;  // f64 16x16x4 D layout
         const int j = j0 + wc * 32 + b * 16 + l16;
         if (i >= neps || j >= neps) continue;
         if (skip_head >= 0 && (i == skip_head || j == skip_head)) continue;
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) k_zgemm_nn(int m, int n, int kdim, double
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 32 + a * 16 + lk * 4 + r;
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;  // f64 16x16x4 D layout
         const int j = j0 + wc * 32 + b * 16 + l16;
         if (i >= m || j >= n) continue;
         cpx<double>* d = C + (size_t)i * ldc + j;
@@ -231,16 +231,28 @@ __global__ void __launch_bounds__(256) k_zgemm_nn(int m, int n, int kdim, double
       }
 }
 
-gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, int lda,
-                   long long sA, const double* B, int ldb, long long sB, double* C, int ldc,
-                   long long sC, int batch) {
-  if (m <= 0 || n <= 0 || k <= 0) return GW_OK;
+// Highest complex-element offset (exclusive) one operand touches across the batch.
+static size_t span(size_t off, int rows, int cols, int ld, long long stride, int batch) {
+  return off + (size_t)(batch - 1) * (size_t)stride + (size_t)(rows - 1) * ld + cols;
+}
+
+gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
+                   int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
+                   double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
+                   size_t extB, size_t extC) {
+  if (m <= 0 || n <= 0 || k <= 0 || batch <= 0) return GW_OK;
+  // every offset, leading dimension and stride is in complex elements; the
+  // extents are the complex elements available behind each base pointer
+  if (span(offA, m, k, lda, sA, batch) > extA || span(offB, k, n, ldb, sB, batch) > extB ||
+      span(offC, m, n, ldc, sC, batch) > extC || lda < k || ldb < n || ldc < n)
+    return fail(c, GW_EINVAL, "zgemm operand out of range (m=%d n=%d k=%d batch=%d)", m, n, k,
+                batch);
   ProfScope ps(c, "zgemm_update");
   dim3 g((n + TM - 1) / TM, (m + TM - 1) / TM, batch);
   hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha,
-                     reinterpret_cast<const cpx<double>*>(A), lda, sA,
-                     reinterpret_cast<const cpx<double>*>(B), ldb, sB,
-                     reinterpret_cast<cpx<double>*>(C), ldc, sC);
+                     reinterpret_cast<const cpx<double>*>(A) + offA, lda, sA,
+                     reinterpret_cast<const cpx<double>*>(B) + offB, ldb, sB,
+                     reinterpret_cast<cpx<double>*>(C) + offC, ldc, sC);
   GW_CHECK_LAUNCH(c, "k_zgemm_nn");
   return GW_OK;
 }

@@ -159,14 +159,12 @@ __global__ void __launch_bounds__(256) k_trsm_block(const cpx<double>* __restric
 }
 
 // Row s of P*I is e_perm[s], perm = identity after the interchanges s <-> ipiv[s].
-__global__ void __launch_bounds__(256) k_perm_identity(const int* __restrict__ ipiv, int N,
-                                                       int* __restrict__ perm,
-                                                       cpx<double>* __restrict__ Y) {
+__global__ void __launch_bounds__(256) k_perm_build(const int* __restrict__ ipiv, int N,
+                                                    int* __restrict__ perm) {
   extern __shared__ int sp[];
   const int f = blockIdx.x;
   ipiv += (size_t)f * N;
   perm += (size_t)f * N;
-  Y += (size_t)f * N * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) sp[i] = i;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -179,10 +177,14 @@ __global__ void __launch_bounds__(256) k_perm_identity(const int* __restrict__ i
   }
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) perm[i] = sp[i];
-  for (size_t e = threadIdx.x; e < (size_t)N * N; e += blockDim.x) {
-    const int s = (int)(e / N), j = (int)(e % N);
-    Y[e] = mk(j == sp[s] ? 1.0 : 0.0, 0.0);
-  }
+}
+
+__global__ void k_perm_identity(const int* __restrict__ perm, int N, cpx<double>* __restrict__ Y) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const int s = (int)(e / N), j = (int)(e % N);
+  Y[(size_t)blockIdx.y * nn + e] = mk(j == perm[(size_t)blockIdx.y * N + s] ? 1.0 : 0.0, 0.0);
 }
 
 gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
@@ -202,7 +204,8 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
                        c->stream, reinterpret_cast<const cpx<double>*>(chi0), vcoul, LU, N);
     GW_CHECK_LAUNCH(c, "k_eps_build");
   }
-  const long long s2 = (long long)nn * 2;  // batch stride in doubles
+  const long long s2 = (long long)nn;  // batch stride in complex elements
+  const size_t ext = (size_t)nfreq * nn;  // complex elements in LU and in epsinv
   double* LUd = reinterpret_cast<double*>(LU);
   for (int k = 0; k < N; k += NB) {
     const int nbk = std::min(NB, N - k);
@@ -226,16 +229,19 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
                            c->stream, LU, N, k, nbk, LU, k + nbk, rest);
         GW_CHECK_LAUNCH(c, "k_trsm_block");
       }
-      st = zgemm_nn(c, rest, rest, nbk, -1.0, LUd + 2 * ((size_t)(k + nbk) * N + k), N, s2,
-                    LUd + 2 * ((size_t)k * N + k + nbk), N, s2,
-                    LUd + 2 * ((size_t)(k + nbk) * N + k + nbk), N, s2, nfreq);
+      st = zgemm_nn(c, rest, rest, nbk, -1.0, LUd, (size_t)(k + nbk) * N + k, N, s2, LUd,
+                    (size_t)k * N + k + nbk, N, s2, LUd, (size_t)(k + nbk) * N + k + nbk, N, s2,
+                    nfreq, ext, ext, ext);
       if (st != GW_OK) return st;
     }
   }
   {
     ProfScope ps(c, "inv_perm");
-    hipLaunchKernelGGL(k_perm_identity, dim3(nfreq), dim3(256), (size_t)N * 4, c->stream, ipiv,
-                       N, perm, Y);
+    hipLaunchKernelGGL(k_perm_build, dim3(nfreq), dim3(256), (size_t)N * 4, c->stream, ipiv, N,
+                       perm);
+    GW_CHECK_LAUNCH(c, "k_perm_build");
+    hipLaunchKernelGGL(k_perm_identity, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, perm, N, Y);
     GW_CHECK_LAUNCH(c, "k_perm_identity");
   }
   // forward: L Y = P I
@@ -249,9 +255,9 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
     }
     const int below = N - kb - nbk;
     if (below > 0) {
-      st = zgemm_nn(c, below, N, nbk, -1.0, LUd + 2 * ((size_t)(kb + nbk) * N + kb), N, s2,
-                    epsinv + 2 * ((size_t)kb * N), N, s2, epsinv + 2 * ((size_t)(kb + nbk) * N),
-                    N, s2, nfreq);
+      st = zgemm_nn(c, below, N, nbk, -1.0, LUd, (size_t)(kb + nbk) * N + kb, N, s2, epsinv,
+                    (size_t)kb * N, N, s2, epsinv, (size_t)(kb + nbk) * N, N, s2, nfreq, ext, ext,
+                    ext);
       if (st != GW_OK) return st;
     }
   }
@@ -267,8 +273,8 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
       GW_CHECK_LAUNCH(c, "k_trsm_block");
     }
     if (kb > 0) {
-      st = zgemm_nn(c, kb, N, nbk, -1.0, LUd + 2 * ((size_t)kb), N, s2,
-                    epsinv + 2 * ((size_t)kb * N), N, s2, epsinv, N, s2, nfreq);
+      st = zgemm_nn(c, kb, N, nbk, -1.0, LUd, (size_t)kb, N, s2, epsinv, (size_t)kb * N, N, s2,
+                    epsinv, 0, N, s2, nfreq, ext, ext, ext);
       if (st != GW_OK) return st;
     }
   }
