@@ -76,18 +76,19 @@ gw_status twiddle_table(gw_ctx* c, int n, bool dbl, const void** out) {
 }
 
 // ---------------------------------------------------------------- radix kernels
-// y_k = sum_j a_j exp(+2 pi i j k / R)
-template <typename T>
-__device__ __forceinline__ void dft(int R, cpx<T>* a) {
-  if (R == 4) {
+// y_k = sum_j a_j exp(+2 pi i j k / R), R fixed at compile time so the
+// butterfly stays in registers.
+template <typename T, int R>
+__device__ __forceinline__ void dft(cpx<T>* a) {
+  if constexpr (R == 4) {
     cpx<T> t0 = a[0] + a[2], t1 = a[0] - a[2];
     cpx<T> t2 = a[1] + a[3], t3 = mul_i(a[1] - a[3]);
     a[0] = t0 + t2; a[2] = t0 - t2;
     a[1] = t1 + t3; a[3] = t1 - t3;
-  } else if (R == 2) {
+  } else if constexpr (R == 2) {
     cpx<T> t = a[0];
     a[0] = t + a[1]; a[1] = t - a[1];
-  } else if (R == 3) {
+  } else if constexpr (R == 3) {
     const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
     cpx<T> t1 = a[1] + a[2];
     cpx<T> t2 = a[0] - scal(t1, (T)0.5);
@@ -110,55 +111,66 @@ __device__ __forceinline__ void dft(int R, cpx<T>* a) {
   }
 }
 
-// Batched in-LDS transform y_k = sum_j x_j exp(+2 pi i jk/n) of `npen` pencils;
-// element i of pencil b lives at buf[off(b) + i*es].  Stockham passes; each
-// pass reads every butterfly of a group of whole pencils into registers before
-// writing, so it runs in place.  Ends with a barrier.
+// One Stockham pass of radix R over `npen` pencils (element i of pencil b at
+// buf[off(b) + i*es]); Ns = product of the radices already applied.  Every
+// butterfly of a group of whole pencils is read into registers before any is
+// written, so the pass runs in place.  Ends with a barrier.
+template <typename T, int R, int MAXB, typename Off>
+__device__ __forceinline__ void stockham_pass(cpx<T>* buf, int npen, int es, Off off, int n,
+                                              int Ns, const cpx<T>* __restrict__ tw) {
+  const int nt = blockDim.x;
+  const int nq = n / R;
+  const int tws = n / (Ns * R);
+  int gp = (nt * MAXB) / nq;
+  if (gp < 1) gp = 1;
+  for (int p0 = 0; p0 < npen; p0 += gp) {
+    const int pend = min(npen, p0 + gp);
+    const int tbeg = p0 * nq, tend = pend * nq;
+    cpx<T> v[MAXB][R];
+#pragma unroll
+    for (int u = 0; u < MAXB; ++u) {
+      const int t = tbeg + u * nt + (int)threadIdx.x;
+      if (t < tend) {
+        const int b = t / nq, j = t - b * nq;
+        const int o = off(b);
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cpx<T> a = buf[o + (j + r * nq) * es];
+          if (r != 0 && k != 0) a = cmul(a, tw[r * k * tws]);
+          v[u][r] = a;
+        }
+        dft<T, R>(v[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXB; ++u) {
+      const int t = tbeg + u * nt + (int)threadIdx.x;
+      if (t < tend) {
+        const int b = t / nq, j = t - b * nq;
+        const int o = off(b);
+        const int k = j % Ns;
+        const int d = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[o + (d + r * Ns) * es] = v[u][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Batched in-LDS transform y_k = sum_j x_j exp(+2 pi i jk/n) of `npen` pencils.
 template <typename T, int MAXB, typename Off>
 __device__ void lds_fft(cpx<T>* buf, int npen, int es, Off off, const FftPlan& pl,
                         const cpx<T>* __restrict__ tw) {
-  const int n = pl.n;
-  const int nt = blockDim.x;
   int Ns = 1;
   for (int s = 0; s < pl.npass; ++s) {
     const int R = pl.radix[s];
-    const int nq = n / R;
-    const int tws = n / (Ns * R);
-    int gp = (nt * MAXB) / nq;
-    if (gp < 1) gp = 1;
-    for (int p0 = 0; p0 < npen; p0 += gp) {
-      const int pend = min(npen, p0 + gp);
-      const int tbeg = p0 * nq, tend = pend * nq;
-      cpx<T> v[MAXB][5];
-#pragma unroll
-      for (int u = 0; u < MAXB; ++u) {
-        const int t = tbeg + u * nt + (int)threadIdx.x;
-        if (t < tend) {
-          const int b = t / nq, j = t - b * nq;
-          const int o = off(b);
-          const int k = j % Ns;
-          for (int r = 0; r < R; ++r) {
-            cpx<T> a = buf[o + (j + r * nq) * es];
-            if (r != 0 && k != 0) a = cmul(a, tw[r * k * tws]);
-            v[u][r] = a;
-          }
-          dft<T>(R, v[u]);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < MAXB; ++u) {
-        const int t = tbeg + u * nt + (int)threadIdx.x;
-        if (t < tend) {
-          const int b = t / nq, j = t - b * nq;
-          const int o = off(b);
-          const int k = j % Ns;
-          const int d = (j / Ns) * Ns * R + k;
-          for (int r = 0; r < R; ++r) buf[o + (d + r * Ns) * es] = v[u][r];
-        }
-      }
-      __syncthreads();
-    }
+    if (R == 4) stockham_pass<T, 4, MAXB>(buf, npen, es, off, pl.n, Ns, tw);
+    else if (R == 2) stockham_pass<T, 2, MAXB>(buf, npen, es, off, pl.n, Ns, tw);
+    else if (R == 3) stockham_pass<T, 3, MAXB>(buf, npen, es, off, pl.n, Ns, tw);
+    else stockham_pass<T, 5, MAXB>(buf, npen, es, off, pl.n, Ns, tw);
     Ns *= R;
   }
 }

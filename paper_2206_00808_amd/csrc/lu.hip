@@ -1,8 +1,18 @@
 // eps = I - diag(v) chi0 and its inverse in double (Sec. II, dielectric matrix;
 // the Performance section names this inversion as a large part of Epsilon).
 //
-// Right-looking blocked LU with partial pivoting (PA = LU), every frequency
-// in the same launches (grid.z / grid.y = frequency):
+// Default path: on the static and imaginary-frequency axis chi0 is Hermitian
+// negative semidefinite, so with S = diag(sqrt(v)) (v > 0)
+//   eps = S (I - S chi0 S) S^-1 = S epst S^-1,  epst Hermitian positive definite
+// (every eigenvalue >= 1).  epst is inverted in place by blocked Gauss-Jordan
+// elimination without pivoting (stable for a positive-definite matrix), whose
+// work is one rank-nb GEMM update of the whole matrix per block, and then
+// eps^-1 = S epst^-1 S^-1.  Each diagonal pivot is checked to be real and
+// positive; if any is not (or some v <= 0), the result is discarded and the
+// general path below runs instead.
+//
+// General path: right-looking blocked LU with partial pivoting (PA = LU), every
+// frequency in the same launches (grid.z / grid.y = frequency):
 //   panel  : one 1024-thread workgroup factors the N x nb column panel
 //            (pivot = largest |re|+|im|, lowest row on ties)
 //   laswp  : the panel's row interchanges applied to the other columns
@@ -187,8 +197,133 @@ __global__ void k_perm_identity(const int* __restrict__ perm, int N, cpx<double>
   Y[(size_t)blockIdx.y * nn + e] = mk(j == perm[(size_t)blockIdx.y * N + s] ? 1.0 : 0.0, 0.0);
 }
 
-gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
-                     double* epsinv) {
+
+// ---------------------------------------------------------------- Gauss-Jordan path
+constexpr int GB = 32;  // Gauss-Jordan block width
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_zero(cpx<double>* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = mk(0.0, 0.0);
+}
+
+// epst = I - S chi0 S with S = diag(sqrt(v)); flag[1] = 1 if some v <= 0 or non-finite.
+__global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* __restrict__ v,
+                             cpx<double>* __restrict__ A, int N, int* __restrict__ flag) {
+  const size_t nn = (size_t)N * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  const double vi = v[i], vj = v[j];
+  if (!(vi > 0.0) || !(vi < INFINITY)) flag[1] = 1;
+  const double s = sqrt(vi) * sqrt(vj);
+  const size_t off = (size_t)blockIdx.y * nn + idx;
+  const cpx<double> x = chi[off];
+  A[off] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
+}
+
+// Invert the nbk x nbk diagonal block A[K][K] (K = k..k+nbk) by unblocked
+// Gauss-Jordan without pivoting; write it to Dw[f].  A pivot that is not
+// real-positive sets flag[1].
+__global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ A, int N, int k,
+                                                  int nbk, cpx<double>* __restrict__ Dw,
+                                                  int* __restrict__ flag) {
+  __shared__ cpx<double> D[GB][GB + 1];
+  __shared__ cpx<double> piv;
+  const int f = blockIdx.x;
+  A += (size_t)f * N * N;
+  Dw += (size_t)f * GB * GB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
+    const int r = e / nbk, cc = e % nbk;
+    D[r][cc] = A[(size_t)(k + r) * N + k + cc];
+  }
+  __syncthreads();
+  for (int t = 0; t < nbk; ++t) {
+    if (tid == 0) {
+      const cpx<double> p = D[t][t];
+      const bool ok = p.x > 0.0 && fabs(p.y) <= 1e-8 * p.x && p.x < INFINITY;
+      if (!ok) flag[1] = 1;
+      const double den = p.x * p.x + p.y * p.y;
+      piv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    const cpx<double> pinv = piv;
+    // row t scaled, then the rank-1 update; the pivot column is handled last
+    cpx<double> rowt = mk(0.0, 0.0), colt = mk(0.0, 0.0);
+    const int i = tid / GB, j = tid % GB;
+    const bool act = tid < GB * GB && i < nbk && j < nbk;
+    if (act) {
+      rowt = cmul(D[t][j], pinv);
+      colt = D[i][t];
+    }
+    __syncthreads();
+    if (act) {
+      if (i == t && j == t) D[i][j] = pinv;
+      else if (i == t) D[i][j] = rowt;
+      else if (j == t) D[i][j] = mk(-(colt.x * pinv.x - colt.y * pinv.y),
+                                   -(colt.x * pinv.y + colt.y * pinv.x));
+      else D[i][j] = D[i][j] - cmul(colt, rowt);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
+    const int r = e / nbk, cc = e % nbk;
+    Dw[r * GB + cc] = D[r][cc];
+  }
+}
+
+// Cb[f][i][t] = A[f][i][k+t] for all rows i (column block K).
+__global__ void k_gj_copy_cols(const cpx<double>* __restrict__ A, int N, int k, int nbk,
+                               cpx<double>* __restrict__ Cb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nbk) return;
+  const int i = e / nbk, t = e % nbk;
+  const size_t f = blockIdx.y;
+  Cb[f * (size_t)N * GB + (size_t)i * GB + t] = A[f * (size_t)N * N + (size_t)i * N + k + t];
+}
+
+// Row block K <- R (columns outside K), diagonal block <- Dinv, column block
+// outside K <- -Cb Dinv.
+__global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
+                         const cpx<double>* __restrict__ R, const cpx<double>* __restrict__ Cb,
+                         const cpx<double>* __restrict__ Dw) {
+  const size_t f = blockIdx.y;
+  A += f * (size_t)N * N;
+  R += f * (size_t)GB * N;
+  Cb += f * (size_t)N * GB;
+  Dw += f * (size_t)GB * GB;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nbk * N) {  // row block
+    const int t = e / N, j = e % N;
+    A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
+    return;
+  }
+  const int e2 = e - nbk * N;
+  if (e2 >= N * nbk) return;
+  const int i = e2 / nbk, t = e2 % nbk;
+  if (i >= k && i < k + nbk) return;
+  cpx<double> s = mk(0.0, 0.0);
+  for (int u = 0; u < nbk; ++u) s = s + cmul(Cb[(size_t)i * GB + u], Dw[u * GB + t]);
+  A[(size_t)i * N + k + t] = mk(-s.x, -s.y);
+}
+
+// eps^-1 = S epst^-1 S^-1, in place.
+__global__ void k_unscale(cpx<double>* __restrict__ A, const double* __restrict__ v, int N) {
+  const size_t nn = (size_t)N * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  const double s = sqrt(v[i]) / sqrt(v[j]);
+  cpx<double>* a = A + (size_t)blockIdx.y * nn + idx;
+  *a = scal(*a, s);
+}
+
+static gw_status epsinv_pivoted(gw_ctx* c, int N, int nfreq, const double* chi0,
+                                const double* vcoul, double* epsinv) {
   const size_t nn = (size_t)N * N;
   const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up((size_t)nfreq * N * 4);
   gw_status st = ws_begin(c, bytes);
@@ -197,7 +332,11 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
   int* ipiv = static_cast<int*>(ws_take(c, (size_t)nfreq * N * 4));
   int* perm = static_cast<int*>(ws_take(c, (size_t)nfreq * N * 4));
   cpx<double>* Y = reinterpret_cast<cpx<double>*>(epsinv);
-  GW_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  {
+    ProfScope ps(c, "flags_clear");
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->d_flag, 16, 0);
+    GW_CHECK_LAUNCH(c, "k_fill_int");
+  }
   {
     ProfScope ps(c, "eps_build");
     hipLaunchKernelGGL(k_eps_build, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
@@ -283,6 +422,85 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
   GW_HIP(c, hipStreamSynchronize(c->stream));
   if (flag) return fail(c, GW_ESINGULAR, "eps has a zero pivot (singular dielectric matrix)");
   return GW_OK;
+}
+
+static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* chi0,
+                                     const double* vcoul, double* epsinv) {
+  const size_t nn = (size_t)N * N;
+  const size_t nR = (size_t)nfreq * GB * N, nC = (size_t)nfreq * N * GB, nD = (size_t)nfreq * GB * GB;
+  gw_status st = ws_begin(c, align_up(nR * 16) + align_up(nC * 16) + align_up(nD * 16));
+  if (st != GW_OK) return st;
+  cpx<double>* R = static_cast<cpx<double>*>(ws_take(c, nR * 16));
+  cpx<double>* Cb = static_cast<cpx<double>*>(ws_take(c, nC * 16));
+  cpx<double>* Dw = static_cast<cpx<double>*>(ws_take(c, nD * 16));
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(epsinv);
+  const double* Ad = epsinv;
+  {
+    ProfScope ps(c, "flags_clear");
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->d_flag, 16, 0);
+    GW_CHECK_LAUNCH(c, "k_fill_int");
+  }
+  {
+    ProfScope ps(c, "eps_build");
+    hipLaunchKernelGGL(k_epst_build, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, reinterpret_cast<const cpx<double>*>(chi0), vcoul, A, N,
+                       c->d_flag);
+    GW_CHECK_LAUNCH(c, "k_epst_build");
+  }
+  const size_t ext = (size_t)nfreq * nn;
+  for (int k = 0; k < N; k += GB) {
+    const int nbk = std::min(GB, N - k);
+    {
+      ProfScope ps(c, "gj_diag");
+      hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->stream, A, N, k, nbk, Dw,
+                         c->d_flag);
+      GW_CHECK_LAUNCH(c, "k_gj_diag");
+    }
+    {
+      ProfScope ps(c, "gj_small");
+      hipLaunchKernelGGL(k_gj_copy_cols, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0,
+                         c->stream, A, N, k, nbk, Cb);
+      GW_CHECK_LAUNCH(c, "k_gj_copy_cols");
+      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nR + 255) / 256)), dim3(256), 0, c->stream,
+                         R, nR);
+      GW_CHECK_LAUNCH(c, "k_fill_zero");
+    }
+    // R = Dinv A[K][:]
+    st = zgemm_nn(c, nbk, N, nbk, 1.0, reinterpret_cast<const double*>(Dw), 0, GB, GB * GB, Ad,
+                  (size_t)k * N, N, (long long)nn, reinterpret_cast<double*>(R), 0, N,
+                  (long long)GB * N, nfreq, nD, ext, nR);
+    if (st != GW_OK) return st;
+    // A -= Cb R over the whole matrix (row and column block K are rewritten next)
+    st = zgemm_nn(c, N, N, nbk, -1.0, reinterpret_cast<const double*>(Cb), 0, GB,
+                  (long long)N * GB, reinterpret_cast<const double*>(R), 0, N, (long long)GB * N,
+                  epsinv, 0, N, (long long)nn, nfreq, nC, nR, ext);
+    if (st != GW_OK) return st;
+    {
+      ProfScope ps(c, "gj_small");
+      hipLaunchKernelGGL(k_gj_fix, dim3((2 * N * nbk + 255) / 256, nfreq), dim3(256), 0,
+                         c->stream, A, N, k, nbk, R, Cb, Dw);
+      GW_CHECK_LAUNCH(c, "k_gj_fix");
+    }
+  }
+  {
+    ProfScope ps(c, "eps_unscale");
+    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, A, vcoul, N);
+    GW_CHECK_LAUNCH(c, "k_unscale");
+  }
+  return GW_OK;
+}
+
+gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
+                     double* epsinv) {
+  gw_status st = epsinv_gauss_jordan(c, N, nfreq, chi0, vcoul, epsinv);
+  if (st != GW_OK) return st;
+  int flags[2] = {0, 0};
+  GW_HIP(c, hipMemcpyAsync(flags, c->d_flag, sizeof flags, hipMemcpyDeviceToHost, c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  if (!flags[1]) return GW_OK;
+  // not positive definite (or v <= 0): general LU with partial pivoting
+  return epsinv_pivoted(c, N, nfreq, chi0, vcoul, epsinv);
 }
 
 }  // namespace gw
