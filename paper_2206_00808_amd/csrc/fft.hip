@@ -118,7 +118,7 @@ __device__ __forceinline__ void dft(cpx<T>* a) {
 template <typename T, int R, int MAXB, typename Off>
 __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int npen, int es, Off off, int n,
                                               int Ns, const cpx<T>* __restrict__ tw) {
-  const int nt = blockDim.x;
+  constexpr int nt = 256;  // every FFT kernel runs 256-thread workgroups
   const int nq = n / R;
   const int tws = n / (Ns * R);
   int gp = (nt * MAXB) / nq;
@@ -175,28 +175,85 @@ __device__ void lds_fft(cpx<T>* buf, int npen, int es, Off off, const FftPlan& p
   }
 }
 
+// Compile-time radix plan (same order as make_fft_plan) for pencil lengths
+// known when the kernel is built: every divisor in the pass index math is then a
+// constant.
+constexpr int cx_npass(int n) {
+  int c = 0;
+  while (n % 4 == 0) { n /= 4; ++c; }
+  while (n % 2 == 0) { n /= 2; ++c; }
+  while (n % 3 == 0) { n /= 3; ++c; }
+  while (n % 5 == 0) { n /= 5; ++c; }
+  return n == 1 ? c : -1;
+}
+constexpr int cx_radix(int n, int s) {
+  int c = 0;
+  while (n % 4 == 0) { n /= 4; if (c++ == s) return 4; }
+  while (n % 2 == 0) { n /= 2; if (c++ == s) return 2; }
+  while (n % 3 == 0) { n /= 3; if (c++ == s) return 3; }
+  while (n % 5 == 0) { n /= 5; if (c++ == s) return 5; }
+  return 0;
+}
+
+template <typename T, int N, int S, int NSC, int MAXB, typename Off>
+__device__ __forceinline__ void fft_ct(cpx<T>* buf, int npen, int es, Off off,
+                                       const cpx<T>* __restrict__ tw) {
+  if constexpr (S < cx_npass(N)) {
+    constexpr int R = cx_radix(N, S);
+    stockham_pass<T, R, MAXB>(buf, npen, es, off, N, NSC, tw);
+    fft_ct<T, N, S + 1, NSC * R, MAXB>(buf, npen, es, off, tw);
+  }
+}
+
+// N > 0: length fixed at build time; N == 0: the runtime plan.
+template <typename T, int N, int MAXB, typename Off>
+__device__ __forceinline__ void fft_any(cpx<T>* buf, int npen, int es, Off off,
+                                        const FftPlan& pl, const cpx<T>* __restrict__ tw) {
+  if constexpr (N > 0) {
+    static_assert(cx_npass(N) > 0, "length must factor into 2, 3, 5");
+    fft_ct<T, N, 0, 1, MAXB>(buf, npen, es, off, tw);
+  } else {
+    lds_fft<T, MAXB>(buf, npen, es, off, pl, tw);
+  }
+}
+
 constexpr int kThreads = 256;
 constexpr int kMaxB = 4;
 
 __device__ __forceinline__ int wrap(int g, int n) { return g < 0 ? g + n : g; }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  Renumber so that XCD k receives the k-th contiguous slice of
+// the logical order; the logical order is x-plane major, so one XCD walks a few
+// x-planes and keeps their valence planes resident in its L2 while the
+// conduction planes stream through once.  Returns -1 for padding blocks.
+constexpr int kXcd = 8;
+__device__ __forceinline__ long long xcd_linear(long long b, long long total) {
+  const long long per = (total + kXcd - 1) / kXcd;
+  const long long l = (b % kXcd) * per + b / kXcd;
+  return l < total ? l : -1;
+}
+
 // ---------------------------------------------------------------- band transforms
+// Each kernel takes its pencil lengths as template arguments (0 = runtime).
+
 // x-pass from the sphere: for each compact column (jy,jz) gather the |gx|<=gmax
 // coefficients, transform along x, write T1[bs][x][col].
-template <typename T>
+template <typename T, int N1>
 __global__ void __launch_bounds__(kThreads) k_band_x(
     const cpx<T>* __restrict__ coef, int ng, const int* __restrict__ cube, int ex, int ey,
-    int ez, int gx, int n1, int ncol, int CH, FftPlan pl, const cpx<T>* __restrict__ tw,
+    int ez, int gx, int n1_rt, int ncol, int CH, FftPlan pl, const cpx<T>* __restrict__ tw,
     cpx<T>* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int n1 = N1 ? N1 : n1_rt;
   const int bs = blockIdx.y;
   const int col0 = blockIdx.x * CH;
   const int nch = min(CH, ncol - col0);
   const cpx<T>* cf = coef + (size_t)bs * ng;
-  for (int i = threadIdx.x; i < n1 * CH; i += blockDim.x) lds[i] = mk<T>(0, 0);
+  for (int i = threadIdx.x; i < n1 * CH; i += kThreads) lds[i] = mk<T>(0, 0);
   __syncthreads();
-  for (int i = threadIdx.x; i < ex * nch; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ex * nch; i += kThreads) {
     const int jx = i / nch, cl = i - jx * nch;
     const int col = col0 + cl;
     const int jy = col / ez, jz = col - jy * ez;
@@ -204,37 +261,41 @@ __global__ void __launch_bounds__(kThreads) k_band_x(
     if (idx >= 0) lds[wrap(jx - gx, n1) * CH + cl] = cf[idx];
   }
   __syncthreads();
-  lds_fft<T, kMaxB>(lds, nch, CH, [](int b) { return b; }, pl, tw);
+  fft_any<T, N1, kMaxB>(lds, nch, CH, [](int b) { return b; }, pl, tw);
   cpx<T>* o = out + (size_t)bs * n1 * ncol;
-  for (int i = threadIdx.x; i < n1 * nch; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n1 * nch; i += kThreads) {
     const int x = i / nch, cl = i - x * nch;
     o[(size_t)x * ncol + col0 + cl] = lds[x * CH + cl];
   }
 }
 
+__host__ __device__ constexpr int plane_pitch(int n3) { return (n3 % 2 == 0) ? n3 + 1 : n3; }
+
 // plane pass: expand the compact (y,z) plane of one x, transform along y on the
 // occupied z columns, then along z on every row; write the full plane.
-template <typename T>
+template <typename T, int N2, int N3>
 __global__ void __launch_bounds__(kThreads) k_band_plane(
-    const cpx<T>* __restrict__ t1, int ey, int ez, int gy, int gz, int n1, int n2, int n3,
-    int P, FftPlan ply, FftPlan plz, const cpx<T>* __restrict__ twy,
-    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ u) {
+    const cpx<T>* __restrict__ t1, int ey, int ez, int gy, int gz, int n1, int n2_rt, int n3_rt,
+    FftPlan ply, FftPlan plz, const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz,
+    cpx<T>* __restrict__ u) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int n2 = N2 ? N2 : n2_rt, n3 = N3 ? N3 : n3_rt;
+  const int P = plane_pitch(n3);
   const int x = blockIdx.x, bs = blockIdx.y;
   const int ncol = ey * ez;
-  for (int i = threadIdx.x; i < n2 * P; i += blockDim.x) pl[i] = mk<T>(0, 0);
+  for (int i = threadIdx.x; i < n2 * P; i += kThreads) pl[i] = mk<T>(0, 0);
   __syncthreads();
   const cpx<T>* src = t1 + ((size_t)bs * n1 + x) * ncol;
-  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ncol; i += kThreads) {
     const int jy = i / ez, jz = i - jy * ez;
     pl[wrap(jy - gy, n2) * P + wrap(jz - gz, n3)] = src[i];
   }
   __syncthreads();
-  lds_fft<T, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
-  lds_fft<T, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
+  fft_any<T, N2, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
+  fft_any<T, N3, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
   cpx<T>* dst = u + ((size_t)bs * n1 + x) * (size_t)n2 * n3;
-  for (int i = threadIdx.x; i < n2 * n3; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n2 * n3; i += kThreads) {
     const int y = i / n3, z = i - y * n3;
     dst[i] = pl[y * P + z];
   }
@@ -243,30 +304,35 @@ __global__ void __launch_bounds__(kThreads) k_band_plane(
 // ---------------------------------------------------------------- pair transforms
 // plane pass: spin-summed product of one x-plane, z transform (keep |gz|<=gmax),
 // y transform of the kept columns (keep |gy|<=gmax), write T2[pair][x][jy][jz].
-template <typename T, int NS>
+template <typename T, int NS, int N2, int N3>
 __global__ void __launch_bounds__(kThreads) k_pair_plane(
     const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
-    int n1, int n2, int n3, int P, int ey, int ez, int gy, int gz, FftPlan ply, FftPlan plz,
-    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+    int n1, int n2_rt, int n3_rt, int ey, int ez, int gy, int gz, FftPlan ply, FftPlan plz,
+    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2,
+    int npairs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int x = blockIdx.x, pr = blockIdx.y;
+  const int n2 = N2 ? N2 : n2_rt, n3 = N3 ? N3 : n3_rt;
+  const int P = plane_pitch(n3);
+  const long long lin = xcd_linear(blockIdx.x, (long long)n1 * npairs);
+  if (lin < 0) return;
+  const int x = (int)(lin / npairs), pr = (int)(lin % npairs);
   const int v = v0 + pr % nvt, c = c0 + pr / nvt;
   const size_t nb = (size_t)n1 * n2 * n3, np = (size_t)n2 * n3;
   const cpx<T>* pv = uv + (size_t)v * NS * nb + (size_t)x * np;
   const cpx<T>* pc = uc + (size_t)c * NS * nb + (size_t)x * np;
-  for (int i = threadIdx.x; i < (int)np; i += blockDim.x) {
+  for (int i = threadIdx.x; i < (int)np; i += kThreads) {
     cpx<T> acc = cmulc(pv[i], pc[i]);
     if (NS == 2) acc = acc + cmulc(pv[nb + i], pc[nb + i]);
     const int y = i / n3, z = i - y * n3;
     pl[y * P + z] = acc;
   }
   __syncthreads();
-  lds_fft<T, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
-  lds_fft<T, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
+  fft_any<T, N3, kMaxB>(pl, n2, 1, [=](int b) { return b * P; }, plz, twz);
+  fft_any<T, N2, kMaxB>(pl, ez, P, [=](int b) { return wrap(b - gz, n3); }, ply, twy);
   const int ncol = ey * ez;
   cpx<T>* dst = t2 + ((size_t)pr * n1 + x) * ncol;
-  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ncol; i += kThreads) {
     const int jy = i / ez, jz = i - jy * ez;
     dst[i] = pl[wrap(jy - gy, n2) * P + wrap(jz - gz, n3)];
   }
@@ -274,25 +340,26 @@ __global__ void __launch_bounds__(kThreads) k_pair_plane(
 
 // x-pass + eps gather: transform the kept (jy,jz) columns along x, keep the
 // |gx|<=gmax outputs that lie on the eps sphere, scale by 1/N.
-template <typename T>
+template <typename T, int N1>
 __global__ void __launch_bounds__(kThreads) k_pair_x(
-    const cpx<T>* __restrict__ t2, int n1, int ncol, int CH, int ex, int ey, int ez, int gx,
+    const cpx<T>* __restrict__ t2, int n1_rt, int ncol, int CH, int ex, int ey, int ez, int gx,
     const int* __restrict__ emap, FftPlan plx, const cpx<T>* __restrict__ twx, T invN, int v0,
     int nvt, int c0, int nct_total, int neps, cpx<T>* __restrict__ M) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int n1 = N1 ? N1 : n1_rt;
   const int col0 = blockIdx.x * CH, pr = blockIdx.y;
   const int nch = min(CH, ncol - col0);
   const cpx<T>* src = t2 + (size_t)pr * n1 * ncol;
-  for (int i = threadIdx.x; i < n1 * nch; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n1 * nch; i += kThreads) {
     const int x = i / nch, cl = i - x * nch;
     lds[x * CH + cl] = src[(size_t)x * ncol + col0 + cl];
   }
   __syncthreads();
-  lds_fft<T, kMaxB>(lds, nch, CH, [](int b) { return b; }, plx, twx);
+  fft_any<T, N1, kMaxB>(lds, nch, CH, [](int b) { return b; }, plx, twx);
   const int v = v0 + pr % nvt, c = c0 + pr / nvt;
   cpx<T>* dst = M + ((size_t)v * nct_total + c) * neps;
-  for (int i = threadIdx.x; i < ex * nch; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ex * nch; i += kThreads) {
     const int jx = i / nch, cl = i - jx * nch;
     const int col = col0 + cl;
     const int jy = col / ez, jz = col - jy * ez;
@@ -301,8 +368,12 @@ __global__ void __launch_bounds__(kThreads) k_pair_x(
   }
 }
 
+// Pencil lengths (x) and plane shapes (y, z) built with constant lengths; any
+// other box factoring into 2, 3, 5 runs the same kernels with runtime lengths.
+#define GW_X_LENGTHS(X) X(16) X(20) X(24) X(30) X(32) X(48) X(60)
+#define GW_PLANE_SHAPES(X) X(16, 16) X(24, 30) X(32, 32) X(48, 48) X(60, 160)
+
 // ---------------------------------------------------------------- launchers
-static int plane_pitch(int n3) { return (n3 % 2 == 0) ? n3 + 1 : n3; }
 
 template <typename T>
 static int col_chunk(int n1) {
@@ -328,6 +399,36 @@ size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, siz
   return (size_t)npairs * box[0] * em->ext[1] * em->ext[2] * elem;
 }
 
+// kernel selection by box shape
+template <typename T>
+static decltype(&k_band_x<T, 0>) pick_band_x(int n1) {
+#define X(N) if (n1 == N) return &k_band_x<T, N>;
+  GW_X_LENGTHS(X)
+#undef X
+  return &k_band_x<T, 0>;
+}
+template <typename T>
+static decltype(&k_pair_x<T, 0>) pick_pair_x(int n1) {
+#define X(N) if (n1 == N) return &k_pair_x<T, N>;
+  GW_X_LENGTHS(X)
+#undef X
+  return &k_pair_x<T, 0>;
+}
+template <typename T>
+static decltype(&k_band_plane<T, 0, 0>) pick_band_plane(int n2, int n3) {
+#define X(A, B) if (n2 == A && n3 == B) return &k_band_plane<T, A, B>;
+  GW_PLANE_SHAPES(X)
+#undef X
+  return &k_band_plane<T, 0, 0>;
+}
+template <typename T, int NS>
+static decltype(&k_pair_plane<T, NS, 0, 0>) pick_pair_plane(int n2, int n3) {
+#define X(A, B) if (n2 == A && n3 == B) return &k_pair_plane<T, NS, A, B>;
+  GW_PLANE_SHAPES(X)
+#undef X
+  return &k_pair_plane<T, NS, 0, 0>;
+}
+
 template <typename T>
 gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
                        const SphereMap* sm, void* u_out, void* scratch, size_t scratch_bytes) {
@@ -348,8 +449,10 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
   const size_t lds_x = (size_t)n1 * CH * sizeof(cpx<T>);
   const int P = plane_pitch(n3);
   const size_t lds_p = (size_t)n2 * P * sizeof(cpx<T>);
-  GW_HIP(c, allow_lds(k_band_x<T>, lds_x));
-  GW_HIP(c, allow_lds(k_band_plane<T>, lds_p));
+  auto kx = pick_band_x<T>(n1);
+  auto kp = pick_band_plane<T>(n2, n3);
+  GW_HIP(c, allow_lds(kx, lds_x));
+  GW_HIP(c, allow_lds(kp, lds_p));
   const cpx<T>* cf = static_cast<const cpx<T>*>(coef);
   cpx<T>* u = static_cast<cpx<T>*>(u_out);
   cpx<T>* t1 = static_cast<cpx<T>*>(scratch);
@@ -358,16 +461,16 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
     {
       ProfScope ps(c, "band_xpass");
       dim3 g((ncol + CH - 1) / CH, nb);
-      hipLaunchKernelGGL(k_band_x<T>, g, dim3(kThreads), lds_x, c->stream, cf + (size_t)b0 * ng,
-                         ng, sm->d_cube, sm->ext[0], sm->ext[1], sm->ext[2], sm->gmax[0], n1,
-                         ncol, CH, px, static_cast<const cpx<T>*>(twx), t1);
+      hipLaunchKernelGGL(kx, g, dim3(kThreads), lds_x, c->stream, cf + (size_t)b0 * ng, ng,
+                         sm->d_cube, sm->ext[0], sm->ext[1], sm->ext[2], sm->gmax[0], n1, ncol,
+                         CH, px, static_cast<const cpx<T>*>(twx), t1);
       GW_CHECK_LAUNCH(c, "k_band_x");
     }
     {
       ProfScope ps(c, "band_plane");
       dim3 g(n1, nb);
-      hipLaunchKernelGGL(k_band_plane<T>, g, dim3(kThreads), lds_p, c->stream, t1, sm->ext[1],
-                         sm->ext[2], sm->gmax[1], sm->gmax[2], n1, n2, n3, P, py, pz,
+      hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, t1, sm->ext[1], sm->ext[2],
+                         sm->gmax[1], sm->gmax[2], n1, n2, n3, py, pz,
                          static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz),
                          u + (size_t)b0 * n1 * n2 * n3);
       GW_CHECK_LAUNCH(c, "k_band_plane");
@@ -395,33 +498,27 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
   const int CH = col_chunk<T>(n1);
   const size_t lds_x = (size_t)n1 * CH * sizeof(cpx<T>);
   cpx<T>* t2 = static_cast<cpx<T>*>(scratch);
-  if (nspinor == 2) {
-    GW_HIP(c, allow_lds(k_pair_plane<T, 2>, lds_p));
-  } else {
-    GW_HIP(c, allow_lds(k_pair_plane<T, 1>, lds_p));
-  }
-  GW_HIP(c, allow_lds(k_pair_x<T>, lds_x));
+  auto kp = nspinor == 2 ? pick_pair_plane<T, 2>(n2, n3) : pick_pair_plane<T, 1>(n2, n3);
+  auto kx = pick_pair_x<T>(n1);
+  GW_HIP(c, allow_lds(kp, lds_p));
+  GW_HIP(c, allow_lds(kx, lds_x));
   {
     ProfScope ps(c, "pair_plane");
-    dim3 g(n1, npairs);
-    if (nspinor == 2)
-      hipLaunchKernelGGL((k_pair_plane<T, 2>), g, dim3(kThreads), lds_p, c->stream,
-                         static_cast<const cpx<T>*>(uv), static_cast<const cpx<T>*>(uc), v0, nvt,
-                         c0, n1, n2, n3, P, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2], py,
-                         pz, static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2);
-    else
-      hipLaunchKernelGGL((k_pair_plane<T, 1>), g, dim3(kThreads), lds_p, c->stream,
-                         static_cast<const cpx<T>*>(uv), static_cast<const cpx<T>*>(uc), v0, nvt,
-                         c0, n1, n2, n3, P, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2], py,
-                         pz, static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2);
+    const long long tot = (long long)n1 * npairs;
+    dim3 g((unsigned)(((tot + kXcd - 1) / kXcd) * kXcd));
+    hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, static_cast<const cpx<T>*>(uv),
+                       static_cast<const cpx<T>*>(uc), v0, nvt, c0, n1, n2, n3, em->ext[1],
+                       em->ext[2], em->gmax[1], em->gmax[2], py, pz,
+                       static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2,
+                       npairs);
     GW_CHECK_LAUNCH(c, "k_pair_plane");
   }
   {
     ProfScope ps(c, "pair_xpass");
     dim3 g((ncol + CH - 1) / CH, npairs);
     const T invN = (T)(1.0 / ((double)n1 * n2 * n3));
-    hipLaunchKernelGGL(k_pair_x<T>, g, dim3(kThreads), lds_x, c->stream, t2, n1, ncol, CH,
-                       em->ext[0], em->ext[1], em->ext[2], em->gmax[0], em->d_cube, px,
+    hipLaunchKernelGGL(kx, g, dim3(kThreads), lds_x, c->stream, t2, n1, ncol, CH, em->ext[0],
+                       em->ext[1], em->ext[2], em->gmax[0], em->d_cube, px,
                        static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,
                        static_cast<cpx<T>*>(mtxel));
     GW_CHECK_LAUNCH(c, "k_pair_x");

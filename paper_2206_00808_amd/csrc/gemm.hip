@@ -60,13 +60,18 @@ __device__ __forceinline__ cpx<double> load_widen(const cpx<Tin>* p) {
   return mk<double>((double)v.x, (double)v.y);
 }
 
+// 64x64 output tile per workgroup (4 waves of 32x32), K-step of 16 pairs.
+// Planar re/im LDS tiles padded so each quarter-wave row group lands on its own
+// half of the banks; the next K-tile is fetched into registers while the
+// matrix cores work on the current one.
+constexpr int PT = TM + 16;
+
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P, int neps,
                                                   const double* __restrict__ wts,
                                                   cpx<double>* __restrict__ chi, int nt,
                                                   int skip_head) {
-  __shared__ cpx<double> As[KT][LP];
-  __shared__ cpx<double> Bs[KT][LP];
+  __shared__ double Ar[KT][PT], Ai[KT][PT], Br[KT][PT], Bi[KT][PT];
   int ti, tj;
   tri_tile(blockIdx.x, nt, &ti, &tj);
   const int f = blockIdx.y;
@@ -75,6 +80,7 @@ __global__ void __launch_bounds__(256) k_chi0_f64(const cpx<Tin>* __restrict__ M
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lk = lane >> 4;
+  constexpr int NE = (KT * TM) / 256;
   d4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -83,41 +89,74 @@ __global__ void __launch_bounds__(256) k_chi0_f64(const cpx<Tin>* __restrict__ M
       cr[a][b] = (d4){0, 0, 0, 0};
       ci[a][b] = (d4){0, 0, 0, 0};
     }
-  for (int p0 = 0; p0 < P; p0 += KT) {
-    __syncthreads();
+  // raw loads from clamped (always valid) addresses; masking and the weight
+  // are applied at the LDS store so the prefetch never waits on its own loads
+  cpx<Tin> ra[NE], rb[NE];
+  double rw[NE];
+  auto gload = [&](int p0) {
 #pragma unroll
-    for (int e = 0; e < (KT * TM) / 256; ++e) {
+    for (int e = 0; e < NE; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx / TM, ii = idx % TM;
-      const int p = p0 + kk;
-      cpx<double> a = mk<double>(0, 0), b = mk<double>(0, 0);
-      if (p < P) {
-        if (i0 + ii < neps) a = load_widen(M + (size_t)p * neps + i0 + ii);
-        if (j0 + ii < neps) b = scal(load_widen(M + (size_t)p * neps + j0 + ii), w[p]);
-      }
-      As[kk][ii] = a;
-      Bs[kk][ii] = b;
+      const int p = min(p0 + kk, P - 1);
+      ra[e] = M[(size_t)p * neps + min(i0 + ii, neps - 1)];
+      rb[e] = M[(size_t)p * neps + min(j0 + ii, neps - 1)];
+      rw[e] = w[p];
+    }
+  };
+  gload(0);
+  for (int p0 = 0; p0 < P; p0 += KT) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx / TM, ii = idx % TM;
+      const bool pk = p0 + kk < P;
+      const double ma = (pk && i0 + ii < neps) ? 1.0 : 0.0;
+      const double mb = (pk && j0 + ii < neps) ? rw[e] : 0.0;
+      Ar[kk][ii] = ma * (double)ra[e].x; Ai[kk][ii] = ma * (double)ra[e].y;
+      Br[kk][ii] = mb * (double)rb[e].x; Bi[kk][ii] = mb * (double)rb[e].y;
     }
     __syncthreads();
+    if (p0 + KT < P) gload(p0 + KT);
 #pragma unroll
     for (int s = 0; s < KT / 4; ++s) {
       const int kk = s * 4 + lk;
-      cpx<double> av[2], bv[2];
+      double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Ar[kk][wr * 32 + a * 16 + l16];
+        ai[a] = Ai[kk][wr * 32 + a * 16 + l16];
+      }
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc * 32 + b * 16 + l16];
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Br[kk][wc * 32 + b * 16 + l16];
+        bi[b] = Bi[kk][wc * 32 + b * 16 + l16];
+      }
+      // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br); the four products are
+      // issued round-robin over the eight accumulators so that no MFMA waits on
+      // the one just issued
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br)
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], br[b], ci[a][b], 0, 0, 0);
     }
+    __syncthreads();
   }
   cpx<double>* C = chi + (size_t)f * neps * neps;
 #pragma unroll
@@ -299,26 +338,33 @@ __global__ void __launch_bounds__(256) k_chi0_bf16x3(const cpx<float>* __restric
       for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
     }
   int since_flush = 0;
-  for (int p0 = 0; p0 < P; p0 += BK) {
-    __syncthreads();
-    // stage: BK pairs x TM columns of A (=M) and B (=w*M), split into hi/lo
+  constexpr int NE = (BK * TM) / 256;
+  // raw prefetch of the next K-tile (clamped addresses); split at the LDS store
+  cpx<float> ra[NE], rb[NE];
+  double rw[NE];
+  auto gload = [&](int p0) {
 #pragma unroll
-    for (int e = 0; e < (BK * TM) / 256; ++e) {
+    for (int e = 0; e < NE; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx / TM, ii = idx % TM;
-      const int p = p0 + kk;
-      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
-      if (p < P) {
-        if (i0 + ii < neps) {
-          cpx<float> v = M[(size_t)p * neps + i0 + ii];
-          ar = v.x; ai = v.y;
-        }
-        if (j0 + ii < neps) {
-          cpx<float> v = M[(size_t)p * neps + j0 + ii];
-          const float wf = (float)w[p];
-          br = v.x * wf; bi = v.y * wf;
-        }
-      }
+      const int p = min(p0 + kk, P - 1);
+      ra[e] = M[(size_t)p * neps + min(i0 + ii, neps - 1)];
+      rb[e] = M[(size_t)p * neps + min(j0 + ii, neps - 1)];
+      rw[e] = w[p];
+    }
+  };
+  gload(0);
+  for (int p0 = 0; p0 < P; p0 += BK) {
+    // stage: BK pairs x TM columns of A (=M) and B (=w*M), split into hi/lo
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx / TM, ii = idx % TM;
+      const bool pk = p0 + kk < P;
+      const float ma = (pk && i0 + ii < neps) ? 1.f : 0.f;
+      const float wf = (pk && j0 + ii < neps) ? (float)rw[e] : 0.f;
+      const float ar = ma * ra[e].x, ai = ma * ra[e].y;
+      const float br = wf * rb[e].x, bi = wf * rb[e].y;
       unsigned short h;
       h = bf16_rn_bits(ar); As[0][ii][kk] = h; As[1][ii][kk] = bf16_rn_bits(ar - bf16_to_f(h));
       h = bf16_rn_bits(ai); As[2][ii][kk] = h; As[3][ii][kk] = bf16_rn_bits(ai - bf16_to_f(h));
@@ -326,6 +372,7 @@ __global__ void __launch_bounds__(256) k_chi0_bf16x3(const cpx<float>* __restric
       h = bf16_rn_bits(bi); Bs[2][ii][kk] = h; Bs[3][ii][kk] = bf16_rn_bits(bi - bf16_to_f(h));
     }
     __syncthreads();
+    if (p0 + BK < P) gload(p0 + BK);
     bf8 a[2][4], b[2][4];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -334,46 +381,38 @@ __global__ void __launch_bounds__(256) k_chi0_bf16x3(const cpx<float>* __restric
         a[x][q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + x * 16 + l16][lk * 8]);
         b[x][q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + x * 16 + l16][lk * 8]);
       }
+    // the fragments are in registers: the tile may be restaged after this point
+    __syncthreads();
+    // -ai as the A operand of the ai*br terms (sign bit of every bf16 lane)
+    bf8 na[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        // Re: ar*br + ai*bi ; Im: ar*bi - ai*br ; each as hi*hi + hi*lo + lo*hi
-        f4 r = cr[x][y], im = ci[x][y];
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][0], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][1], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][1], b[y][0], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][2], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][3], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][3], b[y][2], r, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][2], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][0], b[y][3], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][1], b[y][2], im, 0, 0, 0);
-        cr[x][y] = r;
-        ci[x][y] = im;
-      }
-    // the -ai*br term: negate by accumulating into a separate register set would
-    // cost registers; subtract through a negated copy of the A operands instead.
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int q = 2; q < 4; ++q) {
-        // flip the sign bit of every bf16 lane
+      for (int q = 0; q < 2; ++q) {
         typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-        us8 t = __builtin_bit_cast(us8, a[x][q]);
+        us8 t = __builtin_bit_cast(us8, a[x][2 + q]);
         t ^= (us8)(0x8000);
-        a[x][q] = __builtin_bit_cast(bf8, t);
+        na[x][q] = __builtin_bit_cast(bf8, t);
       }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        f4 im = ci[x][y];
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][0], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][2], b[y][1], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x][3], b[y][0], im, 0, 0, 0);
-        ci[x][y] = im;
-      }
+    // Re += ar*br + ai*bi, Im += ar*bi - ai*br, each real product as
+    // hi*hi + hi*lo + lo*hi; terms outermost so consecutive MFMAs go to
+    // different accumulators
+#define GW_MF(ACC, A, B)                                                              \
+  _Pragma("unroll") for (int x = 0; x < 2; ++x) _Pragma("unroll") for (int y = 0; y < 2; ++y) \
+      ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, ACC[x][y], 0, 0, 0);
+    GW_MF(cr, a[x][0], b[y][0])
+    GW_MF(ci, a[x][0], b[y][2])
+    GW_MF(cr, a[x][0], b[y][1])
+    GW_MF(ci, a[x][0], b[y][3])
+    GW_MF(cr, a[x][1], b[y][0])
+    GW_MF(ci, a[x][1], b[y][2])
+    GW_MF(cr, a[x][2], b[y][2])
+    GW_MF(ci, na[x][0], b[y][0])
+    GW_MF(cr, a[x][2], b[y][3])
+    GW_MF(ci, na[x][0], b[y][1])
+    GW_MF(cr, a[x][3], b[y][2])
+    GW_MF(ci, na[x][1], b[y][0])
+#undef GW_MF
     since_flush += BK;
     if (since_flush >= KFLUSH || p0 + BK >= P) {
 #pragma unroll

@@ -8,8 +8,8 @@
 // elimination without pivoting (stable for a positive-definite matrix), whose
 // work is one rank-nb GEMM update of the whole matrix per block, and then
 // eps^-1 = S epst^-1 S^-1.  Each diagonal pivot is checked to be real and
-// positive; if any is not (or some v <= 0), the result is discarded and the
-// general path below runs instead.
+// positive (>= 1/2, since epst >= I); if any is not (or some v <= 0), the result
+// is discarded and the general path below runs instead.
 //
 // General path: right-looking blocked LU with partial pivoting (PA = LU), every
 // frequency in the same launches (grid.z / grid.y = frequency):
@@ -245,7 +245,10 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
   for (int t = 0; t < nbk; ++t) {
     if (tid == 0) {
       const cpx<double> p = D[t][t];
-      const bool ok = p.x > 0.0 && fabs(p.y) <= 1e-8 * p.x && p.x < INFINITY;
+      // chi0 <= 0 makes epst >= I, so every pivot of the elimination is real and
+      // >= 1 up to rounding; a pivot below 1/2 or far from the real axis means
+      // the input is not of that form and the pivoted path must be used
+      const bool ok = p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY;
       if (!ok) flag[1] = 1;
       const double den = p.x * p.x + p.y * p.y;
       piv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
