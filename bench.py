@@ -71,6 +71,26 @@ def kernel_bytes(name, d, elem, launches):
     return None
 
 
+def measured_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio a plain copy
+    of known size reads back), or None when no record exists for this workload or
+    the kernel's source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{config.lower()}_fp64.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + \
+        rec["write_kib_per_dispatch"] * rec["write_scale"]
+    return kib * 1024.0
+
+
 def chi0_flops(d):
     return 4.0 * d["neps"] ** 2 * d["nv"] * d["nc"] * len(d["omega"])
 
@@ -212,6 +232,7 @@ def main():
             roof = {"kernel": dname, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                     "launches_per_step": dl, "avg_launch_ms": dms / dl}
+    roof["traffic"] = measured_traffic(dname, args.config)
     result["roofline"] = roof
     bb, pb = fft_stage_bytes(d64, 16)
     fft_ms = sum(kt64.get(k, (0, 0))[1] for k in ("band_xpass", "band_plane", "pair_plane",
