@@ -216,3 +216,72 @@ def gw_epsinv(ctx, neps, nfreq, chi0, vcoul, epsinv):
 def raw():
     """The loaded ctypes library (for tests of the exported symbol table)."""
     return _lib
+
+
+class Plan:
+    """gw_plan_* wrapper: one captured graph over many q-points.
+
+    `qs` is a list of dicts holding, per q: host int arrays gv, gc, geps; device
+    tensors cv, cc, ev, ec, vcoul, chi0 (out), epsinv (out); and head_index.
+    The tensors must stay alive (and at the same addresses) for the plan's life.
+    """
+
+    def __init__(self, ctx, box, nspinor, dtype, prec, omega, prefactor, qs):
+        ctx.sync_stream()
+        self.ctx = ctx
+        self._keep = qs
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        self._om = om
+        arr = (QDesc * len(qs))()
+        self._host = []
+        for i, q in enumerate(qs):
+            gv, gc, geps = _host_i32(q["gv"]), _host_i32(q["gc"]), _host_i32(q["geps"])
+            self._host.append((gv, gc, geps))
+            d = arr[i]
+            d.nv, d.ngv, d.gv, d.cv = q["cv"].shape[0], gv.shape[0], gv.ctypes.data, _ptr(q["cv"])
+            d.nc, d.ngc, d.gc, d.cc = q["nc"], gc.shape[0], gc.ctypes.data, _ptr(q["cc"])
+            d.neps, d.geps = geps.shape[0], geps.ctypes.data
+            d.ev, d.ec, d.vcoul = _ptr(q["ev"]), _ptr(q["ec"]), _ptr(q["vcoul"])
+            d.head_index = int(q.get("head_index", -1))
+            d.chi0, d.epsinv = _ptr(q["chi0"]), _ptr(q["epsinv"])
+        h = _vp()
+        box_a = (ct.c_int * 3)(*[int(x) for x in box])
+        s = _lib.gw_plan_create(ctx.handle, ct.byref(h), ct.cast(box_a, _ip), int(nspinor),
+                                int(dtype), int(prec), len(om), om.ctypes.data, float(prefactor),
+                                len(qs), arr)
+        _check(ctx, s)
+        self.handle = h
+
+    def compile(self):
+        self.ctx.sync_stream()
+        return _check(self.ctx, _lib.gw_plan_compile(self.handle))
+
+    def launch(self):
+        self.ctx.sync_stream()
+        return _check(self.ctx, _lib.gw_plan_launch(self.handle))
+
+    def describe(self):
+        return _lib.gw_plan_describe(self.handle).decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gw_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gw_plan_create(ctx, box, nspinor, dtype, prec, omega, prefactor, qs):
+    return Plan(ctx, box, nspinor, dtype, prec, omega, prefactor, qs)
+
+
+def gw_plan_compile(plan):
+    return plan.compile()
+
+
+def gw_plan_launch(plan):
+    return plan.launch()

@@ -80,6 +80,7 @@ struct gw_ctx {
   std::map<std::string, gw::SphereMap> spheres;
   std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
   int* d_flag = nullptr;                          // device status flags
+  bool capturing = false;                         // inside a graph capture: no attribute calls
   // profiling
   bool profiling = false;
   std::vector<gw::ProfRec> prof_pending;

@@ -451,8 +451,10 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
   const size_t lds_p = (size_t)n2 * P * sizeof(cpx<T>);
   auto kx = pick_band_x<T>(n1);
   auto kp = pick_band_plane<T>(n2, n3);
-  GW_HIP(c, allow_lds(kx, lds_x));
-  GW_HIP(c, allow_lds(kp, lds_p));
+  if (!c->capturing) {
+    GW_HIP(c, allow_lds(kx, lds_x));
+    GW_HIP(c, allow_lds(kp, lds_p));
+  }
   const cpx<T>* cf = static_cast<const cpx<T>*>(coef);
   cpx<T>* u = static_cast<cpx<T>*>(u_out);
   cpx<T>* t1 = static_cast<cpx<T>*>(scratch);
@@ -500,8 +502,10 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
   cpx<T>* t2 = static_cast<cpx<T>*>(scratch);
   auto kp = nspinor == 2 ? pick_pair_plane<T, 2>(n2, n3) : pick_pair_plane<T, 1>(n2, n3);
   auto kx = pick_pair_x<T>(n1);
-  GW_HIP(c, allow_lds(kp, lds_p));
-  GW_HIP(c, allow_lds(kx, lds_x));
+  if (!c->capturing) {
+    GW_HIP(c, allow_lds(kp, lds_p));
+    GW_HIP(c, allow_lds(kx, lds_x));
+  }
   {
     ProfScope ps(c, "pair_plane");
     const long long tot = (long long)n1 * npairs;

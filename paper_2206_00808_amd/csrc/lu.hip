@@ -325,8 +325,8 @@ __global__ void k_unscale(cpx<double>* __restrict__ A, const double* __restrict_
   *a = scal(*a, s);
 }
 
-static gw_status epsinv_pivoted(gw_ctx* c, int N, int nfreq, const double* chi0,
-                                const double* vcoul, double* epsinv) {
+gw_status epsinv_pivoted_one(gw_ctx* c, int N, int nfreq, const double* chi0,
+                             const double* vcoul, double* epsinv) {
   const size_t nn = (size_t)N * N;
   const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up((size_t)nfreq * N * 4);
   gw_status st = ws_begin(c, bytes);
@@ -503,7 +503,7 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
   GW_HIP(c, hipStreamSynchronize(c->stream));
   if (!flags[1]) return GW_OK;
   // not positive definite (or v <= 0): general LU with partial pivoting
-  return epsinv_pivoted(c, N, nfreq, chi0, vcoul, epsinv);
+  return epsinv_pivoted_one(c, N, nfreq, chi0, vcoul, epsinv);
 }
 
 }  // namespace gw

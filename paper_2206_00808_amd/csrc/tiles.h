@@ -1,0 +1,362 @@
+// Device-side tile bodies shared by the single-call and the batched (many-q)
+// kernels: the chi0 band-pair contraction in FP64 and in split-BF16, and a
+// plain complex-double GEMM tile.  Included by gemm.hip, lu.hip and plan.hip.
+#pragma once
+
+#include "common.h"
+
+namespace gw {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int KT = 16;       // K step (pairs) of the FP64 tiles
+constexpr int BK = 32;       // K step (pairs) of the split-BF16 tile = one 16x16x32 MFMA
+constexpr int BKP = BK + 8;  // LDS pitch in bf16 (16-byte aligned rows)
+constexpr int KFLUSH = 512;  // pairs accumulated in float before the double flush
+
+// upper-triangle tile index -> (ti, tj), ti <= tj, row-major over the triangle
+__device__ __forceinline__ void tri_tile(int idx, int nt, int* ti, int* tj) {
+  int r = 0, start = 0;
+  while (start + (nt - r) <= idx) { start += nt - r; ++r; }
+  *ti = r;
+  *tj = r + (idx - start);
+}
+
+// bf16 round-to-nearest-even from the IEEE-754 binary32 bit pattern (finite inputs).
+__device__ __forceinline__ unsigned short bf16_rn_bits(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+// Add a finished tile to C (Hermitian update): (i,j) gets the value, and for an
+// off-diagonal tile (j,i) gets its conjugate.  Row/column skip_head is left out.
+__device__ __forceinline__ void herm_add(cpx<double>* C, int neps, int i, int j, double re,
+                                         double im, bool offdiag, int skip_head) {
+  if (i >= neps || j >= neps) return;
+  if (skip_head >= 0 && (i == skip_head || j == skip_head)) return;
+  cpx<double>* d = C + (size_t)i * neps + j;
+  *d = mk(d->x + re, d->y + im);
+  if (offdiag) {
+    cpx<double>* m = C + (size_t)j * neps + i;
+    *m = mk(m->x + re, m->y - im);
+  }
+}
+
+// ------------------------------------------------------------------ FP64 chi0 tile
+// C[i][j] += sum_p conj(M[p][i]) w[p] M[p][j] for the (TM x TM) tile (ti, tj),
+// TM = 32*WM, WM x WM waves of 32x32 (2x2 blocks of v_mfma_f64_16x16x4_f64).
+// Planar re/im LDS tiles padded so each quarter-wave row group lands on its own
+// half of the banks; the next K-tile is fetched into registers (clamped
+// addresses, masked at the store) while the matrix cores work on this one.
+template <int WM, typename Tin>
+__device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, int P, int neps,
+                                              const double* __restrict__ w,
+                                              cpx<double>* __restrict__ C, int ti, int tj,
+                                              int skip_head) {
+  constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (KT * TMv) / NT, PTv = TMv + 16;
+  __shared__ double Ar[KT][PTv], Ai[KT][PTv], Br[KT][PTv], Bi[KT][PTv];
+  const int i0 = ti * TMv, j0 = tj * TMv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WM, wc = wave % WM;
+  const int l16 = lane & 15, lk = lane >> 4;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (d4){0, 0, 0, 0};
+      ci[a][b] = (d4){0, 0, 0, 0};
+    }
+  cpx<Tin> ra[NE], rb[NE];
+  double rw[NE];
+  auto gload = [&](int p0) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * NT;
+      const int kk = idx / TMv, ii = idx % TMv;
+      const int p = min(p0 + kk, P - 1);
+      ra[e] = M[(size_t)p * neps + min(i0 + ii, neps - 1)];
+      rb[e] = M[(size_t)p * neps + min(j0 + ii, neps - 1)];
+      rw[e] = w[p];
+    }
+  };
+  gload(0);
+  for (int p0 = 0; p0 < P; p0 += KT) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * NT;
+      const int kk = idx / TMv, ii = idx % TMv;
+      const bool pk = p0 + kk < P;
+      const double ma = (pk && i0 + ii < neps) ? 1.0 : 0.0;
+      const double mb = (pk && j0 + ii < neps) ? rw[e] : 0.0;
+      Ar[kk][ii] = ma * (double)ra[e].x; Ai[kk][ii] = ma * (double)ra[e].y;
+      Br[kk][ii] = mb * (double)rb[e].x; Bi[kk][ii] = mb * (double)rb[e].y;
+    }
+    __syncthreads();
+    if (p0 + KT < P) gload(p0 + KT);
+#pragma unroll
+    for (int s = 0; s < KT / 4; ++s) {
+      const int kk = s * 4 + lk;
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Ar[kk][wr * 32 + a * 16 + l16];
+        ai[a] = Ai[kk][wr * 32 + a * 16 + l16];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Br[kk][wc * 32 + b * 16 + l16];
+        bi[b] = Bi[kk][wc * 32 + b * 16 + l16];
+      }
+      // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br); the four products are
+      // issued round-robin over the eight accumulators so that no MFMA waits on
+      // the one just issued
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], br[b], ci[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)  // f64 16x16x4 D layout: row lk + 4r, column l16
+        herm_add(C, neps, i0 + wr * 32 + a * 16 + lk + 4 * r, j0 + wc * 32 + b * 16 + l16,
+                 cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
+}
+
+// ------------------------------------------------------------------ split-BF16 chi0 tile
+// Each float x = hi + lo, hi = bf16_rn(x), lo = bf16_rn(x - hi); every real
+// product is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with float
+// accumulation flushed into double registers every KFLUSH pairs.
+template <int WM>
+__device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M, int P, int neps,
+                                               const double* __restrict__ w,
+                                               cpx<double>* __restrict__ C, int ti, int tj,
+                                               int skip_head) {
+  constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (BK * TMv) / NT;
+  __shared__ __align__(16) unsigned short As[4][TMv][BKP];
+  __shared__ __align__(16) unsigned short Bs[4][TMv][BKP];
+  const int i0 = ti * TMv, j0 = tj * TMv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WM, wc = wave % WM;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double dr[2][2][4], di[2][2][4];
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
+    }
+  int since_flush = 0;
+  cpx<float> ra[NE], rb[NE];
+  double rw[NE];
+  auto gload = [&](int p0) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * NT;
+      const int kk = idx / TMv, ii = idx % TMv;
+      const int p = min(p0 + kk, P - 1);
+      ra[e] = M[(size_t)p * neps + min(i0 + ii, neps - 1)];
+      rb[e] = M[(size_t)p * neps + min(j0 + ii, neps - 1)];
+      rw[e] = w[p];
+    }
+  };
+  gload(0);
+  for (int p0 = 0; p0 < P; p0 += BK) {
+    // stage: BK pairs x TM columns of A (=M) and B (=w*M), split into hi/lo
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * NT;
+      const int kk = idx / TMv, ii = idx % TMv;
+      const bool pk = p0 + kk < P;
+      const float ma = (pk && i0 + ii < neps) ? 1.f : 0.f;
+      const float wf = (pk && j0 + ii < neps) ? (float)rw[e] : 0.f;
+      const float ar = ma * ra[e].x, ai = ma * ra[e].y;
+      const float br = wf * rb[e].x, bi = wf * rb[e].y;
+      unsigned short h;
+      h = bf16_rn_bits(ar); As[0][ii][kk] = h; As[1][ii][kk] = bf16_rn_bits(ar - bf16_to_f(h));
+      h = bf16_rn_bits(ai); As[2][ii][kk] = h; As[3][ii][kk] = bf16_rn_bits(ai - bf16_to_f(h));
+      h = bf16_rn_bits(br); Bs[0][ii][kk] = h; Bs[1][ii][kk] = bf16_rn_bits(br - bf16_to_f(h));
+      h = bf16_rn_bits(bi); Bs[2][ii][kk] = h; Bs[3][ii][kk] = bf16_rn_bits(bi - bf16_to_f(h));
+    }
+    __syncthreads();
+    if (p0 + BK < P) gload(p0 + BK);
+    bf8 a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[x][q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + x * 16 + l16][lk * 8]);
+        b[x][q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + x * 16 + l16][lk * 8]);
+      }
+    // the fragments are in registers: the tile may be restaged after this point
+    __syncthreads();
+    // -ai as the A operand of the ai*br terms (sign bit of every bf16 lane)
+    bf8 na[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 t = __builtin_bit_cast(us8, a[x][2 + q]);
+        t ^= (us8)(0x8000);
+        na[x][q] = __builtin_bit_cast(bf8, t);
+      }
+    // Re += ar*br + ai*bi, Im += ar*bi - ai*br, each real product as
+    // hi*hi + hi*lo + lo*hi; terms outermost so consecutive MFMAs go to
+    // different accumulators
+#define GW_MF(ACC, A, B)                                                      \
+  _Pragma("unroll") for (int x = 0; x < 2; ++x) _Pragma("unroll") for (int y = 0; y < 2; ++y) \
+      ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, ACC[x][y], 0, 0, 0);
+    GW_MF(cr, a[x][0], b[y][0])
+    GW_MF(ci, a[x][0], b[y][2])
+    GW_MF(cr, a[x][0], b[y][1])
+    GW_MF(ci, a[x][0], b[y][3])
+    GW_MF(cr, a[x][1], b[y][0])
+    GW_MF(ci, a[x][1], b[y][2])
+    GW_MF(cr, a[x][2], b[y][2])
+    GW_MF(ci, na[x][0], b[y][0])
+    GW_MF(cr, a[x][2], b[y][3])
+    GW_MF(ci, na[x][0], b[y][1])
+    GW_MF(cr, a[x][3], b[y][2])
+    GW_MF(ci, na[x][1], b[y][0])
+#undef GW_MF
+    since_flush += BK;
+    if (since_flush >= KFLUSH || p0 + BK >= P) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dr[x][y][r] += (double)cr[x][y][r];
+            di[x][y][r] += (double)ci[x][y][r];
+          }
+          cr[x][y] = (f4){0, 0, 0, 0};
+          ci[x][y] = (f4){0, 0, 0, 0};
+        }
+      since_flush = 0;
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)  // f32 16x16x32 D layout: row 4*lk + r, column l16
+        herm_add(C, neps, i0 + wr * 32 + x * 16 + lk * 4 + r, j0 + wc * 32 + y * 16 + l16,
+                 dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+}
+
+// ------------------------------------------------------------------ complex-double GEMM tile
+// C[i][j] += alpha * sum_k A[i][k] B[k][j] on the 64x64 tile at (i0, j0), 256 threads.
+constexpr int ZTM = 64, ZLP = ZTM + 1;
+__device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
+                                           const cpx<double>* __restrict__ A, int lda,
+                                           const cpx<double>* __restrict__ B, int ldb,
+                                           cpx<double>* __restrict__ C, int ldc, int i0, int j0) {
+  __shared__ cpx<double> As[KT][ZLP];
+  __shared__ cpx<double> Bs[KT][ZLP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (d4){0, 0, 0, 0};
+      ci[a][b] = (d4){0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < kdim; k0 += KT) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < (KT * ZTM) / 256; ++e) {
+      const int idx = tid + e * 256;
+      // A tile: ZTM rows x KT columns, k fastest for coalescing
+      const int ai = idx / KT, ak = idx % KT;
+      cpx<double> a = mk<double>(0, 0);
+      if (i0 + ai < m && k0 + ak < kdim) a = A[(size_t)(i0 + ai) * lda + k0 + ak];
+      As[ak][ai] = a;
+      const int bk = idx / ZTM, bj = idx % ZTM;
+      cpx<double> b = mk<double>(0, 0);
+      if (k0 + bk < kdim && j0 + bj < n) b = B[(size_t)(k0 + bk) * ldb + j0 + bj];
+      Bs[bk][bj] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KT / 4; ++s) {
+      const int kk = s * 4 + lk;
+      cpx<double> av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc * 32 + b * 16 + l16];
+      // a * b = (ar br - ai bi) + i (ar bi + ai br)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;  // f64 16x16x4 D layout
+        const int j = j0 + wc * 32 + b * 16 + l16;
+        if (i >= m || j >= n) continue;
+        cpx<double>* d = C + (size_t)i * ldc + j;
+        *d = mk(d->x + alpha * cr[a][b][r], d->y + alpha * ci[a][b][r]);
+      }
+}
+
+}  // namespace gw

@@ -64,3 +64,33 @@ def run_path(ctx, d, out, prec=B.GW_PREC_FP64, prefactor=1.0, stages=("mtxel", "
     if "epsinv" in stages:
         B.gw_epsinv(ctx, d["neps"], len(d["omega"]), out["chi0"], d["vcoul"], out["epsinv"])
     return out
+
+
+def upload_batch(systems, dtype="c64", device="cuda:0"):
+    """Device copies for a list of per-q systems (synth.batch_systems); the
+    conduction coefficients shared by every q are uploaded once."""
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    shared = {}
+    qs = []
+    for s in systems:
+        key = id(s["cc"])
+        if key not in shared:
+            shared[key] = torch.from_numpy(np.ascontiguousarray(s["cc"])).to(device=device, dtype=cdt)
+        cc = shared[key]
+        nc = int(s.get("nc", s["cc"].shape[0]))
+        neps = s["geps"].shape[0]
+        nf = len(s["omega"])
+        qs.append(dict(
+            gv=np.ascontiguousarray(s["gv"], dtype=np.int32),
+            gc=np.ascontiguousarray(s["gc"], dtype=np.int32),
+            geps=np.ascontiguousarray(s["geps"], dtype=np.int32),
+            cv=torch.from_numpy(np.ascontiguousarray(s["cv"])).to(device=device, dtype=cdt),
+            cc=cc, nc=nc,
+            ev=torch.from_numpy(np.ascontiguousarray(s["ev"])).to(device),
+            ec=torch.from_numpy(np.ascontiguousarray(s["ec"][:nc])).to(device),
+            vcoul=torch.from_numpy(np.ascontiguousarray(s["vcoul"])).to(device),
+            head_index=int(s.get("head_index", -1)),
+            chi0=torch.zeros((nf, neps, neps), dtype=torch.complex128, device=device),
+            epsinv=torch.zeros((nf, neps, neps), dtype=torch.complex128, device=device),
+        ))
+    return qs
