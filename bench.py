@@ -163,8 +163,64 @@ def cpu_baseline(sysd, seconds):
     }
 
 
+def bench_batch(args):
+    """The many-q workload: 64 q-points of a 4x4x4 grid (Gamma replaced by a small
+    q0 with FP64 head/wings), per-q eps spheres of 600-2400 G and N_c of 400-1600,
+    N_v = 16, box 48^3; complex64 matrix elements, split-BF16 contraction, FP64
+    eps^-1; all q in one captured graph."""
+    import torch
+
+    import synth
+    import paper_2206_00808_amd as P
+    from paper_2206_00808_amd import pipeline
+    from paper_2206_00808_amd.binding import Plan
+
+    systems = synth.batch_systems()
+    ctx = P.Context(0)
+    qs = pipeline.upload_batch(systems, dtype="c64")
+    plan = Plan(ctx, systems[0]["box"], 2, P.GW_C64, P.GW_PREC_SPLITBF16, systems[0]["omega"],
+                1.0, qs)
+    t0 = time.perf_counter()
+    plan.compile()
+    compile_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    pairs = sum(int(s["cv"].shape[0]) * int(s["nc"]) for s in systems)
+    flops = sum(4.0 * s["geps"].shape[0] ** 2 * s["cv"].shape[0] * s["nc"] * len(s["omega"])
+                for s in systems)
+    result = {
+        "metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "(v,c) pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 transforms, split-bf16x3 contraction, f64 eps^-1", "data": "synthetic",
+        "config": {"workload": "C4: 64 q-points (4x4x4 grid, Gamma -> q0), N_eps 600-2400, "
+                               "N_c 400-1600, N_v 16, box 48^3, one captured graph",
+                   "global_batch": len(systems), "pairs": pairs, "parallelism": "single GPU"},
+        "chi0_tflops_whole_step": flops / (ms * 1e-3) / 1e12,
+        "compile_s": compile_s, "autotune": plan.describe(),
+    }
+    plan.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.config == "C4":
+        if args.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        bench_batch(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not built)"}))

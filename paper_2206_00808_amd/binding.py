@@ -285,3 +285,80 @@ def gw_plan_compile(plan):
 
 def gw_plan_launch(plan):
     return plan.launch()
+
+
+class Mlp:
+    """gw_mlp_* wrapper (the closure network)."""
+
+    def __init__(self, ctx, nin=7, width=256, depth=3, nout=2, seed=0):
+        self.ctx = ctx
+        h = _vp()
+        _check(ctx, _lib.gw_mlp_create(ctx.handle, ct.byref(h), int(nin), int(width), int(depth),
+                                       int(nout), ct.c_uint64(seed)))
+        self.handle = h
+        self.shape = (nin, width, depth, nout)
+
+    def save(self):
+        n = ct.c_size_t(0)
+        _check(self.ctx, _lib.gw_mlp_save(self.handle, None, ct.byref(n)))
+        buf = ct.create_string_buffer(n.value)
+        _check(self.ctx, _lib.gw_mlp_save(self.handle, buf, ct.byref(n)))
+        return bytes(buf.raw[:n.value])
+
+    def load(self, blob):
+        buf = ct.create_string_buffer(blob, len(blob))
+        _check(self.ctx, _lib.gw_mlp_load(self.handle, buf, len(blob)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gw_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gw_chi0_closure(ctx, net, mode, neps, qg, chi0_trunc, gap, emax, chi0_full=None, lr=0.0,
+                    chi0_out=None):
+    """Returns (status, loss): status GW_OK or GW_EFALLBACK; loss for TRAIN_STEP."""
+    ctx.sync_stream()
+    loss = ct.c_float(float("nan"))
+    s = _lib.gw_chi0_closure(ctx.handle, net.handle if net is not None else None, int(mode),
+                             int(neps), _ptr(qg), _ptr(chi0_trunc), float(gap), float(emax),
+                             _ptr(chi0_full), ct.c_float(lr), ct.byref(loss), _ptr(chi0_out))
+    _check(ctx, s, ok=(GW_OK, GW_EFALLBACK))
+    return s, loss.value
+
+
+# serialised network layout (gw_mlp_save): header then float arrays
+MLP_HEADER_BYTES = 48
+
+
+def mlp_blob_unpack(blob):
+    hdr = np.frombuffer(blob, dtype=np.uint32, count=2)
+    dims = np.frombuffer(blob, dtype=np.int32, count=6, offset=8)
+    step, count = np.frombuffer(blob, dtype=np.int64, count=2, offset=32)
+    arr = np.frombuffer(blob, dtype=np.float32, offset=MLP_HEADER_BYTES).reshape(3, count)
+    return dict(magic=int(hdr[0]), nin=int(dims[0]), width=int(dims[1]), depth=int(dims[2]),
+                nout=int(dims[3]), kpad=int(dims[4]), opad=int(dims[5]), step=int(step),
+                params=arr[0].copy(), m=arr[1].copy(), v=arr[2].copy())
+
+
+def mlp_blob_pack(meta, params, m=None, v=None):
+    count = params.size
+    m = np.zeros(count, np.float32) if m is None else m
+    v = np.zeros(count, np.float32) if v is None else v
+    head = np.array([meta["magic"], 1], dtype=np.uint32).tobytes()
+    head += np.array([meta["nin"], meta["width"], meta["depth"], meta["nout"], meta["kpad"],
+                      meta["opad"]], dtype=np.int32).tobytes()
+    head += np.array([meta["step"], count], dtype=np.int64).tobytes()
+    return head + np.concatenate([params, m, v]).astype(np.float32).tobytes()
+
+
+def mlp_layers(meta):
+    """(din, dout) of each padded linear layer, in the order stored."""
+    dims = [meta["kpad"]] + [meta["width"]] * meta["depth"] + [meta["opad"]]
+    return list(zip(dims[:-1], dims[1:]))

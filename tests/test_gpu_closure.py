@@ -1,0 +1,167 @@
+"""GPU checks of the learned closure: forward pass and gradients against the
+FP64 oracle (same weights, loaded into the network), the Cholesky fallback, and
+the gain of a trained network over the truncated sum on held-out systems."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2206_00808_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+def small_systems(indices):
+    # smaller cousins of the closure workload: box 24^3, N_v 8, N_c 600, N_eps 60-150
+    return synth.closure_systems(indices, seed0=9100, box=(24, 24, 24), ecut_wfn=8.0, nv=8,
+                                 nc_full=600, neps_range=(60, 150))
+
+
+@pytest.fixture(scope="module")
+def data(P, ctx):
+    from paper_2206_00808_amd.closure import closure_dataset
+    systems = small_systems(range(20))
+    return systems, closure_dataset(ctx, systems, nc_trunc=60)
+
+
+def gpu_layout_params(rng, meta):
+    """Glorot weights in the oracle's real shapes, and the same values laid out
+    (zero-padded) the way the network stores them."""
+    from paper_2206_00808_amd.binding import mlp_layers
+    real = [7] + [meta["width"]] * meta["depth"] + [2]
+    params = oracle.init_params(rng, real)
+    params = [(w, rng.normal(size=b.shape) * 0.05) for w, b in params]
+    flat = []
+    for (w, b), (din, dout) in zip(params, mlp_layers(meta)):
+        W = np.zeros((dout, din))
+        W[:w.shape[0], :w.shape[1]] = w
+        bb = np.zeros(dout)
+        bb[:b.shape[0]] = b
+        flat += [W.ravel(), bb]
+    return params, np.concatenate(flat).astype(np.float32)
+
+
+def oracle_params_from_flat(flat, meta):
+    from paper_2206_00808_amd.binding import mlp_layers
+    real = [7] + [meta["width"]] * meta["depth"] + [2]
+    out, off = [], 0
+    for l, (din, dout) in enumerate(mlp_layers(meta)):
+        W = flat[off:off + din * dout].reshape(dout, din).astype(np.float64)
+        off += din * dout
+        b = flat[off:off + dout].astype(np.float64)
+        off += dout
+        out.append((W[:real[l + 1], :real[l]], b[:real[l + 1]]))
+    return out
+
+
+def _net_with(P, ctx, params_flat, width=128, depth=3):
+    from paper_2206_00808_amd.binding import Mlp, mlp_blob_pack, mlp_blob_unpack
+    net = Mlp(ctx, 7, width, depth, 2, seed=1)
+    meta = mlp_blob_unpack(net.save())
+    net.load(mlp_blob_pack(meta, params_flat))
+    return net, meta
+
+
+def test_forward_matches_oracle(P, ctx, data):
+    from paper_2206_00808_amd.binding import Mlp, mlp_blob_unpack
+    systems, items = data
+    it = items[0]
+    meta = mlp_blob_unpack(Mlp(ctx, 7, 128, 3, 2, seed=1).save())
+    params, flat = gpu_layout_params(np.random.default_rng(4), meta)
+    net, _ = _net_with(P, ctx, flat)
+    out = torch.empty_like(it["chi_f"])
+    P.binding.gw_chi0_closure(ctx, net, P.GW_CLOSURE_INFER, it["neps"], it["qg"], it["chi_t"],
+                              it["gap"], it["emax"], chi0_out=out)
+    chi_t = it["chi_t"].cpu().numpy()
+    f, _, s = oracle.closure_features(it["qg"].cpu().numpy(), chi_t, it["gap"], it["emax"])
+    y, _ = oracle.mlp_forward(params, f)
+    ref = oracle.closure_apply(chi_t, y, s) - chi_t
+    got = out.cpu().numpy() - chi_t
+    # bf16 operands (8-bit mantissa) through four layers
+    assert oracle.rel_f(got, ref) < 3e-2
+
+
+def test_gradients_and_loss_match_oracle(P, ctx, data):
+    from paper_2206_00808_amd.binding import Mlp, mlp_blob_unpack
+    systems, items = data
+    it = items[1]
+    meta = mlp_blob_unpack(Mlp(ctx, 7, 128, 3, 2, seed=1).save())
+    params, flat = gpu_layout_params(np.random.default_rng(5), meta)
+    net, _ = _net_with(P, ctx, flat)
+    _, loss = P.binding.gw_chi0_closure(ctx, net, P.GW_CLOSURE_TRAIN_STEP, it["neps"], it["qg"],
+                                        it["chi_t"], it["gap"], it["emax"],
+                                        chi0_full=it["chi_f"], lr=0.0)
+    st = P.binding.mlp_blob_unpack(net.save())
+    # Adam's first moment after one step from zero is (1 - beta1) g
+    g = oracle_params_from_flat(st["m"] / 0.1, meta)
+    chi_t = it["chi_t"].cpu().numpy()
+    f, _, s = oracle.closure_features(it["qg"].cpu().numpy(), chi_t, it["gap"], it["emax"])
+    t = oracle.closure_target(chi_t, it["chi_f"].cpu().numpy(), s)
+    ref_loss, ref_g = oracle.mlp_loss_and_grads(params, f, t, nout=2)
+    assert abs(loss - ref_loss) / ref_loss < 2e-2
+    for (gw, gb), (rw, rb) in zip(g, ref_g):
+        assert oracle.rel_f(gw, rw) < 5e-2
+        assert oracle.rel_f(gb, rb) < 5e-2
+
+
+def test_fallback_when_not_negative_semidefinite(P, ctx, data):
+    from paper_2206_00808_amd.binding import Mlp, mlp_blob_unpack, mlp_layers
+    systems, items = data
+    it = items[2]
+    meta = mlp_blob_unpack(Mlp(ctx, 7, 128, 3, 2, seed=1).save())
+    flat = np.zeros(sum(a * b + b for a, b in mlp_layers(meta)), np.float32)
+    # output bias of +50 on Re: adds 50 s to every entry, far from negative semidefinite
+    din, dout = mlp_layers(meta)[-1]
+    flat[-dout] = 50.0
+    net, _ = _net_with(P, ctx, flat)
+    out = torch.empty_like(it["chi_f"])
+    stt, _ = P.binding.gw_chi0_closure(ctx, net, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
+                                       it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
+                                       chi0_out=out)
+    assert stt == P.GW_EFALLBACK
+    assert torch.equal(out, it["chi_f"])
+    # a zero network keeps the truncated sum, which is negative definite: no fallback
+    net0, _ = _net_with(P, ctx, np.zeros_like(flat))
+    stt, _ = P.binding.gw_chi0_closure(ctx, net0, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
+                                       it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
+                                       chi0_out=out)
+    assert stt == P.GW_OK
+    assert torch.allclose(out, it["chi_t"], rtol=0, atol=1e-14)
+
+
+def test_untrained_network_refuses_inference(P, ctx, data):
+    from paper_2206_00808_amd.binding import Mlp
+    systems, items = data
+    it = items[0]
+    net = Mlp(ctx, 7, 128, 3, 2, seed=3)
+    out = torch.empty_like(it["chi_f"])
+    with pytest.raises(P.GwError) as ei:
+        P.binding.gw_chi0_closure(ctx, net, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
+                                  it["chi_t"], it["gap"], it["emax"], chi0_out=out)
+    assert ei.value.status == P.GW_ENOTTRAINED
+
+
+def test_training_gains_over_truncation(P, ctx, data):
+    from paper_2206_00808_amd.binding import Mlp
+    from paper_2206_00808_amd.closure import evaluate, train
+    systems, items = data
+    net = Mlp(ctx, 7, 128, 3, 2, seed=11)
+    losses = train(ctx, net, items[:16], epochs=40, lr=2e-3, lr_final=2e-4)
+    assert losses[-1] < 0.5 * losses[0]
+    rows = evaluate(ctx, net, items[16:])
+    trunc = np.mean([r["chi_trunc"] for r in rows])
+    corr = np.mean([r["chi_closure"] for r in rows if not r["fallback"]] or [0.0])
+    print("held-out chi0 rel error: truncated %.3f, closure %.3f" % (trunc, corr),
+          [(r["chi_trunc"], r["chi_closure"], r["fallback"]) for r in rows])
+    assert corr < 0.8 * trunc
