@@ -46,7 +46,7 @@ def closure_dataset(ctx, systems, nc_trunc, device="cuda:0"):
     return items
 
 
-def train(ctx, net, items, epochs, lr=1e-3, lr_final=1e-4, seed=0):
+def train(ctx, net, items, epochs, lr=1e-3, lr_final=1e-4, seed=0, log=None):
     """One Adam step per system per epoch, systems in a seeded order; the
     learning rate decays geometrically from lr to lr_final."""
     rng = np.random.default_rng(seed)
@@ -64,6 +64,8 @@ def train(ctx, net, items, epochs, lr=1e-3, lr_final=1e-4, seed=0):
             ep.append(loss)
             k += 1
         losses.append(float(np.mean(ep)))
+        if log is not None:
+            log(len(losses), losses[-1])
     return losses
 
 

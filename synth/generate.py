@@ -271,6 +271,12 @@ def closure_systems(indices, seed0=5000, cell=(10.0, 10.4, 10.8), box=(32, 32, 3
         qv = qs[i % len(qs)]
         target = int(rng.integers(neps_range[0], neps_range[1] + 1))
         ecut_eps = cutoff_for_count(cl, qv, target)
-        cfg = SystemConfig(f"S{i}", seed0 + 100000 + i, cl, box, ecut_wfn, ecut_eps, nv, nc_full, qv)
+        # a shrunken cell holds fewer plane waves: raise the cutoff until both
+        # spheres carry enough spinor components for N_v + N_c orthonormal bands
+        ec_i = ecut_wfn
+        while min(len(g_sphere(cl, (0.0, 0.0, 0.0), ec_i)), len(g_sphere(cl, qv, ec_i))) * 2 < \
+                nv + nc_full + 16:
+            ec_i *= 1.05
+        cfg = SystemConfig(f"S{i}", seed0 + 100000 + i, cl, box, ec_i, ecut_eps, nv, nc_full, qv)
         out.append(build_system(cfg))
     return out
