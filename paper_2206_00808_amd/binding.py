@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import weakref
 
 import numpy as np
 
@@ -122,9 +123,13 @@ class Context:
             raise GwError(s, "gw_ctx_create failed (no usable HIP device?)")
         self.handle = h
         self.device = device
+        self._children = weakref.WeakSet()
 
     def close(self):
         if getattr(self, "handle", None):
+            # the library frees networks and plans with their context
+            for ch in list(self._children):
+                ch.handle = None
             _lib.gw_ctx_destroy(self.handle)
             self.handle = None
 
@@ -251,6 +256,7 @@ class Plan:
                                 len(qs), arr)
         _check(ctx, s)
         self.handle = h
+        ctx._children.add(self)
 
     def compile(self):
         self.ctx.sync_stream()
@@ -264,9 +270,9 @@ class Plan:
         return _lib.gw_plan_describe(self.handle).decode()
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and getattr(self.ctx, "handle", None):
             _lib.gw_plan_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -297,6 +303,7 @@ class Mlp:
                                        int(nout), ct.c_uint64(seed)))
         self.handle = h
         self.shape = (nin, width, depth, nout)
+        ctx._children.add(self)
 
     def save(self):
         n = ct.c_size_t(0)
@@ -310,9 +317,9 @@ class Mlp:
         _check(self.ctx, _lib.gw_mlp_load(self.handle, buf, len(blob)))
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and getattr(self.ctx, "handle", None):
             _lib.gw_mlp_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

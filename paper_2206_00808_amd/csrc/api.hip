@@ -182,6 +182,9 @@ gw_status gw_ctx_destroy(gw_ctx* c) {
   if (!c) return GW_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  // children still alive are released with their context
+  for (gw_mlp* n : std::vector<gw_mlp*>(c->mlps.begin(), c->mlps.end())) mlp_free(n);
+  for (gw_plan* p : std::vector<gw_plan*>(c->plans.begin(), c->plans.end())) plan_free(p);
   for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& kv : c->spheres) (void)hipFree(kv.second.d_cube);

@@ -380,6 +380,12 @@ struct gw_mlp {
 
 namespace gw {
 
+void mlp_free(gw_mlp* n) {
+  if (n->p) (void)hipFree(n->p);
+  if (n->act) (void)hipFree(n->act);
+  delete n;
+}
+
 static uint64_t splitmix64(uint64_t& s) {
   uint64_t z = (s += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -616,6 +622,7 @@ gw_status gw_mlp_create(gw_ctx* c, gw_mlp** out, int nin, int width, int depth, 
     delete n;
     return hip_fail(c, e, "network init");
   }
+  c->mlps.insert(n);
   *out = n;
   return GW_OK;
 }
@@ -623,9 +630,8 @@ gw_status gw_mlp_create(gw_ctx* c, gw_mlp** out, int nin, int width, int depth, 
 gw_status gw_mlp_destroy(gw_mlp* n) {
   if (!n) return GW_EINVAL;
   (void)hipStreamSynchronize(n->ctx->stream);
-  if (n->p) (void)hipFree(n->p);
-  if (n->act) (void)hipFree(n->act);
-  delete n;
+  n->ctx->mlps.erase(n);
+  gw::mlp_free(n);
   return GW_OK;
 }
 

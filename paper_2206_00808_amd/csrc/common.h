@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <map>
 #include <memory>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -81,6 +82,9 @@ struct gw_ctx {
   std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
   int* d_flag = nullptr;                          // device status flags
   bool capturing = false;                         // inside a graph capture: no attribute calls
+  // networks and plans created on this context (freed with it)
+  std::set<gw_mlp*> mlps;
+  std::set<gw_plan*> plans;
   // profiling
   bool profiling = false;
   std::vector<gw::ProfRec> prof_pending;
@@ -92,6 +96,8 @@ struct gw_ctx {
 namespace gw {
 
 gw_status fail(gw_ctx* c, gw_status s, const char* fmt, ...);
+void mlp_free(gw_mlp* n);    // closure.hip: release without touching the context
+void plan_free(gw_plan* p);  // plan.hip
 gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what);
 
 // Workspace: reset at the start of a call, then carve aligned pieces.

@@ -12,6 +12,7 @@
 // Pruning keeps only the |g_i| <= gmax_i rows/columns of the transforms whose
 // input (band) or output (pair) is confined to a sphere.
 #include "common.h"
+#include "regfft.h"
 
 #include <cmath>
 
@@ -368,10 +369,416 @@ __global__ void __launch_bounds__(kThreads) k_pair_x(
   }
 }
 
+// ---------------------------------------------------------------- two-factor plane kernels
+// A pencil of length N = A*B is transformed by A threads holding B elements
+// each (element t + A*m in thread t): a B-point DFT in registers, the twiddle
+// exp(+2 pi i t k2 / N), one exchange through LDS, and A-point DFTs in
+// registers over the B columns (thread t takes k2 = t, t+A, ...).  Output
+// k = k2 + B*k1.  One LDS round trip per transform instead of one per radix.
+
+// frequency of transform index k on an axis of length n, kept if |f| <= g
+__device__ __forceinline__ int kept(int k, int n, int g) {
+  const int f = (2 * k <= n) ? k : k - n;
+  return (f >= -g && f <= g) ? f + g : -1;
+}
+
+template <int N>
+__host__ __device__ constexpr int ex_pitch() { return N + 1; }
+
+// pair plane: product, z transform keeping |gz| <= g, y transform keeping |gy| <= g
+template <typename T, int NS, int N2, int N3>
+__global__ void __launch_bounds__(kThreads) k_pair_plane_rf(
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
+    int n1, int ey, int ez, int gy, int gz, const cpx<T>* __restrict__ twy,
+    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2, int npairs) {
+  constexpr int A3 = split_n1(N3), B3 = N3 / A3, RZ = kThreads / A3, EP3 = ex_pitch<N3>();
+  constexpr int A2 = split_n1(N2), B2 = N2 / A2, RY = kThreads / A2, EP2 = ex_pitch<N2>();
+  constexpr int ER3 = RZ < N2 ? RZ : N2, ER2 = RY < N3 ? RY : N3;
+  constexpr int ESZ = (ER3 * EP3 > ER2 * EP2) ? ER3 * EP3 : ER2 * EP2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* E = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* Zb = E + ESZ;
+  const int ZP = ez | 1;
+  const long long lin = xcd_linear(blockIdx.x, (long long)n1 * npairs);
+  if (lin < 0) return;
+  const int x = (int)(lin / npairs), pr = (int)(lin % npairs);
+  const int v = v0 + pr % nvt, c = c0 + pr / nvt;
+  const size_t nb = (size_t)n1 * N2 * N3, np = (size_t)N2 * N3;
+  const cpx<T>* pv = uv + (size_t)v * NS * nb + (size_t)x * np;
+  const cpx<T>* pc = uc + (size_t)c * NS * nb + (size_t)x * np;
+  const int tid = threadIdx.x;
+  // ---- z transforms of the rows
+  {
+    const int rr = tid / A3, t = tid % A3;
+    for (int y0 = 0; y0 < N2; y0 += RZ) {
+      const int y = y0 + rr;
+      const bool act = y < N2;
+      cpx<T> a[B3];
+      if (act) {
+#pragma unroll
+        for (int m = 0; m < B3; ++m) {
+          const size_t o = (size_t)y * N3 + t + A3 * m;
+          cpx<T> r = cmulc(pv[o], pc[o]);
+          if (NS == 2) r = r + cmulc(pv[nb + o], pc[nb + o]);
+          a[m] = r;
+        }
+        reg_dft<T, B3>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B3; ++k2)
+          if (t) a[k2] = cmul(a[k2], twz[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < B3; ++k2) E[rr * EP3 + k2 * A3 + t] = a[k2];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < (B3 + A3 - 1) / A3; ++s) {
+          const int k2 = t + A3 * s;
+          if (k2 < B3) {
+            cpx<T> u[A3];
+#pragma unroll
+            for (int n = 0; n < A3; ++n) u[n] = E[rr * EP3 + k2 * A3 + n];
+            reg_dft<T, A3>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < A3; ++k1) {
+              const int jz = kept(k2 + B3 * k1, N3, gz);
+              if (jz >= 0) Zb[y * ZP + jz] = u[k1];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- y transforms of the kept columns
+  {
+    const int pp = tid / A2, t = tid % A2;
+    const int ncol = ey * ez;
+    cpx<T>* dst = t2 + ((size_t)pr * n1 + x) * ncol;
+    for (int p0 = 0; p0 < ez; p0 += RY) {
+      const int jz = p0 + pp;
+      const bool act = jz < ez;
+      cpx<T> a[B2];
+      if (act) {
+#pragma unroll
+        for (int m = 0; m < B2; ++m) a[m] = Zb[(t + A2 * m) * ZP + jz];
+        reg_dft<T, B2>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B2; ++k2)
+          if (t) a[k2] = cmul(a[k2], twy[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < B2; ++k2) E[pp * EP2 + k2 * A2 + t] = a[k2];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < (B2 + A2 - 1) / A2; ++s) {
+          const int k2 = t + A2 * s;
+          if (k2 < B2) {
+            cpx<T> u[A2];
+#pragma unroll
+            for (int n = 0; n < A2; ++n) u[n] = E[pp * EP2 + k2 * A2 + n];
+            reg_dft<T, A2>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < A2; ++k1) {
+              const int jy = kept(k2 + B2 * k1, N2, gy);
+              if (jy >= 0) dst[jy * ez + jz] = u[k1];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// band plane: compact (y,z) input, y transform on the occupied columns, z
+// transform of every row, full plane written
+template <typename T, int N2, int N3>
+__global__ void __launch_bounds__(kThreads) k_band_plane_rf(
+    const cpx<T>* __restrict__ t1, int ey, int ez, int gy, int gz, int n1,
+    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ u) {
+  constexpr int A3 = split_n1(N3), B3 = N3 / A3, RZ = kThreads / A3, EP3 = ex_pitch<N3>();
+  constexpr int A2 = split_n1(N2), B2 = N2 / A2, RY = kThreads / A2, EP2 = ex_pitch<N2>();
+  constexpr int ER3 = RZ < N2 ? RZ : N2, ER2 = RY < N3 ? RY : N3;
+  constexpr int ESZ = (ER3 * EP3 > ER2 * EP2) ? ER3 * EP3 : ER2 * EP2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* E = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* Zb = E + ESZ;
+  const int ZP = ez | 1;
+  const int x = blockIdx.x, bs = blockIdx.y;
+  const int ncol = ey * ez;
+  const cpx<T>* src = t1 + ((size_t)bs * n1 + x) * ncol;
+  const int tid = threadIdx.x;
+  // ---- y transforms of the occupied columns (input rows |gy| <= g only)
+  {
+    const int pp = tid / A2, t = tid % A2;
+    for (int p0 = 0; p0 < ez; p0 += RY) {
+      const int jz = p0 + pp;
+      const bool act = jz < ez;
+      cpx<T> a[B2];
+      if (act) {
+#pragma unroll
+        for (int m = 0; m < B2; ++m) {
+          const int jy = kept(t + A2 * m, N2, gy);
+          a[m] = jy >= 0 ? src[jy * ez + jz] : mk<T>(0, 0);
+        }
+        reg_dft<T, B2>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B2; ++k2)
+          if (t) a[k2] = cmul(a[k2], twy[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < B2; ++k2) E[pp * EP2 + k2 * A2 + t] = a[k2];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < (B2 + A2 - 1) / A2; ++s) {
+          const int k2 = t + A2 * s;
+          if (k2 < B2) {
+            cpx<T> w[A2];
+#pragma unroll
+            for (int n = 0; n < A2; ++n) w[n] = E[pp * EP2 + k2 * A2 + n];
+            reg_dft<T, A2>(w);
+#pragma unroll
+            for (int k1 = 0; k1 < A2; ++k1) Zb[(k2 + B2 * k1) * ZP + jz] = w[k1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- z transforms of every row (input columns |gz| <= g only)
+  {
+    const int rr = tid / A3, t = tid % A3;
+    cpx<T>* dst = u + ((size_t)bs * n1 + x) * (size_t)N2 * N3;
+    for (int y0 = 0; y0 < N2; y0 += RZ) {
+      const int y = y0 + rr;
+      const bool act = y < N2;
+      cpx<T> a[B3];
+      if (act) {
+#pragma unroll
+        for (int m = 0; m < B3; ++m) {
+          const int jz = kept(t + A3 * m, N3, gz);
+          a[m] = jz >= 0 ? Zb[y * ZP + jz] : mk<T>(0, 0);
+        }
+        reg_dft<T, B3>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B3; ++k2)
+          if (t) a[k2] = cmul(a[k2], twz[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < B3; ++k2) E[rr * EP3 + k2 * A3 + t] = a[k2];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < (B3 + A3 - 1) / A3; ++s) {
+          const int k2 = t + A3 * s;
+          if (k2 < B3) {
+            cpx<T> w[A3];
+#pragma unroll
+            for (int n = 0; n < A3; ++n) w[n] = E[rr * EP3 + k2 * A3 + n];
+            reg_dft<T, A3>(w);
+#pragma unroll
+            for (int k1 = 0; k1 < A3; ++k1) dst[(size_t)y * N3 + k2 + B3 * k1] = w[k1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- conduction-stationary pair planes
+// One block owns the x-plane of one conduction band and walks every valence
+// band of the launch.
+//   - The conduction plane (all spinor components) stays in registers.
+//   - The next valence plane is fetched while the current one is transformed.
+//   - VB valence bands share one y pass, so that its columns fill the block.
+// Each pair costs one plane load from the caches instead of two. The output
+// layout is the one k_pair_plane_rf writes. Barriers order LDS only, so the
+// prefetch stays in flight across them; the twiddles live in LDS for the
+// same reason (a global load issued after the prefetch would wait for it).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+template <int N2, int N3>
+struct CsShape {
+  static constexpr int NP = N2 * N3;                        // plane elements
+  static constexpr int NI = (NP + kThreads - 1) / kThreads;  // per thread
+  static constexpr int PP = N3 + 1;                          // product row pitch
+  // z pass: A3 lanes (padded to L3, a power of two) per row, B3 values each
+  static constexpr int A3 = split_n1(N3), B3 = N3 / A3, L3 = pow2_at_least(A3), R3 = kThreads / L3;
+  static constexpr int A2 = split_n1(N2), B2 = N2 / A2, L2 = pow2_at_least(A2), R2 = kThreads / L2;
+  static constexpr int VB = 4;  // valence bands per y pass
+  static_assert(64 % L3 == 0 && 64 % L2 == 0, "a row or column must sit in one wavefront");
+};
+
+// LDS elements: twiddles (N3 + N2), product plane, VB kept-column slabs
+template <int N2, int N3>
+static size_t cs_lds_elems(int ez) {
+  using S = CsShape<N2, N3>;
+  return (size_t)N3 + N2 + (size_t)N2 * S::PP + (size_t)S::VB * N2 * (ez | 1);
+}
+
+template <typename T, int NS, int N2, int N3>
+__global__ void __launch_bounds__(kThreads) k_pair_cs(
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
+    int nct, int n1, int ey, int ez, int gy, int gz, const cpx<T>* __restrict__ twy,
+    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+  using S = CsShape<N2, N3>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* tw3 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw2 = tw3 + N3;
+  cpx<T>* P = tw2 + N2;
+  cpx<T>* Zb = P + N2 * S::PP;
+  const int ZP = ez | 1, zslab = N2 * ZP, ncol = ey * ez;
+  const long long lin = xcd_linear(blockIdx.x, (long long)n1 * nct);
+  if (lin < 0) return;
+  const int x = (int)(lin / nct), cl = (int)(lin % nct);
+  const size_t nb = (size_t)n1 * S::NP;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N3; i += kThreads) tw3[i] = twz[i];
+  for (int i = tid; i < N2; i += kThreads) tw2[i] = twy[i];
+
+  cpx<T> cr[NS][S::NI], vr[NS][S::NI];
+  {
+    const cpx<T>* pc = uc + (size_t)(c0 + cl) * NS * nb + (size_t)x * S::NP;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i < S::NI; ++i) {
+        const int e = tid + kThreads * i;
+        cr[s][i] = (S::NP % kThreads == 0 || e < S::NP) ? pc[s * nb + e] : mk<T>(0, 0);
+      }
+  }
+  auto fetch_v = [&](int vl) {
+    const cpx<T>* pv = uv + (size_t)(v0 + vl) * NS * nb + (size_t)x * S::NP;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i < S::NI; ++i) {
+        const int e = tid + kThreads * i;
+        vr[s][i] = (S::NP % kThreads == 0 || e < S::NP) ? pv[s * nb + e] : mk<T>(0, 0);
+      }
+  };
+  fetch_v(0);
+
+  for (int g0 = 0; g0 < nvt; g0 += S::VB) {
+    const int nbv = min(S::VB, nvt - g0);
+    for (int j = 0; j < nbv; ++j) {
+      const int vl = g0 + j;
+      lds_sync();  // the previous z pass has read P
+      // spinor-summed product conj(psi_v) psi_c of this plane
+#pragma unroll
+      for (int i = 0; i < S::NI; ++i) {
+        const int e = tid + kThreads * i;
+        cpx<T> r = cmulc(vr[0][i], cr[0][i]);
+        if (NS == 2) r = r + cmulc(vr[1][i], cr[1][i]);
+        if (S::NP % kThreads == 0 || e < S::NP) P[(e / N3) * S::PP + e % N3] = r;
+      }
+      if (vl + 1 < nvt) fetch_v(vl + 1);
+      lds_sync();
+      // z transforms of the rows; the kept |gz| <= g entries go to slab j
+      cpx<T>* Z = Zb + j * zslab;
+      const int rr = tid / S::L3, t = tid % S::L3;
+      for (int y0 = 0; y0 < N2; y0 += S::R3) {
+        const int y = y0 + rr;
+        if (y < N2 && t < S::A3) {
+          cpx<T>* row = P + y * S::PP;
+          cpx<T> a[S::B3];
+#pragma unroll
+          for (int m = 0; m < S::B3; ++m) a[m] = row[t + S::A3 * m];
+          reg_dft<T, S::B3>(a);
+          // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
+#pragma unroll
+          for (int k2 = 1; k2 < S::B3; ++k2) a[k2] = cmul(a[k2], tw3[t * k2]);
+          // each lane rewrites the row entries it read; the row's lanes share a
+          // wavefront, whose LDS accesses complete in order
+#pragma unroll
+          for (int k2 = 0; k2 < S::B3; ++k2) row[k2 * S::A3 + t] = a[k2];
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int s = 0; s < (S::B3 + S::A3 - 1) / S::A3; ++s) {
+            const int k2 = t + S::A3 * s;
+            if (k2 < S::B3) {
+              cpx<T> u[S::A3];
+#pragma unroll
+              for (int n = 0; n < S::A3; ++n) u[n] = row[k2 * S::A3 + n];
+              reg_dft<T, S::A3>(u);
+#pragma unroll
+              for (int k1 = 0; k1 < S::A3; ++k1) {
+                const int jz = kept(k2 + S::B3 * k1, N3, gz);
+                if (jz >= 0) Z[y * ZP + jz] = u[k1];
+              }
+            }
+          }
+        }
+      }
+    }
+    lds_sync();  // every slab of the group is complete
+    // y transforms of the kept columns of the group's valence bands
+    const int pp = tid / S::L2, t = tid % S::L2;
+    const int tot = nbv * ez;
+    for (int q0 = 0; q0 < tot; q0 += S::R2) {
+      const int q = q0 + pp;
+      if (q < tot && t < S::A2) {
+        const int j = q / ez, jz = q % ez;
+        cpx<T>* col = Zb + j * zslab + jz;
+        cpx<T> a[S::B2];
+#pragma unroll
+        for (int m = 0; m < S::B2; ++m) a[m] = col[(t + S::A2 * m) * ZP];
+        reg_dft<T, S::B2>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < S::B2; ++k2) a[k2] = cmul(a[k2], tw2[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + t) * ZP] = a[k2];
+        __builtin_amdgcn_wave_barrier();
+        cpx<T>* dst = t2 + ((size_t)(cl * nvt + g0 + j) * n1 + x) * ncol;
+#pragma unroll
+        for (int s = 0; s < (S::B2 + S::A2 - 1) / S::A2; ++s) {
+          const int k2 = t + S::A2 * s;
+          if (k2 < S::B2) {
+            cpx<T> u[S::A2];
+#pragma unroll
+            for (int n = 0; n < S::A2; ++n) u[n] = col[(k2 * S::A2 + n) * ZP];
+            reg_dft<T, S::A2>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < S::A2; ++k1) {
+              const int jy = kept(k2 + S::B2 * k1, N2, gy);
+              if (jy >= 0) dst[jy * ez + jz] = u[k1];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int N2, int N3>
+static size_t rf_lds_elems(int ez) {
+  constexpr int A3 = split_n1(N3), RZ = kThreads / A3, EP3 = N3 + 1;
+  constexpr int A2 = split_n1(N2), RY = kThreads / A2, EP2 = N2 + 1;
+  constexpr int ER3 = RZ < N2 ? RZ : N2, ER2 = RY < N3 ? RY : N3;
+  constexpr int ESZ = (ER3 * EP3 > ER2 * EP2) ? ER3 * EP3 : ER2 * EP2;
+  return (size_t)ESZ + (size_t)N2 * (ez | 1);
+}
+
 // Pencil lengths (x) and plane shapes (y, z) built with constant lengths; any
 // other box factoring into 2, 3, 5 runs the same kernels with runtime lengths.
 #define GW_X_LENGTHS(X) X(16) X(20) X(24) X(30) X(32) X(48) X(60)
 #define GW_PLANE_SHAPES(X) X(16, 16) X(24, 30) X(32, 32) X(48, 48) X(60, 160)
+// plane shapes whose conduction plane fits in registers (conduction-stationary pairs)
+#define GW_CS_SHAPES(X) X(16, 16) X(24, 30) X(32, 32) X(48, 48)
 
 // ---------------------------------------------------------------- launchers
 
@@ -455,6 +862,10 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
     GW_HIP(c, allow_lds(kx, lds_x));
     GW_HIP(c, allow_lds(kp, lds_p));
   }
+  bool rf = false;
+#define X(A, B) if (n2 == A && n3 == B) rf = true;
+  GW_PLANE_SHAPES(X)
+#undef X
   const cpx<T>* cf = static_cast<const cpx<T>*>(coef);
   cpx<T>* u = static_cast<cpx<T>*>(u_out);
   cpx<T>* t1 = static_cast<cpx<T>*>(scratch);
@@ -471,10 +882,23 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
     {
       ProfScope ps(c, "band_plane");
       dim3 g(n1, nb);
-      hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, t1, sm->ext[1], sm->ext[2],
-                         sm->gmax[1], sm->gmax[2], n1, n2, n3, py, pz,
-                         static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz),
-                         u + (size_t)b0 * n1 * n2 * n3);
+      cpx<T>* ub = u + (size_t)b0 * n1 * n2 * n3;
+      const cpx<T>* ty = static_cast<const cpx<T>*>(twy);
+      const cpx<T>* tz = static_cast<const cpx<T>*>(twz);
+      if (rf) {
+#define X(A, B)                                                                           \
+  if (n2 == A && n3 == B) {                                                               \
+    const size_t lds = rf_lds_elems<A, B>(sm->ext[2]) * sizeof(cpx<T>);                   \
+    if (!c->capturing) GW_HIP(c, allow_lds(k_band_plane_rf<T, A, B>, lds));               \
+    hipLaunchKernelGGL((k_band_plane_rf<T, A, B>), g, dim3(kThreads), lds, c->stream, t1, \
+                       sm->ext[1], sm->ext[2], sm->gmax[1], sm->gmax[2], n1, ty, tz, ub); \
+  }
+        GW_PLANE_SHAPES(X)
+#undef X
+      } else {
+        hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, t1, sm->ext[1], sm->ext[2],
+                           sm->gmax[1], sm->gmax[2], n1, n2, n3, py, pz, ty, tz, ub);
+      }
       GW_CHECK_LAUNCH(c, "k_band_plane");
     }
   }
@@ -510,11 +934,54 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
     ProfScope ps(c, "pair_plane");
     const long long tot = (long long)n1 * npairs;
     dim3 g((unsigned)(((tot + kXcd - 1) / kXcd) * kXcd));
-    hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, static_cast<const cpx<T>*>(uv),
-                       static_cast<const cpx<T>*>(uc), v0, nvt, c0, n1, n2, n3, em->ext[1],
-                       em->ext[2], em->gmax[1], em->gmax[2], py, pz,
-                       static_cast<const cpx<T>*>(twy), static_cast<const cpx<T>*>(twz), t2,
-                       npairs);
+    const cpx<T>* pu = static_cast<const cpx<T>*>(uv);
+    const cpx<T>* pc = static_cast<const cpx<T>*>(uc);
+    const cpx<T>* ty = static_cast<const cpx<T>*>(twy);
+    const cpx<T>* tz = static_cast<const cpx<T>*>(twz);
+    bool rf = false;
+    if (nvt > 0 && nct > 0) {
+      const unsigned gcs = (unsigned)((((long long)n1 * nct + kXcd - 1) / kXcd) * kXcd);
+#define X(A, B)                                                                              \
+  if (!rf && n2 == A && n3 == B) {                                                           \
+    rf = true;                                                                               \
+    const size_t lds = cs_lds_elems<A, B>(em->ext[2]) * sizeof(cpx<T>);                      \
+    if (nspinor == 2) {                                                                      \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 2, A, B>, lds));                   \
+      hipLaunchKernelGGL((k_pair_cs<T, 2, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
+                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],  \
+                         em->gmax[2], ty, tz, t2);                                           \
+    } else {                                                                                 \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 1, A, B>, lds));                   \
+      hipLaunchKernelGGL((k_pair_cs<T, 1, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
+                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],  \
+                         em->gmax[2], ty, tz, t2);                                           \
+    }                                                                                        \
+  }
+      GW_CS_SHAPES(X)
+#undef X
+    }
+#define X(A, B)                                                                              \
+  if (!rf && n2 == A && n3 == B) {                                                           \
+    rf = true;                                                                               \
+    const size_t lds = rf_lds_elems<A, B>(em->ext[2]) * sizeof(cpx<T>);                      \
+    if (nspinor == 2) {                                                                      \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_plane_rf<T, 2, A, B>, lds));             \
+      hipLaunchKernelGGL((k_pair_plane_rf<T, 2, A, B>), g, dim3(kThreads), lds, c->stream, pu, \
+                         pc, v0, nvt, c0, n1, em->ext[1], em->ext[2], em->gmax[1],           \
+                         em->gmax[2], ty, tz, t2, npairs);                                   \
+    } else {                                                                                 \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_plane_rf<T, 1, A, B>, lds));             \
+      hipLaunchKernelGGL((k_pair_plane_rf<T, 1, A, B>), g, dim3(kThreads), lds, c->stream, pu, \
+                         pc, v0, nvt, c0, n1, em->ext[1], em->ext[2], em->gmax[1],           \
+                         em->gmax[2], ty, tz, t2, npairs);                                   \
+    }                                                                                        \
+  }
+    GW_PLANE_SHAPES(X)
+#undef X
+    if (!rf)
+      hipLaunchKernelGGL(kp, g, dim3(kThreads), lds_p, c->stream, pu, pc, v0, nvt, c0, n1, n2, n3,
+                         em->ext[1], em->ext[2], em->gmax[1], em->gmax[2], py, pz, ty, tz, t2,
+                         npairs);
     GW_CHECK_LAUNCH(c, "k_pair_plane");
   }
   {

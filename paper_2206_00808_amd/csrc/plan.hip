@@ -250,6 +250,14 @@ struct gw_plan {
 
 namespace gw {
 
+void plan_free(gw_plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->base) (void)hipFree(p->base);
+  delete p;
+}
+
 static gw_status plan_fail(gw_plan* p, gw_status s, const std::string& m) {
   return fail(p->ctx, s, "%s", m.c_str());
 }
@@ -571,6 +579,7 @@ gw_status gw_plan_create(gw_ctx* c, gw_plan** out, const int box[3], int nspinor
   for (int i = 1; i < nq; ++i)
     if (qd[i].cc != qd[0].cc || p->q[i].sc != p->q[0].sc) p->shared_c = false;
   for (int i = 0; i < nq; ++i) p->nc_shared = std::max(p->nc_shared, qd[i].nc);
+  c->plans.insert(p);
   *out = p;
   return GW_OK;
 }
@@ -795,11 +804,8 @@ gw_status gw_plan_destroy(gw_plan* p) {
   if (!p) return GW_EINVAL;
   (void)hipSetDevice(p->ctx->device);
   (void)hipStreamSynchronize(p->ctx->stream);
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->cap) (void)hipStreamDestroy(p->cap);
-  if (p->base) (void)hipFree(p->base);
-  delete p;
+  p->ctx->plans.erase(p);
+  gw::plan_free(p);
   return GW_OK;
 }
 
