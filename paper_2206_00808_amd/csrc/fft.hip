@@ -611,14 +611,17 @@ constexpr int pow2_at_least(int n) {
   return p;
 }
 
+constexpr int cs_split(int n) { return n == 48 ? 8 : split_n1(n); }
+
 template <int N2, int N3>
 struct CsShape {
   static constexpr int NP = N2 * N3;                        // plane elements
   static constexpr int NI = (NP + kThreads - 1) / kThreads;  // per thread
   static constexpr int PP = N3 + 1;                          // product row pitch
   // z pass: A3 lanes (padded to L3, a power of two) per row, B3 values each
-  static constexpr int A3 = split_n1(N3), B3 = N3 / A3, L3 = pow2_at_least(A3), R3 = kThreads / L3;
-  static constexpr int A2 = split_n1(N2), B2 = N2 / A2, L2 = pow2_at_least(A2), R2 = kThreads / L2;
+  // 8 lanes x 6 values for length 48 keeps the FP64 instance within 256 VGPRs
+  static constexpr int A3 = cs_split(N3), B3 = N3 / A3, L3 = pow2_at_least(A3), R3 = kThreads / L3;
+  static constexpr int A2 = cs_split(N2), B2 = N2 / A2, L2 = pow2_at_least(A2), R2 = kThreads / L2;
   static constexpr int VB = 4;  // valence bands per y pass
   static_assert(64 % L3 == 0 && 64 % L2 == 0, "a row or column must sit in one wavefront");
 };
@@ -631,7 +634,7 @@ static size_t cs_lds_elems(int ez) {
 }
 
 template <typename T, int NS, int N2, int N3>
-__global__ void __launch_bounds__(kThreads) k_pair_cs(
+__global__ void __launch_bounds__(kThreads, 2) k_pair_cs(
     const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
     int nct, int n1, int ey, int ez, int gy, int gz, const cpx<T>* __restrict__ twy,
     const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
@@ -764,6 +767,170 @@ __global__ void __launch_bounds__(kThreads) k_pair_cs(
   }
 }
 
+// ---------------------------------------------------------------- row-resident pair planes
+// Like k_pair_cs, one block owns the x-plane of one conduction band and walks
+// the valence bands, but every row of the plane belongs to one group of lanes
+// inside one wavefront.
+//   - Those lanes load their row slice of both bands straight from memory and
+//     form the spinor product in registers.
+//   - They exchange the row through LDS for the second factor of the z
+//     transform without a block barrier: a wavefront's LDS accesses complete
+//     in order.
+// Block barriers remain only around the y pass, which runs once per group of
+// vb valence bands. There is no register prefetch: at three wavefronts per SIMD,
+// the other block covers the load latency. This is the FP32 kernel; in FP64
+// the conduction row plus its working set leave too few wavefronts, and
+// k_pair_cs is faster.
+
+
+template <typename T, int N2, int N3>
+struct RrShape {
+  static constexpr int A3 = split_n1(N3), B3 = N3 / A3, L3 = pow2_at_least(A3);
+  static constexpr int A2 = split_n1(N2), B2 = N2 / A2, L2 = pow2_at_least(A2);
+  static constexpr int NTH = N2 * L3;  // threads: one lane group per row
+  static constexpr int PP = N3 + 1;    // exchange row pitch
+  static constexpr int CPP = NTH / L2; // y columns per pass
+  static_assert(64 % L3 == 0 && 64 % L2 == 0, "a row or column must sit in one wavefront");
+  static_assert(NTH <= 1024 && NTH % 64 == 0, "block must be whole wavefronts");
+};
+
+template <typename T, int N2, int N3>
+static size_t rr_lds_elems(int ez, int vb) {
+  using S = RrShape<T, N2, N3>;
+  return (size_t)N3 + N2 + (size_t)N2 * S::PP + (size_t)vb * N2 * (ez | 1);
+}
+
+// valence bands per y pass: fill the pass's columns, keep LDS within half a CU
+template <typename T, int N2, int N3>
+static int rr_group(int ez) {
+  using S = RrShape<T, N2, N3>;
+  int vb = std::max(1, std::min(8, S::CPP / std::max(1, ez)));
+  while (vb > 1 && rr_lds_elems<T, N2, N3>(ez, vb) * sizeof(cpx<T>) > 80 * 1024) --vb;
+  return vb;
+}
+
+template <typename T, int NS, int N2, int N3>
+__global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
+    int nct, int n1, int ey, int ez, int gy, int gz, int vb, const cpx<T>* __restrict__ twy,
+    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+  using S = RrShape<T, N2, N3>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* tw3 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw2 = tw3 + N3;
+  cpx<T>* X = tw2 + N2;
+  cpx<T>* Zb = X + N2 * S::PP;
+  const int ZP = ez | 1, zslab = N2 * ZP, ncol = ey * ez;
+  const long long lin = xcd_linear(blockIdx.x, (long long)n1 * nct);
+  if (lin < 0) return;
+  const int x = (int)(lin / nct), cl = (int)(lin % nct);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N3; i += S::NTH) tw3[i] = twz[i];
+  for (int i = tid; i < N2; i += S::NTH) tw2[i] = twy[i];
+  const int y = tid / S::L3, t = tid % S::L3;
+  const bool act = t < S::A3;
+  const size_t nb = (size_t)n1 * N2 * N3;
+  const size_t roff = ((size_t)x * N2 + y) * N3 + t;
+
+  cpx<T> cr[NS][S::B3], vr[NS][S::B3];
+  if (act) {
+    const cpx<T>* pc = uc + (size_t)(c0 + cl) * NS * nb + roff;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < S::B3; ++m) cr[s][m] = pc[s * nb + S::A3 * m];
+  }
+  auto fetch_v = [&](int vl) {
+    const cpx<T>* pv = uv + (size_t)(v0 + vl) * NS * nb + roff;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < S::B3; ++m) vr[s][m] = pv[s * nb + S::A3 * m];
+  };
+  lds_sync();  // twiddles in place
+
+  cpx<T>* Xr = X + y * S::PP;
+  for (int g0 = 0; g0 < nvt; g0 += vb) {
+    const int nbv = min(vb, nvt - g0);
+    for (int j = 0; j < nbv; ++j) {
+      const int vl = g0 + j;
+      if (act) {
+        fetch_v(vl);
+        // spinor-summed product conj(psi_v) psi_c on the lane's row slice
+        cpx<T> a[S::B3];
+#pragma unroll
+        for (int m = 0; m < S::B3; ++m) {
+          a[m] = cmulc(vr[0][m], cr[0][m]);
+          if (NS == 2) a[m] = a[m] + cmulc(vr[1][m], cr[1][m]);
+        }
+        reg_dft<T, S::B3>(a);
+        // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
+#pragma unroll
+        for (int k2 = 1; k2 < S::B3; ++k2) a[k2] = cmul(a[k2], tw3[t * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < S::B3; ++k2) Xr[k2 * S::A3 + t] = a[k2];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+        cpx<T>* Z = Zb + j * zslab + y * ZP;
+#pragma unroll
+        for (int s = 0; s < (S::B3 + S::A3 - 1) / S::A3; ++s) {
+          const int k2 = t + S::A3 * s;
+          if (k2 < S::B3) {
+            cpx<T> u[S::A3];
+#pragma unroll
+            for (int n = 0; n < S::A3; ++n) u[n] = Xr[k2 * S::A3 + n];
+            reg_dft<T, S::A3>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < S::A3; ++k1) {
+              const int jz = kept(k2 + S::B3 * k1, N3, gz);
+              if (jz >= 0) Z[jz] = u[k1];
+            }
+          }
+        }
+      }
+      // the next band's exchange writes follow these reads in the same wavefront
+      __builtin_amdgcn_wave_barrier();
+    }
+    lds_sync();  // every slab of the group is complete
+    const int pp = tid / S::L2, tt = tid % S::L2;
+    const int tot = nbv * ez;
+    for (int q0 = 0; q0 < tot; q0 += S::CPP) {
+      const int q = q0 + pp;
+      if (q < tot && tt < S::A2) {
+        const int j = q / ez, jz = q % ez;
+        cpx<T>* col = Zb + j * zslab + jz;
+        cpx<T> a[S::B2];
+#pragma unroll
+        for (int m = 0; m < S::B2; ++m) a[m] = col[(tt + S::A2 * m) * ZP];
+        reg_dft<T, S::B2>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < S::B2; ++k2) a[k2] = cmul(a[k2], tw2[tt * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + tt) * ZP] = a[k2];
+        __builtin_amdgcn_wave_barrier();
+        cpx<T>* dst = t2 + ((size_t)(cl * nvt + g0 + j) * n1 + x) * ncol;
+#pragma unroll
+        for (int s = 0; s < (S::B2 + S::A2 - 1) / S::A2; ++s) {
+          const int k2 = tt + S::A2 * s;
+          if (k2 < S::B2) {
+            cpx<T> u[S::A2];
+#pragma unroll
+            for (int n = 0; n < S::A2; ++n) u[n] = col[(k2 * S::A2 + n) * ZP];
+            reg_dft<T, S::A2>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < S::A2; ++k1) {
+              const int jy = kept(k2 + S::B2 * k1, N2, gy);
+              if (jy >= 0) dst[jy * ez + jz] = u[k1];
+            }
+          }
+        }
+      }
+    }
+    lds_sync();  // the group's slabs are consumed before the next z pass
+  }
+}
+
 template <int N2, int N3>
 static size_t rf_lds_elems(int ez) {
   constexpr int A3 = split_n1(N3), RZ = kThreads / A3, EP3 = N3 + 1;
@@ -777,7 +944,7 @@ static size_t rf_lds_elems(int ez) {
 // other box factoring into 2, 3, 5 runs the same kernels with runtime lengths.
 #define GW_X_LENGTHS(X) X(16) X(20) X(24) X(30) X(32) X(48) X(60)
 #define GW_PLANE_SHAPES(X) X(16, 16) X(24, 30) X(32, 32) X(48, 48) X(60, 160)
-// plane shapes whose conduction plane fits in registers (conduction-stationary pairs)
+// plane shapes of the conduction-stationary pair kernels (k_pair_cs in FP64, k_pair_rr in FP32)
 #define GW_CS_SHAPES(X) X(16, 16) X(24, 30) X(32, 32) X(48, 48)
 
 // ---------------------------------------------------------------- launchers
@@ -941,24 +1108,47 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
     bool rf = false;
     if (nvt > 0 && nct > 0) {
       const unsigned gcs = (unsigned)((((long long)n1 * nct + kXcd - 1) / kXcd) * kXcd);
-#define X(A, B)                                                                              \
-  if (!rf && n2 == A && n3 == B) {                                                           \
-    rf = true;                                                                               \
-    const size_t lds = cs_lds_elems<A, B>(em->ext[2]) * sizeof(cpx<T>);                      \
-    if (nspinor == 2) {                                                                      \
-      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 2, A, B>, lds));                   \
+      if constexpr (sizeof(T) == 8) {
+#define X(A, B)                                                                               \
+  if (!rf && n2 == A && n3 == B) {                                                            \
+    rf = true;                                                                                \
+    const size_t lds = cs_lds_elems<A, B>(em->ext[2]) * sizeof(cpx<T>);                       \
+    if (nspinor == 2) {                                                                       \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 2, A, B>, lds));                    \
       hipLaunchKernelGGL((k_pair_cs<T, 2, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
-                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],  \
-                         em->gmax[2], ty, tz, t2);                                           \
-    } else {                                                                                 \
-      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 1, A, B>, lds));                   \
+                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],   \
+                         em->gmax[2], ty, tz, t2);                                            \
+    } else {                                                                                  \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 1, A, B>, lds));                    \
       hipLaunchKernelGGL((k_pair_cs<T, 1, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
-                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],  \
-                         em->gmax[2], ty, tz, t2);                                           \
-    }                                                                                        \
+                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],   \
+                         em->gmax[2], ty, tz, t2);                                            \
+    }                                                                                         \
   }
-      GW_CS_SHAPES(X)
+        GW_CS_SHAPES(X)
 #undef X
+      } else {
+#define X(A, B)                                                                               \
+  if (!rf && n2 == A && n3 == B) {                                                            \
+    rf = true;                                                                                \
+    const int vb = rr_group<T, A, B>(em->ext[2]);                                             \
+    const size_t lds = rr_lds_elems<T, A, B>(em->ext[2], vb) * sizeof(cpx<T>);                \
+    const dim3 blk(RrShape<T, A, B>::NTH);                                                    \
+    if (nspinor == 2) {                                                                       \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_rr<T, 2, A, B>, lds));                    \
+      hipLaunchKernelGGL((k_pair_rr<T, 2, A, B>), dim3(gcs), blk, lds, c->stream, pu, pc, v0, \
+                         nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],  \
+                         vb, ty, tz, t2);                                                     \
+    } else {                                                                                  \
+      if (!c->capturing) GW_HIP(c, allow_lds(k_pair_rr<T, 1, A, B>, lds));                    \
+      hipLaunchKernelGGL((k_pair_rr<T, 1, A, B>), dim3(gcs), blk, lds, c->stream, pu, pc, v0, \
+                         nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],  \
+                         vb, ty, tz, t2);                                                     \
+    }                                                                                         \
+  }
+        GW_CS_SHAPES(X)
+#undef X
+      }
     }
 #define X(A, B)                                                                              \
   if (!rf && n2 == A && n3 == B) {                                                           \
