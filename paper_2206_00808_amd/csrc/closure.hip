@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(256) k_chol_update(cpx<double>* __restrict__ A
   const int i0 = blockIdx.y * ZTM, j0 = blockIdx.x * ZTM;
   if (i0 >= rest || j0 >= rest) return;
   // A22 -= L21 L21^H, L21 = A[s:, k:k+nbk] (ld N), L21^H = R[:, s:] (ld N)
-  zgemm_tile(rest, rest, nbk, -1.0, A + (size_t)s * N + k, N, R + s, N, A + (size_t)s * N + s, N,
+  zgemm_tile(rest, rest, nbk, -1.0, 1.0, A + (size_t)s * N + k, N, R + s, N, A + (size_t)s * N + s, N,
              i0, j0);
 }
 

@@ -156,12 +156,13 @@ gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, 
                     const double* wts, int skip_head, double* chi0);
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
                          const double* wts, int skip_head, double* chi0);
-// generic batched C[i][j] += alpha * sum_k A[i][k] B[k][j] (complex double, row-major);
-// offsets, leading dimensions, batch strides and extents in complex elements
+// generic batched C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] (complex
+// double, row-major, beta 0 or 1); offsets, leading dimensions, batch strides and
+// extents in complex elements
 gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
                    int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
-                   size_t extB, size_t extC);
+                   size_t extB, size_t extC, double beta = 1.0);
 
 // eps and its inverse (lu.hip)
 gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,

@@ -931,6 +931,67 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
   }
 }
 
+// ---------------------------------------------------------------- pair x pass, register resident
+// The x pencils of one pair's kept (y, z) columns: A lanes per column each hold
+// B values (x = t + A m), B-point DFT in registers, twiddle, exchange through
+// the column's LDS row inside the wavefront, A-point DFTs. Only the kept
+// |gx| <= g outputs are written, scaled by 1/N and scattered to the sphere.
+template <typename T, int N1>
+struct XpShape {
+  static constexpr int A = split_n1(N1), B = N1 / A, L = pow2_at_least(A), CPB = kThreads / L;
+  static_assert(64 % L == 0, "a column must sit in one wavefront");
+};
+
+template <typename T, int N1>
+__global__ void __launch_bounds__(kThreads) k_pair_x_rf(
+    const cpx<T>* __restrict__ t2, int ncol, int ey, int ez, int gx,
+    const int* __restrict__ emap, const cpx<T>* __restrict__ twx, T invN, int v0, int nvt,
+    int c0, int nct_total, int neps, cpx<T>* __restrict__ M) {
+  using S = XpShape<T, N1>;
+  __shared__ cpx<T> X[S::CPB][N1 + 1];
+  __shared__ cpx<T> tw[N1];
+  const int pr = blockIdx.y, tid = threadIdx.x;
+  for (int i = tid; i < N1; i += kThreads) tw[i] = twx[i];
+  __syncthreads();
+  const int cq = tid / S::L, t = tid % S::L;
+  const int col = blockIdx.x * S::CPB + cq;
+  if (col >= ncol || t >= S::A) return;
+  const cpx<T>* src = t2 + (size_t)pr * N1 * ncol + col;
+  cpx<T> a[S::B];
+#pragma unroll
+  for (int m = 0; m < S::B; ++m) a[m] = src[(size_t)(t + S::A * m) * ncol];
+  reg_dft<T, S::B>(a);
+  // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
+#pragma unroll
+  for (int k2 = 1; k2 < S::B; ++k2) a[k2] = cmul(a[k2], tw[t * k2]);
+  cpx<T>* Xr = X[cq];
+#pragma unroll
+  for (int k2 = 0; k2 < S::B; ++k2) Xr[k2 * S::A + t] = a[k2];
+  // the column's lanes share a wavefront, whose LDS accesses complete in order
+  __builtin_amdgcn_wave_barrier();
+  const int v = v0 + pr % nvt, c = c0 + pr / nvt;
+  cpx<T>* dst = M + ((size_t)v * nct_total + c) * neps;
+  const int jy = col / ez, jz = col - jy * ez;
+#pragma unroll
+  for (int s = 0; s < (S::B + S::A - 1) / S::A; ++s) {
+    const int k2 = t + S::A * s;
+    if (k2 < S::B) {
+      cpx<T> u[S::A];
+#pragma unroll
+      for (int n = 0; n < S::A; ++n) u[n] = Xr[k2 * S::A + n];
+      reg_dft<T, S::A>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < S::A; ++k1) {
+        const int jx = kept(k2 + S::B * k1, N1, gx);
+        if (jx >= 0) {
+          const int idx = emap[(jx * ey + jy) * ez + jz];
+          if (idx >= 0) dst[idx] = scal(u[k1], invN);
+        }
+      }
+    }
+  }
+}
+
 template <int N2, int N3>
 static size_t rf_lds_elems(int ez) {
   constexpr int A3 = split_n1(N3), RZ = kThreads / A3, EP3 = N3 + 1;
@@ -1176,12 +1237,26 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
   }
   {
     ProfScope ps(c, "pair_xpass");
-    dim3 g((ncol + CH - 1) / CH, npairs);
     const T invN = (T)(1.0 / ((double)n1 * n2 * n3));
-    hipLaunchKernelGGL(kx, g, dim3(kThreads), lds_x, c->stream, t2, n1, ncol, CH, em->ext[0],
-                       em->ext[1], em->ext[2], em->gmax[0], em->d_cube, px,
-                       static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,
-                       static_cast<cpx<T>*>(mtxel));
+    bool done = false;
+#define X(N)                                                                                   \
+  if (!done && n1 == N) {                                                                      \
+    done = true;                                                                               \
+    dim3 g((ncol + XpShape<T, N>::CPB - 1) / XpShape<T, N>::CPB, npairs);                      \
+    hipLaunchKernelGGL((k_pair_x_rf<T, N>), g, dim3(kThreads), 0, c->stream, t2, ncol,         \
+                       em->ext[1], em->ext[2], em->gmax[0], em->d_cube,                        \
+                       static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,    \
+                       static_cast<cpx<T>*>(mtxel));                                           \
+  }
+    GW_X_LENGTHS(X)
+#undef X
+    if (!done) {
+      dim3 g((ncol + CH - 1) / CH, npairs);
+      hipLaunchKernelGGL(kx, g, dim3(kThreads), lds_x, c->stream, t2, n1, ncol, CH, em->ext[0],
+                         em->ext[1], em->ext[2], em->gmax[0], em->d_cube, px,
+                         static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,
+                         static_cast<cpx<T>*>(mtxel));
+    }
     GW_CHECK_LAUNCH(c, "k_pair_x");
   }
   return GW_OK;

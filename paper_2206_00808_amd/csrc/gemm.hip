@@ -97,11 +97,12 @@ gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfre
 // ---------------------------------------------------------------- generic ZGEMM
 // C[i][j] += alpha * sum_k A[i][k] B[k][j], complex double, row-major, batched on z.
 __global__ void __launch_bounds__(256) k_zgemm_nn(int m, int n, int kdim, double alpha,
+                                                  double beta,
                                                   const cpx<double>* __restrict__ A, int lda,
                                                   long long sA, const cpx<double>* __restrict__ B,
                                                   int ldb, long long sB, cpx<double>* __restrict__ C,
                                                   int ldc, long long sC) {
-  zgemm_tile(m, n, kdim, alpha, A + (size_t)blockIdx.z * sA, lda, B + (size_t)blockIdx.z * sB,
+  zgemm_tile(m, n, kdim, alpha, beta, A + (size_t)blockIdx.z * sA, lda, B + (size_t)blockIdx.z * sB,
              ldb, C + (size_t)blockIdx.z * sC, ldc, blockIdx.y * ZTM, blockIdx.x * ZTM);
 }
 
@@ -113,7 +114,8 @@ static size_t span(size_t off, int rows, int cols, int ld, long long stride, int
 gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
                    int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
-                   size_t extB, size_t extC) {
+                   size_t extB, size_t extC, double beta) {
+  if (beta != 0.0 && beta != 1.0) return fail(c, GW_EINVAL, "zgemm beta must be 0 or 1");
   if (m <= 0 || n <= 0 || k <= 0 || batch <= 0) return GW_OK;
   // every offset, leading dimension and stride is in complex elements; the
   // extents are the complex elements available behind each base pointer
@@ -123,7 +125,7 @@ gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A
                 batch);
   ProfScope ps(c, "zgemm_update");
   dim3 g((n + ZTM - 1) / ZTM, (m + ZTM - 1) / ZTM, batch);
-  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha,
+  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha, beta,
                      reinterpret_cast<const cpx<double>*>(A) + offA, lda, sA,
                      reinterpret_cast<const cpx<double>*>(B) + offB, ldb, sB,
                      reinterpret_cast<cpx<double>*>(C) + offC, ldc, sC);

@@ -199,16 +199,12 @@ __global__ void k_perm_identity(const int* __restrict__ perm, int N, cpx<double>
 
 
 // ---------------------------------------------------------------- Gauss-Jordan path
-constexpr int GB = 32;  // Gauss-Jordan block width
+constexpr int GB = 64;  // Gauss-Jordan block width
 
 __global__ void k_fill_int(int* p, int n, int v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-__global__ void k_fill_zero(cpx<double>* p, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = mk(0.0, 0.0);
-}
 
 // epst = I - S chi0 S with S = diag(sqrt(v)); flag[1] = 1 if some v <= 0 or non-finite.
 __global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* __restrict__ v,
@@ -228,90 +224,115 @@ __global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* 
 // Invert the nbk x nbk diagonal block A[K][K] (K = k..k+nbk) by unblocked
 // Gauss-Jordan without pivoting; write it to Dw[f].  A pivot that is not
 // real-positive sets flag[1].
+// Inverse of the diagonal block D = A[K][K] by Gauss-Jordan without pivoting,
+// register resident: thread (ti, tj) of a 32x32 grid holds entries
+// (ti + 32a, tj + 32b). Each step publishes the pivot row and column through
+// double-buffered LDS (one barrier per step). The in-place update is written
+// without branches:
+//   row t     <- (row t with 1 at the pivot) / p
+//   other i   <- (row i with 0 at the pivot) - a_it * (new row t)
+// A ragged block is padded with the identity, which leaves the leading
+// nbk x nbk inverse unchanged.
 __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ A, int N, int k,
                                                   int nbk, cpx<double>* __restrict__ Dw,
                                                   int* __restrict__ flag) {
-  __shared__ cpx<double> D[GB][GB + 1];
-  __shared__ cpx<double> piv;
+  constexpr int TG = 32, TE = GB / TG;
+  __shared__ cpx<double> rowb[2][GB], colb[2][GB];
   const int f = blockIdx.x;
   A += (size_t)f * N * N;
   Dw += (size_t)f * GB * GB;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
-    const int r = e / nbk, cc = e % nbk;
-    D[r][cc] = A[(size_t)(k + r) * N + k + cc];
-  }
-  __syncthreads();
+  const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
+  cpx<double> d[TE][TE];
+#pragma unroll
+  for (int a = 0; a < TE; ++a)
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int i = ti + TG * a, j = tj + TG * b;
+      d[a][b] = (i < nbk && j < nbk) ? A[(size_t)(k + i) * N + k + j]
+                                     : mk(i == j ? 1.0 : 0.0, 0.0);
+    }
   for (int t = 0; t < nbk; ++t) {
-    if (tid == 0) {
-      const cpx<double> p = D[t][t];
-      // chi0 <= 0 makes epst >= I, so every pivot of the elimination is real and
-      // >= 1 up to rounding; a pivot below 1/2 or far from the real axis means
-      // the input is not of that form and the pivoted path must be used
-      const bool ok = p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY;
-      if (!ok) flag[1] = 1;
-      const double den = p.x * p.x + p.y * p.y;
-      piv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
+    const int buf = t & 1, ta = t / TG, tr = t % TG;
+    // the pivot row and column, selected with constant indices so that d
+    // stays in registers
+#pragma unroll
+    for (int q = 0; q < TE; ++q) {
+      if (ti == tr && ta == q) {
+#pragma unroll
+        for (int b = 0; b < TE; ++b) rowb[buf][tj + TG * b] = d[q][b];
+      }
+      if (tj == tr && ta == q) {
+#pragma unroll
+        for (int a = 0; a < TE; ++a) colb[buf][ti + TG * a] = d[a][q];
+      }
     }
     __syncthreads();
-    const cpx<double> pinv = piv;
-    // row t scaled, then the rank-1 update; the pivot column is handled last
-    cpx<double> rowt = mk(0.0, 0.0), colt = mk(0.0, 0.0);
-    const int i = tid / GB, j = tid % GB;
-    const bool act = tid < GB * GB && i < nbk && j < nbk;
-    if (act) {
-      rowt = cmul(D[t][j], pinv);
-      colt = D[i][t];
+    const cpx<double> p = rowb[buf][t];
+    // chi0 <= 0 makes epst >= I, so every pivot of the elimination is real and
+    // >= 1 up to rounding; a pivot below 1/2 or far from the real axis means
+    // the input is not of that form and the pivoted path must be used
+    if (tid == 0 && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY)) flag[1] = 1;
+    const double den = p.x * p.x + p.y * p.y;
+    const cpx<double> pinv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
+    cpx<double> rs[TE], cc[TE];
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int j = tj + TG * b;
+      rs[b] = (j == t) ? pinv : cmul(rowb[buf][j], pinv);
     }
-    __syncthreads();
-    if (act) {
-      if (i == t && j == t) D[i][j] = pinv;
-      else if (i == t) D[i][j] = rowt;
-      else if (j == t) D[i][j] = mk(-(colt.x * pinv.x - colt.y * pinv.y),
-                                   -(colt.x * pinv.y + colt.y * pinv.x));
-      else D[i][j] = D[i][j] - cmul(colt, rowt);
-    }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < TE; ++a) cc[a] = colb[buf][ti + TG * a];
+#pragma unroll
+    for (int a = 0; a < TE; ++a)
+#pragma unroll
+      for (int b = 0; b < TE; ++b) {
+        const int i = ti + TG * a, j = tj + TG * b;
+        const cpx<double> dd = (j == t) ? mk(0.0, 0.0) : d[a][b];
+        d[a][b] = (i == t) ? rs[b] : dd - cmul(cc[a], rs[b]);
+      }
+    // the other buffer pair was last read before this step's barrier
   }
-  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
-    const int r = e / nbk, cc = e % nbk;
-    Dw[r * GB + cc] = D[r][cc];
-  }
+#pragma unroll
+  for (int a = 0; a < TE; ++a)
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int i = ti + TG * a, j = tj + TG * b;
+      if (i < nbk && j < nbk) Dw[i * GB + j] = d[a][b];
+    }
 }
 
-// Cb[f][i][t] = A[f][i][k+t] for all rows i (column block K).
-__global__ void k_gj_copy_cols(const cpx<double>* __restrict__ A, int N, int k, int nbk,
-                               cpx<double>* __restrict__ Cb) {
+// Before the rank-nbk update of step K:
+//   - Cb[f][i][t] = A[f][i][k+t] for all rows i (column block K);
+//   - R[t][k+j] = delta_tj + Dinv[t][j].
+// With R in the K columns set this way, A[:,K] - Cb R leaves -Cb Dinv in the
+// column block, which is its Gauss-Jordan value.
+__global__ void k_gj_prep(const cpx<double>* __restrict__ A, int N, int k, int nbk,
+                          cpx<double>* __restrict__ Cb, cpx<double>* __restrict__ R,
+                          const cpx<double>* __restrict__ Dw) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * nbk) return;
-  const int i = e / nbk, t = e % nbk;
   const size_t f = blockIdx.y;
-  Cb[f * (size_t)N * GB + (size_t)i * GB + t] = A[f * (size_t)N * N + (size_t)i * N + k + t];
+  if (e < N * nbk) {
+    const int i = e / nbk, t = e % nbk;
+    Cb[f * (size_t)N * GB + (size_t)i * GB + t] = A[f * (size_t)N * N + (size_t)i * N + k + t];
+  }
+  if (e < nbk * nbk) {
+    const int t = e / nbk, j = e % nbk;
+    const cpx<double> dv = Dw[f * GB * GB + t * GB + j];
+    R[f * (size_t)GB * N + (size_t)t * N + k + j] = mk(dv.x + (t == j ? 1.0 : 0.0), dv.y);
+  }
 }
 
-// Row block K <- R (columns outside K), diagonal block <- Dinv, column block
-// outside K <- -Cb Dinv.
+// Row block K <- R outside the K columns and Dinv inside.
 __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
-                         const cpx<double>* __restrict__ R, const cpx<double>* __restrict__ Cb,
-                         const cpx<double>* __restrict__ Dw) {
+                         const cpx<double>* __restrict__ R, const cpx<double>* __restrict__ Dw) {
   const size_t f = blockIdx.y;
   A += f * (size_t)N * N;
   R += f * (size_t)GB * N;
-  Cb += f * (size_t)N * GB;
   Dw += f * (size_t)GB * GB;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nbk * N) {  // row block
-    const int t = e / N, j = e % N;
-    A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
-    return;
-  }
-  const int e2 = e - nbk * N;
-  if (e2 >= N * nbk) return;
-  const int i = e2 / nbk, t = e2 % nbk;
-  if (i >= k && i < k + nbk) return;
-  cpx<double> s = mk(0.0, 0.0);
-  for (int u = 0; u < nbk; ++u) s = s + cmul(Cb[(size_t)i * GB + u], Dw[u * GB + t]);
-  A[(size_t)i * N + k + t] = mk(-s.x, -s.y);
+  if (e >= nbk * N) return;
+  const int t = e / N, j = e % N;
+  A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
 }
 
 // eps^-1 = S epst^-1 S^-1, in place.
@@ -459,29 +480,27 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
                          c->d_flag);
       GW_CHECK_LAUNCH(c, "k_gj_diag");
     }
-    {
-      ProfScope ps(c, "gj_small");
-      hipLaunchKernelGGL(k_gj_copy_cols, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0,
-                         c->stream, A, N, k, nbk, Cb);
-      GW_CHECK_LAUNCH(c, "k_gj_copy_cols");
-      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nR + 255) / 256)), dim3(256), 0, c->stream,
-                         R, nR);
-      GW_CHECK_LAUNCH(c, "k_fill_zero");
-    }
-    // R = Dinv A[K][:]
+    // R = Dinv A[K][:] (rows nbk.. of R are never read)
     st = zgemm_nn(c, nbk, N, nbk, 1.0, reinterpret_cast<const double*>(Dw), 0, GB, GB * GB, Ad,
                   (size_t)k * N, N, (long long)nn, reinterpret_cast<double*>(R), 0, N,
-                  (long long)GB * N, nfreq, nD, ext, nR);
+                  (long long)GB * N, nfreq, nD, ext, nR, 0.0);
     if (st != GW_OK) return st;
-    // A -= Cb R over the whole matrix (row and column block K are rewritten next)
+    {
+      ProfScope ps(c, "gj_small");
+      hipLaunchKernelGGL(k_gj_prep, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
+                         A, N, k, nbk, Cb, R, Dw);
+      GW_CHECK_LAUNCH(c, "k_gj_prep");
+    }
+    // A -= Cb R over the whole matrix: every row outside K is final, including
+    // its K columns; row block K is rewritten next
     st = zgemm_nn(c, N, N, nbk, -1.0, reinterpret_cast<const double*>(Cb), 0, GB,
                   (long long)N * GB, reinterpret_cast<const double*>(R), 0, N, (long long)GB * N,
                   epsinv, 0, N, (long long)nn, nfreq, nC, nR, ext);
     if (st != GW_OK) return st;
     {
       ProfScope ps(c, "gj_small");
-      hipLaunchKernelGGL(k_gj_fix, dim3((2 * N * nbk + 255) / 256, nfreq), dim3(256), 0,
-                         c->stream, A, N, k, nbk, R, Cb, Dw);
+      hipLaunchKernelGGL(k_gj_fix, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
+                         A, N, k, nbk, R, Dw);
       GW_CHECK_LAUNCH(c, "k_gj_fix");
     }
   }

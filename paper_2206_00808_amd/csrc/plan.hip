@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_gjb_update(const GjM* __restrict__ ms, 
   const int N = m.N, nbk = min(PB, N - k);
   const int i0 = blockIdx.y * ZTM, j0 = blockIdx.x * ZTM;
   if (i0 >= N || j0 >= N) return;
-  zgemm_tile(N, N, nbk, -1.0, m.Cb, PB, m.R, N, m.A, N, i0, j0);
+  zgemm_tile(N, N, nbk, -1.0, 1.0, m.Cb, PB, m.R, N, m.A, N, i0, j0);
 }
 
 // row block K <- R, diagonal block <- Dinv, column block outside K <- -Cb Dinv

@@ -279,14 +279,19 @@ __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M,
 }
 
 // ------------------------------------------------------------------ complex-double GEMM tile
-// C[i][j] += alpha * sum_k A[i][k] B[k][j] on the 64x64 tile at (i0, j0), 256 threads.
+// C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
+// (i0, j0), 256 threads (beta is 0 or 1: with 0, C is only written). K advances
+// in slabs of KT through two LDS buffers. The next slab is loaded into
+// registers while the current one feeds the MFMAs, so there is one barrier per
+// slab.
 constexpr int ZTM = 64, ZLP = ZTM + 1;
-__device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
+__device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha, double beta,
                                            const cpx<double>* __restrict__ A, int lda,
                                            const cpx<double>* __restrict__ B, int ldb,
                                            cpx<double>* __restrict__ C, int ldc, int i0, int j0) {
-  __shared__ cpx<double> As[KT][ZLP];
-  __shared__ cpx<double> Bs[KT][ZLP];
+  __shared__ cpx<double> As[2][KT][ZLP];
+  __shared__ cpx<double> Bs[2][KT][ZLP];
+  constexpr int PER = (KT * ZTM) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -298,30 +303,39 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
       cr[a][b] = (d4){0, 0, 0, 0};
       ci[a][b] = (d4){0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < kdim; k0 += KT) {
-    __syncthreads();
+  cpx<double> ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < (KT * ZTM) / 256; ++e) {
+    for (int e = 0; e < PER; ++e) {
       const int idx = tid + e * 256;
-      // A tile: ZTM rows x KT columns, k fastest for coalescing
+      // A slab: ZTM rows x KT columns, k fastest for coalescing
       const int ai = idx / KT, ak = idx % KT;
-      cpx<double> a = mk<double>(0, 0);
-      if (i0 + ai < m && k0 + ak < kdim) a = A[(size_t)(i0 + ai) * lda + k0 + ak];
-      As[ak][ai] = a;
+      ra[e] = (i0 + ai < m && k0 + ak < kdim) ? A[(size_t)(i0 + ai) * lda + k0 + ak]
+                                              : mk<double>(0, 0);
       const int bk = idx / ZTM, bj = idx % ZTM;
-      cpx<double> b = mk<double>(0, 0);
-      if (k0 + bk < kdim && j0 + bj < n) b = B[(size_t)(k0 + bk) * ldb + j0 + bj];
-      Bs[bk][bj] = b;
+      rb[e] = (k0 + bk < kdim && j0 + bj < n) ? B[(size_t)(k0 + bk) * ldb + j0 + bj]
+                                              : mk<double>(0, 0);
+    }
+  };
+  fetch(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < kdim; k0 += KT) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + e * 256;
+      As[buf][idx % KT][idx / KT] = ra[e];
+      Bs[buf][idx / ZTM][idx % ZTM] = rb[e];
     }
     __syncthreads();
+    if (k0 + KT < kdim) fetch(k0 + KT);
 #pragma unroll
     for (int s = 0; s < KT / 4; ++s) {
       const int kk = s * 4 + lk;
       cpx<double> av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+      for (int a = 0; a < 2; ++a) av[a] = As[buf][kk][wr * 32 + a * 16 + l16];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc * 32 + b * 16 + l16];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wc * 32 + b * 16 + l16];
       // a * b = (ar br - ai bi) + i (ar bi + ai br)
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -344,6 +358,9 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
         for (int b = 0; b < 2; ++b)
           ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
     }
+    // the other buffer was last read before this slab's barrier, so the next
+    // slab can be stored into it without another barrier
+    buf ^= 1;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -355,7 +372,10 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
         const int j = j0 + wc * 32 + b * 16 + l16;
         if (i >= m || j >= n) continue;
         cpx<double>* d = C + (size_t)i * ldc + j;
-        *d = mk(d->x + alpha * cr[a][b][r], d->y + alpha * ci[a][b][r]);
+        if (beta != 0.0)
+          *d = mk(beta * d->x + alpha * cr[a][b][r], beta * d->y + alpha * ci[a][b][r]);
+        else
+          *d = mk(alpha * cr[a][b][r], alpha * ci[a][b][r]);
       }
 }
 
