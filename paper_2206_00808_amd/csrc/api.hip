@@ -172,6 +172,10 @@ gw_status gw_ctx_create(gw_ctx** out, int device, void* stream) {
   gw_ctx* c = new gw_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    c->cus = cus;
   if (hipMalloc(&c->d_flag, 64) != hipSuccess) { delete c; return GW_ENOMEM; }
   if (hipMemset(c->d_flag, 0, 64) != hipSuccess) { (void)hipFree(c->d_flag); delete c; return GW_EDEVICE; }
   *out = c;
@@ -369,17 +373,21 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
   (void)hipSetDevice(c->device);
   const int P = nv * nc;
   const bool use_head = mhead != nullptr && head_index >= 0;
-  gw_status st = ws_begin(c, align_up((size_t)nfreq * 8) + align_up((size_t)nfreq * P * 8));
+  const int split = chi0_split(c, P, neps, nfreq, prec, dtype);
+  const size_t part_bytes = (size_t)(split - 1) * nfreq * neps * neps * 16;
+  gw_status st = ws_begin(c, align_up((size_t)nfreq * 8) + align_up((size_t)nfreq * P * 8) +
+                                 align_up(part_bytes));
   if (st != GW_OK) return st;
   double* d_om = static_cast<double*>(ws_take(c, (size_t)nfreq * 8));
   double* wts = static_cast<double*>(ws_take(c, (size_t)nfreq * P * 8));
+  double* part = part_bytes ? static_cast<double*>(ws_take(c, part_bytes)) : nullptr;
   GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
   if ((st = chi0_weights(c, nv, nc, ev, ec, nfreq, d_om, prefactor, wts)) != GW_OK) return st;
   const int skip = use_head ? head_index : -1;
   if (prec == GW_PREC_FP64)
-    st = chi0_fp64(c, P, neps, mtxel, dtype, nfreq, wts, skip, chi0);
+    st = chi0_fp64(c, P, neps, mtxel, dtype, nfreq, wts, skip, chi0, split, part);
   else
-    st = chi0_splitbf16(c, P, neps, mtxel, nfreq, wts, skip, chi0);
+    st = chi0_splitbf16(c, P, neps, mtxel, nfreq, wts, skip, chi0, split, part);
   if (st != GW_OK) return st;
   if (use_head) {
     if ((st = chi0_wings(c, P, neps, mtxel, dtype, mhead, head_index, nfreq, wts, chi0)) != GW_OK)

@@ -71,6 +71,7 @@ struct ProfAcc {
 
 struct gw_ctx {
   int device = 0;
+  int cus = 256;                                  // compute units of the device
   hipStream_t stream = nullptr;
   std::string err;
   // growable workspace (bump sub-allocation per call)
@@ -152,10 +153,14 @@ gw_status chi0_wings(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt,
 // chi0 contraction (gemm.hip)
 gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double* ec, int nfreq,
                        const double* d_omega, double pref, double* wts);
+// The pair sum of the contraction is cut into `split` ranges when that fills
+// the last round of workgroups better; ranges 1.. write their tiles to `part`
+// (split-1 matrices per frequency), which are then added to chi0 in order.
+int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt);
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
-                    const double* wts, int skip_head, double* chi0);
+                    const double* wts, int skip_head, double* chi0, int split, double* part);
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
-                         const double* wts, int skip_head, double* chi0);
+                         const double* wts, int skip_head, double* chi0, int split, double* part);
 // generic batched C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] (complex
 // double, row-major, beta 0 or 1); offsets, leading dimensions, batch strides and
 // extents in complex elements

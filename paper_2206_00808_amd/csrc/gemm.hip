@@ -38,16 +38,25 @@ gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double
 }
 
 // ---------------------------------------------------------------- single-q contractions
+// Grid (upper-triangle tiles, frequencies, pair ranges). Range 0 adds into chi0;
+// range s >= 1 covers pairs [s pc, (s+1) pc) and stores into partial matrix s-1.
 template <int WM, typename Tin>
 __global__ void __launch_bounds__(64 * WM * WM) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P,
                                                            int neps, const double* __restrict__ wts,
                                                            cpx<double>* __restrict__ chi, int nt,
-                                                           int skip_head) {
+                                                           int skip_head, int pc,
+                                                           cpx<double>* __restrict__ part) {
   int ti, tj;
   tri_tile(blockIdx.x, nt, &ti, &tj);
-  const int f = blockIdx.y;
-  chi0_f64_tile<WM, Tin>(M, P, neps, wts + (size_t)f * P, chi + (size_t)f * neps * neps, ti, tj,
-                         skip_head);
+  const int f = blockIdx.y, s = blockIdx.z, nf = gridDim.y;
+  const int p0 = s * pc, np = min(P, p0 + pc) - p0;
+  const size_t nn = (size_t)neps * neps;
+  if (s == 0)
+    chi0_f64_tile<WM, Tin>(M, np, neps, wts + (size_t)f * P, chi + (size_t)f * nn, ti, tj,
+                           skip_head);
+  else
+    chi0_f64_tile<WM, Tin>(M + (size_t)p0 * neps, np, neps, wts + (size_t)f * P + p0,
+                           part + ((size_t)(s - 1) * nf + f) * nn, ti, tj, skip_head, true);
 }
 
 template <int WM>
@@ -55,43 +64,118 @@ __global__ void __launch_bounds__(64 * WM * WM) k_chi0_bf16x3(const cpx<float>* 
                                                               int P, int neps,
                                                               const double* __restrict__ wts,
                                                               cpx<double>* __restrict__ chi,
-                                                              int nt, int skip_head) {
+                                                              int nt, int skip_head, int pc,
+                                                              cpx<double>* __restrict__ part) {
   int ti, tj;
   tri_tile(blockIdx.x, nt, &ti, &tj);
-  const int f = blockIdx.y;
-  chi0_bf16_tile<WM>(M, P, neps, wts + (size_t)f * P, chi + (size_t)f * neps * neps, ti, tj,
-                     skip_head);
+  const int f = blockIdx.y, s = blockIdx.z, nf = gridDim.y;
+  const int p0 = s * pc, np = min(P, p0 + pc) - p0;
+  const size_t nn = (size_t)neps * neps;
+  if (s == 0)
+    chi0_bf16_tile<WM>(M, np, neps, wts + (size_t)f * P, chi + (size_t)f * nn, ti, tj, skip_head);
+  else
+    chi0_bf16_tile<WM>(M + (size_t)p0 * neps, np, neps, wts + (size_t)f * P + p0,
+                       part + ((size_t)(s - 1) * nf + f) * nn, ti, tj, skip_head, true);
+}
+
+// chi0 += part[0] + part[1] + ... (fixed order, so the result does not depend on
+// which range finished first)
+__global__ void k_chi0_reduce(cpx<double>* __restrict__ chi, const cpx<double>* __restrict__ part,
+                              int nparts, size_t total) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  cpx<double> v = chi[e];
+  for (int s = 0; s < nparts; ++s) v = v + part[(size_t)s * total + e];
+  chi[e] = v;
+}
+
+constexpr int kChiWM = 2, kChiTM = 32 * kChiWM;
+
+int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt) {
+  const int nt = (neps + kChiTM - 1) / kChiTM;
+  const long long b1 = (long long)nt * (nt + 1) / 2 * nfreq;
+  int per_cu = 0;
+  hipError_t e;
+  if (prec == GW_PREC_SPLITBF16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_bf16x3<kChiWM>, 64 * kChiWM * kChiWM, 0);
+  else if (dt == GW_C128)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_f64<kChiWM, double>, 64 * kChiWM * kChiWM, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_f64<kChiWM, float>, 64 * kChiWM * kChiWM, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const double conc = (double)per_cu * c->cus;
+  // fraction of the last round of workgroups that does work
+  auto fill = [&](long long b) {
+    const double r = (double)b / conc;
+    return r / std::ceil(r);
+  };
+  int best = 1;
+  double bf = fill(b1);
+  for (int s = 2; s <= 4; ++s) {
+    if (P / s < 1024) break;  // keep each range long against its epilogue and the extra pass
+    const double f = fill(b1 * s);
+    if (f > bf + 0.05) { best = s; bf = f; }
+  }
+  return best;
+}
+
+static int range_len(int P, int split) {
+  int pc = (P + split - 1) / split;
+  return (pc + BK - 1) / BK * BK;  // whole MFMA K steps; the last range is the short one
+}
+
+static gw_status chi0_reduce(gw_ctx* c, int neps, int nfreq, double* chi0, int split,
+                             const double* part) {
+  if (split <= 1) return GW_OK;
+  ProfScope ps(c, "chi0_reduce");
+  const size_t total = (size_t)nfreq * neps * neps;
+  hipLaunchKernelGGL(k_chi0_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
+                     reinterpret_cast<cpx<double>*>(chi0),
+                     reinterpret_cast<const cpx<double>*>(part), split - 1, total);
+  GW_CHECK_LAUNCH(c, "k_chi0_reduce");
+  return GW_OK;
 }
 
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
-                    const double* wts, int skip_head, double* chi0) {
-  constexpr int WM = 2, TMv = 32 * WM;
-  const int nt = (neps + TMv - 1) / TMv;
+                    const double* wts, int skip_head, double* chi0, int split, double* part) {
+  const int nt = (neps + kChiTM - 1) / kChiTM;
   const int ntri = nt * (nt + 1) / 2;
-  ProfScope ps(c, "chi0_fp64");
-  if (dt == GW_C128)
-    hipLaunchKernelGGL((k_chi0_f64<WM, double>), dim3(ntri, nfreq), dim3(64 * WM * WM), 0,
-                       c->stream, static_cast<const cpx<double>*>(mtxel), P, neps, wts,
-                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
-  else
-    hipLaunchKernelGGL((k_chi0_f64<WM, float>), dim3(ntri, nfreq), dim3(64 * WM * WM), 0,
-                       c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts,
-                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
-  GW_CHECK_LAUNCH(c, "k_chi0_f64");
-  return GW_OK;
+  const int pc = range_len(P, split);
+  if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
+    return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
+  {
+    ProfScope ps(c, "chi0_fp64");
+    const dim3 g(ntri, nfreq, split);
+    auto* pp = reinterpret_cast<cpx<double>*>(part);
+    if (dt == GW_C128)
+      hipLaunchKernelGGL((k_chi0_f64<kChiWM, double>), g, dim3(64 * kChiWM * kChiWM), 0, c->stream,
+                         static_cast<const cpx<double>*>(mtxel), P, neps, wts,
+                         reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc, pp);
+    else
+      hipLaunchKernelGGL((k_chi0_f64<kChiWM, float>), g, dim3(64 * kChiWM * kChiWM), 0, c->stream,
+                         static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+                         reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc, pp);
+    GW_CHECK_LAUNCH(c, "k_chi0_f64");
+  }
+  return chi0_reduce(c, neps, nfreq, chi0, split, part);
 }
 
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
-                         const double* wts, int skip_head, double* chi0) {
-  constexpr int WM = 2, TMv = 32 * WM;
-  const int nt = (neps + TMv - 1) / TMv;
+                         const double* wts, int skip_head, double* chi0, int split, double* part) {
+  const int nt = (neps + kChiTM - 1) / kChiTM;
   const int ntri = nt * (nt + 1) / 2;
-  ProfScope ps(c, "chi0_bf16x3");
-  hipLaunchKernelGGL(k_chi0_bf16x3<WM>, dim3(ntri, nfreq), dim3(64 * WM * WM), 0, c->stream,
-                     static_cast<const cpx<float>*>(mtxel), P, neps, wts,
-                     reinterpret_cast<cpx<double>*>(chi0), nt, skip_head);
-  GW_CHECK_LAUNCH(c, "k_chi0_bf16x3");
-  return GW_OK;
+  const int pc = range_len(P, split);
+  if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
+    return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
+  {
+    ProfScope ps(c, "chi0_bf16x3");
+    hipLaunchKernelGGL(k_chi0_bf16x3<kChiWM>, dim3(ntri, nfreq, split), dim3(64 * kChiWM * kChiWM),
+                       0, c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc,
+                       reinterpret_cast<cpx<double>*>(part));
+    GW_CHECK_LAUNCH(c, "k_chi0_bf16x3");
+  }
+  return chi0_reduce(c, neps, nfreq, chi0, split, part);
 }
 
 // ---------------------------------------------------------------- generic ZGEMM

@@ -272,8 +272,14 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
     // >= 1 up to rounding; a pivot below 1/2 or far from the real axis means
     // the input is not of that form and the pivoted path must be used
     if (tid == 0 && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY)) flag[1] = 1;
+    // 1/|p|^2 from the hardware reciprocal and two Newton steps (every thread
+    // computes it, so the full division sequence would dominate the step);
+    // a pivot that fails the check above is replaced on the pivoted path
     const double den = p.x * p.x + p.y * p.y;
-    const cpx<double> pinv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const cpx<double> pinv = (den > 0.0) ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
     cpx<double> rs[TE], cc[TE];
 #pragma unroll
     for (int b = 0; b < TE; ++b) {

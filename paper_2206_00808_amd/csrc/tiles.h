@@ -48,6 +48,17 @@ __device__ __forceinline__ void herm_add(cpx<double>* C, int neps, int i, int j,
   }
 }
 
+// Store a finished tile into a partial-sum matrix: (i,j) gets the value and, off
+// the diagonal, (j,i) its conjugate; the skipped row/column get zeros so that
+// every entry of the matrix is defined.
+__device__ __forceinline__ void herm_store(cpx<double>* C, int neps, int i, int j, double re,
+                                           double im, bool offdiag, int skip_head) {
+  if (i >= neps || j >= neps) return;
+  if (skip_head >= 0 && (i == skip_head || j == skip_head)) re = im = 0.0;
+  C[(size_t)i * neps + j] = mk(re, im);
+  if (offdiag) C[(size_t)j * neps + i] = mk(re, -im);
+}
+
 // ------------------------------------------------------------------ FP64 chi0 tile
 // C[i][j] += sum_p conj(M[p][i]) w[p] M[p][j] for the (TM x TM) tile (ti, tj),
 // TM = 32*WM, WM x WM waves of 32x32 (2x2 blocks of v_mfma_f64_16x16x4_f64).
@@ -58,7 +69,7 @@ template <int WM, typename Tin>
 __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, int P, int neps,
                                               const double* __restrict__ w,
                                               cpx<double>* __restrict__ C, int ti, int tj,
-                                              int skip_head) {
+                                              int skip_head, bool overwrite = false) {
   constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (KT * TMv) / NT, PTv = TMv + 16;
   __shared__ double Ar[KT][PTv], Ai[KT][PTv], Br[KT][PTv], Bi[KT][PTv];
   const int i0 = ti * TMv, j0 = tj * TMv;
@@ -145,9 +156,11 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)  // f64 16x16x4 D layout: row lk + 4r, column l16
-        herm_add(C, neps, i0 + wr * 32 + a * 16 + lk + 4 * r, j0 + wc * 32 + b * 16 + l16,
-                 cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
+      for (int r = 0; r < 4; ++r) {  // f64 16x16x4 D layout: row lk + 4r, column l16
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r, j = j0 + wc * 32 + b * 16 + l16;
+        if (overwrite) herm_store(C, neps, i, j, cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
+        else herm_add(C, neps, i, j, cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
+      }
 }
 
 // ------------------------------------------------------------------ split-BF16 chi0 tile
@@ -158,7 +171,7 @@ template <int WM>
 __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M, int P, int neps,
                                                const double* __restrict__ w,
                                                cpx<double>* __restrict__ C, int ti, int tj,
-                                               int skip_head) {
+                                               int skip_head, bool overwrite = false) {
   constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (BK * TMv) / NT;
   __shared__ __align__(16) unsigned short As[4][TMv][BKP];
   __shared__ __align__(16) unsigned short Bs[4][TMv][BKP];
@@ -273,9 +286,11 @@ __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M,
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)  // f32 16x16x32 D layout: row 4*lk + r, column l16
-        herm_add(C, neps, i0 + wr * 32 + x * 16 + lk * 4 + r, j0 + wc * 32 + y * 16 + l16,
-                 dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+      for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
+        const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
+        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+        else herm_add(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+      }
 }
 
 // ------------------------------------------------------------------ complex-double GEMM tile

@@ -144,6 +144,45 @@ def test_chi0_accumulates_in_chunks(P, ctx):
     assert oracle.rel_f(acc.cpu().numpy(), full.cpu().numpy()) < 1e-14
 
 
+def _split_case(seed, dtype):
+    """Random matrix elements large enough that the library cuts the pair sum
+    into ranges on a full device (12 frequencies x 55 upper tiles, 3200 pairs)."""
+    rng = np.random.default_rng(seed)
+    nv, nc, neps, nf = 16, 200, 600, 12
+    m = (rng.standard_normal((nv, nc, neps)) + 1j * rng.standard_normal((nv, nc, neps))) / np.sqrt(2)
+    m = m.astype(dtype)
+    ev = rng.uniform(-0.44, 0.0, nv)
+    ec = rng.uniform(0.07, 1.5, nc)
+    omega = np.concatenate([[0.0], np.geomspace(0.02, 3.0, nf - 1)])
+    mh = (rng.standard_normal(nv * nc) + 1j * rng.standard_normal(nv * nc)) / np.sqrt(2)
+    return m, ev, ec, omega, mh
+
+
+@pytest.mark.parametrize("prec", ["fp64", "splitbf16"])
+def test_chi0_pair_ranges_and_wings_match_oracle(P, ctx, prec):
+    """Pair-sum ranges, their ordered reduction and the head/wings on top: the
+    wings are the contraction with column h of M replaced by the head overlaps."""
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    m, ev, ec, omega, mh = _split_case(4242, dt)
+    nv, nc, neps = m.shape
+    h = 7
+    mx = m.astype(np.complex128).copy()
+    mx[:, :, h] = mh.reshape(nv, nc)
+    x = oracle.chi0(mx, ev, ec, omega)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    chi = torch.zeros((len(omega), neps, neps), dtype=torch.complex128, device="cuda:0")
+    code = P.GW_PREC_FP64 if prec == "fp64" else P.GW_PREC_SPLITBF16
+    P.gw_chi0_accumulate(ctx, nv, nc, neps, dev(m), dev(ev), dev(ec), omega, 1.0, code, chi,
+                         mhead=dev(mh), head_index=h)
+    torch.cuda.synchronize()
+    got = chi.cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for f in range(len(omega)):
+        assert oracle.rel_f(got[f], x[f]) < tol, (prec, f)
+        # head row and column come from the FP64 wing sums in both precisions
+        assert np.abs(got[f][h] - x[f][h]).max() <= 1e-12 * np.abs(x[f][h]).max(), (prec, f)
+
+
 # ----------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("name", ["C1", "T1", "T2"])
 def test_mixed_path_within_1e4(P, ctx, name):
