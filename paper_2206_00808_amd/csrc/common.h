@@ -83,6 +83,10 @@ struct gw_ctx {
   std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
   int* d_flag = nullptr;                          // device status flags
   bool capturing = false;                         // inside a graph capture: no attribute calls
+  // second stream and events for work that overlaps the main stream (created on
+  // first use; default priority)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // networks and plans created on this context (freed with it)
   std::set<gw_mlp*> mlps;
   std::set<gw_plan*> plans;
@@ -97,6 +101,7 @@ struct gw_ctx {
 namespace gw {
 
 gw_status fail(gw_ctx* c, gw_status s, const char* fmt, ...);
+gw_status side_stream(gw_ctx* c);  // create c->side and its events if needed
 void mlp_free(gw_mlp* n);    // closure.hip: release without touching the context
 void plan_free(gw_plan* p);  // plan.hip
 gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what);
@@ -114,8 +119,9 @@ gw_status twiddle_table(gw_ctx* c, int n, bool dbl, const void** out);
 struct ProfScope {
   gw_ctx* c;
   const char* name;
+  hipStream_t st;  // stream the scope's work runs on (the context's by default)
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(gw_ctx* cc, const char* nm);
+  ProfScope(gw_ctx* cc, const char* nm, hipStream_t s = nullptr);
   ~ProfScope();
 };
 

@@ -233,13 +233,15 @@ __global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* 
 //   other i   <- (row i with 0 at the pivot) - a_it * (new row t)
 // A ragged block is padded with the identity, which leaves the leading
 // nbk x nbk inverse unchanged.
-__global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ A, int N, int k,
-                                                  int nbk, cpx<double>* __restrict__ Dw,
+// The block of frequency f is src[f * sstride + i * ld + j].
+__global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ src, int ld,
+                                                  size_t sstride, int nbk,
+                                                  cpx<double>* __restrict__ Dw,
                                                   int* __restrict__ flag) {
   constexpr int TG = 32, TE = GB / TG;
   __shared__ cpx<double> rowb[2][GB], colb[2][GB];
   const int f = blockIdx.x;
-  A += (size_t)f * N * N;
+  src += (size_t)f * sstride;
   Dw += (size_t)f * GB * GB;
   const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
   cpx<double> d[TE][TE];
@@ -248,8 +250,7 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
 #pragma unroll
     for (int b = 0; b < TE; ++b) {
       const int i = ti + TG * a, j = tj + TG * b;
-      d[a][b] = (i < nbk && j < nbk) ? A[(size_t)(k + i) * N + k + j]
-                                     : mk(i == j ? 1.0 : 0.0, 0.0);
+      d[a][b] = (i < nbk && j < nbk) ? src[(size_t)i * ld + j] : mk(i == j ? 1.0 : 0.0, 0.0);
     }
   for (int t = 0; t < nbk; ++t) {
     const int buf = t & 1, ta = t / TG, tr = t % TG;
@@ -339,6 +340,16 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
   if (e >= nbk * N) return;
   const int t = e / N, j = e % N;
   A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
+}
+
+// Dn[f] = A[f][K'][K'] (the next diagonal block, before this step's update)
+__global__ void k_gj_blkcopy(const cpx<double>* __restrict__ A, int N, int k, int nbk,
+                             cpx<double>* __restrict__ Dn) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nbk * nbk) return;
+  const size_t f = blockIdx.y;
+  const int i = e / nbk, j = e % nbk;
+  Dn[f * GB * GB + (size_t)i * GB + j] = A[f * (size_t)N * N + (size_t)(k + i) * N + k + j];
 }
 
 // eps^-1 = S epst^-1 S^-1, in place.
@@ -458,11 +469,15 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
                                      const double* vcoul, double* epsinv) {
   const size_t nn = (size_t)N * N;
   const size_t nR = (size_t)nfreq * GB * N, nC = (size_t)nfreq * N * GB, nD = (size_t)nfreq * GB * GB;
-  gw_status st = ws_begin(c, align_up(nR * 16) + align_up(nC * 16) + align_up(nD * 16));
+  gw_status st = side_stream(c);
+  if (st != GW_OK) return st;
+  st = ws_begin(c, align_up(nR * 16) + align_up(nC * 16) + 3 * align_up(nD * 16));
   if (st != GW_OK) return st;
   cpx<double>* R = static_cast<cpx<double>*>(ws_take(c, nR * 16));
   cpx<double>* Cb = static_cast<cpx<double>*>(ws_take(c, nC * 16));
-  cpx<double>* Dw = static_cast<cpx<double>*>(ws_take(c, nD * 16));
+  cpx<double>* Dw[2] = {static_cast<cpx<double>*>(ws_take(c, nD * 16)),
+                        static_cast<cpx<double>*>(ws_take(c, nD * 16))};
+  cpx<double>* Dn = static_cast<cpx<double>*>(ws_take(c, nD * 16));
   cpx<double>* A = reinterpret_cast<cpx<double>*>(epsinv);
   const double* Ad = epsinv;
   {
@@ -477,25 +492,52 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
                        c->d_flag);
     GW_CHECK_LAUNCH(c, "k_epst_build");
   }
+  {
+    ProfScope ps(c, "gj_diag");
+    hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->stream, A, N, nn,
+                       std::min(GB, N), Dw[0], c->d_flag);
+    GW_CHECK_LAUNCH(c, "k_gj_diag");
+  }
   const size_t ext = (size_t)nfreq * nn;
-  for (int k = 0; k < N; k += GB) {
+  // Look-ahead: once the row panel of step K exists, the next diagonal block's
+  // updated value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed and inverted on the
+  // side stream while the main stream runs the full rank update of step K.
+  for (int k = 0, s = 0; k < N; k += GB, ++s) {
     const int nbk = std::min(GB, N - k);
-    {
-      ProfScope ps(c, "gj_diag");
-      hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->stream, A, N, k, nbk, Dw,
-                         c->d_flag);
-      GW_CHECK_LAUNCH(c, "k_gj_diag");
-    }
+    cpx<double>* D = Dw[s & 1];
     // R = Dinv A[K][:] (rows nbk.. of R are never read)
-    st = zgemm_nn(c, nbk, N, nbk, 1.0, reinterpret_cast<const double*>(Dw), 0, GB, GB * GB, Ad,
+    st = zgemm_nn(c, nbk, N, nbk, 1.0, reinterpret_cast<const double*>(D), 0, GB, GB * GB, Ad,
                   (size_t)k * N, N, (long long)nn, reinterpret_cast<double*>(R), 0, N,
                   (long long)GB * N, nfreq, nD, ext, nR, 0.0);
     if (st != GW_OK) return st;
     {
       ProfScope ps(c, "gj_small");
       hipLaunchKernelGGL(k_gj_prep, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
-                         A, N, k, nbk, Cb, R, Dw);
+                         A, N, k, nbk, Cb, R, D);
       GW_CHECK_LAUNCH(c, "k_gj_prep");
+    }
+    const int k2 = k + GB, nb2 = std::min(GB, N - k2);
+    if (nb2 > 0) {
+      {
+        ProfScope ps(c, "gj_small");
+        hipLaunchKernelGGL(k_gj_blkcopy, dim3((nb2 * nb2 + 255) / 256, nfreq), dim3(256), 0,
+                           c->stream, A, N, k2, nb2, Dn);
+        GW_CHECK_LAUNCH(c, "k_gj_blkcopy");
+      }
+      st = zgemm_nn(c, nb2, nb2, nbk, -1.0, reinterpret_cast<const double*>(Cb), (size_t)k2 * GB,
+                    GB, (long long)N * GB, reinterpret_cast<const double*>(R), (size_t)k2, N,
+                    (long long)GB * N, reinterpret_cast<double*>(Dn), 0, GB, (long long)GB * GB,
+                    nfreq, nC, nR, nD, 1.0);
+      if (st != GW_OK) return st;
+      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      {
+        ProfScope ps(c, "gj_diag", c->side);
+        hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->side, Dn, GB,
+                           (size_t)GB * GB, nb2, Dw[(s + 1) & 1], c->d_flag);
+        GW_CHECK_LAUNCH(c, "k_gj_diag");
+      }
+      GW_HIP(c, hipEventRecord(c->ev_join, c->side));
     }
     // A -= Cb R over the whole matrix: every row outside K is final, including
     // its K columns; row block K is rewritten next
@@ -506,9 +548,11 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
     {
       ProfScope ps(c, "gj_small");
       hipLaunchKernelGGL(k_gj_fix, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
-                         A, N, k, nbk, R, Dw);
+                         A, N, k, nbk, R, D);
       GW_CHECK_LAUNCH(c, "k_gj_fix");
     }
+    // the next step reads the inverse made on the side stream, and reuses Dn
+    if (nb2 > 0) GW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   }
   {
     ProfScope ps(c, "eps_unscale");

@@ -295,10 +295,13 @@ __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M,
 
 // ------------------------------------------------------------------ complex-double GEMM tile
 // C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
-// (i0, j0), 256 threads (beta is 0 or 1: with 0, C is only written). K advances
-// in slabs of KT through two LDS buffers. The next slab is loaded into
-// registers while the current one feeds the MFMAs, so there is one barrier per
-// slab.
+// (i0, j0), 256 threads (beta is 0 or 1).
+//   - With beta 1 the accumulators start from C, loaded before the first slab,
+//     so reading C overlaps the slab loads and the epilogue is a plain store.
+//   - alpha scales A as it is staged in LDS.
+//   - K advances in slabs of KT through two LDS buffers; the next slab is
+//     loaded into registers while the current one feeds the MFMAs, so there
+//     is one barrier per slab.
 constexpr int ZTM = 64, ZLP = ZTM + 1;
 __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha, double beta,
                                            const cpx<double>* __restrict__ A, int lda,
@@ -314,10 +317,15 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cr[a][b] = (d4){0, 0, 0, 0};
-      ci[a][b] = (d4){0, 0, 0, 0};
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // f64 16x16x4 D layout: row lk + 4r, column l16
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r, j = j0 + wc * 32 + b * 16 + l16;
+        cpx<double> v = mk(0.0, 0.0);
+        if (beta != 0.0 && i < m && j < n) v = C[(size_t)i * ldc + j];
+        cr[a][b][r] = v.x;
+        ci[a][b][r] = v.y;
+      }
   cpx<double> ra[PER], rb[PER];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -338,7 +346,7 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = tid + e * 256;
-      As[buf][idx % KT][idx / KT] = ra[e];
+      As[buf][idx % KT][idx / KT] = scal(ra[e], alpha);
       Bs[buf][idx / ZTM][idx % ZTM] = rb[e];
     }
     __syncthreads();
@@ -383,14 +391,9 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;  // f64 16x16x4 D layout
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;
         const int j = j0 + wc * 32 + b * 16 + l16;
-        if (i >= m || j >= n) continue;
-        cpx<double>* d = C + (size_t)i * ldc + j;
-        if (beta != 0.0)
-          *d = mk(beta * d->x + alpha * cr[a][b][r], beta * d->y + alpha * ci[a][b][r]);
-        else
-          *d = mk(alpha * cr[a][b][r], alpha * ci[a][b][r]);
+        if (i < m && j < n) C[(size_t)i * ldc + j] = mk(cr[a][b][r], ci[a][b][r]);
       }
 }
 
