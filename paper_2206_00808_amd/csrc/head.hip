@@ -67,29 +67,41 @@ gw_status head_overlap(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int ngv, con
 }
 
 // chi0[f][h][j] += sum_p conj(mh_p) w_f(p) X_p(j), X_p(j) = M_p(j) (j != h) or mh_p (j = h);
-// chi0[f][j][h] += the conjugate for j != h.  One thread per column j.
+// chi0[f][j][h] += the conjugate for j != h. A block takes kWingCols columns; its
+// kWingSlices thread rows split the pair sum and are added in a fixed order.
+constexpr int kWingCols = 32, kWingSlices = 8;
 template <typename Tin>
-__global__ void __launch_bounds__(256) k_wings(const cpx<Tin>* __restrict__ M, int P, int neps,
-                                               const cpx<double>* __restrict__ mh, int h,
-                                               const double* __restrict__ wts,
-                                               cpx<double>* __restrict__ chi) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kWingCols * kWingSlices) k_wings(
+    const cpx<Tin>* __restrict__ M, int P, int neps, const cpx<double>* __restrict__ mh, int h,
+    const double* __restrict__ wts, cpx<double>* __restrict__ chi) {
+  __shared__ double red[kWingSlices][kWingCols][2];
+  const int cl = threadIdx.x % kWingCols, r = threadIdx.x / kWingCols;
+  const int j = blockIdx.x * kWingCols + cl;
   const int f = blockIdx.y;
-  if (j >= neps) return;
   const double* w = wts + (size_t)f * P;
   double sr = 0.0, si = 0.0;
-  for (int p = 0; p < P; ++p) {
-    const cpx<double> a = mh[p];
-    double xr, xi;
-    if (j == h) {
-      xr = a.x; xi = a.y;
-    } else {
-      const cpx<Tin> m = M[(size_t)p * neps + j];
-      xr = m.x; xi = m.y;
+  if (j < neps) {
+    for (int p = r; p < P; p += kWingSlices) {
+      const cpx<double> a = mh[p];
+      double xr, xi;
+      if (j == h) {
+        xr = a.x; xi = a.y;
+      } else {
+        const cpx<Tin> m = M[(size_t)p * neps + j];
+        xr = m.x; xi = m.y;
+      }
+      const double wp = w[p];
+      sr += wp * (a.x * xr + a.y * xi);
+      si += wp * (a.x * xi - a.y * xr);
     }
-    const double wp = w[p];
-    sr += wp * (a.x * xr + a.y * xi);
-    si += wp * (a.x * xi - a.y * xr);
+  }
+  red[r][cl][0] = sr;
+  red[r][cl][1] = si;
+  __syncthreads();
+  if (r != 0 || j >= neps) return;
+  for (int q = 1; q < kWingSlices; ++q) {
+    sr += red[q][cl][0];
+    si += red[q][cl][1];
   }
   cpx<double>* C = chi + (size_t)f * neps * neps;
   cpx<double>* d = C + (size_t)h * neps + j;
@@ -103,14 +115,14 @@ __global__ void __launch_bounds__(256) k_wings(const cpx<Tin>* __restrict__ M, i
 gw_status chi0_wings(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt,
                      const double* mhead, int head, int nfreq, const double* wts, double* chi0) {
   ProfScope ps(c, "chi0_wings");
-  dim3 g((neps + 255) / 256, nfreq);
+  dim3 g((neps + kWingCols - 1) / kWingCols, nfreq);
   if (dt == GW_C128)
-    hipLaunchKernelGGL(k_wings<double>, g, dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_wings<double>, g, dim3(kWingCols * kWingSlices), 0, c->stream,
                        static_cast<const cpx<double>*>(mtxel), P, neps,
                        reinterpret_cast<const cpx<double>*>(mhead), head, wts,
                        reinterpret_cast<cpx<double>*>(chi0));
   else
-    hipLaunchKernelGGL(k_wings<float>, g, dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_wings<float>, g, dim3(kWingCols * kWingSlices), 0, c->stream,
                        static_cast<const cpx<float>*>(mtxel), P, neps,
                        reinterpret_cast<const cpx<double>*>(mhead), head, wts,
                        reinterpret_cast<cpx<double>*>(chi0));

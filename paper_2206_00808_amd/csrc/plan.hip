@@ -41,13 +41,13 @@ struct GjM {
   cpx<double>* A;          // eps~ in place, then eps^-1 (the caller's epsinv slice)
   const cpx<double>* chi;  // chi0 slice
   const double* v;         // v(q+G)
-  cpx<double>* R;          // [32][N]
-  cpx<double>* Cb;         // [N][32]
-  cpx<double>* D;          // [32][32]
+  cpx<double>* R;          // [PB][N]
+  cpx<double>* Cb;         // [N][PB]
+  cpx<double>* D;          // [PB][PB]
   int N, pad;
 };
 
-constexpr int PB = 32;  // Gauss-Jordan block width of the batched inversion
+constexpr int PB = 64;  // Gauss-Jordan block width of the batched inversion
 
 // ------------------------------------------------------------------ batched contraction
 template <int WM, int BF16, typename Tin>
@@ -92,54 +92,88 @@ __global__ void k_gjb_build(const GjM* __restrict__ ms, int* __restrict__ flags)
   m.A[idx] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
 }
 
+// Inverse of the diagonal block, register resident and branch free, as in the
+// single-matrix inversion: thread (ti, tj) of a 32x32 grid holds entries
+// (ti + 32a, tj + 32b); each step publishes the pivot row and column through
+// double-buffered LDS; a ragged block is padded with the identity.
 __global__ void __launch_bounds__(1024) k_gjb_diag(const GjM* __restrict__ ms, int k,
                                                    int* __restrict__ flags) {
+  constexpr int TG = 32, TE = PB / TG;
   const GjM m = ms[blockIdx.x];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
-  __shared__ cpx<double> D[PB][PB + 1];
-  __shared__ cpx<double> piv;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
-    const int r = e / nbk, cc = e % nbk;
-    D[r][cc] = m.A[(size_t)(k + r) * N + k + cc];
-  }
-  __syncthreads();
+  __shared__ cpx<double> rowb[2][PB], colb[2][PB];
+  const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
+  cpx<double> d[TE][TE];
+#pragma unroll
+  for (int a = 0; a < TE; ++a)
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int i = ti + TG * a, j = tj + TG * b;
+      d[a][b] = (i < nbk && j < nbk) ? m.A[(size_t)(k + i) * N + k + j]
+                                     : mk(i == j ? 1.0 : 0.0, 0.0);
+    }
   for (int t = 0; t < nbk; ++t) {
-    if (tid == 0) {
-      const cpx<double> p = D[t][t];
-      const bool ok = p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY;
-      if (!ok) flags[blockIdx.x] = 1;
-      const double den = p.x * p.x + p.y * p.y;
-      piv = (den > 0.0) ? mk(p.x / den, -p.y / den) : mk(0.0, 0.0);
+    const int buf = t & 1, ta = t / TG, tr = t % TG;
+#pragma unroll
+    for (int q = 0; q < TE; ++q) {
+      if (ti == tr && ta == q) {
+#pragma unroll
+        for (int b = 0; b < TE; ++b) rowb[buf][tj + TG * b] = d[q][b];
+      }
+      if (tj == tr && ta == q) {
+#pragma unroll
+        for (int a = 0; a < TE; ++a) colb[buf][ti + TG * a] = d[a][q];
+      }
     }
     __syncthreads();
-    const cpx<double> pinv = piv;
-    cpx<double> rowt = mk(0.0, 0.0), colt = mk(0.0, 0.0);
-    const int i = tid / PB, j = tid % PB;
-    const bool act = tid < PB * PB && i < nbk && j < nbk;
-    if (act) {
-      rowt = cmul(D[t][j], pinv);
-      colt = D[i][t];
+    const cpx<double> p = rowb[buf][t];
+    if (tid == 0 && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY))
+      flags[blockIdx.x] = 1;
+    const double den = p.x * p.x + p.y * p.y;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const cpx<double> pinv = (den > 0.0) ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
+    cpx<double> rs[TE], cc[TE];
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int j = tj + TG * b;
+      rs[b] = (j == t) ? pinv : cmul(rowb[buf][j], pinv);
     }
-    __syncthreads();
-    if (act) {
-      if (i == t && j == t) D[i][j] = pinv;
-      else if (i == t) D[i][j] = rowt;
-      else if (j == t) D[i][j] = mk(-(colt.x * pinv.x - colt.y * pinv.y),
-                                   -(colt.x * pinv.y + colt.y * pinv.x));
-      else D[i][j] = D[i][j] - cmul(colt, rowt);
-    }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < TE; ++a) cc[a] = colb[buf][ti + TG * a];
+#pragma unroll
+    for (int a = 0; a < TE; ++a)
+#pragma unroll
+      for (int b = 0; b < TE; ++b) {
+        const int i = ti + TG * a, j = tj + TG * b;
+        const cpx<double> dd = (j == t) ? mk(0.0, 0.0) : d[a][b];
+        d[a][b] = (i == t) ? rs[b] : dd - cmul(cc[a], rs[b]);
+      }
   }
-  for (int e = tid; e < nbk * nbk; e += blockDim.x) {
-    const int r = e / nbk, cc = e % nbk;
-    m.D[r * PB + cc] = D[r][cc];
-  }
+#pragma unroll
+  for (int a = 0; a < TE; ++a)
+#pragma unroll
+    for (int b = 0; b < TE; ++b) {
+      const int i = ti + TG * a, j = tj + TG * b;
+      if (i < nbk && j < nbk) m.D[i * PB + j] = d[a][b];
+    }
 }
 
-// Cb = A[:, K]; R = Dinv A[K, :]
-__global__ void k_gjb_panels(const GjM* __restrict__ ms, int k) {
+// R = Dinv A[K, :] (rows nbk.. of R are never read)
+__global__ void __launch_bounds__(256) k_gjb_rpanel(const GjM* __restrict__ ms, int k) {
+  const GjM m = ms[blockIdx.z];
+  if (k >= m.N) return;
+  const int N = m.N, nbk = min(PB, N - k);
+  const int j0 = blockIdx.x * ZTM;
+  if (j0 >= N) return;
+  zgemm_tile(nbk, N, nbk, 1.0, 0.0, m.D, PB, m.A + (size_t)k * N, N, m.R, N, 0, j0);
+}
+
+// Cb = A[:, K]; R[:, K] = I + Dinv, so that A - Cb R leaves -Cb Dinv in the
+// column block (its Gauss-Jordan value)
+__global__ void k_gjb_prep(const GjM* __restrict__ ms, int k) {
   const GjM m = ms[blockIdx.y];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
@@ -148,11 +182,10 @@ __global__ void k_gjb_panels(const GjM* __restrict__ ms, int k) {
     const int i = e / nbk, t = e % nbk;
     m.Cb[(size_t)i * PB + t] = m.A[(size_t)i * N + k + t];
   }
-  if (e < nbk * N) {
-    const int t = e / N, j = e % N;
-    cpx<double> s = mk(0.0, 0.0);
-    for (int u = 0; u < nbk; ++u) s = s + cmul(m.D[t * PB + u], m.A[(size_t)(k + u) * N + j]);
-    m.R[(size_t)t * N + j] = s;
+  if (e < nbk * nbk) {
+    const int t = e / nbk, j = e % nbk;
+    const cpx<double> dv = m.D[t * PB + j];
+    m.R[(size_t)t * N + k + j] = mk(dv.x + (t == j ? 1.0 : 0.0), dv.y);
   }
 }
 
@@ -166,25 +199,16 @@ __global__ void __launch_bounds__(256) k_gjb_update(const GjM* __restrict__ ms, 
   zgemm_tile(N, N, nbk, -1.0, 1.0, m.Cb, PB, m.R, N, m.A, N, i0, j0);
 }
 
-// row block K <- R, diagonal block <- Dinv, column block outside K <- -Cb Dinv
+// row block K <- R outside the K columns and Dinv inside
 __global__ void k_gjb_fix(const GjM* __restrict__ ms, int k) {
   const GjM m = ms[blockIdx.y];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nbk * N) {
-    const int t = e / N, j = e % N;
-    m.A[(size_t)(k + t) * N + j] =
-        (j >= k && j < k + nbk) ? m.D[t * PB + (j - k)] : m.R[(size_t)t * N + j];
-    return;
-  }
-  const int e2 = e - nbk * N;
-  if (e2 >= N * nbk) return;
-  const int i = e2 / nbk, t = e2 % nbk;
-  if (i >= k && i < k + nbk) return;
-  cpx<double> s = mk(0.0, 0.0);
-  for (int u = 0; u < nbk; ++u) s = s + cmul(m.Cb[(size_t)i * PB + u], m.D[u * PB + t]);
-  m.A[(size_t)i * N + k + t] = mk(-s.x, -s.y);
+  if (e >= nbk * N) return;
+  const int t = e / N, j = e % N;
+  m.A[(size_t)(k + t) * N + j] =
+      (j >= k && j < k + nbk) ? m.D[t * PB + (j - k)] : m.R[(size_t)t * N + j];
 }
 
 __global__ void k_gjb_unscale(const GjM* __restrict__ ms) {
@@ -419,9 +443,12 @@ static gw_status enqueue_back(gw_plan* p) {
       hipLaunchKernelGGL(k_gjb_diag, dim3(p->nmat), dim3(1024), 0, c->stream, p->d_gj, k,
                          p->d_flags);
       GW_CHECK_LAUNCH(c, "k_gjb_diag");
-      hipLaunchKernelGGL(k_gjb_panels, dim3((PB * p->nmax + 255) / 256, p->nmat), dim3(256), 0,
+      hipLaunchKernelGGL(k_gjb_rpanel, dim3(tiles, 1, p->nmat), dim3(256), 0, c->stream,
+                         p->d_gj, k);
+      GW_CHECK_LAUNCH(c, "k_gjb_rpanel");
+      hipLaunchKernelGGL(k_gjb_prep, dim3((PB * p->nmax + 255) / 256, p->nmat), dim3(256), 0,
                          c->stream, p->d_gj, k);
-      GW_CHECK_LAUNCH(c, "k_gjb_panels");
+      GW_CHECK_LAUNCH(c, "k_gjb_prep");
     }
     {
       ProfScope ps(c, "plan_gj_update");
@@ -431,7 +458,7 @@ static gw_status enqueue_back(gw_plan* p) {
     }
     {
       ProfScope ps(c, "plan_gj_small");
-      hipLaunchKernelGGL(k_gjb_fix, dim3((2 * PB * p->nmax + 255) / 256, p->nmat), dim3(256), 0,
+      hipLaunchKernelGGL(k_gjb_fix, dim3((PB * p->nmax + 255) / 256, p->nmat), dim3(256), 0,
                          c->stream, p->d_gj, k);
       GW_CHECK_LAUNCH(c, "k_gjb_fix");
     }
