@@ -86,9 +86,10 @@ def measured_traffic(kernel, config):
     rec = json.load(open(path)).get(kernel)
     if rec is None:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
+    for src, digest in rec["sources"].items():
+        path = os.path.join(ROOT, src)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
     kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + \
         rec["write_kib_per_dispatch"] * rec["write_scale"]
     return kib * 1024.0
