@@ -390,19 +390,21 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
   const bool use_head = mhead != nullptr && head_index >= 0;
   const int split = chi0_split(c, P, neps, nfreq, prec, dtype);
   const size_t part_bytes = (size_t)(split - 1) * nfreq * neps * neps * 16;
+  const size_t xs_bytes = prec == GW_PREC_SPLITBF16 ? bf16_split_bytes(P, neps, nfreq) : 0;
   gw_status st = ws_begin(c, align_up((size_t)nfreq * 8) + align_up((size_t)nfreq * P * 8) +
-                                 align_up(part_bytes));
+                                 align_up(part_bytes) + align_up(xs_bytes));
   if (st != GW_OK) return st;
   double* d_om = static_cast<double*>(ws_take(c, (size_t)nfreq * 8));
   double* wts = static_cast<double*>(ws_take(c, (size_t)nfreq * P * 8));
   double* part = part_bytes ? static_cast<double*>(ws_take(c, part_bytes)) : nullptr;
+  void* xsplit = xs_bytes ? ws_take(c, xs_bytes) : nullptr;
   GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
   if ((st = chi0_weights(c, nv, nc, ev, ec, nfreq, d_om, prefactor, wts)) != GW_OK) return st;
   const int skip = use_head ? head_index : -1;
   if (prec == GW_PREC_FP64)
     st = chi0_fp64(c, P, neps, mtxel, dtype, nfreq, wts, skip, chi0, split, part);
   else
-    st = chi0_splitbf16(c, P, neps, mtxel, nfreq, wts, skip, chi0, split, part);
+    st = chi0_splitbf16(c, P, neps, mtxel, nfreq, wts, skip, chi0, split, part, xsplit);
   if (st != GW_OK) return st;
   if (use_head) {
     if ((st = chi0_wings(c, P, neps, mtxel, dtype, mhead, head_index, nfreq, wts, chi0)) != GW_OK)

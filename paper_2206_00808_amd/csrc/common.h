@@ -165,8 +165,12 @@ gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double
 int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt);
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
                     const double* wts, int skip_head, double* chi0, int split, double* part);
+// The split-BF16 contraction first splits its operands into `xsplit`
+// (bf16_split_bytes(P, neps, nfreq) bytes of device workspace).
+size_t bf16_split_bytes(int P, int neps, int nfreq);
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
-                         const double* wts, int skip_head, double* chi0, int split, double* part);
+                         const double* wts, int skip_head, double* chi0, int split, double* part,
+                         void* xsplit);
 // generic batched C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] (complex
 // double, row-major, beta 0 or 1); offsets, leading dimensions, batch strides and
 // extents in complex elements

@@ -59,23 +59,67 @@ __global__ void __launch_bounds__(64 * WM * WM) k_chi0_f64(const cpx<Tin>* __res
                            part + ((size_t)(s - 1) * nf + f) * nn, ti, tj, skip_head, true);
 }
 
+// Split the contraction operands once: X_0 = M and X_{1+f} = w_f * M (the
+// product taken in float), each component x as hi = bf16_rn(x) and
+// lo = bf16_rn(x - hi). Output layout X_o[pb][q][G][32] (see chi0_bf16s_tile),
+// zero past P. A block takes 32 pairs x 64 columns of one output through LDS,
+// so that both the reads of M and the writes are contiguous; each thread forms
+// 8 values of one column and writes all four planes of them.
+__global__ void __launch_bounds__(256) k_bf16_split(const cpx<float>* __restrict__ M, int P,
+                                                    int neps, const double* __restrict__ wts,
+                                                    unsigned short* __restrict__ X) {
+  __shared__ cpx<float> Ms[BK][64 + 1];
+  __shared__ float Wsh[BK];
+  typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+  const int pb = blockIdx.x, Pb = gridDim.x, g0 = blockIdx.y * 64, o = blockIdx.z;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BK * 64; e += 256) {
+    const int k = e / 64, g = e % 64, p = pb * BK + k;
+    Ms[k][g] = (p < P && g0 + g < neps) ? M[(size_t)p * neps + g0 + g] : mk(0.f, 0.f);
+  }
+  if (tid < BK) {
+    const int p = pb * BK + tid;
+    Wsh[tid] = (o == 0) ? 1.f : (p < P ? (float)wts[(size_t)(o - 1) * P + p] : 0.f);
+  }
+  __syncthreads();
+  const int row = tid / 4, kc = tid % 4, g = g0 + row;
+  if (g >= neps) return;
+  us8 v[4];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int k = kc * 8 + t;
+    const cpx<float> m = Ms[k][row];
+    const float xr = Wsh[k] * m.x, xi = Wsh[k] * m.y;
+    const unsigned short hr = bf16_rn_bits(xr), hi = bf16_rn_bits(xi);
+    v[0][t] = hr;
+    v[1][t] = bf16_rn_bits(xr - bf16_to_f(hr));
+    v[2][t] = hi;
+    v[3][t] = bf16_rn_bits(xi - bf16_to_f(hi));
+  }
+  unsigned short* Xo = X + (size_t)o * Pb * 4 * neps * BK;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    *reinterpret_cast<us8*>(Xo + (((size_t)pb * 4 + q) * neps + g) * BK + kc * 8) = v[q];
+}
+
+// Range s of the pair blocks of frequency f, from the pre-split operands.
 template <int WM>
-__global__ void __launch_bounds__(64 * WM * WM) k_chi0_bf16x3(const cpx<float>* __restrict__ M,
-                                                              int P, int neps,
-                                                              const double* __restrict__ wts,
-                                                              cpx<double>* __restrict__ chi,
-                                                              int nt, int skip_head, int pc,
-                                                              cpx<double>* __restrict__ part) {
+__global__ void __launch_bounds__(64 * WM * WM) k_chi0_bf16s(const unsigned short* __restrict__ X,
+                                                             int Pb, int neps,
+                                                             cpx<double>* __restrict__ chi, int nt,
+                                                             int skip_head, int pbc,
+                                                             cpx<double>* __restrict__ part) {
   int ti, tj;
   tri_tile(blockIdx.x, nt, &ti, &tj);
   const int f = blockIdx.y, s = blockIdx.z, nf = gridDim.y;
-  const int p0 = s * pc, np = min(P, p0 + pc) - p0;
-  const size_t nn = (size_t)neps * neps;
+  const int pb0 = s * pbc, npb = min(Pb, pb0 + pbc) - pb0;
+  const size_t nn = (size_t)neps * neps, osz = (size_t)Pb * 4 * neps * BK;
+  const unsigned short* XB = X + (size_t)(1 + f) * osz;
   if (s == 0)
-    chi0_bf16_tile<WM>(M, np, neps, wts + (size_t)f * P, chi + (size_t)f * nn, ti, tj, skip_head);
+    chi0_bf16s_tile<WM>(X, XB, pb0, npb, neps, chi + (size_t)f * nn, ti, tj, skip_head, false);
   else
-    chi0_bf16_tile<WM>(M + (size_t)p0 * neps, np, neps, wts + (size_t)f * P + p0,
-                       part + ((size_t)(s - 1) * nf + f) * nn, ti, tj, skip_head, true);
+    chi0_bf16s_tile<WM>(X, XB, pb0, npb, neps, part + ((size_t)(s - 1) * nf + f) * nn, ti, tj,
+                        skip_head, true);
 }
 
 // chi0 += part[0] + part[1] + ... (fixed order, so the result does not depend on
@@ -97,7 +141,7 @@ int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt)
   int per_cu = 0;
   hipError_t e;
   if (prec == GW_PREC_SPLITBF16)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_bf16x3<kChiWM>, 64 * kChiWM * kChiWM, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_bf16s<kChiWM>, 64 * kChiWM * kChiWM, 0);
   else if (dt == GW_C128)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_f64<kChiWM, double>, 64 * kChiWM * kChiWM, 0);
   else
@@ -160,20 +204,32 @@ gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, 
   return chi0_reduce(c, neps, nfreq, chi0, split, part);
 }
 
+size_t bf16_split_bytes(int P, int neps, int nfreq) {
+  const size_t Pb = (size_t)(P + BK - 1) / BK;
+  return (size_t)(1 + nfreq) * Pb * 4 * neps * BK * sizeof(unsigned short);
+}
+
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
-                         const double* wts, int skip_head, double* chi0, int split, double* part) {
+                         const double* wts, int skip_head, double* chi0, int split, double* part,
+                         void* xsplit) {
   const int nt = (neps + kChiTM - 1) / kChiTM;
   const int ntri = nt * (nt + 1) / 2;
-  const int pc = range_len(P, split);
+  const int pc = range_len(P, split), Pb = (P + BK - 1) / BK;
   if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
     return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
+  auto* X = static_cast<unsigned short*>(xsplit);
+  {
+    ProfScope ps(c, "bf16_split");
+    hipLaunchKernelGGL(k_bf16_split, dim3(Pb, (neps + 63) / 64, 1 + nfreq), dim3(256), 0,
+                       c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts, X);
+    GW_CHECK_LAUNCH(c, "k_bf16_split");
+  }
   {
     ProfScope ps(c, "chi0_bf16x3");
-    hipLaunchKernelGGL(k_chi0_bf16x3<kChiWM>, dim3(ntri, nfreq, split), dim3(64 * kChiWM * kChiWM),
-                       0, c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts,
-                       reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc,
-                       reinterpret_cast<cpx<double>*>(part));
-    GW_CHECK_LAUNCH(c, "k_chi0_bf16x3");
+    hipLaunchKernelGGL(k_chi0_bf16s<kChiWM>, dim3(ntri, nfreq, split), dim3(64 * kChiWM * kChiWM),
+                       0, c->stream, X, Pb, neps, reinterpret_cast<cpx<double>*>(chi0), nt,
+                       skip_head, pc / BK, reinterpret_cast<cpx<double>*>(part));
+    GW_CHECK_LAUNCH(c, "k_chi0_bf16s");
   }
   return chi0_reduce(c, neps, nfreq, chi0, split, part);
 }

@@ -293,6 +293,128 @@ __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M,
       }
 }
 
+// ------------------------------------------------------------------ split-BF16 chi0 tile, pre-split operands
+// The same contraction with the operands split once in advance (k_bf16_split):
+// X[pb][q][G][32] holds, for pair block pb (32 pairs, zero-padded past P) and
+// plane q = (re hi, re lo, im hi, im lo), the bf16 bits of column G. A slab is
+// then a contiguous 4 KiB per plane and is staged with 16-byte loads and LDS
+// stores, leaving the VALU free for the MFMA issue. The arithmetic is the
+// split-on-the-fly tile's, so the two give identical results.
+template <int WM>
+__device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict__ XA,
+                                                const unsigned short* __restrict__ XB, int pb0,
+                                                int npb, int neps, cpx<double>* __restrict__ C,
+                                                int ti, int tj, int skip_head, bool overwrite) {
+  constexpr int TMv = 32 * WM, NT = 64 * WM * WM;
+  constexpr int CH = 4 * TMv * (BK / 8);  // 16-byte chunks per operand slab
+  constexpr int NE = CH / NT;
+  static_assert(CH % NT == 0, "whole chunks per thread");
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  __shared__ __align__(16) unsigned short As[4][TMv][BKP];
+  __shared__ __align__(16) unsigned short Bs[4][TMv][BKP];
+  const int i0 = ti * TMv, j0 = tj * TMv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WM, wc = wave % WM;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double dr[2][2][4], di[2][2][4];
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
+    }
+  int since_flush = 0;
+  u4 ra[NE], rb[NE];
+  auto gload = [&](int pb) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int c = tid + e * NT;
+      const int q = c / (TMv * 4), row = (c / 4) % TMv, kc = c % 4;
+      const size_t base = ((size_t)pb * 4 + q) * neps;
+      ra[e] = *reinterpret_cast<const u4*>(XA + (base + min(i0 + row, neps - 1)) * BK + kc * 8);
+      rb[e] = *reinterpret_cast<const u4*>(XB + (base + min(j0 + row, neps - 1)) * BK + kc * 8);
+    }
+  };
+  gload(pb0);
+  for (int pb = pb0; pb < pb0 + npb; ++pb) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int c = tid + e * NT;
+      const int q = c / (TMv * 4), row = (c / 4) % TMv, kc = c % 4;
+      *reinterpret_cast<u4*>(&As[q][row][kc * 8]) = ra[e];
+      *reinterpret_cast<u4*>(&Bs[q][row][kc * 8]) = rb[e];
+    }
+    __syncthreads();
+    if (pb + 1 < pb0 + npb) gload(pb + 1);
+    bf8 a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[x][q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + x * 16 + l16][lk * 8]);
+        b[x][q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + x * 16 + l16][lk * 8]);
+      }
+    // the fragments are in registers: the slab may be restaged after this point
+    __syncthreads();
+    bf8 na[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 t = __builtin_bit_cast(us8, a[x][2 + q]);
+        t ^= (us8)(0x8000);
+        na[x][q] = __builtin_bit_cast(bf8, t);
+      }
+#define GW_MF(ACC, A, B)                                                      \
+  _Pragma("unroll") for (int x = 0; x < 2; ++x) _Pragma("unroll") for (int y = 0; y < 2; ++y) \
+      ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, ACC[x][y], 0, 0, 0);
+    GW_MF(cr, a[x][0], b[y][0])
+    GW_MF(ci, a[x][0], b[y][2])
+    GW_MF(cr, a[x][0], b[y][1])
+    GW_MF(ci, a[x][0], b[y][3])
+    GW_MF(cr, a[x][1], b[y][0])
+    GW_MF(ci, a[x][1], b[y][2])
+    GW_MF(cr, a[x][2], b[y][2])
+    GW_MF(ci, na[x][0], b[y][0])
+    GW_MF(cr, a[x][2], b[y][3])
+    GW_MF(ci, na[x][0], b[y][1])
+    GW_MF(cr, a[x][3], b[y][2])
+    GW_MF(ci, na[x][1], b[y][0])
+#undef GW_MF
+    since_flush += BK;
+    if (since_flush >= KFLUSH || pb + 1 >= pb0 + npb) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dr[x][y][r] += (double)cr[x][y][r];
+            di[x][y][r] += (double)ci[x][y][r];
+          }
+          cr[x][y] = (f4){0, 0, 0, 0};
+          ci[x][y] = (f4){0, 0, 0, 0};
+        }
+      since_flush = 0;
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
+        const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
+        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+        else herm_add(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+      }
+}
+
 // ------------------------------------------------------------------ complex-double GEMM tile
 // C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
 // (i0, j0), 256 threads (beta is 0 or 1).
