@@ -51,7 +51,7 @@ constexpr int PB = 64;  // Gauss-Jordan block width of the batched inversion
 
 // ------------------------------------------------------------------ batched contraction
 template <int WM, int BF16, typename Tin>
-__global__ void __launch_bounds__(64 * WM * WM) k_chi0_items(const ChiQ* __restrict__ qs,
+__global__ void __launch_bounds__(64 * WM * WM, WM == 2 ? 2 : 1) k_chi0_items(const ChiQ* __restrict__ qs,
                                                              const int4* __restrict__ items,
                                                              const int* __restrict__ bins) {
   for (int it = bins[blockIdx.x]; it < bins[blockIdx.x + 1]; ++it) {

@@ -36,6 +36,19 @@ __device__ __forceinline__ float bf16_to_f(unsigned short h) {
 
 // Add a finished tile to C (Hermitian update): (i,j) gets the value, and for an
 // off-diagonal tile (j,i) gets its conjugate.  Row/column skip_head is left out.
+// A diagonal tile keeps its upper triangle only, mirrors it, and takes the
+// diagonal as real, so that chi0 is Hermitian to the last bit.
+__device__ __forceinline__ bool herm_keep(bool diag_tile, int i, int j, double* im, bool* offdiag) {
+  if (!diag_tile) {
+    *offdiag = true;
+    return true;
+  }
+  if (i > j) return false;
+  if (i == j) *im = 0.0;
+  *offdiag = i < j;
+  return true;
+}
+
 __device__ __forceinline__ void herm_add(cpx<double>* C, int neps, int i, int j, double re,
                                          double im, bool offdiag, int skip_head) {
   if (i >= neps || j >= neps) return;
@@ -76,13 +89,17 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WM, wc = wave % WM;
   const int l16 = lane & 15, lk = lane >> 4;
-  d4 cr[2][2], ci[2][2];
+  // t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar - ai)(br + bi); then
+  // Re conj(a) b = t1 + t2 and Im = t3 - t1 + t2 (three real products per
+  // complex one instead of four)
+  d4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = (d4){0, 0, 0, 0};
-      ci[a][b] = (d4){0, 0, 0, 0};
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
     }
   cpx<Tin> ra[NE], rb[NE];
   double rw[NE];
@@ -125,29 +142,28 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
         br[b] = Br[kk][wc * 32 + b * 16 + l16];
         bi[b] = Bi[kk][wc * 32 + b * 16 + l16];
       }
-      // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br); the four products are
-      // issued round-robin over the eight accumulators so that no MFMA waits on
-      // the one just issued
+      double dd[2], ss[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) dd[a] = ar[a] - ai[a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) ss[b] = br[b] + bi[b];
+      // the three products are issued round-robin over the twelve accumulators
+      // so that no MFMA waits on the one just issued
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], t2[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cr[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], br[b], ci[a][b], 0, 0, 0);
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(dd[a], ss[b], t3[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -158,8 +174,12 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // f64 16x16x4 D layout: row lk + 4r, column l16
         const int i = i0 + wr * 32 + a * 16 + lk + 4 * r, j = j0 + wc * 32 + b * 16 + l16;
-        if (overwrite) herm_store(C, neps, i, j, cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
-        else herm_add(C, neps, i, j, cr[a][b][r], ci[a][b][r], ti != tj, skip_head);
+        const double re = t1[a][b][r] + t2[a][b][r];
+        double im = (t3[a][b][r] - t1[a][b][r]) + t2[a][b][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, re, im, od, skip_head);
+        else herm_add(C, neps, i, j, re, im, od, skip_head);
       }
 }
 
@@ -288,8 +308,11 @@ __device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
         const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
-        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
-        else herm_add(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+        double im = di[x][y][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], im, od, skip_head);
+        else herm_add(C, neps, i, j, dr[x][y][r], im, od, skip_head);
       }
 }
 
@@ -410,8 +433,11 @@ __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
         const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
-        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
-        else herm_add(C, neps, i, j, dr[x][y][r], di[x][y][r], ti != tj, skip_head);
+        double im = di[x][y][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], im, od, skip_head);
+        else herm_add(C, neps, i, j, dr[x][y][r], im, od, skip_head);
       }
 }
 
