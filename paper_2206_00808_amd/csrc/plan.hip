@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(1024) k_gjb_diag(const GjM* __restrict__ ms, i
 }
 
 // R = Dinv A[K, :] (rows nbk.. of R are never read)
-__global__ void __launch_bounds__(256) k_gjb_rpanel(const GjM* __restrict__ ms, int k) {
+__global__ void __launch_bounds__(256, 2) k_gjb_rpanel(const GjM* __restrict__ ms, int k) {
   const GjM m = ms[blockIdx.z];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
@@ -190,7 +190,7 @@ __global__ void k_gjb_prep(const GjM* __restrict__ ms, int k) {
 }
 
 // A -= Cb R over the whole matrix
-__global__ void __launch_bounds__(256) k_gjb_update(const GjM* __restrict__ ms, int k) {
+__global__ void __launch_bounds__(256, 2) k_gjb_update(const GjM* __restrict__ ms, int k) {
   const GjM m = ms[blockIdx.z];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);

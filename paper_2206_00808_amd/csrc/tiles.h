@@ -444,8 +444,11 @@ __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict
 // ------------------------------------------------------------------ complex-double GEMM tile
 // C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
 // (i0, j0), 256 threads (beta is 0 or 1).
-//   - With beta 1 the accumulators start from C, loaded before the first slab,
-//     so reading C overlaps the slab loads and the epilogue is a plain store.
+//   - Three real products per complex one: t1 = ar br, t2 = ai bi,
+//     t3 = (ar + ai)(br + bi); Re = t1 - t2 and Im = t3 - t1 - t2.
+//   - With beta 1 the accumulators start from C (t1 = Re C, t3 = Re C + Im C),
+//     loaded before the first slab, so reading C overlaps the slab loads and
+//     the epilogue is a plain store.
 //   - alpha scales A as it is staged in LDS.
 //   - K advances in slabs of KT through two LDS buffers; the next slab is
 //     loaded into registers while the current one feeds the MFMAs, so there
@@ -461,7 +464,7 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lk = lane >> 4;
-  d4 cr[2][2], ci[2][2];
+  d4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -471,8 +474,9 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
         const int i = i0 + wr * 32 + a * 16 + lk + 4 * r, j = j0 + wc * 32 + b * 16 + l16;
         cpx<double> v = mk(0.0, 0.0);
         if (beta != 0.0 && i < m && j < n) v = C[(size_t)i * ldc + j];
-        cr[a][b][r] = v.x;
-        ci[a][b][r] = v.y;
+        t1[a][b][r] = v.x;
+        t2[a][b][r] = 0.0;
+        t3[a][b][r] = v.x + v.y;
       }
   cpx<double> ra[PER], rb[PER];
   auto fetch = [&](int k0) {
@@ -507,27 +511,26 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
       for (int a = 0; a < 2; ++a) av[a] = As[buf][kk][wr * 32 + a * 16 + l16];
 #pragma unroll
       for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wc * 32 + b * 16 + l16];
-      // a * b = (ar br - ai bi) + i (ar bi + ai br)
+      double sa[2], sb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) sa[a] = av[a].x + av[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) sb[b] = bv[b].x + bv[b].y;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, t1[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].y, t2[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
     }
     // the other buffer was last read before this slab's barrier, so the next
     // slab can be stored into it without another barrier
@@ -541,7 +544,9 @@ __device__ __forceinline__ void zgemm_tile(int m, int n, int kdim, double alpha,
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wr * 32 + a * 16 + lk + 4 * r;
         const int j = j0 + wc * 32 + b * 16 + l16;
-        if (i < m && j < n) C[(size_t)i * ldc + j] = mk(cr[a][b][r], ci[a][b][r]);
+        if (i < m && j < n)
+          C[(size_t)i * ldc + j] = mk(t1[a][b][r] - t2[a][b][r],
+                                      (t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]);
       }
 }
 
