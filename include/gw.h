@@ -79,10 +79,14 @@ const char* gw_last_error(const gw_ctx* ctx);
 const char* gw_status_string(gw_status s);
 
 /* Per-kernel timing.  When enabled, every kernel the library launches is
- * bracketed by HIP events on the context stream; gw_ctx_profile_entry
+ * bracketed by HIP events on the stream it runs on; gw_ctx_profile_entry
  * synchronises the stream and reports, per kernel name, the launch count and
- * the summed event time in milliseconds.  Disabled by default. */
+ * the summed event time in milliseconds.  Disabled by default.
+ * gw_ctx_profile_only restricts the events to the kernels of one name (NULL:
+ * all), so that a timed run carries events around that kernel only; events
+ * between short dependent kernels lengthen the gaps between them. */
 gw_status gw_ctx_profile(gw_ctx* ctx, int enable);
+gw_status gw_ctx_profile_only(gw_ctx* ctx, const char* name);
 gw_status gw_ctx_profile_reset(gw_ctx* ctx);
 int gw_ctx_profile_count(gw_ctx* ctx);
 gw_status gw_ctx_profile_entry(gw_ctx* ctx, int i, const char** name, int* launches,

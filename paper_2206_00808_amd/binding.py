@@ -24,7 +24,8 @@ GW_CLOSURE_INFER, GW_CLOSURE_TRAIN_STEP, GW_CLOSURE_FULL_FALLBACK = 0, 1, 2
 
 EXPORTED = [
     "gw_ctx_create", "gw_ctx_destroy", "gw_ctx_set_stream", "gw_last_error", "gw_status_string",
-    "gw_ctx_profile", "gw_ctx_profile_reset", "gw_ctx_profile_count", "gw_ctx_profile_entry",
+    "gw_ctx_profile", "gw_ctx_profile_only", "gw_ctx_profile_reset", "gw_ctx_profile_count",
+    "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
@@ -57,6 +58,7 @@ _SIG = {
     "gw_last_error": (ct.c_char_p, [_vp]),
     "gw_status_string": (ct.c_char_p, [_i]),
     "gw_ctx_profile": (_i, [_vp, _i]),
+    "gw_ctx_profile_only": (_i, [_vp, ct.c_char_p]),
     "gw_ctx_profile_reset": (_i, [_vp]),
     "gw_ctx_profile_count": (_i, [_vp]),
     "gw_ctx_profile_entry": (_i, [_vp, _i, ct.POINTER(ct.c_char_p), _ip, ct.POINTER(_d)]),
@@ -147,6 +149,10 @@ class Context:
     # profiling -------------------------------------------------------------
     def profile(self, enable=True):
         _check(self, _lib.gw_ctx_profile(self.handle, 1 if enable else 0))
+
+    def profile_only(self, name=None):
+        """Record events around kernels of this name only (None: all)."""
+        _check(self, _lib.gw_ctx_profile_only(self.handle, None if name is None else name.encode()))
 
     def profile_reset(self):
         _check(self, _lib.gw_ctx_profile_reset(self.handle))

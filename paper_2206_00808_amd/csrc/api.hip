@@ -105,6 +105,7 @@ gw_status side_stream(gw_ctx* c) {
 ProfScope::ProfScope(gw_ctx* cc, const char* nm, hipStream_t s)
     : c(cc), name(nm), st(s ? s : cc->stream) {
   if (!c->profiling) return;
+  if (!c->prof_only.empty() && c->prof_only != name) return;
   auto get = [&]() {
     hipEvent_t e;
     if (!c->ev_pool.empty()) { e = c->ev_pool.back(); c->ev_pool.pop_back(); }
@@ -225,6 +226,12 @@ const char* gw_last_error(const gw_ctx* c) { return c ? c->err.c_str() : "null c
 gw_status gw_ctx_profile(gw_ctx* c, int enable) {
   if (!c) return GW_EINVAL;
   c->profiling = enable != 0;
+  return GW_OK;
+}
+
+gw_status gw_ctx_profile_only(gw_ctx* c, const char* name) {
+  if (!c) return GW_EINVAL;
+  c->prof_only = name ? name : "";
   return GW_OK;
 }
 

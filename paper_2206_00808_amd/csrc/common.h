@@ -92,6 +92,7 @@ struct gw_ctx {
   std::set<gw_plan*> plans;
   // profiling
   bool profiling = false;
+  std::string prof_only;  // non-empty: only scopes of this name record events
   std::vector<gw::ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, gw::ProfAcc> prof;
