@@ -303,7 +303,11 @@ gw_status gw_mtxel_spinor(gw_ctx* c, const int box[3], int nspinor, int nv, int 
   const size_t elem = dtype == GW_C128 ? 16 : 8;
   const size_t nbox = (size_t)box[0] * box[1] * box[2];
   const size_t uv_bytes = (size_t)nv * nspinor * nbox * elem;
-  const size_t uc_bytes = (size_t)nc * nspinor * nbox * elem;
+  // conduction bands: compact x-transformed slabs when the pair kernels build
+  // their planes themselves, full real-space fields otherwise
+  const bool compact = pair_compact_shape(box);
+  const size_t uc_bytes = compact ? band_compact_bytes(box, sc, nc * nspinor, elem)
+                                  : (size_t)nc * nspinor * nbox * elem;
   // band scratch: a chunk of band-spins of the compact x-pass output
   const size_t band_per = band_scratch_bytes(box, sv, 1, elem) > band_scratch_bytes(box, sc, 1, elem)
                               ? band_scratch_bytes(box, sv, 1, elem)
@@ -341,19 +345,27 @@ gw_status gw_mtxel_spinor(gw_ctx* c, const int box[3], int nspinor, int nv, int 
 
   if (dtype == GW_C128) {
     if ((st = band_to_grid<double>(c, box, nv * nspinor, ngv, cv, sv, uv, bscr, band_bytes)) != GW_OK) return st;
-    if ((st = band_to_grid<double>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes)) != GW_OK) return st;
+    st = compact ? band_compact<double>(c, box, nc * nspinor, ngc, cc, sc, uc)
+                 : band_to_grid<double>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes);
+    if (st != GW_OK) return st;
   } else {
     if ((st = band_to_grid<float>(c, box, nv * nspinor, ngv, cv, sv, uv, bscr, band_bytes)) != GW_OK) return st;
-    if ((st = band_to_grid<float>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes)) != GW_OK) return st;
+    st = compact ? band_compact<float>(c, box, nc * nspinor, ngc, cc, sc, uc)
+                 : band_to_grid<float>(c, box, nc * nspinor, ngc, cc, sc, uc, bscr, band_bytes);
+    if (st != GW_OK) return st;
   }
   for (int v0 = 0; v0 < nv; v0 += vt) {
     const int nvt = std::min(vt, nv - v0);
     for (int c0 = 0; c0 < nc; c0 += ct) {
       const int nct = std::min(ct, nc - c0);
+      const void* ucf = compact ? nullptr : uc;
+      const void* tcs = compact ? uc : nullptr;
       if (dtype == GW_C128)
-        st = pair_to_eps<double>(c, box, nspinor, uv, uc, v0, nvt, c0, nct, nc, se, mtxel, pscr);
+        st = pair_to_eps<double>(c, box, nspinor, uv, ucf, tcs, sc, v0, nvt, c0, nct, nc, se,
+                                 mtxel, pscr);
       else
-        st = pair_to_eps<float>(c, box, nspinor, uv, uc, v0, nvt, c0, nct, nc, se, mtxel, pscr);
+        st = pair_to_eps<float>(c, box, nspinor, uv, ucf, tcs, sc, v0, nvt, c0, nct, nc, se,
+                                mtxel, pscr);
       if (st != GW_OK) return st;
     }
   }

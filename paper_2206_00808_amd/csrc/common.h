@@ -143,10 +143,19 @@ struct ProfScope {
 template <typename T>
 gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
                        const SphereMap* sm, void* u_out, void* scratch, size_t scratch_bytes);
+// Pairs (v, c) for v in [v0, v0+nvt), c in [c0, c0+nct) into M. The conduction
+// bands come either as full real-space fields uc, or (box shapes for which
+// pair_compact_shape holds) as compact x-transformed slabs tc on sphere sc,
+// from which the pair kernels build each plane themselves.
 template <typename T>
 gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, const void* uc,
-                      int v0, int nvt, int c0, int nct, int nc_total, const SphereMap* em,
-                      void* mtxel, void* scratch);
+                      const void* tc, const SphereMap* sc, int v0, int nvt, int c0, int nct,
+                      int nc_total, const SphereMap* em, void* mtxel, void* scratch);
+template <typename T>
+gw_status band_compact(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                       const SphereMap* sm, void* out);
+bool pair_compact_shape(const int box[3]);
+size_t band_compact_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
 size_t band_scratch_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
 size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem);
 

@@ -613,6 +613,103 @@ constexpr int pow2_at_least(int n) {
 
 constexpr int cs_split(int n) { return n == 48 ? 8 : split_n1(n); }
 
+// Full x-plane of one band and spinor component, built in LDS from its slab of
+// the compact (y,z) cube that k_band_x writes (src[jy * ezw + jz], |g| <= gyw,
+// gzw). It takes the y transforms of the occupied z columns (into Zw, pitch
+// ZWP), then the z transforms of every row (into P, pitch PP). A2/A3 lanes per
+// pencil, all in one wavefront: each exchange goes through the pencil's own LDS
+// line, with every read of a stage finished before its writes.
+template <typename T, int N2, int N3, int A2, int A3, int NTH>
+__device__ __forceinline__ void build_plane(const cpx<T>* __restrict__ src, int ezw, int gyw,
+                                            int gzw, const cpx<T>* tw2, const cpx<T>* tw3,
+                                            cpx<T>* Zw, int ZWP, cpx<T>* P, int PP, int tid) {
+  constexpr int B2 = N2 / A2, L2 = pow2_at_least(A2), R2 = NTH / L2, NR2 = (B2 + A2 - 1) / A2;
+  constexpr int B3 = N3 / A3, L3 = pow2_at_least(A3), R3 = NTH / L3, NR3 = (B3 + A3 - 1) / A3;
+  static_assert(64 % L2 == 0 && 64 % L3 == 0, "a pencil must sit in one wavefront");
+  {
+    const int pp = tid / L2, t = tid % L2;
+    for (int q0 = 0; q0 < ezw; q0 += R2) {
+      const int jz = q0 + pp;
+      if (jz < ezw && t < A2) {
+        cpx<T> a[B2];
+#pragma unroll
+        for (int m = 0; m < B2; ++m) {
+          const int jy = kept(t + A2 * m, N2, gyw);
+          a[m] = jy >= 0 ? src[jy * ezw + jz] : mk<T>(0, 0);
+        }
+        reg_dft<T, B2>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B2; ++k2) a[k2] = cmul(a[k2], tw2[t * k2]);
+        cpx<T>* col = Zw + jz;
+#pragma unroll
+        for (int k2 = 0; k2 < B2; ++k2) col[(k2 * A2 + t) * ZWP] = a[k2];
+        __builtin_amdgcn_wave_barrier();
+        cpx<T> o[NR2][A2];
+#pragma unroll
+        for (int r = 0; r < NR2; ++r) {
+          const int k2 = t + A2 * r;
+          if (k2 < B2) {
+#pragma unroll
+            for (int n = 0; n < A2; ++n) o[r][n] = col[(k2 * A2 + n) * ZWP];
+            reg_dft<T, A2>(o[r]);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < NR2; ++r) {
+          const int k2 = t + A2 * r;
+          if (k2 < B2) {
+#pragma unroll
+            for (int k1 = 0; k1 < A2; ++k1) col[(k2 + B2 * k1) * ZWP] = o[r][k1];
+          }
+        }
+      }
+    }
+  }
+  lds_sync();
+  {
+    const int rr = tid / L3, t = tid % L3;
+    for (int y0 = 0; y0 < N2; y0 += R3) {
+      const int y = y0 + rr;
+      if (y < N2 && t < A3) {
+        cpx<T> a[B3];
+#pragma unroll
+        for (int m = 0; m < B3; ++m) {
+          const int jz = kept(t + A3 * m, N3, gzw);
+          a[m] = jz >= 0 ? Zw[y * ZWP + jz] : mk<T>(0, 0);
+        }
+        reg_dft<T, B3>(a);
+#pragma unroll
+        for (int k2 = 1; k2 < B3; ++k2) a[k2] = cmul(a[k2], tw3[t * k2]);
+        cpx<T>* row = P + y * PP;
+#pragma unroll
+        for (int k2 = 0; k2 < B3; ++k2) row[k2 * A3 + t] = a[k2];
+        __builtin_amdgcn_wave_barrier();
+        cpx<T> o[NR3][A3];
+#pragma unroll
+        for (int r = 0; r < NR3; ++r) {
+          const int k2 = t + A3 * r;
+          if (k2 < B3) {
+#pragma unroll
+            for (int n = 0; n < A3; ++n) o[r][n] = row[k2 * A3 + n];
+            reg_dft<T, A3>(o[r]);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < NR3; ++r) {
+          const int k2 = t + A3 * r;
+          if (k2 < B3) {
+#pragma unroll
+            for (int k1 = 0; k1 < A3; ++k1) row[k2 + B3 * k1] = o[r][k1];
+          }
+        }
+      }
+    }
+  }
+  lds_sync();
+}
+
 template <int N2, int N3>
 struct CsShape {
   static constexpr int NP = N2 * N3;                        // plane elements
@@ -626,18 +723,21 @@ struct CsShape {
   static_assert(64 % L3 == 0 && 64 % L2 == 0, "a row or column must sit in one wavefront");
 };
 
-// LDS elements: twiddles (N3 + N2), product plane, VB kept-column slabs
+// LDS elements: twiddles (N3 + N2), product plane, and a region that holds the
+// VB kept-column slabs of the valence loop and, before it, the y-transformed
+// columns of the conduction plane being built
 template <int N2, int N3>
-static size_t cs_lds_elems(int ez) {
+static size_t cs_lds_elems(int ez, int ezw) {
   using S = CsShape<N2, N3>;
-  return (size_t)N3 + N2 + (size_t)N2 * S::PP + (size_t)S::VB * N2 * (ez | 1);
+  const size_t slabs = std::max((size_t)S::VB * N2 * (ez | 1), (size_t)N2 * (ezw | 1));
+  return (size_t)N3 + N2 + (size_t)N2 * S::PP + slabs;
 }
 
 template <typename T, int NS, int N2, int N3>
 __global__ void __launch_bounds__(kThreads, 2) k_pair_cs(
-    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
-    int nct, int n1, int ey, int ez, int gy, int gz, const cpx<T>* __restrict__ twy,
-    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ tc, int ezw, int gyw, int gzw,
+    int ncw, int v0, int nvt, int c0, int nct, int n1, int ey, int ez, int gy, int gz,
+    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
   using S = CsShape<N2, N3>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw3 = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -654,16 +754,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_pair_cs(
   for (int i = tid; i < N2; i += kThreads) tw2[i] = twy[i];
 
   cpx<T> cr[NS][S::NI], vr[NS][S::NI];
-  {
-    const cpx<T>* pc = uc + (size_t)(c0 + cl) * NS * nb + (size_t)x * S::NP;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int i = 0; i < S::NI; ++i) {
-        const int e = tid + kThreads * i;
-        cr[s][i] = (S::NP % kThreads == 0 || e < S::NP) ? pc[s * nb + e] : mk<T>(0, 0);
-      }
-  }
   auto fetch_v = [&](int vl) {
     const cpx<T>* pv = uv + (size_t)(v0 + vl) * NS * nb + (size_t)x * S::NP;
 #pragma unroll
@@ -675,12 +765,26 @@ __global__ void __launch_bounds__(kThreads, 2) k_pair_cs(
       }
   };
   fetch_v(0);
+  lds_sync();  // twiddles in place
+  // the conduction plane (every spinor component), built from its compact slab
+  // and kept in registers in the flat layout
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const cpx<T>* src = tc + (((size_t)(c0 + cl) * NS + s) * n1 + x) * ncw;
+    build_plane<T, N2, N3, S::A2, S::A3, kThreads>(src, ezw, gyw, gzw, tw2, tw3, Zb, ezw | 1, P,
+                                                   S::PP, tid);
+#pragma unroll
+    for (int i = 0; i < S::NI; ++i) {
+      const int e = tid + kThreads * i;
+      cr[s][i] = (S::NP % kThreads == 0 || e < S::NP) ? P[(e / N3) * S::PP + e % N3] : mk<T>(0, 0);
+    }
+  }
 
   for (int g0 = 0; g0 < nvt; g0 += S::VB) {
     const int nbv = min(S::VB, nvt - g0);
     for (int j = 0; j < nbv; ++j) {
       const int vl = g0 + j;
-      lds_sync();  // the previous z pass has read P
+      lds_sync();  // the previous z pass (or the plane build) has read P
       // spinor-summed product conj(psi_v) psi_c of this plane
 #pragma unroll
       for (int i = 0; i < S::NI; ++i) {
@@ -794,26 +898,29 @@ struct RrShape {
   static_assert(NTH <= 1024 && NTH % 64 == 0, "block must be whole wavefronts");
 };
 
+// LDS elements: twiddles, exchange plane, and a region for the vb kept-column
+// slabs (before the valence loop: the conduction plane's y-transformed columns)
 template <typename T, int N2, int N3>
-static size_t rr_lds_elems(int ez, int vb) {
+static size_t rr_lds_elems(int ez, int vb, int ezw) {
   using S = RrShape<T, N2, N3>;
-  return (size_t)N3 + N2 + (size_t)N2 * S::PP + (size_t)vb * N2 * (ez | 1);
+  const size_t slabs = std::max((size_t)vb * N2 * (ez | 1), (size_t)N2 * (ezw | 1));
+  return (size_t)N3 + N2 + (size_t)N2 * S::PP + slabs;
 }
 
 // valence bands per y pass: fill the pass's columns, keep LDS within half a CU
 template <typename T, int N2, int N3>
-static int rr_group(int ez) {
+static int rr_group(int ez, int ezw) {
   using S = RrShape<T, N2, N3>;
   int vb = std::max(1, std::min(8, S::CPP / std::max(1, ez)));
-  while (vb > 1 && rr_lds_elems<T, N2, N3>(ez, vb) * sizeof(cpx<T>) > 80 * 1024) --vb;
+  while (vb > 1 && rr_lds_elems<T, N2, N3>(ez, vb, ezw) * sizeof(cpx<T>) > 80 * 1024) --vb;
   return vb;
 }
 
 template <typename T, int NS, int N2, int N3>
 __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
-    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ uc, int v0, int nvt, int c0,
-    int nct, int n1, int ey, int ez, int gy, int gz, int vb, const cpx<T>* __restrict__ twy,
-    const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
+    const cpx<T>* __restrict__ uv, const cpx<T>* __restrict__ tc, int ezw, int gyw, int gzw,
+    int ncw, int v0, int nvt, int c0, int nct, int n1, int ey, int ez, int gy, int gz, int vb,
+    const cpx<T>* __restrict__ twy, const cpx<T>* __restrict__ twz, cpx<T>* __restrict__ t2) {
   using S = RrShape<T, N2, N3>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw3 = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -833,13 +940,6 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
   const size_t roff = ((size_t)x * N2 + y) * N3 + t;
 
   cpx<T> cr[NS][S::B3], vr[NS][S::B3];
-  if (act) {
-    const cpx<T>* pc = uc + (size_t)(c0 + cl) * NS * nb + roff;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int m = 0; m < S::B3; ++m) cr[s][m] = pc[s * nb + S::A3 * m];
-  }
   auto fetch_v = [&](int vl) {
     const cpx<T>* pv = uv + (size_t)(v0 + vl) * NS * nb + roff;
 #pragma unroll
@@ -848,6 +948,18 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
       for (int m = 0; m < S::B3; ++m) vr[s][m] = pv[s * nb + S::A3 * m];
   };
   lds_sync();  // twiddles in place
+  // the conduction plane, built from its compact slab; the z pass of the build
+  // leaves row y with the lanes that own it here
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const cpx<T>* src = tc + (((size_t)(c0 + cl) * NS + s) * n1 + x) * ncw;
+    build_plane<T, N2, N3, S::A2, S::A3, S::NTH>(src, ezw, gyw, gzw, tw2, tw3, Zb, ezw | 1, X,
+                                                 S::PP, tid);
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < S::B3; ++m) cr[s][m] = X[y * S::PP + t + S::A3 * m];
+    }
+  }
 
   cpx<T>* Xr = X + y * S::PP;
   for (int g0 = 0; g0 < nvt; g0 += vb) {
@@ -1133,10 +1245,51 @@ gw_status band_to_grid(gw_ctx* c, const int box[3], int nbs, int ng, const void*
   return GW_OK;
 }
 
+bool pair_compact_shape(const int box[3]) {
+  bool yes = false;
+#define X(A, B) if (box[1] == A && box[2] == B) yes = true;
+  GW_CS_SHAPES(X)
+#undef X
+  return yes;
+}
+
+size_t band_compact_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem) {
+  return (size_t)nbs * box[0] * sm->ext[1] * sm->ext[2] * elem;
+}
+
+// x transform only: out[bs][x][jy][jz] on the band's compact (y,z) cube, for the
+// pair kernels that build each conduction plane themselves
+template <typename T>
+gw_status band_compact(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                       const SphereMap* sm, void* out) {
+  const int n1 = box[0];
+  FftPlan px = make_fft_plan(n1);
+  const void* twx;
+  gw_status st;
+  if ((st = twiddle_table(c, n1, sizeof(T) == 8, &twx)) != GW_OK) return st;
+  const int ncol = sm->ext[1] * sm->ext[2];
+  const int CH = col_chunk<T>(n1);
+  const size_t lds_x = (size_t)n1 * CH * sizeof(cpx<T>);
+  auto kx = pick_band_x<T>(n1);
+  if (!c->capturing) GW_HIP(c, allow_lds(kx, lds_x));
+  const cpx<T>* cf = static_cast<const cpx<T>*>(coef);
+  cpx<T>* o = static_cast<cpx<T>*>(out);
+  ProfScope ps(c, "band_xpass");
+  for (int b0 = 0; b0 < nbs; b0 += 65535) {
+    const int nb = std::min(65535, nbs - b0);
+    dim3 g((ncol + CH - 1) / CH, nb);
+    hipLaunchKernelGGL(kx, g, dim3(kThreads), lds_x, c->stream, cf + (size_t)b0 * ng, ng,
+                       sm->d_cube, sm->ext[0], sm->ext[1], sm->ext[2], sm->gmax[0], n1, ncol, CH,
+                       px, static_cast<const cpx<T>*>(twx), o + (size_t)b0 * n1 * ncol);
+    GW_CHECK_LAUNCH(c, "k_band_x");
+  }
+  return GW_OK;
+}
+
 template <typename T>
 gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, const void* uc,
-                      int v0, int nvt, int c0, int nct, int nc_total, const SphereMap* em,
-                      void* mtxel, void* scratch) {
+                      const void* tc, const SphereMap* sc, int v0, int nvt, int c0, int nct,
+                      int nc_total, const SphereMap* em, void* mtxel, void* scratch) {
   const int n1 = box[0], n2 = box[1], n3 = box[2];
   FftPlan px = make_fft_plan(n1), py = make_fft_plan(n2), pz = make_fft_plan(n3);
   const void *twx, *twy, *twz;
@@ -1167,22 +1320,26 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
     const cpx<T>* ty = static_cast<const cpx<T>*>(twy);
     const cpx<T>* tz = static_cast<const cpx<T>*>(twz);
     bool rf = false;
-    if (nvt > 0 && nct > 0) {
+    if (tc && nvt > 0 && nct > 0) {
       const unsigned gcs = (unsigned)((((long long)n1 * nct + kXcd - 1) / kXcd) * kXcd);
+      const cpx<T>* ptc = static_cast<const cpx<T>*>(tc);
+      const int ncw = sc->ext[1] * sc->ext[2];
       if constexpr (sizeof(T) == 8) {
 #define X(A, B)                                                                               \
   if (!rf && n2 == A && n3 == B) {                                                            \
     rf = true;                                                                                \
-    const size_t lds = cs_lds_elems<A, B>(em->ext[2]) * sizeof(cpx<T>);                       \
+    const size_t lds = cs_lds_elems<A, B>(em->ext[2], sc->ext[2]) * sizeof(cpx<T>);           \
     if (nspinor == 2) {                                                                       \
       if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 2, A, B>, lds));                    \
       hipLaunchKernelGGL((k_pair_cs<T, 2, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
-                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],   \
+                         pu, ptc, sc->ext[2], sc->gmax[1], sc->gmax[2], ncw, v0, nvt, c0, nct, \
+                         n1, em->ext[1], em->ext[2], em->gmax[1],                             \
                          em->gmax[2], ty, tz, t2);                                            \
     } else {                                                                                  \
       if (!c->capturing) GW_HIP(c, allow_lds(k_pair_cs<T, 1, A, B>, lds));                    \
       hipLaunchKernelGGL((k_pair_cs<T, 1, A, B>), dim3(gcs), dim3(kThreads), lds, c->stream,  \
-                         pu, pc, v0, nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1],   \
+                         pu, ptc, sc->ext[2], sc->gmax[1], sc->gmax[2], ncw, v0, nvt, c0, nct, \
+                         n1, em->ext[1], em->ext[2], em->gmax[1],                             \
                          em->gmax[2], ty, tz, t2);                                            \
     }                                                                                         \
   }
@@ -1192,18 +1349,20 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
 #define X(A, B)                                                                               \
   if (!rf && n2 == A && n3 == B) {                                                            \
     rf = true;                                                                                \
-    const int vb = rr_group<T, A, B>(em->ext[2]);                                             \
-    const size_t lds = rr_lds_elems<T, A, B>(em->ext[2], vb) * sizeof(cpx<T>);                \
+    const int vb = rr_group<T, A, B>(em->ext[2], sc->ext[2]);                                 \
+    const size_t lds = rr_lds_elems<T, A, B>(em->ext[2], vb, sc->ext[2]) * sizeof(cpx<T>);    \
     const dim3 blk(RrShape<T, A, B>::NTH);                                                    \
     if (nspinor == 2) {                                                                       \
       if (!c->capturing) GW_HIP(c, allow_lds(k_pair_rr<T, 2, A, B>, lds));                    \
-      hipLaunchKernelGGL((k_pair_rr<T, 2, A, B>), dim3(gcs), blk, lds, c->stream, pu, pc, v0, \
-                         nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],  \
+      hipLaunchKernelGGL((k_pair_rr<T, 2, A, B>), dim3(gcs), blk, lds, c->stream, pu, ptc,    \
+                         sc->ext[2], sc->gmax[1], sc->gmax[2], ncw, v0, nvt, c0, nct, n1,      \
+                         em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],                     \
                          vb, ty, tz, t2);                                                     \
     } else {                                                                                  \
       if (!c->capturing) GW_HIP(c, allow_lds(k_pair_rr<T, 1, A, B>, lds));                    \
-      hipLaunchKernelGGL((k_pair_rr<T, 1, A, B>), dim3(gcs), blk, lds, c->stream, pu, pc, v0, \
-                         nvt, c0, nct, n1, em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],  \
+      hipLaunchKernelGGL((k_pair_rr<T, 1, A, B>), dim3(gcs), blk, lds, c->stream, pu, ptc,    \
+                         sc->ext[2], sc->gmax[1], sc->gmax[2], ncw, v0, nvt, c0, nct, n1,      \
+                         em->ext[1], em->ext[2], em->gmax[1], em->gmax[2],                     \
                          vb, ty, tz, t2);                                                     \
     }                                                                                         \
   }
@@ -1266,9 +1425,15 @@ template gw_status band_to_grid<double>(gw_ctx*, const int*, int, int, const voi
                                         const SphereMap*, void*, void*, size_t);
 template gw_status band_to_grid<float>(gw_ctx*, const int*, int, int, const void*,
                                        const SphereMap*, void*, void*, size_t);
-template gw_status pair_to_eps<double>(gw_ctx*, const int*, int, const void*, const void*, int,
-                                       int, int, int, int, const SphereMap*, void*, void*);
-template gw_status pair_to_eps<float>(gw_ctx*, const int*, int, const void*, const void*, int,
-                                      int, int, int, int, const SphereMap*, void*, void*);
+template gw_status pair_to_eps<double>(gw_ctx*, const int*, int, const void*, const void*,
+                                       const void*, const SphereMap*, int, int, int, int, int,
+                                       const SphereMap*, void*, void*);
+template gw_status pair_to_eps<float>(gw_ctx*, const int*, int, const void*, const void*,
+                                      const void*, const SphereMap*, int, int, int, int, int,
+                                      const SphereMap*, void*, void*);
+template gw_status band_compact<double>(gw_ctx*, const int*, int, int, const void*,
+                                        const SphereMap*, void*);
+template gw_status band_compact<float>(gw_ctx*, const int*, int, int, const void*,
+                                       const SphereMap*, void*);
 
 }  // namespace gw

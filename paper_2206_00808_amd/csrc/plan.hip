@@ -247,6 +247,7 @@ struct gw_plan {
   std::vector<gw_plan_q> q;
   bool shared_c = false;
   int nc_shared = 0;
+  bool compact = false;  // conduction kept as compact x-transformed slabs
   // device memory (one allocation)
   char* base = nullptr;
   size_t bytes = 0;
@@ -372,22 +373,23 @@ static gw_status enqueue_front(gw_plan* p) {
   gw_status st;
   const bool dbl = p->dtype == GW_C128;
   const int ns = p->nspinor;
+  auto conduction = [&](int nbs, int ng, const void* cc, const SphereMap* sc) {
+    if (p->compact)
+      return dbl ? band_compact<double>(c, p->box, nbs, ng, cc, sc, p->uc)
+                 : band_compact<float>(c, p->box, nbs, ng, cc, sc, p->uc);
+    return dbl ? band_to_grid<double>(c, p->box, nbs, ng, cc, sc, p->uc, p->bscr, p->bscr_bytes)
+               : band_to_grid<float>(c, p->box, nbs, ng, cc, sc, p->uc, p->bscr, p->bscr_bytes);
+  };
   if (p->shared_c) {
     const auto& q0 = p->q[0];
-    st = dbl ? band_to_grid<double>(c, p->box, p->nc_shared * ns, q0.d.ngc, q0.d.cc, q0.sc, p->uc,
-                                    p->bscr, p->bscr_bytes)
-             : band_to_grid<float>(c, p->box, p->nc_shared * ns, q0.d.ngc, q0.d.cc, q0.sc, p->uc,
-                                   p->bscr, p->bscr_bytes);
-    if (st != GW_OK) return st;
+    if ((st = conduction(p->nc_shared * ns, q0.d.ngc, q0.d.cc, q0.sc)) != GW_OK) return st;
   }
+  const void* ucf = p->compact ? nullptr : p->uc;
+  const void* tcs = p->compact ? p->uc : nullptr;
   for (auto& q : p->q) {
     const int nv = q.d.nv, nc = q.d.nc;
     if (!p->shared_c) {
-      st = dbl ? band_to_grid<double>(c, p->box, nc * ns, q.d.ngc, q.d.cc, q.sc, p->uc, p->bscr,
-                                      p->bscr_bytes)
-               : band_to_grid<float>(c, p->box, nc * ns, q.d.ngc, q.d.cc, q.sc, p->uc, p->bscr,
-                                     p->bscr_bytes);
-      if (st != GW_OK) return st;
+      if ((st = conduction(nc * ns, q.d.ngc, q.d.cc, q.sc)) != GW_OK) return st;
     }
     st = dbl ? band_to_grid<double>(c, p->box, nv * ns, q.d.ngv, q.d.cv, q.sv, p->uv, p->bscr,
                                     p->bscr_bytes)
@@ -399,10 +401,10 @@ static gw_status enqueue_front(gw_plan* p) {
     for (int v0 = 0; v0 < nv; v0 += vt)
       for (int c0 = 0; c0 < nc; c0 += ct) {
         const int nvt = std::min(vt, nv - v0), nct = std::min(ct, nc - c0);
-        st = dbl ? pair_to_eps<double>(c, p->box, ns, p->uv, p->uc, v0, nvt, c0, nct, nc, q.se,
-                                       q.M, p->pscr)
-                 : pair_to_eps<float>(c, p->box, ns, p->uv, p->uc, v0, nvt, c0, nct, nc, q.se,
-                                      q.M, p->pscr);
+        st = dbl ? pair_to_eps<double>(c, p->box, ns, p->uv, ucf, tcs, q.sc, v0, nvt, c0, nct, nc,
+                                       q.se, q.M, p->pscr)
+                 : pair_to_eps<float>(c, p->box, ns, p->uv, ucf, tcs, q.sc, v0, nvt, c0, nct, nc,
+                                      q.se, q.M, p->pscr);
         if (st != GW_OK) return st;
       }
     if (q.mhead) {
@@ -651,7 +653,15 @@ gw_status gw_plan_compile(gw_plan* p) {
   p->nitems = (int)items;
   // one allocation
   std::vector<std::pair<void**, size_t>> parts;
-  const size_t uc_bytes = (size_t)(p->shared_c ? p->nc_shared : nc_max) * ns * nbox * elem;
+  p->compact = pair_compact_shape(p->box);
+  size_t uc_bytes = (size_t)(p->shared_c ? p->nc_shared : nc_max) * ns * nbox * elem;
+  if (p->compact) {
+    uc_bytes = 0;
+    for (auto& q : p->q)
+      uc_bytes = std::max(uc_bytes, band_compact_bytes(p->box, q.sc,
+                                                       (p->shared_c ? p->nc_shared : q.d.nc) * ns,
+                                                       elem));
+  }
   const size_t uv_bytes = (size_t)nv_max * ns * nbox * elem;
   parts.push_back({&p->uc, uc_bytes});
   parts.push_back({&p->uv, uv_bytes});
