@@ -187,7 +187,8 @@ gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfre
 gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
                    int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
-                   size_t extB, size_t extC, double beta = 1.0);
+                   size_t extB, size_t extC, double beta = 1.0,
+                   hipStream_t stream = nullptr);  // nullptr: the context stream
 
 // eps and its inverse (lu.hip)
 gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,

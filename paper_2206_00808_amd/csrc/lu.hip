@@ -308,24 +308,50 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
     }
 }
 
-// Before the rank-nbk update of step K:
-//   - Cb[f][i][t] = A[f][i][k+t] for all rows i (column block K);
-//   - R[t][k+j] = delta_tj + Dinv[t][j].
-// With R in the K columns set this way, A[:,K] - Cb R leaves -Cb Dinv in the
-// column block, which is its Gauss-Jordan value.
-__global__ void k_gj_prep(const cpx<double>* __restrict__ A, int N, int k, int nbk,
+// The one launch between the row panel and the rank update of step K (block
+// k, width nbk):
+//   - row block of the previous step (kp, nbp; none when nbp is 0) <- Rp outside
+//     its columns and Dp inside, its Gauss-Jordan value;
+//   - Cb[i][t] = A[i][k+t], the rows of the previous block taking those values;
+//   - R[t][k+j] = delta_tj + D[t][j]; with R in the K columns set this way,
+//     A[:,K] - Cb R leaves -Cb D in the column block, its Gauss-Jordan value;
+//   - Dn = A[K'][K'] for the look-ahead (k2, nb2; none when nb2 is 0).
+// No entry is both read and written: the previous block's rows are taken from
+// Rp and Dp, and the look-ahead block lies below both row blocks.
+__global__ void k_gj_step(cpx<double>* __restrict__ A, int N, int k, int nbk,
                           cpx<double>* __restrict__ Cb, cpx<double>* __restrict__ R,
-                          const cpx<double>* __restrict__ Dw) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+                          const cpx<double>* __restrict__ D, int kp, int nbp,
+                          const cpx<double>* __restrict__ Rp, const cpx<double>* __restrict__ Dp,
+                          int k2, int nb2, cpx<double>* __restrict__ Dn) {
   const size_t f = blockIdx.y;
+  A += f * (size_t)N * N;
+  Cb += f * (size_t)N * GB;
+  R += f * (size_t)GB * N;
+  Rp += f * (size_t)GB * N;
+  D += f * (size_t)GB * GB;
+  Dp += f * (size_t)GB * GB;
+  Dn += f * (size_t)GB * GB;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  auto fixed = [&](int t, int j) {
+    return (j >= kp && j < kp + nbp) ? Dp[t * GB + (j - kp)] : Rp[(size_t)t * N + j];
+  };
+  if (e < nbp * N) {
+    const int t = e / N, j = e % N;
+    A[(size_t)(kp + t) * N + j] = fixed(t, j);
+  }
   if (e < N * nbk) {
     const int i = e / nbk, t = e % nbk;
-    Cb[f * (size_t)N * GB + (size_t)i * GB + t] = A[f * (size_t)N * N + (size_t)i * N + k + t];
+    Cb[(size_t)i * GB + t] = (i >= kp && i < kp + nbp) ? fixed(i - kp, k + t)
+                                                       : A[(size_t)i * N + k + t];
   }
   if (e < nbk * nbk) {
     const int t = e / nbk, j = e % nbk;
-    const cpx<double> dv = Dw[f * GB * GB + t * GB + j];
-    R[f * (size_t)GB * N + (size_t)t * N + k + j] = mk(dv.x + (t == j ? 1.0 : 0.0), dv.y);
+    const cpx<double> dv = D[t * GB + j];
+    R[(size_t)t * N + k + j] = mk(dv.x + (t == j ? 1.0 : 0.0), dv.y);
+  }
+  if (e < nb2 * nb2) {
+    const int i = e / nb2, j = e % nb2;
+    Dn[(size_t)i * GB + j] = A[(size_t)(k2 + i) * N + k2 + j];
   }
 }
 
@@ -340,16 +366,6 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
   if (e >= nbk * N) return;
   const int t = e / N, j = e % N;
   A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
-}
-
-// Dn[f] = A[f][K'][K'] (the next diagonal block, before this step's update)
-__global__ void k_gj_blkcopy(const cpx<double>* __restrict__ A, int N, int k, int nbk,
-                             cpx<double>* __restrict__ Dn) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nbk * nbk) return;
-  const size_t f = blockIdx.y;
-  const int i = e / nbk, j = e % nbk;
-  Dn[f * GB * GB + (size_t)i * GB + j] = A[f * (size_t)N * N + (size_t)(k + i) * N + k + j];
 }
 
 // eps^-1 = S epst^-1 S^-1, in place.
@@ -471,9 +487,10 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
   const size_t nR = (size_t)nfreq * GB * N, nC = (size_t)nfreq * N * GB, nD = (size_t)nfreq * GB * GB;
   gw_status st = side_stream(c);
   if (st != GW_OK) return st;
-  st = ws_begin(c, align_up(nR * 16) + align_up(nC * 16) + 3 * align_up(nD * 16));
+  st = ws_begin(c, 2 * align_up(nR * 16) + align_up(nC * 16) + 3 * align_up(nD * 16));
   if (st != GW_OK) return st;
-  cpx<double>* R = static_cast<cpx<double>*>(ws_take(c, nR * 16));
+  cpx<double>* Rw[2] = {static_cast<cpx<double>*>(ws_take(c, nR * 16)),
+                        static_cast<cpx<double>*>(ws_take(c, nR * 16))};
   cpx<double>* Cb = static_cast<cpx<double>*>(ws_take(c, nC * 16));
   cpx<double>* Dw[2] = {static_cast<cpx<double>*>(ws_take(c, nD * 16)),
                         static_cast<cpx<double>*>(ws_take(c, nD * 16))};
@@ -499,38 +516,38 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
     GW_CHECK_LAUNCH(c, "k_gj_diag");
   }
   const size_t ext = (size_t)nfreq * nn;
-  // Look-ahead: once the row panel of step K exists, the next diagonal block's
-  // updated value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed and inverted on the
-  // side stream while the main stream runs the full rank update of step K.
+  // Per step K the main stream runs the row panel, one small kernel and the rank
+  // update. Look-ahead: once the panels exist, the next diagonal block's updated
+  // value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed and inverted on the side
+  // stream while the main stream runs the update. The panels R and the
+  // diagonal inverses alternate between two buffers by step parity; the main
+  // stream joins the side stream before the next step rewrites Cb and Dn.
+  int kp = 0, nbp = 0;
   for (int k = 0, s = 0; k < N; k += GB, ++s) {
     const int nbk = std::min(GB, N - k);
     cpx<double>* D = Dw[s & 1];
+    cpx<double>* R = Rw[s & 1];
     // R = Dinv A[K][:] (rows nbk.. of R are never read)
     st = zgemm_nn(c, nbk, N, nbk, 1.0, reinterpret_cast<const double*>(D), 0, GB, GB * GB, Ad,
                   (size_t)k * N, N, (long long)nn, reinterpret_cast<double*>(R), 0, N,
                   (long long)GB * N, nfreq, nD, ext, nR, 0.0);
     if (st != GW_OK) return st;
+    const int k2 = k + GB, nb2 = std::min(GB, N - k2) > 0 ? std::min(GB, N - k2) : 0;
     {
       ProfScope ps(c, "gj_small");
-      hipLaunchKernelGGL(k_gj_prep, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
-                         A, N, k, nbk, Cb, R, D);
-      GW_CHECK_LAUNCH(c, "k_gj_prep");
+      hipLaunchKernelGGL(k_gj_step, dim3((N * GB + 255) / 256, nfreq), dim3(256), 0, c->stream,
+                         A, N, k, nbk, Cb, R, D, kp, nbp, Rw[(s + 1) & 1], Dw[(s + 1) & 1], k2,
+                         nb2, Dn);
+      GW_CHECK_LAUNCH(c, "k_gj_step");
     }
-    const int k2 = k + GB, nb2 = std::min(GB, N - k2);
     if (nb2 > 0) {
-      {
-        ProfScope ps(c, "gj_small");
-        hipLaunchKernelGGL(k_gj_blkcopy, dim3((nb2 * nb2 + 255) / 256, nfreq), dim3(256), 0,
-                           c->stream, A, N, k2, nb2, Dn);
-        GW_CHECK_LAUNCH(c, "k_gj_blkcopy");
-      }
+      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
       st = zgemm_nn(c, nb2, nb2, nbk, -1.0, reinterpret_cast<const double*>(Cb), (size_t)k2 * GB,
                     GB, (long long)N * GB, reinterpret_cast<const double*>(R), (size_t)k2, N,
                     (long long)GB * N, reinterpret_cast<double*>(Dn), 0, GB, (long long)GB * GB,
-                    nfreq, nC, nR, nD, 1.0);
+                    nfreq, nC, nR, nD, 1.0, c->side);
       if (st != GW_OK) return st;
-      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
-      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
       {
         ProfScope ps(c, "gj_diag", c->side);
         hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->side, Dn, GB,
@@ -540,19 +557,21 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
       GW_HIP(c, hipEventRecord(c->ev_join, c->side));
     }
     // A -= Cb R over the whole matrix: every row outside K is final, including
-    // its K columns; row block K is rewritten next
+    // its K columns; row block K is rewritten by the next step's small kernel
     st = zgemm_nn(c, N, N, nbk, -1.0, reinterpret_cast<const double*>(Cb), 0, GB,
                   (long long)N * GB, reinterpret_cast<const double*>(R), 0, N, (long long)GB * N,
                   epsinv, 0, N, (long long)nn, nfreq, nC, nR, ext);
     if (st != GW_OK) return st;
-    {
-      ProfScope ps(c, "gj_small");
-      hipLaunchKernelGGL(k_gj_fix, dim3((N * nbk + 255) / 256, nfreq), dim3(256), 0, c->stream,
-                         A, N, k, nbk, R, D);
-      GW_CHECK_LAUNCH(c, "k_gj_fix");
-    }
-    // the next step reads the inverse made on the side stream, and reuses Dn
     if (nb2 > 0) GW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    kp = k;
+    nbp = nbk;
+  }
+  {
+    ProfScope ps(c, "gj_small");
+    const int s_last = (N + GB - 1) / GB - 1;
+    hipLaunchKernelGGL(k_gj_fix, dim3((N * nbp + 255) / 256, nfreq), dim3(256), 0, c->stream,
+                       A, N, kp, nbp, Rw[s_last & 1], Dw[s_last & 1]);
+    GW_CHECK_LAUNCH(c, "k_gj_fix");
   }
   {
     ProfScope ps(c, "eps_unscale");
