@@ -518,7 +518,7 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
   const size_t ext = (size_t)nfreq * nn;
   // Per step K the main stream runs the row panel, one small kernel and the rank
   // update. Look-ahead: once the panels exist, the next diagonal block's updated
-  // value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed and inverted on the side
+  // value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed, and inverted on the side
   // stream while the main stream runs the update. The panels R and the
   // diagonal inverses alternate between two buffers by step parity; the main
   // stream joins the side stream before the next step rewrites Cb and Dn.
@@ -541,13 +541,15 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
       GW_CHECK_LAUNCH(c, "k_gj_step");
     }
     if (nb2 > 0) {
-      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
-      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      // the look-ahead product runs alone on the main stream (short there), only
+      // the inversion overlaps the update
       st = zgemm_nn(c, nb2, nb2, nbk, -1.0, reinterpret_cast<const double*>(Cb), (size_t)k2 * GB,
                     GB, (long long)N * GB, reinterpret_cast<const double*>(R), (size_t)k2, N,
                     (long long)GB * N, reinterpret_cast<double*>(Dn), 0, GB, (long long)GB * GB,
-                    nfreq, nC, nR, nD, 1.0, c->side);
+                    nfreq, nC, nR, nD, 1.0);
       if (st != GW_OK) return st;
+      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
       {
         ProfScope ps(c, "gj_diag", c->side);
         hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->side, Dn, GB,
