@@ -69,6 +69,10 @@ CONFIGS = {
                          6, 20, (1e-3, 0.0, 0.0), (0.0, 2.0), q0_head=True),
     "T2": SystemConfig("T2", 13, (10.0, 10.4, 10.8), (20, 24, 30), 9.0, 4.5,
                        6, 40, (0.25, -0.25, 0.5), (0.0, 3.0)),
+    # Box lengths outside the compile-time FFT lengths and plane shapes: the
+    # runtime-length transform kernels.
+    "T3": SystemConfig("T3", 14, (10.0, 10.4, 10.8), (18, 20, 25), 8.0, 3.5,
+                       5, 30, (0.25, 0.0, -0.25), (0.0, 2.0)),
 }
 
 

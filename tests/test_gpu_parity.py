@@ -45,7 +45,7 @@ def _max_rel(x, ref):
 
 
 # ----------------------------------------------------------------- matrix elements
-@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
 def test_mtxel_fp64_matches_definition(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s)
@@ -53,7 +53,7 @@ def test_mtxel_fp64_matches_definition(P, ctx, name):
     assert _max_rel(out["mtxel"], ref) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["C1", "T2"])
+@pytest.mark.parametrize("name", ["C1", "T2", "T3"])
 def test_mtxel_fp32_matches_definition(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
@@ -111,7 +111,7 @@ def test_orthonormal_head_vanishes_at_q0(P, ctx):
 
 
 # ----------------------------------------------------------------- chi0 and eps^-1, FP64
-@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
 def test_chi0_and_epsinv_fp64(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s)
@@ -184,7 +184,7 @@ def test_chi0_pair_ranges_and_wings_match_oracle(P, ctx, prec):
 
 
 # ----------------------------------------------------------------- mixed precision
-@pytest.mark.parametrize("name", ["C1", "T1", "T2"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
 def test_mixed_path_within_1e4(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
