@@ -39,6 +39,17 @@ __host__ __device__ __forceinline__ cpx<T> scal(cpx<T> a, T s) { return mk(a.x *
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return mk(-a.y, a.x); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  Renumber so that XCD k receives the k-th contiguous slice of
+// the logical order (a grid of kXcd * ceil(total / kXcd) blocks); returns -1
+// for padding blocks.
+constexpr int kXcd = 8;
+__device__ __forceinline__ long long xcd_linear(long long b, long long total) {
+  const long long per = (total + kXcd - 1) / kXcd;
+  const long long l = (b % kXcd) * per + b / kXcd;
+  return l < total ? l : -1;
+}
+
 // ---------------------------------------------------------------- FFT plan
 // Length n = product of radices (each 2, 3, 4 or 5), executed as Stockham passes.
 struct FftPlan {

@@ -223,17 +223,9 @@ constexpr int kMaxB = 4;
 
 __device__ __forceinline__ int wrap(int g, int n) { return g < 0 ? g + n : g; }
 
-// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each XCD
-// has its own L2.  Renumber so that XCD k receives the k-th contiguous slice of
-// the logical order; the logical order is x-plane major, so one XCD walks a few
-// x-planes and keeps their valence planes resident in its L2 while the
-// conduction planes stream through once.  Returns -1 for padding blocks.
-constexpr int kXcd = 8;
-__device__ __forceinline__ long long xcd_linear(long long b, long long total) {
-  const long long per = (total + kXcd - 1) / kXcd;
-  const long long l = (b % kXcd) * per + b / kXcd;
-  return l < total ? l : -1;
-}
+// The pair kernels' logical order (xcd_linear) is x-plane major, so one XCD
+// walks a few x-planes and keeps their valence planes resident in its L2 while
+// the conduction planes stream through once.
 
 // ---------------------------------------------------------------- band transforms
 // Each kernel takes its pencil lengths as template arguments (0 = runtime).

@@ -20,6 +20,7 @@
 //   update : A22 -= L21 U12 on the FP64 matrix cores
 // then eps^-1 = U^-1 L^-1 P by blocked forward/back substitution on P*I.
 #include "common.h"
+#include "tiles.h"
 
 namespace gw {
 
@@ -221,89 +222,34 @@ __global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* 
   A[off] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
 }
 
-// Invert the nbk x nbk diagonal block A[K][K] (K = k..k+nbk) by unblocked
-// Gauss-Jordan without pivoting; write it to Dw[f].  A pivot that is not
-// real-positive sets flag[1].
-// Inverse of the diagonal block D = A[K][K] by Gauss-Jordan without pivoting,
-// register resident: thread (ti, tj) of a 32x32 grid holds entries
-// (ti + 32a, tj + 32b). Each step publishes the pivot row and column through
-// double-buffered LDS (one barrier per step). The in-place update is written
-// without branches:
-//   row t     <- (row t with 1 at the pivot) / p
-//   other i   <- (row i with 0 at the pivot) - a_it * (new row t)
-// A ragged block is padded with the identity, which leaves the leading
-// nbk x nbk inverse unchanged.
-// The block of frequency f is src[f * sstride + i * ld + j].
+// Inverse of the diagonal block D = A[K][K] (nbk <= GB = 64) by Gauss-Jordan
+// without pivoting, register resident (gj_invert_64); the block of frequency f
+// is src[f * sstride + i * ld + j] and its inverse goes to Dw[f]. A pivot that
+// is not real and >= 1/2 sets flag[1].
 __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ src, int ld,
                                                   size_t sstride, int nbk,
                                                   cpx<double>* __restrict__ Dw,
                                                   int* __restrict__ flag) {
-  constexpr int TG = 32, TE = GB / TG;
+  static_assert(GB == 64, "gj_invert_64 holds a 64x64 block");
   __shared__ cpx<double> rowb[2][GB], colb[2][GB];
   const int f = blockIdx.x;
   src += (size_t)f * sstride;
   Dw += (size_t)f * GB * GB;
-  const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
-  cpx<double> d[TE][TE];
+  const int tid = threadIdx.x, ti = tid / 32, tj = tid % 32;
+  cpx<double> d[2][2];
 #pragma unroll
-  for (int a = 0; a < TE; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int i = ti + TG * a, j = tj + TG * b;
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 32 * a, j = tj + 32 * b;
       d[a][b] = (i < nbk && j < nbk) ? src[(size_t)i * ld + j] : mk(i == j ? 1.0 : 0.0, 0.0);
     }
-  for (int t = 0; t < nbk; ++t) {
-    const int buf = t & 1, ta = t / TG, tr = t % TG;
-    // the pivot row and column, selected with constant indices so that d
-    // stays in registers
+  if (gj_invert_64(d, nbk, rowb, colb)) flag[1] = 1;
 #pragma unroll
-    for (int q = 0; q < TE; ++q) {
-      if (ti == tr && ta == q) {
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < TE; ++b) rowb[buf][tj + TG * b] = d[q][b];
-      }
-      if (tj == tr && ta == q) {
-#pragma unroll
-        for (int a = 0; a < TE; ++a) colb[buf][ti + TG * a] = d[a][q];
-      }
-    }
-    __syncthreads();
-    const cpx<double> p = rowb[buf][t];
-    // chi0 <= 0 makes epst >= I, so every pivot of the elimination is real and
-    // >= 1 up to rounding; a pivot below 1/2 or far from the real axis means
-    // the input is not of that form and the pivoted path must be used
-    if (tid == 0 && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY)) flag[1] = 1;
-    // 1/|p|^2 from the hardware reciprocal and two Newton steps (every thread
-    // computes it, so the full division sequence would dominate the step);
-    // a pivot that fails the check above is replaced on the pivoted path
-    const double den = p.x * p.x + p.y * p.y;
-    double r = __builtin_amdgcn_rcp(den);
-    r = fma(r, fma(-den, r, 1.0), r);
-    r = fma(r, fma(-den, r, 1.0), r);
-    const cpx<double> pinv = (den > 0.0) ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
-    cpx<double> rs[TE], cc[TE];
-#pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int j = tj + TG * b;
-      rs[b] = (j == t) ? pinv : cmul(rowb[buf][j], pinv);
-    }
-#pragma unroll
-    for (int a = 0; a < TE; ++a) cc[a] = colb[buf][ti + TG * a];
-#pragma unroll
-    for (int a = 0; a < TE; ++a)
-#pragma unroll
-      for (int b = 0; b < TE; ++b) {
-        const int i = ti + TG * a, j = tj + TG * b;
-        const cpx<double> dd = (j == t) ? mk(0.0, 0.0) : d[a][b];
-        d[a][b] = (i == t) ? rs[b] : dd - cmul(cc[a], rs[b]);
-      }
-    // the other buffer pair was last read before this step's barrier
-  }
-#pragma unroll
-  for (int a = 0; a < TE; ++a)
-#pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int i = ti + TG * a, j = tj + TG * b;
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 32 * a, j = tj + 32 * b;
       if (i < nbk && j < nbk) Dw[i * GB + j] = d[a][b];
     }
 }
@@ -366,6 +312,112 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
   if (e >= nbk * N) return;
   const int t = e / N, j = e % N;
   A[(size_t)(k + t) * N + j] = (j >= k && j < k + nbk) ? Dw[t * GB + (j - k)] : R[(size_t)t * N + j];
+}
+
+// The rank-nbk update A -= Cb R of every row and column (one matrix per
+// frequency), the bulk of each Gauss-Jordan step. With K at most GB the
+// product per output is short, and the C tile only streams through once, so the
+// kernel uses no LDS and no barrier: each wavefront computes a 32x32 block
+// (2x2 v_mfma_f64_16x16x4_f64, three real products per complex one) with its
+// fragments loaded straight from Cb (N x GB) and R (GB x N), which stay in L2;
+// the next four K are loaded while the current ones feed the matrix cores. C is
+// read in the epilogue and written back; the occupancy this allows (three
+// workgroups per CU) covers that latency with the other wavefronts' products.
+// Tiles of 64x64 are numbered frequency, row band, column band and renumbered
+// per XCD, so one XCD's L2 holds the panels of the tiles it runs.
+constexpr int UT = 64;  // workgroup tile (2x2 wavefronts of 32x32)
+__global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ A, int N,
+                                                      int kdim, const cpx<double>* __restrict__ Cb,
+                                                      const cpx<double>* __restrict__ R,
+                                                      int nfreq) {
+  const int nt = (N + UT - 1) / UT;
+  const long long lin = xcd_linear(blockIdx.x, (long long)nt * nt * nfreq);
+  if (lin < 0) return;
+  const int f = (int)(lin / ((long long)nt * nt));
+  const int rem = (int)(lin % ((long long)nt * nt));
+  const int ti = rem / nt, tj = rem % nt;
+  A += (size_t)f * N * N;
+  Cb += (size_t)f * N * GB;
+  R += (size_t)f * GB * N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int i0 = ti * UT + (wave >> 1) * 32, j0 = tj * UT + (wave & 1) * 32;
+  // fragment rows of Cb and columns of R; rows or columns past N are clamped
+  // (their products land in outputs that are not stored)
+  const int ia[2] = {min(i0 + l16, N - 1), min(i0 + 16 + l16, N - 1)};
+  const int jb[2] = {min(j0 + l16, N - 1), min(j0 + 16 + l16, N - 1)};
+  d4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
+    }
+  // K past kdim reads row/column kdim - 1 and is zeroed by selection (stale
+  // panel entries may hold anything, so they are never multiplied)
+  auto load = [&](int k0, cpx<double> (&fa)[2], cpx<double> (&fb)[2]) {
+    const int k = k0 + lk, kc = min(k, kdim - 1);
+    const bool ok = k < kdim;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const cpx<double> v = Cb[(size_t)ia[a] * GB + kc];
+      fa[a] = ok ? v : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const cpx<double> v = R[(size_t)kc * N + jb[b]];
+      fb[b] = ok ? v : mk(0.0, 0.0);
+    }
+  };
+  cpx<double> fa[2], fb[2];
+  load(0, fa, fb);
+  for (int k0 = 0; k0 < kdim; k0 += 4) {
+    cpx<double> na[2], nb[2];
+    if (k0 + 4 < kdim) load(k0 + 4, na, nb);
+    double sa[2], sb[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) sa[a] = fa[a].x + fa[a].y;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, t1[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].y, t2[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      fa[a] = na[a];
+      fb[a] = nb[a];
+    }
+  }
+  // C -= product: Re = t1 - t2, Im = t3 - t1 - t2 (f64 16x16x4 D layout:
+  // row lk + 4r, column l16)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + a * 16 + lk + 4 * r, j = j0 + b * 16 + l16;
+        if (i < N && j < N) {
+          cpx<double>* p = A + (size_t)i * N + j;
+          const cpx<double> v = *p;
+          *p = mk(v.x - (t1[a][b][r] - t2[a][b][r]),
+                  v.y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
+        }
+      }
 }
 
 // eps^-1 = S epst^-1 S^-1, in place.
@@ -560,10 +612,14 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
     }
     // A -= Cb R over the whole matrix: every row outside K is final, including
     // its K columns; row block K is rewritten by the next step's small kernel
-    st = zgemm_nn(c, N, N, nbk, -1.0, reinterpret_cast<const double*>(Cb), 0, GB,
-                  (long long)N * GB, reinterpret_cast<const double*>(R), 0, N, (long long)GB * N,
-                  epsinv, 0, N, (long long)nn, nfreq, nC, nR, ext);
-    if (st != GW_OK) return st;
+    {
+      ProfScope ps(c, "gj_update");
+      const int nt = (N + UT - 1) / UT;
+      const long long tiles = (long long)nt * nt * nfreq;
+      hipLaunchKernelGGL(k_gj_update, dim3((unsigned)(((tiles + kXcd - 1) / kXcd) * kXcd)),
+                         dim3(256), 0, c->stream, A, N, nbk, Cb, R, nfreq);
+      GW_CHECK_LAUNCH(c, "k_gj_update");
+    }
     if (nb2 > 0) GW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     kp = k;
     nbp = nbk;

@@ -92,71 +92,31 @@ __global__ void k_gjb_build(const GjM* __restrict__ ms, int* __restrict__ flags)
   m.A[idx] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
 }
 
-// Inverse of the diagonal block, register resident and branch free, as in the
-// single-matrix inversion: thread (ti, tj) of a 32x32 grid holds entries
-// (ti + 32a, tj + 32b); each step publishes the pivot row and column through
-// double-buffered LDS; a ragged block is padded with the identity.
+// Inverse of the diagonal block, register resident (gj_invert_64), as in the
+// single-matrix inversion; a ragged block is padded with the identity.
 __global__ void __launch_bounds__(1024) k_gjb_diag(const GjM* __restrict__ ms, int k,
                                                    int* __restrict__ flags) {
-  constexpr int TG = 32, TE = PB / TG;
+  static_assert(PB == 64, "gj_invert_64 holds a 64x64 block");
   const GjM m = ms[blockIdx.x];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
   __shared__ cpx<double> rowb[2][PB], colb[2][PB];
-  const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
-  cpx<double> d[TE][TE];
+  const int tid = threadIdx.x, ti = tid / 32, tj = tid % 32;
+  cpx<double> d[2][2];
 #pragma unroll
-  for (int a = 0; a < TE; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int i = ti + TG * a, j = tj + TG * b;
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 32 * a, j = tj + 32 * b;
       d[a][b] = (i < nbk && j < nbk) ? m.A[(size_t)(k + i) * N + k + j]
                                      : mk(i == j ? 1.0 : 0.0, 0.0);
     }
-  for (int t = 0; t < nbk; ++t) {
-    const int buf = t & 1, ta = t / TG, tr = t % TG;
+  if (gj_invert_64(d, nbk, rowb, colb)) flags[blockIdx.x] = 1;
 #pragma unroll
-    for (int q = 0; q < TE; ++q) {
-      if (ti == tr && ta == q) {
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < TE; ++b) rowb[buf][tj + TG * b] = d[q][b];
-      }
-      if (tj == tr && ta == q) {
-#pragma unroll
-        for (int a = 0; a < TE; ++a) colb[buf][ti + TG * a] = d[a][q];
-      }
-    }
-    __syncthreads();
-    const cpx<double> p = rowb[buf][t];
-    if (tid == 0 && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY))
-      flags[blockIdx.x] = 1;
-    const double den = p.x * p.x + p.y * p.y;
-    double r = __builtin_amdgcn_rcp(den);
-    r = fma(r, fma(-den, r, 1.0), r);
-    r = fma(r, fma(-den, r, 1.0), r);
-    const cpx<double> pinv = (den > 0.0) ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
-    cpx<double> rs[TE], cc[TE];
-#pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int j = tj + TG * b;
-      rs[b] = (j == t) ? pinv : cmul(rowb[buf][j], pinv);
-    }
-#pragma unroll
-    for (int a = 0; a < TE; ++a) cc[a] = colb[buf][ti + TG * a];
-#pragma unroll
-    for (int a = 0; a < TE; ++a)
-#pragma unroll
-      for (int b = 0; b < TE; ++b) {
-        const int i = ti + TG * a, j = tj + TG * b;
-        const cpx<double> dd = (j == t) ? mk(0.0, 0.0) : d[a][b];
-        d[a][b] = (i == t) ? rs[b] : dd - cmul(cc[a], rs[b]);
-      }
-  }
-#pragma unroll
-  for (int a = 0; a < TE; ++a)
-#pragma unroll
-    for (int b = 0; b < TE; ++b) {
-      const int i = ti + TG * a, j = tj + TG * b;
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 32 * a, j = tj + 32 * b;
       if (i < nbk && j < nbk) m.D[i * PB + j] = d[a][b];
     }
 }

@@ -441,6 +441,85 @@ __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict
       }
 }
 
+// ------------------------------------------------------------------ 64x64 Gauss-Jordan inverse
+// In-place inverse of the leading nbk x nbk block of a 64x64 matrix held by a
+// 1024-thread workgroup: thread (ti, tj) = (tid / 32, tid % 32) holds entries
+// (ti + 32a, tj + 32b) in d[a][b], the identity outside nbk (which leaves the
+// leading inverse unchanged). Gauss-Jordan without pivoting; step t:
+//   - the 32 lanes that hold row t (half a wavefront) take the pivot p from
+//     the lane on the diagonal, form 1/p (hardware reciprocal and two Newton
+//     steps), and publish row t times 1/p with 1/p at the pivot: that is also
+//     the row's final value;
+//   - the lanes that hold column t publish it with a zero in row t, and clear
+//     their entries of it outside row t;
+//   - after one barrier every thread subtracts col(i) row(j) from each entry.
+// Only the owners of the pivot row and column branch, and 1/p is formed once
+// per step. rowb and colb are two LDS buffers of 64 each, alternating by step
+// parity. Returns true on the diagonal lane of a step whose pivot is not real
+// and >= 1/2, which I minus a negative semidefinite matrix cannot give.
+__device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[2][2], int nbk,
+                                             cpx<double> (*rowb)[64], cpx<double> (*colb)[64]) {
+  const int tid = threadIdx.x, ti = tid >> 5, tj = tid & 31;
+  bool bad = false;
+  for (int t = 0; t < nbk; ++t) {
+    const int buf = t & 1, ta = t >> 5, tr = t & 31;
+    if (ti == tr) {
+      const cpx<double> own = ta == 0 ? d[0][0] : d[1][1];
+      const int src = (tid & 32) + tr;  // the diagonal lane of this half-wavefront
+      const cpx<double> p = mk(__shfl(own.x, src), __shfl(own.y, src));
+      if (tj == tr && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY)) bad = true;
+      const double den = p.x * p.x + p.y * p.y;
+      double r = __builtin_amdgcn_rcp(den);
+      r = fma(r, fma(-den, r, 1.0), r);
+      r = fma(r, fma(-den, r, 1.0), r);
+      const cpx<double> pinv = den > 0.0 ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (ta == q) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int j = tj + 32 * b;
+            const cpx<double> v = j == t ? pinv : cmul(d[q][b], pinv);
+            rowb[buf][j] = v;
+            d[q][b] = v;
+          }
+        }
+    }
+    if (tj == tr) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (ta == q) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            // row t's entry was replaced by 1/p above (same lane) and is not read
+            if (ti + 32 * a == t) {
+              colb[buf][t] = mk(0.0, 0.0);
+            } else {
+              colb[buf][ti + 32 * a] = d[a][q];
+              d[a][q] = mk(0.0, 0.0);
+            }
+          }
+        }
+    }
+    __syncthreads();
+    cpx<double> rs[2], cc[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) rs[b] = rowb[buf][tj + 32 * b];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) cc[a] = colb[buf][ti + 32 * a];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double xr = fma(-cc[a].x, rs[b].x, d[a][b].x);
+        const double xi = fma(-cc[a].x, rs[b].y, d[a][b].y);
+        d[a][b] = mk(fma(cc[a].y, rs[b].y, xr), fma(-cc[a].y, rs[b].x, xi));
+      }
+    // the other buffer pair was last read before this step's barrier
+  }
+  return bad;
+}
+
 // ------------------------------------------------------------------ complex-double GEMM tile
 // C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
 // (i0, j0), 256 threads (beta is 0 or 1).
