@@ -94,14 +94,6 @@ gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], Spher
   return GW_OK;
 }
 
-gw_status side_stream(gw_ctx* c) {
-  if (c->side) return GW_OK;
-  GW_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-  GW_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-  GW_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-  return GW_OK;
-}
-
 ProfScope::ProfScope(gw_ctx* cc, const char* nm, hipStream_t s)
     : c(cc), name(nm), st(s ? s : cc->stream) {
   if (!c->profiling) return;
@@ -203,12 +195,6 @@ gw_status gw_ctx_destroy(gw_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& kv : c->spheres) (void)hipFree(kv.second.d_cube);
   for (auto& kv : c->twiddles) (void)hipFree(kv.second);
-  if (c->side) {
-    (void)hipStreamSynchronize(c->side);
-    (void)hipEventDestroy(c->ev_fork);
-    (void)hipEventDestroy(c->ev_join);
-    (void)hipStreamDestroy(c->side);
-  }
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_flag) (void)hipFree(c->d_flag);
   delete c;

@@ -94,10 +94,6 @@ struct gw_ctx {
   std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
   int* d_flag = nullptr;                          // device status flags
   bool capturing = false;                         // inside a graph capture: no attribute calls
-  // second stream and events for work that overlaps the main stream (created on
-  // first use; default priority)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // networks and plans created on this context (freed with it)
   std::set<gw_mlp*> mlps;
   std::set<gw_plan*> plans;
@@ -113,7 +109,6 @@ struct gw_ctx {
 namespace gw {
 
 gw_status fail(gw_ctx* c, gw_status s, const char* fmt, ...);
-gw_status side_stream(gw_ctx* c);  // create c->side and its events if needed
 void mlp_free(gw_mlp* n);    // closure.hip: release without touching the context
 void plan_free(gw_plan* p);  // plan.hip
 gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what);

@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
       const int i = ti + 32 * a, j = tj + 32 * b;
       d[a][b] = (i < nbk && j < nbk) ? src[(size_t)i * ld + j] : mk(i == j ? 1.0 : 0.0, 0.0);
     }
-  if (gj_invert_64(d, nbk, rowb, colb)) flag[1] = 1;
+  if (gj_invert_64<32>(d, nbk, rowb, colb)) flag[1] = 1;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -260,15 +260,13 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
 //     its columns and Dp inside, its Gauss-Jordan value;
 //   - Cb[i][t] = A[i][k+t], the rows of the previous block taking those values;
 //   - R[t][k+j] = delta_tj + D[t][j]; with R in the K columns set this way,
-//     A[:,K] - Cb R leaves -Cb D in the column block, its Gauss-Jordan value;
-//   - Dn = A[K'][K'] for the look-ahead (k2, nb2; none when nb2 is 0).
+//     A[:,K] - Cb R leaves -Cb D in the column block, its Gauss-Jordan value.
 // No entry is both read and written: the previous block's rows are taken from
-// Rp and Dp, and the look-ahead block lies below both row blocks.
+// Rp and Dp.
 __global__ void k_gj_step(cpx<double>* __restrict__ A, int N, int k, int nbk,
                           cpx<double>* __restrict__ Cb, cpx<double>* __restrict__ R,
                           const cpx<double>* __restrict__ D, int kp, int nbp,
-                          const cpx<double>* __restrict__ Rp, const cpx<double>* __restrict__ Dp,
-                          int k2, int nb2, cpx<double>* __restrict__ Dn) {
+                          const cpx<double>* __restrict__ Rp, const cpx<double>* __restrict__ Dp) {
   const size_t f = blockIdx.y;
   A += f * (size_t)N * N;
   Cb += f * (size_t)N * GB;
@@ -276,7 +274,6 @@ __global__ void k_gj_step(cpx<double>* __restrict__ A, int N, int k, int nbk,
   Rp += f * (size_t)GB * N;
   D += f * (size_t)GB * GB;
   Dp += f * (size_t)GB * GB;
-  Dn += f * (size_t)GB * GB;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   auto fixed = [&](int t, int j) {
     return (j >= kp && j < kp + nbp) ? Dp[t * GB + (j - kp)] : Rp[(size_t)t * N + j];
@@ -295,10 +292,6 @@ __global__ void k_gj_step(cpx<double>* __restrict__ A, int N, int k, int nbk,
     const cpx<double> dv = D[t * GB + j];
     R[(size_t)t * N + k + j] = mk(dv.x + (t == j ? 1.0 : 0.0), dv.y);
   }
-  if (e < nb2 * nb2) {
-    const int i = e / nb2, j = e % nb2;
-    Dn[(size_t)i * GB + j] = A[(size_t)(k2 + i) * N + k2 + j];
-  }
 }
 
 // Row block K <- R outside the K columns and Dinv inside.
@@ -315,33 +308,32 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
 }
 
 // The rank-nbk update A -= Cb R of every row and column (one matrix per
-// frequency), the bulk of each Gauss-Jordan step. With K at most GB the
-// product per output is short, and the C tile only streams through once, so the
-// kernel uses no LDS and no barrier: each wavefront computes a 32x32 block
-// (2x2 v_mfma_f64_16x16x4_f64, three real products per complex one) with its
-// fragments loaded straight from Cb (N x GB) and R (GB x N), which stay in L2;
-// the next four K are loaded while the current ones feed the matrix cores. C is
-// read in the epilogue and written back; the occupancy this allows (three
-// workgroups per CU) covers that latency with the other wavefronts' products.
-// Tiles of 64x64 are numbered frequency, row band, column band and renumbered
-// per XCD, so one XCD's L2 holds the panels of the tiles it runs.
+// frequency), the bulk of each Gauss-Jordan step, with the next step's
+// diagonal inverse in the same launch.
+//   - Update tiles: with K at most GB the product per output is short and the C
+//     tile streams through once, so there is no LDS staging and no barrier.
+//     Each wavefront computes a 32x32 block (2x2 v_mfma_f64_16x16x4_f64, three
+//     real products per complex one) with its fragments loaded straight from
+//     Cb (N x GB) and R (GB x N), which stay in L2; the next four K are loaded
+//     while the current ones feed the matrix cores. C is read in the epilogue;
+//     three workgroups per CU cover that latency with the other wavefronts'
+//     products. Tiles of 64x64 are numbered frequency, row band, column band
+//     and renumbered per XCD, so one XCD's L2 holds the panels of its tiles.
+//   - Look-ahead (nb2 > 0): the first nfreq workgroups each form the next
+//     diagonal block Dn = A[K'][K'] - Cb[K'] R[:, K'] with the same tile code,
+//     invert it in registers (gj_invert_64, 16x16 threads holding 4x4 entries)
+//     and write the inverse to Dw. The update skips tile (K', K'): that block
+//     is only ever read into values that a later step overwrites (the next
+//     panel's K' columns and row block K', which the step after rewrites from
+//     R and Dinv), so no workgroup writes what another reads.
 constexpr int UT = 64;  // workgroup tile (2x2 wavefronts of 32x32)
-__global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ A, int N,
-                                                      int kdim, const cpx<double>* __restrict__ Cb,
-                                                      const cpx<double>* __restrict__ R,
-                                                      int nfreq) {
-  const int nt = (N + UT - 1) / UT;
-  const long long lin = xcd_linear(blockIdx.x, (long long)nt * nt * nfreq);
-  if (lin < 0) return;
-  const int f = (int)(lin / ((long long)nt * nt));
-  const int rem = (int)(lin % ((long long)nt * nt));
-  const int ti = rem / nt, tj = rem % nt;
-  A += (size_t)f * N * N;
-  Cb += (size_t)f * N * GB;
-  R += (size_t)f * GB * N;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void gj_update_tile(const cpx<double>* __restrict__ Cb,
+                                               const cpx<double>* __restrict__ R,
+                                               const cpx<double>* __restrict__ A, int N, int kdim,
+                                               int i0, int j0, int lim, cpx<double>* dst,
+                                               int ldd, int doff) {
+  const int lane = threadIdx.x & 63;
   const int l16 = lane & 15, lk = lane >> 4;
-  const int i0 = ti * UT + (wave >> 1) * 32, j0 = tj * UT + (wave & 1) * 32;
   // fragment rows of Cb and columns of R; rows or columns past N are clamped
   // (their products land in outputs that are not stored)
   const int ia[2] = {min(i0 + l16, N - 1), min(i0 + 16 + l16, N - 1)};
@@ -402,8 +394,8 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
       fb[a] = nb[a];
     }
   }
-  // C -= product: Re = t1 - t2, Im = t3 - t1 - t2 (f64 16x16x4 D layout:
-  // row lk + 4r, column l16)
+  // dst = A - product for rows and columns below lim: Re = t1 - t2,
+  // Im = t3 - t1 - t2 (f64 16x16x4 D layout: row lk + 4r, column l16)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -411,13 +403,64 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + a * 16 + lk + 4 * r, j = j0 + b * 16 + l16;
-        if (i < N && j < N) {
-          cpx<double>* p = A + (size_t)i * N + j;
-          const cpx<double> v = *p;
-          *p = mk(v.x - (t1[a][b][r] - t2[a][b][r]),
-                  v.y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
+        if (i < lim && j < lim) {
+          const cpx<double> v = A[(size_t)i * N + j];
+          dst[(size_t)(i - doff) * ldd + (j - doff)] =
+              mk(v.x - (t1[a][b][r] - t2[a][b][r]),
+                 v.y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
         }
       }
+}
+
+__global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ A, int N,
+                                                      int kdim, const cpx<double>* __restrict__ Cb,
+                                                      const cpx<double>* __restrict__ R,
+                                                      int nfreq, int k2, int nb2,
+                                                      cpx<double>* __restrict__ Dn,
+                                                      cpx<double>* __restrict__ Dw,
+                                                      int* __restrict__ flag) {
+  const int nt = (N + UT - 1) / UT;
+  const int wave = threadIdx.x >> 6;
+  const int ndiag = nb2 > 0 ? nfreq : 0;
+  if ((int)blockIdx.x < ndiag) {
+    static_assert(GB == 64 && UT == GB, "the look-ahead block is one 64x64 tile");
+    __shared__ cpx<double> rowb[2][GB], colb[2][GB];
+    const int f = blockIdx.x;
+    A += (size_t)f * N * N;
+    Dn += (size_t)f * GB * GB;
+    Dw += (size_t)f * GB * GB;
+    gj_update_tile(Cb + (size_t)f * N * GB, R + (size_t)f * GB * N, A, N, kdim,
+                   k2 + (wave >> 1) * 32, k2 + (wave & 1) * 32, k2 + nb2, Dn, GB, k2);
+    __syncthreads();  // Dn complete and visible to the workgroup
+    constexpr int TG = 16, TE = GB / TG;
+    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
+    cpx<double> d[TE][TE];
+#pragma unroll
+    for (int a = 0; a < TE; ++a)
+#pragma unroll
+      for (int b = 0; b < TE; ++b) {
+        const int i = ti + TG * a, j = tj + TG * b;
+        d[a][b] = (i < nb2 && j < nb2) ? Dn[i * GB + j] : mk(i == j ? 1.0 : 0.0, 0.0);
+      }
+    if (gj_invert_64<TG>(d, nb2, rowb, colb)) flag[1] = 1;
+#pragma unroll
+    for (int a = 0; a < TE; ++a)
+#pragma unroll
+      for (int b = 0; b < TE; ++b) {
+        const int i = ti + TG * a, j = tj + TG * b;
+        if (i < nb2 && j < nb2) Dw[i * GB + j] = d[a][b];
+      }
+    return;
+  }
+  const long long lin = xcd_linear(blockIdx.x - ndiag, (long long)nt * nt * nfreq);
+  if (lin < 0) return;
+  const int f = (int)(lin / ((long long)nt * nt));
+  const int rem = (int)(lin % ((long long)nt * nt));
+  const int ti = rem / nt, tj = rem % nt;
+  if (nb2 > 0 && ti == k2 / UT && tj == k2 / UT) return;
+  A += (size_t)f * N * N;
+  gj_update_tile(Cb + (size_t)f * N * GB, R + (size_t)f * GB * N, A, N, kdim,
+                 ti * UT + (wave >> 1) * 32, tj * UT + (wave & 1) * 32, N, A, N, 0);
 }
 
 // eps^-1 = S epst^-1 S^-1, in place.
@@ -537,9 +580,7 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
                                      const double* vcoul, double* epsinv) {
   const size_t nn = (size_t)N * N;
   const size_t nR = (size_t)nfreq * GB * N, nC = (size_t)nfreq * N * GB, nD = (size_t)nfreq * GB * GB;
-  gw_status st = side_stream(c);
-  if (st != GW_OK) return st;
-  st = ws_begin(c, 2 * align_up(nR * 16) + align_up(nC * 16) + 3 * align_up(nD * 16));
+  gw_status st = ws_begin(c, 2 * align_up(nR * 16) + align_up(nC * 16) + 3 * align_up(nD * 16));
   if (st != GW_OK) return st;
   cpx<double>* Rw[2] = {static_cast<cpx<double>*>(ws_take(c, nR * 16)),
                         static_cast<cpx<double>*>(ws_take(c, nR * 16))};
@@ -568,12 +609,10 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
     GW_CHECK_LAUNCH(c, "k_gj_diag");
   }
   const size_t ext = (size_t)nfreq * nn;
-  // Per step K the main stream runs the row panel, one small kernel and the rank
-  // update. Look-ahead: once the panels exist, the next diagonal block's updated
-  // value Dn = A[K'][K'] - Cb[K'] R[:,K'] is formed, and inverted on the side
-  // stream while the main stream runs the update. The panels R and the
-  // diagonal inverses alternate between two buffers by step parity; the main
-  // stream joins the side stream before the next step rewrites Cb and Dn.
+  // Per step K: the row panel R = Dinv A[K][:], one small kernel, and the rank
+  // update, whose launch also forms and inverts the next diagonal block (the
+  // look-ahead) on its first workgroups. The panels R and the diagonal inverses
+  // alternate between two buffers by step parity.
   int kp = 0, nbp = 0;
   for (int k = 0, s = 0; k < N; k += GB, ++s) {
     const int nbk = std::min(GB, N - k);
@@ -584,43 +623,24 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
                   (size_t)k * N, N, (long long)nn, reinterpret_cast<double*>(R), 0, N,
                   (long long)GB * N, nfreq, nD, ext, nR, 0.0);
     if (st != GW_OK) return st;
-    const int k2 = k + GB, nb2 = std::min(GB, N - k2) > 0 ? std::min(GB, N - k2) : 0;
     {
       ProfScope ps(c, "gj_small");
       hipLaunchKernelGGL(k_gj_step, dim3((N * GB + 255) / 256, nfreq), dim3(256), 0, c->stream,
-                         A, N, k, nbk, Cb, R, D, kp, nbp, Rw[(s + 1) & 1], Dw[(s + 1) & 1], k2,
-                         nb2, Dn);
+                         A, N, k, nbk, Cb, R, D, kp, nbp, Rw[(s + 1) & 1], Dw[(s + 1) & 1]);
       GW_CHECK_LAUNCH(c, "k_gj_step");
-    }
-    if (nb2 > 0) {
-      // the look-ahead product runs alone on the main stream (short there), only
-      // the inversion overlaps the update
-      st = zgemm_nn(c, nb2, nb2, nbk, -1.0, reinterpret_cast<const double*>(Cb), (size_t)k2 * GB,
-                    GB, (long long)N * GB, reinterpret_cast<const double*>(R), (size_t)k2, N,
-                    (long long)GB * N, reinterpret_cast<double*>(Dn), 0, GB, (long long)GB * GB,
-                    nfreq, nC, nR, nD, 1.0);
-      if (st != GW_OK) return st;
-      GW_HIP(c, hipEventRecord(c->ev_fork, c->stream));
-      GW_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-      {
-        ProfScope ps(c, "gj_diag", c->side);
-        hipLaunchKernelGGL(k_gj_diag, dim3(nfreq), dim3(1024), 0, c->side, Dn, GB,
-                           (size_t)GB * GB, nb2, Dw[(s + 1) & 1], c->d_flag);
-        GW_CHECK_LAUNCH(c, "k_gj_diag");
-      }
-      GW_HIP(c, hipEventRecord(c->ev_join, c->side));
     }
     // A -= Cb R over the whole matrix: every row outside K is final, including
     // its K columns; row block K is rewritten by the next step's small kernel
+    const int k2 = k + GB, nb2 = std::max(0, std::min(GB, N - k2));
     {
       ProfScope ps(c, "gj_update");
       const int nt = (N + UT - 1) / UT;
       const long long tiles = (long long)nt * nt * nfreq;
-      hipLaunchKernelGGL(k_gj_update, dim3((unsigned)(((tiles + kXcd - 1) / kXcd) * kXcd)),
-                         dim3(256), 0, c->stream, A, N, nbk, Cb, R, nfreq);
+      const long long grid = (nb2 > 0 ? nfreq : 0) + ((tiles + kXcd - 1) / kXcd) * kXcd;
+      hipLaunchKernelGGL(k_gj_update, dim3((unsigned)grid), dim3(256), 0, c->stream, A, N, nbk,
+                         Cb, R, nfreq, k2, nb2, Dn, Dw[(s + 1) & 1], c->d_flag);
       GW_CHECK_LAUNCH(c, "k_gj_update");
     }
-    if (nb2 > 0) GW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     kp = k;
     nbp = nbk;
   }

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(1024) k_gjb_diag(const GjM* __restrict__ ms, i
       d[a][b] = (i < nbk && j < nbk) ? m.A[(size_t)(k + i) * N + k + j]
                                      : mk(i == j ? 1.0 : 0.0, 0.0);
     }
-  if (gj_invert_64(d, nbk, rowb, colb)) flags[blockIdx.x] = 1;
+  if (gj_invert_64<32>(d, nbk, rowb, colb)) flags[blockIdx.x] = 1;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll

@@ -443,13 +443,13 @@ __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict
 
 // ------------------------------------------------------------------ 64x64 Gauss-Jordan inverse
 // In-place inverse of the leading nbk x nbk block of a 64x64 matrix held by a
-// 1024-thread workgroup: thread (ti, tj) = (tid / 32, tid % 32) holds entries
-// (ti + 32a, tj + 32b) in d[a][b], the identity outside nbk (which leaves the
-// leading inverse unchanged). Gauss-Jordan without pivoting; step t:
-//   - the 32 lanes that hold row t (half a wavefront) take the pivot p from
-//     the lane on the diagonal, form 1/p (hardware reciprocal and two Newton
-//     steps), and publish row t times 1/p with 1/p at the pivot: that is also
-//     the row's final value;
+// workgroup of TG*TG threads: thread (ti, tj) = (tid / TG, tid % TG) holds
+// entries (ti + TG a, tj + TG b) in d[a][b], the identity outside nbk (which
+// leaves the leading inverse unchanged). Gauss-Jordan without pivoting; step t:
+//   - the TG lanes that hold row t (one group inside a wavefront) take the
+//     pivot p from the lane on the diagonal, form 1/p (hardware reciprocal and
+//     two Newton steps), and publish row t times 1/p with 1/p at the pivot: that
+//     is also the row's final value;
 //   - the lanes that hold column t publish it with a zero in row t, and clear
 //     their entries of it outside row t;
 //   - after one barrier every thread subtracts col(i) row(j) from each entry.
@@ -457,15 +457,21 @@ __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict
 // per step. rowb and colb are two LDS buffers of 64 each, alternating by step
 // parity. Returns true on the diagonal lane of a step whose pivot is not real
 // and >= 1/2, which I minus a negative semidefinite matrix cannot give.
-__device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[2][2], int nbk,
+template <int TG>
+__device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[64 / TG][64 / TG], int nbk,
                                              cpx<double> (*rowb)[64], cpx<double> (*colb)[64]) {
-  const int tid = threadIdx.x, ti = tid >> 5, tj = tid & 31;
+  constexpr int TE = 64 / TG;
+  static_assert(TG * TE == 64 && 64 % TG == 0, "a row's owners must share a wavefront");
+  const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
   bool bad = false;
   for (int t = 0; t < nbk; ++t) {
-    const int buf = t & 1, ta = t >> 5, tr = t & 31;
+    const int buf = t & 1, ta = t / TG, tr = t % TG;
     if (ti == tr) {
-      const cpx<double> own = ta == 0 ? d[0][0] : d[1][1];
-      const int src = (tid & 32) + tr;  // the diagonal lane of this half-wavefront
+      cpx<double> own = d[0][0];
+#pragma unroll
+      for (int q = 1; q < TE; ++q)
+        if (ta == q) own = d[q][q];
+      const int src = (tid & 63 & ~(TG - 1)) + tr;  // the diagonal lane of this group
       const cpx<double> p = mk(__shfl(own.x, src), __shfl(own.y, src));
       if (tj == tr && !(p.x >= 0.5 && fabs(p.y) <= 0.25 * p.x && p.x < INFINITY)) bad = true;
       const double den = p.x * p.x + p.y * p.y;
@@ -474,11 +480,11 @@ __device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[2][2], int nbk,
       r = fma(r, fma(-den, r, 1.0), r);
       const cpx<double> pinv = den > 0.0 ? mk(p.x * r, -p.y * r) : mk(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < TE; ++q)
         if (ta == q) {
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int j = tj + 32 * b;
+          for (int b = 0; b < TE; ++b) {
+            const int j = tj + TG * b;
             const cpx<double> v = j == t ? pinv : cmul(d[q][b], pinv);
             rowb[buf][j] = v;
             d[q][b] = v;
@@ -487,30 +493,30 @@ __device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[2][2], int nbk,
     }
     if (tj == tr) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < TE; ++q)
         if (ta == q) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a) {
+          for (int a = 0; a < TE; ++a) {
             // row t's entry was replaced by 1/p above (same lane) and is not read
-            if (ti + 32 * a == t) {
+            if (ti + TG * a == t) {
               colb[buf][t] = mk(0.0, 0.0);
             } else {
-              colb[buf][ti + 32 * a] = d[a][q];
+              colb[buf][ti + TG * a] = d[a][q];
               d[a][q] = mk(0.0, 0.0);
             }
           }
         }
     }
     __syncthreads();
-    cpx<double> rs[2], cc[2];
+    cpx<double> rs[TE], cc[TE];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) rs[b] = rowb[buf][tj + 32 * b];
+    for (int b = 0; b < TE; ++b) rs[b] = rowb[buf][tj + TG * b];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) cc[a] = colb[buf][ti + 32 * a];
+    for (int a = 0; a < TE; ++a) cc[a] = colb[buf][ti + TG * a];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TE; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < TE; ++b) {
         const double xr = fma(-cc[a].x, rs[b].x, d[a][b].x);
         const double xi = fma(-cc[a].x, rs[b].y, d[a][b].y);
         d[a][b] = mk(fma(cc[a].y, rs[b].y, xr), fma(-cc[a].y, rs[b].x, xi));
