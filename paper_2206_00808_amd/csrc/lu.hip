@@ -327,90 +327,6 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
 //     panel's K' columns and row block K', which the step after rewrites from
 //     R and Dinv), so no workgroup writes what another reads.
 constexpr int UT = 64;  // workgroup tile (2x2 wavefronts of 32x32)
-__device__ __forceinline__ void gj_update_tile(const cpx<double>* __restrict__ Cb,
-                                               const cpx<double>* __restrict__ R,
-                                               const cpx<double>* __restrict__ A, int N, int kdim,
-                                               int i0, int j0, int lim, cpx<double>* dst,
-                                               int ldd, int doff) {
-  const int lane = threadIdx.x & 63;
-  const int l16 = lane & 15, lk = lane >> 4;
-  // fragment rows of Cb and columns of R; rows or columns past N are clamped
-  // (their products land in outputs that are not stored)
-  const int ia[2] = {min(i0 + l16, N - 1), min(i0 + 16 + l16, N - 1)};
-  const int jb[2] = {min(j0 + l16, N - 1), min(j0 + 16 + l16, N - 1)};
-  d4 t1[2][2], t2[2][2], t3[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      t1[a][b] = (d4){0, 0, 0, 0};
-      t2[a][b] = (d4){0, 0, 0, 0};
-      t3[a][b] = (d4){0, 0, 0, 0};
-    }
-  // K past kdim reads row/column kdim - 1 and is zeroed by selection (stale
-  // panel entries may hold anything, so they are never multiplied)
-  auto load = [&](int k0, cpx<double> (&fa)[2], cpx<double> (&fb)[2]) {
-    const int k = k0 + lk, kc = min(k, kdim - 1);
-    const bool ok = k < kdim;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const cpx<double> v = Cb[(size_t)ia[a] * GB + kc];
-      fa[a] = ok ? v : mk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const cpx<double> v = R[(size_t)kc * N + jb[b]];
-      fb[b] = ok ? v : mk(0.0, 0.0);
-    }
-  };
-  cpx<double> fa[2], fb[2];
-  load(0, fa, fb);
-  for (int k0 = 0; k0 < kdim; k0 += 4) {
-    cpx<double> na[2], nb[2];
-    if (k0 + 4 < kdim) load(k0 + 4, na, nb);
-    double sa[2], sb[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) sa[a] = fa[a].x + fa[a].y;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) sb[b] = fb[b].x + fb[b].y;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, t1[a][b], 0, 0, 0);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].y, t2[a][b], 0, 0, 0);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      fa[a] = na[a];
-      fb[a] = nb[a];
-    }
-  }
-  // dst = A - product for rows and columns below lim: Re = t1 - t2,
-  // Im = t3 - t1 - t2 (f64 16x16x4 D layout: row lk + 4r, column l16)
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + a * 16 + lk + 4 * r, j = j0 + b * 16 + l16;
-        if (i < lim && j < lim) {
-          const cpx<double> v = A[(size_t)i * N + j];
-          dst[(size_t)(i - doff) * ldd + (j - doff)] =
-              mk(v.x - (t1[a][b][r] - t2[a][b][r]),
-                 v.y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
-        }
-      }
-}
 
 __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ A, int N,
                                                       int kdim, const cpx<double>* __restrict__ Cb,
@@ -429,7 +345,7 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
     A += (size_t)f * N * N;
     Dn += (size_t)f * GB * GB;
     Dw += (size_t)f * GB * GB;
-    gj_update_tile(Cb + (size_t)f * N * GB, R + (size_t)f * GB * N, A, N, kdim,
+    gj_update_tile(Cb + (size_t)f * N * GB, GB, R + (size_t)f * GB * N, A, N, kdim,
                    k2 + (wave >> 1) * 32, k2 + (wave & 1) * 32, k2 + nb2, Dn, GB, k2);
     __syncthreads();  // Dn complete and visible to the workgroup
     constexpr int TG = 16, TE = GB / TG;
@@ -459,7 +375,7 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
   const int ti = rem / nt, tj = rem % nt;
   if (nb2 > 0 && ti == k2 / UT && tj == k2 / UT) return;
   A += (size_t)f * N * N;
-  gj_update_tile(Cb + (size_t)f * N * GB, R + (size_t)f * GB * N, A, N, kdim,
+  gj_update_tile(Cb + (size_t)f * N * GB, GB, R + (size_t)f * GB * N, A, N, kdim,
                  ti * UT + (wave >> 1) * 32, tj * UT + (wave & 1) * 32, N, A, N, 0);
 }
 

@@ -149,14 +149,17 @@ __global__ void k_gjb_prep(const GjM* __restrict__ ms, int k) {
   }
 }
 
-// A -= Cb R over the whole matrix
-__global__ void __launch_bounds__(256, 2) k_gjb_update(const GjM* __restrict__ ms, int k) {
+// A -= Cb R over the whole matrix (the LDS-free rank-update tile)
+__global__ void __launch_bounds__(256, 3) k_gjb_update(const GjM* __restrict__ ms, int k) {
+  static_assert(PB == 64, "one 64x64 tile per workgroup");
   const GjM m = ms[blockIdx.z];
   if (k >= m.N) return;
   const int N = m.N, nbk = min(PB, N - k);
-  const int i0 = blockIdx.y * ZTM, j0 = blockIdx.x * ZTM;
+  const int i0 = blockIdx.y * PB, j0 = blockIdx.x * PB;
   if (i0 >= N || j0 >= N) return;
-  zgemm_tile(N, N, nbk, -1.0, 1.0, m.Cb, PB, m.R, N, m.A, N, i0, j0);
+  const int wave = threadIdx.x >> 6;
+  gj_update_tile(m.Cb, PB, m.R, m.A, N, nbk, i0 + (wave >> 1) * 32, j0 + (wave & 1) * 32, N,
+                 m.A, N, 0);
 }
 
 // row block K <- R outside the K columns and Dinv inside

@@ -526,6 +526,100 @@ __device__ __forceinline__ bool gj_invert_64(cpx<double> (&d)[64 / TG][64 / TG],
   return bad;
 }
 
+// ------------------------------------------------------------------ Gauss-Jordan rank-update tile
+// dst = A - Cb R on one 64x64 tile (i0, j0 per wavefront: 2x2 wavefronts of
+// 32x32) for K = kdim <= 64, rows and columns below lim, dst entry (i, j) at
+// (i - doff) * ldd + (j - doff). No LDS and no barrier: fragments come straight
+// from Cb (N x ldcb) and R (kdim x N, row stride N), which stay in L2, with the
+// next four K loaded while the current ones feed the matrix cores; 2x2
+// v_mfma_f64_16x16x4_f64 blocks, three real products per complex one; A is read
+// in the epilogue (dst may be A: each entry is read before it is written, by
+// the same lane).
+__device__ __forceinline__ void gj_update_tile(const cpx<double>* __restrict__ Cb, int ldcb,
+                                               const cpx<double>* __restrict__ R,
+                                               const cpx<double>* A, int N, int kdim,
+                                               int i0, int j0, int lim, cpx<double>* dst,
+                                               int ldd, int doff) {
+  const int lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // fragment rows of Cb and columns of R; rows or columns past N are clamped
+  // (their products land in outputs that are not stored)
+  const int ia[2] = {min(i0 + l16, N - 1), min(i0 + 16 + l16, N - 1)};
+  const int jb[2] = {min(j0 + l16, N - 1), min(j0 + 16 + l16, N - 1)};
+  d4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
+    }
+  // K past kdim reads row/column kdim - 1 and is zeroed by selection (stale
+  // panel entries may hold anything, so they are never multiplied)
+  auto load = [&](int k0, cpx<double> (&fa)[2], cpx<double> (&fb)[2]) {
+    const int k = k0 + lk, kc = min(k, kdim - 1);
+    const bool ok = k < kdim;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const cpx<double> v = Cb[(size_t)ia[a] * ldcb + kc];
+      fa[a] = ok ? v : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const cpx<double> v = R[(size_t)kc * N + jb[b]];
+      fb[b] = ok ? v : mk(0.0, 0.0);
+    }
+  };
+  cpx<double> fa[2], fb[2];
+  load(0, fa, fb);
+  for (int k0 = 0; k0 < kdim; k0 += 4) {
+    cpx<double> na[2], nb[2];
+    if (k0 + 4 < kdim) load(k0 + 4, na, nb);
+    double sa[2], sb[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) sa[a] = fa[a].x + fa[a].y;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, t1[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].y, t2[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      fa[a] = na[a];
+      fb[a] = nb[a];
+    }
+  }
+  // dst = A - product for rows and columns below lim: Re = t1 - t2,
+  // Im = t3 - t1 - t2 (f64 16x16x4 D layout: row lk + 4r, column l16)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + a * 16 + lk + 4 * r, j = j0 + b * 16 + l16;
+        if (i < lim && j < lim) {
+          const cpx<double> v = A[(size_t)i * N + j];
+          dst[(size_t)(i - doff) * ldd + (j - doff)] =
+              mk(v.x - (t1[a][b][r] - t2[a][b][r]),
+                 v.y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
+        }
+      }
+}
+
 // ------------------------------------------------------------------ complex-double GEMM tile
 // C[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C[i][j] on the 64x64 tile at
 // (i0, j0), 256 threads (beta is 0 or 1).
