@@ -605,13 +605,22 @@ constexpr int pow2_at_least(int n) {
 
 constexpr int cs_split(int n) { return n == 48 ? 8 : split_n1(n); }
 
+// Offset of entry k within a row of an LDS plane. LAYOUT 1 (8-byte entries, 4
+// lanes per row, row pitch 60 for length 48) puts one pad entry after every 4,
+// so that the z pass's accesses (4 consecutive entries of 8 rows, or entries 4
+// apart) fall in distinct banks (64 banks of 4 bytes); LAYOUT 0 is plain rows.
+template <int LAYOUT>
+__device__ __forceinline__ int zoff(int k) {
+  return LAYOUT == 1 ? k + (k >> 2) : k;
+}
+
 // Full x-plane of one band and spinor component, built in LDS from its slab of
 // the compact (y,z) cube that k_band_x writes (src[jy * ezw + jz], |g| <= gyw,
 // gzw). It takes the y transforms of the occupied z columns (into Zw, pitch
 // ZWP), then the z transforms of every row (into P, pitch PP). A2/A3 lanes per
 // pencil, all in one wavefront: each exchange goes through the pencil's own LDS
 // line, with every read of a stage finished before its writes.
-template <typename T, int N2, int N3, int A2, int A3, int NTH>
+template <typename T, int N2, int N3, int A2, int A3, int NTH, int LAYOUT>
 __device__ __forceinline__ void build_plane(const cpx<T>* __restrict__ src, int ezw, int gyw,
                                             int gzw, const cpx<T>* tw2, const cpx<T>* tw3,
                                             cpx<T>* Zw, int ZWP, cpx<T>* P, int PP, int tid) {
@@ -675,7 +684,7 @@ __device__ __forceinline__ void build_plane(const cpx<T>* __restrict__ src, int 
         for (int k2 = 1; k2 < B3; ++k2) a[k2] = cmul(a[k2], tw3[t * k2]);
         cpx<T>* row = P + y * PP;
 #pragma unroll
-        for (int k2 = 0; k2 < B3; ++k2) row[k2 * A3 + t] = a[k2];
+        for (int k2 = 0; k2 < B3; ++k2) row[zoff<LAYOUT>(k2 * A3 + t)] = a[k2];
         __builtin_amdgcn_wave_barrier();
         cpx<T> o[NR3][A3];
 #pragma unroll
@@ -683,7 +692,7 @@ __device__ __forceinline__ void build_plane(const cpx<T>* __restrict__ src, int 
           const int k2 = t + A3 * r;
           if (k2 < B3) {
 #pragma unroll
-            for (int n = 0; n < A3; ++n) o[r][n] = row[k2 * A3 + n];
+            for (int n = 0; n < A3; ++n) o[r][n] = row[zoff<LAYOUT>(k2 * A3 + n)];
             reg_dft<T, A3>(o[r]);
           }
         }
@@ -693,7 +702,7 @@ __device__ __forceinline__ void build_plane(const cpx<T>* __restrict__ src, int 
           const int k2 = t + A3 * r;
           if (k2 < B3) {
 #pragma unroll
-            for (int k1 = 0; k1 < A3; ++k1) row[k2 + B3 * k1] = o[r][k1];
+            for (int k1 = 0; k1 < A3; ++k1) row[zoff<LAYOUT>(k2 + B3 * k1)] = o[r][k1];
           }
         }
       }
@@ -763,8 +772,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_pair_cs(
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const cpx<T>* src = tc + (((size_t)(c0 + cl) * NS + s) * n1 + x) * ncw;
-    build_plane<T, N2, N3, S::A2, S::A3, kThreads>(src, ezw, gyw, gzw, tw2, tw3, Zb, ezw | 1, P,
-                                                   S::PP, tid);
+    build_plane<T, N2, N3, S::A2, S::A3, kThreads, 0>(src, ezw, gyw, gzw, tw2, tw3, Zb, ezw | 1,
+                                                      P, S::PP, tid);
 #pragma unroll
     for (int i = 0; i < S::NI; ++i) {
       const int e = tid + kThreads * i;
@@ -884,7 +893,8 @@ struct RrShape {
   static constexpr int A3 = split_n1(N3), B3 = N3 / A3, L3 = pow2_at_least(A3);
   static constexpr int A2 = split_n1(N2), B2 = N2 / A2, L2 = pow2_at_least(A2);
   static constexpr int NTH = N2 * L3;  // threads: one lane group per row
-  static constexpr int PP = N3 + 1;    // exchange row pitch
+  static constexpr int LAYOUT = N3 == 48 && A3 == 4 ? 1 : 0;  // exchange row layout (zoff)
+  static constexpr int PP = LAYOUT ? N3 + N3 / 4 : N3 + 1;     // exchange row pitch
   static constexpr int CPP = NTH / L2; // y columns per pass
   static_assert(64 % L3 == 0 && 64 % L2 == 0, "a row or column must sit in one wavefront");
   static_assert(NTH <= 1024 && NTH % 64 == 0, "block must be whole wavefronts");
@@ -928,6 +938,7 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
   for (int i = tid; i < N2; i += S::NTH) tw2[i] = twy[i];
   const int y = tid / S::L3, t = tid % S::L3;
   const bool act = t < S::A3;
+  cpx<T>* Xr = X + y * S::PP;
   const size_t nb = (size_t)n1 * N2 * N3;
   const size_t roff = ((size_t)x * N2 + y) * N3 + t;
 
@@ -945,15 +956,15 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const cpx<T>* src = tc + (((size_t)(c0 + cl) * NS + s) * n1 + x) * ncw;
-    build_plane<T, N2, N3, S::A2, S::A3, S::NTH>(src, ezw, gyw, gzw, tw2, tw3, Zb, ezw | 1, X,
+    build_plane<T, N2, N3, S::A2, S::A3, S::NTH, S::LAYOUT>(src, ezw, gyw, gzw, tw2, tw3, Zb,
+                                                           ezw | 1, X,
                                                  S::PP, tid);
     if (act) {
 #pragma unroll
-      for (int m = 0; m < S::B3; ++m) cr[s][m] = X[y * S::PP + t + S::A3 * m];
+      for (int m = 0; m < S::B3; ++m) cr[s][m] = Xr[zoff<S::LAYOUT>(t + S::A3 * m)];
     }
   }
 
-  cpx<T>* Xr = X + y * S::PP;
   for (int g0 = 0; g0 < nvt; g0 += vb) {
     const int nbv = min(vb, nvt - g0);
     for (int j = 0; j < nbv; ++j) {
@@ -972,7 +983,7 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
 #pragma unroll
         for (int k2 = 1; k2 < S::B3; ++k2) a[k2] = cmul(a[k2], tw3[t * k2]);
 #pragma unroll
-        for (int k2 = 0; k2 < S::B3; ++k2) Xr[k2 * S::A3 + t] = a[k2];
+        for (int k2 = 0; k2 < S::B3; ++k2) Xr[zoff<S::LAYOUT>(k2 * S::A3 + t)] = a[k2];
       }
       __builtin_amdgcn_wave_barrier();
       if (act) {
@@ -983,7 +994,7 @@ __global__ void __launch_bounds__((RrShape<T, N2, N3>::NTH), 3) k_pair_rr(
           if (k2 < S::B3) {
             cpx<T> u[S::A3];
 #pragma unroll
-            for (int n = 0; n < S::A3; ++n) u[n] = Xr[k2 * S::A3 + n];
+            for (int n = 0; n < S::A3; ++n) u[n] = Xr[zoff<S::LAYOUT>(k2 * S::A3 + n)];
             reg_dft<T, S::A3>(u);
 #pragma unroll
             for (int k1 = 0; k1 < S::A3; ++k1) {
