@@ -184,6 +184,8 @@ gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, 
 // The split-BF16 contraction first splits its operands into `xsplit`
 // (bf16_split_bytes(P, neps, nfreq) bytes of device workspace).
 size_t bf16_split_bytes(int P, int neps, int nfreq);
+gw_status split_bf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq, const double* wts,
+                     void* xsplit);
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
                          const double* wts, int skip_head, double* chi0, int split, double* part,
                          void* xsplit);

@@ -209,6 +209,19 @@ size_t bf16_split_bytes(int P, int neps, int nfreq) {
   return (size_t)(1 + nfreq) * Pb * 4 * neps * BK * sizeof(unsigned short);
 }
 
+// X_0 = M and X_{1+f} = w_f M, split into bf16 hi/lo planes (k_bf16_split)
+gw_status split_bf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq, const double* wts,
+                     void* xsplit) {
+  if (P <= 0 || neps <= 0) return GW_OK;
+  const int Pb = (P + BK - 1) / BK;
+  ProfScope ps(c, "bf16_split");
+  hipLaunchKernelGGL(k_bf16_split, dim3(Pb, (neps + 63) / 64, 1 + nfreq), dim3(256), 0,
+                     c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+                     static_cast<unsigned short*>(xsplit));
+  GW_CHECK_LAUNCH(c, "k_bf16_split");
+  return GW_OK;
+}
+
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
                          const double* wts, int skip_head, double* chi0, int split, double* part,
                          void* xsplit) {
@@ -218,12 +231,8 @@ gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfre
   if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
     return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
   auto* X = static_cast<unsigned short*>(xsplit);
-  {
-    ProfScope ps(c, "bf16_split");
-    hipLaunchKernelGGL(k_bf16_split, dim3(Pb, (neps + 63) / 64, 1 + nfreq), dim3(256), 0,
-                       c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts, X);
-    GW_CHECK_LAUNCH(c, "k_bf16_split");
-  }
+  gw_status st = split_bf16(c, P, neps, mtxel, nfreq, wts, xsplit);
+  if (st != GW_OK) return st;
   {
     ProfScope ps(c, "chi0_bf16x3");
     hipLaunchKernelGGL(k_chi0_bf16s<kChiWM>, dim3(ntri, nfreq, split), dim3(64 * kChiWM * kChiWM),

@@ -32,6 +32,7 @@ gw_status epsinv_pivoted_one(gw_ctx* c, int N, int nfreq, const double* chi0, co
 
 struct ChiQ {
   const void* M;
+  const unsigned short* X;  // split-BF16 operands (split_bf16 layout), or null
   const double* w;
   double* chi;
   int P, neps, skip, pad;
@@ -59,9 +60,12 @@ __global__ void __launch_bounds__(64 * WM * WM, WM == 2 ? 2 : 1) k_chi0_items(co
     const ChiQ q = qs[m.x];
     const double* w = q.w + (size_t)m.w * q.P;
     cpx<double>* C = reinterpret_cast<cpx<double>*>(q.chi) + (size_t)m.w * q.neps * q.neps;
-    if constexpr (BF16)
-      chi0_bf16_tile<WM>(static_cast<const cpx<float>*>(q.M), q.P, q.neps, w, C, m.y, m.z, q.skip);
-    else
+    if constexpr (BF16) {
+      const int Pb = (q.P + BK - 1) / BK;
+      const size_t osz = (size_t)Pb * 4 * q.neps * BK;
+      chi0_bf16s_tile<WM>(q.X, q.X + (size_t)(1 + m.w) * osz, 0, Pb, q.neps, C, m.y, m.z, q.skip,
+                          false);
+    } else
       chi0_f64_tile<WM, Tin>(static_cast<const cpx<Tin>*>(q.M), q.P, q.neps, w, C, m.y, m.z,
                              q.skip);
   }
@@ -195,6 +199,7 @@ struct gw_plan_q {
   int* dmatch = nullptr;
   int nmatch = 0;
   double* wts = nullptr;
+  void* X = nullptr;  // split-BF16 operands of the contraction
   std::vector<int> match;
 };
 
@@ -377,6 +382,10 @@ static gw_status enqueue_front(gw_plan* p) {
     }
     st = chi0_weights(c, nv, nc, q.d.ev, q.d.ec, p->nfreq, p->d_omega, p->pref, q.wts);
     if (st != GW_OK) return st;
+    if (q.X) {
+      st = split_bf16(c, q.P, q.d.neps, q.M, p->nfreq, q.wts, q.X);
+      if (st != GW_OK) return st;
+    }
   }
   return GW_OK;
 }
@@ -640,6 +649,8 @@ gw_status gw_plan_compile(gw_plan* p) {
   for (auto& q : p->q) {
     parts.push_back({&q.M, (size_t)q.P * q.d.neps * elem});
     parts.push_back({reinterpret_cast<void**>(&q.wts), (size_t)p->nfreq * q.P * sizeof(double)});
+    if (p->prec == GW_PREC_SPLITBF16)
+      parts.push_back({&q.X, bf16_split_bytes(q.P, q.d.neps, p->nfreq)});
     if (q.d.head_index >= 0) {
       parts.push_back({reinterpret_cast<void**>(&q.mhead), (size_t)q.P * 16});
       parts.push_back({reinterpret_cast<void**>(&q.dmatch), std::max<size_t>(16, q.match.size() * 4)});
@@ -676,6 +687,7 @@ gw_status gw_plan_compile(gw_plan* p) {
     if (q.d.head_index >= 0 && q.nmatch == 0)
       return fail(c, GW_EINVAL, "q %zu: no common G between the valence and conduction spheres", i);
     hq[i].M = q.M;
+    hq[i].X = static_cast<const unsigned short*>(q.X);
     hq[i].w = q.wts;
     hq[i].chi = q.d.chi0;
     hq[i].P = q.P;

@@ -186,143 +186,12 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
 // ------------------------------------------------------------------ split-BF16 chi0 tile
 // Each float x = hi + lo, hi = bf16_rn(x), lo = bf16_rn(x - hi); every real
 // product is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with float
-// accumulation flushed into double registers every KFLUSH pairs.
-template <int WM>
-__device__ __forceinline__ void chi0_bf16_tile(const cpx<float>* __restrict__ M, int P, int neps,
-                                               const double* __restrict__ w,
-                                               cpx<double>* __restrict__ C, int ti, int tj,
-                                               int skip_head, bool overwrite = false) {
-  constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (BK * TMv) / NT;
-  __shared__ __align__(16) unsigned short As[4][TMv][BKP];
-  __shared__ __align__(16) unsigned short Bs[4][TMv][BKP];
-  const int i0 = ti * TMv, j0 = tj * TMv;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / WM, wc = wave % WM;
-  const int l16 = lane & 15, lk = lane >> 4;
-  double dr[2][2][4], di[2][2][4];
-  f4 cr[2][2], ci[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cr[a][b] = (f4){0, 0, 0, 0};
-      ci[a][b] = (f4){0, 0, 0, 0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
-    }
-  int since_flush = 0;
-  cpx<float> ra[NE], rb[NE];
-  double rw[NE];
-  auto gload = [&](int p0) {
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int idx = tid + e * NT;
-      const int kk = idx / TMv, ii = idx % TMv;
-      const int p = min(p0 + kk, P - 1);
-      ra[e] = M[(size_t)p * neps + min(i0 + ii, neps - 1)];
-      rb[e] = M[(size_t)p * neps + min(j0 + ii, neps - 1)];
-      rw[e] = w[p];
-    }
-  };
-  gload(0);
-  for (int p0 = 0; p0 < P; p0 += BK) {
-    // stage: BK pairs x TM columns of A (=M) and B (=w*M), split into hi/lo
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int idx = tid + e * NT;
-      const int kk = idx / TMv, ii = idx % TMv;
-      const bool pk = p0 + kk < P;
-      const float ma = (pk && i0 + ii < neps) ? 1.f : 0.f;
-      const float wf = (pk && j0 + ii < neps) ? (float)rw[e] : 0.f;
-      const float ar = ma * ra[e].x, ai = ma * ra[e].y;
-      const float br = wf * rb[e].x, bi = wf * rb[e].y;
-      unsigned short h;
-      h = bf16_rn_bits(ar); As[0][ii][kk] = h; As[1][ii][kk] = bf16_rn_bits(ar - bf16_to_f(h));
-      h = bf16_rn_bits(ai); As[2][ii][kk] = h; As[3][ii][kk] = bf16_rn_bits(ai - bf16_to_f(h));
-      h = bf16_rn_bits(br); Bs[0][ii][kk] = h; Bs[1][ii][kk] = bf16_rn_bits(br - bf16_to_f(h));
-      h = bf16_rn_bits(bi); Bs[2][ii][kk] = h; Bs[3][ii][kk] = bf16_rn_bits(bi - bf16_to_f(h));
-    }
-    __syncthreads();
-    if (p0 + BK < P) gload(p0 + BK);
-    bf8 a[2][4], b[2][4];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[x][q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + x * 16 + l16][lk * 8]);
-        b[x][q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + x * 16 + l16][lk * 8]);
-      }
-    // the fragments are in registers: the tile may be restaged after this point
-    __syncthreads();
-    // -ai as the A operand of the ai*br terms (sign bit of every bf16 lane)
-    bf8 na[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-        us8 t = __builtin_bit_cast(us8, a[x][2 + q]);
-        t ^= (us8)(0x8000);
-        na[x][q] = __builtin_bit_cast(bf8, t);
-      }
-    // Re += ar*br + ai*bi, Im += ar*bi - ai*br, each real product as
-    // hi*hi + hi*lo + lo*hi; terms outermost so consecutive MFMAs go to
-    // different accumulators
-#define GW_MF(ACC, A, B)                                                      \
-  _Pragma("unroll") for (int x = 0; x < 2; ++x) _Pragma("unroll") for (int y = 0; y < 2; ++y) \
-      ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, ACC[x][y], 0, 0, 0);
-    GW_MF(cr, a[x][0], b[y][0])
-    GW_MF(ci, a[x][0], b[y][2])
-    GW_MF(cr, a[x][0], b[y][1])
-    GW_MF(ci, a[x][0], b[y][3])
-    GW_MF(cr, a[x][1], b[y][0])
-    GW_MF(ci, a[x][1], b[y][2])
-    GW_MF(cr, a[x][2], b[y][2])
-    GW_MF(ci, na[x][0], b[y][0])
-    GW_MF(cr, a[x][2], b[y][3])
-    GW_MF(ci, na[x][0], b[y][1])
-    GW_MF(cr, a[x][3], b[y][2])
-    GW_MF(ci, na[x][1], b[y][0])
-#undef GW_MF
-    since_flush += BK;
-    if (since_flush >= KFLUSH || p0 + BK >= P) {
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            dr[x][y][r] += (double)cr[x][y][r];
-            di[x][y][r] += (double)ci[x][y][r];
-          }
-          cr[x][y] = (f4){0, 0, 0, 0};
-          ci[x][y] = (f4){0, 0, 0, 0};
-        }
-      since_flush = 0;
-    }
-  }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
-        const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
-        double im = di[x][y][r];
-        bool od;
-        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
-        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], im, od, skip_head);
-        else herm_add(C, neps, i, j, dr[x][y][r], im, od, skip_head);
-      }
-}
-
-// ------------------------------------------------------------------ split-BF16 chi0 tile, pre-split operands
-// The same contraction with the operands split once in advance (k_bf16_split):
-// X[pb][q][G][32] holds, for pair block pb (32 pairs, zero-padded past P) and
-// plane q = (re hi, re lo, im hi, im lo), the bf16 bits of column G. A slab is
-// then a contiguous 4 KiB per plane and is staged with 16-byte loads and LDS
-// stores, leaving the VALU free for the MFMA issue. The arithmetic is the
-// split-on-the-fly tile's, so the two give identical results.
+// accumulation flushed into double registers every KFLUSH pairs. The operands
+// are split once in advance (k_bf16_split): X[pb][q][G][32] holds, for pair
+// block pb (32 pairs, zero-padded past P) and plane q = (re hi, re lo, im hi,
+// im lo), the bf16 bits of column G. A slab is then a contiguous 4 KiB per
+// plane and is staged with 16-byte loads and LDS stores, leaving the VALU free
+// for the MFMA issue.
 template <int WM>
 __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict__ XA,
                                                 const unsigned short* __restrict__ XB, int pb0,
