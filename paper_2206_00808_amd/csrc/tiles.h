@@ -72,6 +72,135 @@ __device__ __forceinline__ void herm_store(cpx<double>* C, int neps, int i, int 
   if (offdiag) C[(size_t)j * neps + i] = mk(re, -im);
 }
 
+// ------------------------------------------------------------------ FP64 chi0 tile, direct LDS loads
+// The 64x64 complex-double tile (2x2 wavefronts of 32x32) with its operand rows
+// loaded straight into LDS by global_load_lds_dwordx4: a row of 64 columns of
+// M (1 KiB) is one wavefront instruction, each lane's 16 bytes landing at
+// lane * 16 of the row, so the slab needs no registers, no VALU and no LDS
+// stores on its way in. Two slabs of KT pairs alternate; the next one is in
+// flight while the matrix cores work on the current one, and one barrier per
+// slab both publishes it and retires the old one. The weight w[p] multiplies
+// the B fragment as it is read; pairs past P read row P-1 and get weight 0,
+// and columns past neps read column neps-1 and feed outputs that are not
+// stored, so no operand needs a mask.
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void chi0_f64_tile_dl(const cpx<double>* __restrict__ M, int P,
+                                                 int neps, const double* __restrict__ w,
+                                                 cpx<double>* __restrict__ C, int ti, int tj,
+                                                 int skip_head, bool overwrite) {
+  constexpr int TMv = 64;
+  static_assert(KT % 4 == 0, "each wavefront loads KT/4 rows of each operand");
+  // two slabs as separate LDS objects, so that the compiler can tell the
+  // in-flight loads into one from the reads of the other
+  __shared__ __align__(16) cpx<double> As0[KT][TMv], Bs0[KT][TMv];
+  __shared__ __align__(16) cpx<double> As1[KT][TMv], Bs1[KT][TMv];
+  __shared__ double Ws0[KT], Ws1[KT];
+  const int i0 = ti * TMv, j0 = tj * TMv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int ca = min(i0 + lane, neps - 1), cb = min(j0 + lane, neps - 1);
+  d4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
+    }
+  // rows wave*KT/4 .. of both operands of the slab at p0
+  auto issue = [&](cpx<double> (*As)[TMv], cpx<double> (*Bs)[TMv], int p0) {
+#pragma unroll
+    for (int r = 0; r < KT / 4; ++r) {
+      const int kk = wave * (KT / 4) + r;
+      const size_t row = (size_t)min(p0 + kk, P - 1) * neps;
+      __builtin_amdgcn_global_load_lds((const void*)(M + row + ca), (lds_void*)&As[kk][0], 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void*)(M + row + cb), (lds_void*)&Bs[kk][0], 16, 0,
+                                       0);
+    }
+  };
+  auto weight = [&](int p0) { return (tid < KT && p0 + tid < P) ? w[p0 + tid] : 0.0; };
+  auto compute = [&](const cpx<double> (*As)[TMv], const cpx<double> (*Bs)[TMv],
+                     const double* Ws) {
+#pragma unroll
+    for (int s = 0; s < KT / 4; ++s) {
+      const int kk = s * 4 + lk;
+      const double wk = Ws[kk];
+      cpx<double> av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr * 32 + a * 16 + l16];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const cpx<double> v = Bs[kk][wc * 32 + b * 16 + l16];
+        bv[b] = mk(wk * v.x, wk * v.y);
+      }
+      double dd[2], ss[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) dd[a] = av[a].x - av[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) ss[b] = bv[b].x + bv[b].y;
+      // t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar - ai)(br + bi): Re conj(a) b
+      // = t1 + t2 and Im = t3 - t1 + t2
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, t1[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].y, t2[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(dd[a], ss[b], t3[a][b], 0, 0, 0);
+    }
+  };
+  // one slab step: compute from (Ac, Bc, Wc) while the slab at pn streams into
+  // (An, Bn, Wn); this wavefront's loads land before the barrier, which makes
+  // every wavefront's visible and ends the reads of the current slab
+  auto step = [&](const cpx<double> (*Ac)[TMv], const cpx<double> (*Bc)[TMv], const double* Wc,
+                  cpx<double> (*An)[TMv], cpx<double> (*Bn)[TMv], double* Wn, int pn) {
+    const bool more = pn < P;
+    double wn = 0.0;
+    if (more) {
+      issue(An, Bn, pn);
+      wn = weight(pn);
+    }
+    compute(Ac, Bc, Wc);
+    if (more && tid < KT) Wn[tid] = wn;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  issue(As0, Bs0, 0);
+  const double w0 = weight(0);
+  if (tid < KT) Ws0[tid] = w0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int p0 = 0; p0 < P; p0 += 2 * KT) {
+    step(As0, Bs0, Ws0, As1, Bs1, Ws1, p0 + KT);
+    if (p0 + KT < P) step(As1, Bs1, Ws1, As0, Bs0, Ws0, p0 + 2 * KT);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // f64 16x16x4 D layout: row lk + 4r, column l16
+        const int i = i0 + wr * 32 + a * 16 + lk + 4 * r, j = j0 + wc * 32 + b * 16 + l16;
+        const double re = t1[a][b][r] + t2[a][b][r];
+        double im = (t3[a][b][r] - t1[a][b][r]) + t2[a][b][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, re, im, od, skip_head);
+        else herm_add(C, neps, i, j, re, im, od, skip_head);
+      }
+}
+
 // ------------------------------------------------------------------ FP64 chi0 tile
 // C[i][j] += sum_p conj(M[p][i]) w[p] M[p][j] for the (TM x TM) tile (ti, tj),
 // TM = 32*WM, WM x WM waves of 32x32 (2x2 blocks of v_mfma_f64_16x16x4_f64).
@@ -83,6 +212,11 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
                                               const double* __restrict__ w,
                                               cpx<double>* __restrict__ C, int ti, int tj,
                                               int skip_head, bool overwrite = false) {
+  if constexpr (WM == 2 && sizeof(Tin) == 8) {
+    chi0_f64_tile_dl(reinterpret_cast<const cpx<double>*>(M), P, neps, w, C, ti, tj, skip_head,
+                     overwrite);
+    return;
+  }
   constexpr int TMv = 32 * WM, NT = 64 * WM * WM, NE = (KT * TMv) / NT, PTv = TMv + 16;
   __shared__ double Ar[KT][PTv], Ai[KT][PTv], Br[KT][PTv], Bi[KT][PTv];
   const int i0 = ti * TMv, j0 = tj * TMv;
