@@ -326,11 +326,148 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
 // im lo), the bf16 bits of column G. A slab is then a contiguous 4 KiB per
 // plane and is staged with 16-byte loads and LDS stores, leaving the VALU free
 // for the MFMA issue.
+// WM = 2 form of the pre-split tile with the slabs loaded straight into LDS by
+// global_load_lds_dwordx4 (one wavefront instruction = 16 rows x 64 bytes of
+// one plane), into two slabs kept as separate LDS objects and alternated, one
+// barrier per slab. Rows are stored unpadded; the four 16-byte chunks of row r
+// are permuted by XOR with (r >> 2) & 3 on the way in and on the way out, so
+// that a fragment read (16 rows, one chunk each) hits 16 distinct bank groups.
+__device__ __forceinline__ void chi0_bf16s_tile_dl(const unsigned short* __restrict__ XA,
+                                                   const unsigned short* __restrict__ XB, int pb0,
+                                                   int npb, int neps, cpx<double>* __restrict__ C,
+                                                   int ti, int tj, int skip_head, bool overwrite) {
+  constexpr int TMv = 64;
+  __shared__ __align__(16) unsigned short As0[4][TMv][BK], Bs0[4][TMv][BK];
+  __shared__ __align__(16) unsigned short As1[4][TMv][BK], Bs1[4][TMv][BK];
+  typedef unsigned short (*Slab)[TMv][BK];
+  const int i0 = ti * TMv, j0 = tj * TMv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double dr[2][2][4], di[2][2][4];
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
+    }
+  // this lane's row within a 16-row block and the logical chunk it carries
+  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lrow >> 2) & 3);
+  const int ra = min(i0 + lrow, neps - 1), rb = min(j0 + lrow, neps - 1);
+  // the wavefront's 8 of the slab's 32 row blocks (operand, plane, 16-row block)
+  auto issue = [&](Slab A, Slab B, int pb) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = wave * 8 + u, opnd = idx >> 4, q = (idx >> 2) & 3, blk = idx & 3;
+      const size_t plane = ((size_t)pb * 4 + q) * neps;
+      const unsigned short* src =
+          (opnd ? XB + (plane + min(rb + 16 * blk, neps - 1)) * BK
+                : XA + (plane + min(ra + 16 * blk, neps - 1)) * BK) + lchunk * 8;
+      unsigned short* dst = opnd ? &B[q][16 * blk][0] : &A[q][16 * blk][0];
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)dst, 16, 0, 0);
+    }
+  };
+  // physical chunk of logical chunk lk in this lane's fragment rows
+  const int pch = (lk ^ ((l16 >> 2) & 3)) * 8;
+  int since_flush = 0;
+  auto compute = [&](Slab A, Slab B, bool last) {
+    bf8 a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[x][q] = *reinterpret_cast<const bf8*>(&A[q][wr * 32 + x * 16 + l16][pch]);
+        b[x][q] = *reinterpret_cast<const bf8*>(&B[q][wc * 32 + x * 16 + l16][pch]);
+      }
+    bf8 na[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 t = __builtin_bit_cast(us8, a[x][2 + q]);
+        t ^= (us8)(0x8000);
+        na[x][q] = __builtin_bit_cast(bf8, t);
+      }
+#define GW_MF(ACC, A_, B_)                                                    \
+  _Pragma("unroll") for (int x = 0; x < 2; ++x) _Pragma("unroll") for (int y = 0; y < 2; ++y) \
+      ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_, B_, ACC[x][y], 0, 0, 0);
+    GW_MF(cr, a[x][0], b[y][0])
+    GW_MF(ci, a[x][0], b[y][2])
+    GW_MF(cr, a[x][0], b[y][1])
+    GW_MF(ci, a[x][0], b[y][3])
+    GW_MF(cr, a[x][1], b[y][0])
+    GW_MF(ci, a[x][1], b[y][2])
+    GW_MF(cr, a[x][2], b[y][2])
+    GW_MF(ci, na[x][0], b[y][0])
+    GW_MF(cr, a[x][2], b[y][3])
+    GW_MF(ci, na[x][0], b[y][1])
+    GW_MF(cr, a[x][3], b[y][2])
+    GW_MF(ci, na[x][1], b[y][0])
+#undef GW_MF
+    since_flush += BK;
+    if (since_flush >= KFLUSH || last) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dr[x][y][r] += (double)cr[x][y][r];
+            di[x][y][r] += (double)ci[x][y][r];
+          }
+          cr[x][y] = (f4){0, 0, 0, 0};
+          ci[x][y] = (f4){0, 0, 0, 0};
+        }
+      since_flush = 0;
+    }
+  };
+  // compute from (Ac, Bc) while the slab pn streams into (An, Bn); this
+  // wavefront's loads land before the barrier, which publishes every
+  // wavefront's and ends the reads of the current slab
+  const int pend = pb0 + npb;
+  auto step = [&](Slab Ac, Slab Bc, Slab An, Slab Bn, int pn) {
+    if (pn < pend) issue(An, Bn, pn);
+    compute(Ac, Bc, pn >= pend);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  if (npb <= 0) return;
+  issue(As0, Bs0, pb0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int pb = pb0; pb < pend; pb += 2) {
+    step(As0, Bs0, As1, Bs1, pb + 1);
+    if (pb + 1 < pend) step(As1, Bs1, As0, Bs0, pb + 2);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
+        const int i = i0 + wr * 32 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
+        double im = di[x][y][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, dr[x][y][r], im, od, skip_head);
+        else herm_add(C, neps, i, j, dr[x][y][r], im, od, skip_head);
+      }
+}
+
 template <int WM>
 __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict__ XA,
                                                 const unsigned short* __restrict__ XB, int pb0,
                                                 int npb, int neps, cpx<double>* __restrict__ C,
                                                 int ti, int tj, int skip_head, bool overwrite) {
+  if constexpr (WM == 2) {
+    chi0_bf16s_tile_dl(XA, XB, pb0, npb, neps, C, ti, tj, skip_head, overwrite);
+    return;
+  }
   constexpr int TMv = 32 * WM, NT = 64 * WM * WM;
   constexpr int CH = 4 * TMv * (BK / 8);  // 16-byte chunks per operand slab
   constexpr int NE = CH / NT;
