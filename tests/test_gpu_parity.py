@@ -183,6 +183,33 @@ def test_chi0_pair_ranges_and_wings_match_oracle(P, ctx, prec):
         assert np.abs(got[f][h] - x[f][h]).max() <= 1e-12 * np.abs(x[f][h]).max(), (prec, f)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "splitbf16"])
+@pytest.mark.parametrize("shape", [(1, 3, 5), (3, 37, 70), (5, 41, 129), (2, 17, 64)])
+def test_chi0_ragged_sizes_match_oracle(P, ctx, prec, shape):
+    """Pair counts that are not a multiple of the 16/32-pair slabs and sphere sizes
+    that are not a multiple of the 64-wide tile (including a sphere smaller than
+    one tile and fewer pairs than one slab): the clamped rows and the zero weights
+    past the last pair must leave exactly the oracle's sum."""
+    nv, nc, neps = shape
+    rng = np.random.default_rng(100 + nv * 1000 + nc + neps)
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    m = ((rng.standard_normal((nv, nc, neps)) + 1j * rng.standard_normal((nv, nc, neps)))
+         / np.sqrt(2)).astype(dt)
+    ev = rng.uniform(-0.44, 0.0, nv)
+    ec = rng.uniform(0.07, 1.5, nc)
+    omega = np.array([0.0, 0.3])
+    x = oracle.chi0(m.astype(np.complex128), ev, ec, omega)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    chi = torch.zeros((len(omega), neps, neps), dtype=torch.complex128, device="cuda:0")
+    code = P.GW_PREC_FP64 if prec == "fp64" else P.GW_PREC_SPLITBF16
+    P.gw_chi0_accumulate(ctx, nv, nc, neps, dev(m), dev(ev), dev(ec), omega, 1.0, code, chi)
+    torch.cuda.synchronize()
+    got = chi.cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for f in range(len(omega)):
+        assert oracle.rel_f(got[f], x[f]) < tol, (prec, shape, f)
+
+
 # ----------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
 def test_mixed_path_within_1e4(P, ctx, name):
