@@ -94,8 +94,7 @@ gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], Spher
   return GW_OK;
 }
 
-ProfScope::ProfScope(gw_ctx* cc, const char* nm, hipStream_t s)
-    : c(cc), name(nm), st(s ? s : cc->stream) {
+ProfScope::ProfScope(gw_ctx* cc, const char* nm) : c(cc), name(nm) {
   if (!c->profiling) return;
   if (!c->prof_only.empty() && c->prof_only != name) return;
   auto get = [&]() {
@@ -106,12 +105,12 @@ ProfScope::ProfScope(gw_ctx* cc, const char* nm, hipStream_t s)
   };
   a = get();
   b = get();
-  (void)hipEventRecord(a, st);
+  (void)hipEventRecord(a, c->stream);
 }
 
 ProfScope::~ProfScope() {
   if (!a) return;
-  (void)hipEventRecord(b, st);
+  (void)hipEventRecord(b, c->stream);
   c->prof_pending.push_back(ProfRec{name, a, b});
 }
 

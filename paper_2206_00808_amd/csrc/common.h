@@ -126,9 +126,8 @@ gw_status twiddle_table(gw_ctx* c, int n, bool dbl, const void** out);
 struct ProfScope {
   gw_ctx* c;
   const char* name;
-  hipStream_t st;  // stream the scope's work runs on (the context's by default)
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(gw_ctx* cc, const char* nm, hipStream_t s = nullptr);
+  ProfScope(gw_ctx* cc, const char* nm);
   ~ProfScope();
 };
 
@@ -195,8 +194,7 @@ gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfre
 gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
                    int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
-                   size_t extB, size_t extC, double beta = 1.0,
-                   hipStream_t stream = nullptr);  // nullptr: the context stream
+                   size_t extB, size_t extC, double beta = 1.0);
 
 // eps and its inverse (lu.hip)
 gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,

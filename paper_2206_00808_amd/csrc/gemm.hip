@@ -263,8 +263,7 @@ static size_t span(size_t off, int rows, int cols, int ld, long long stride, int
 gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A, size_t offA,
                    int lda, long long sA, const double* B, size_t offB, int ldb, long long sB,
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
-                   size_t extB, size_t extC, double beta, hipStream_t stream) {
-  hipStream_t st = stream ? stream : c->stream;
+                   size_t extB, size_t extC, double beta) {
   if (beta != 0.0 && beta != 1.0) return fail(c, GW_EINVAL, "zgemm beta must be 0 or 1");
   if (m <= 0 || n <= 0 || k <= 0 || batch <= 0) return GW_OK;
   // every offset, leading dimension and stride is in complex elements; the
@@ -273,9 +272,9 @@ gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A
       span(offC, m, n, ldc, sC, batch) > extC || lda < k || ldb < n || ldc < n)
     return fail(c, GW_EINVAL, "zgemm operand out of range (m=%d n=%d k=%d batch=%d)", m, n, k,
                 batch);
-  ProfScope ps(c, "zgemm_update", st);
+  ProfScope ps(c, "zgemm");
   dim3 g((n + ZTM - 1) / ZTM, (m + ZTM - 1) / ZTM, batch);
-  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, st, m, n, k, alpha, beta,
+  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha, beta,
                      reinterpret_cast<const cpx<double>*>(A) + offA, lda, sA,
                      reinterpret_cast<const cpx<double>*>(B) + offB, ldb, sB,
                      reinterpret_cast<cpx<double>*>(C) + offC, ldc, sC);
