@@ -41,7 +41,7 @@ gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double
 // Grid (upper-triangle tiles, frequencies, pair ranges). Range 0 adds into chi0;
 // range s >= 1 covers pairs [s pc, (s+1) pc) and stores into partial matrix s-1.
 template <int WM, typename Tin>
-__global__ void __launch_bounds__(64 * WM * WM, 2) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P,
+__global__ void __launch_bounds__(64 * WM * WM, sizeof(Tin) == 8 ? 3 : 2) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P,
                                                            int neps, const double* __restrict__ wts,
                                                            cpx<double>* __restrict__ chi, int nt,
                                                            int skip_head, int pc,

@@ -77,7 +77,8 @@ __device__ __forceinline__ void herm_store(cpx<double>* C, int neps, int i, int 
 // loaded straight into LDS by global_load_lds_dwordx4: a row of 64 columns of
 // M (1 KiB) is one wavefront instruction, each lane's 16 bytes landing at
 // lane * 16 of the row, so the slab needs no registers, no VALU and no LDS
-// stores on its way in. Two slabs of KT pairs alternate; the next one is in
+// stores on its way in. Two slabs of 12 pairs alternate (49 KiB of LDS, so
+// three workgroups fit a CU); the next one is in
 // flight while the matrix cores work on the current one, and one barrier per
 // slab both publishes it and retires the old one. The weight w[p] multiplies
 // the B fragment as it is read; pairs past P read row P-1 and get weight 0,
@@ -88,13 +89,13 @@ __device__ __forceinline__ void chi0_f64_tile_dl(const cpx<double>* __restrict__
                                                  int neps, const double* __restrict__ w,
                                                  cpx<double>* __restrict__ C, int ti, int tj,
                                                  int skip_head, bool overwrite) {
-  constexpr int TMv = 64;
-  static_assert(KT % 4 == 0, "each wavefront loads KT/4 rows of each operand");
+  constexpr int TMv = 64, KD = 12;  // pairs per slab: 3 rows per wavefront and operand
+  static_assert(KD % 4 == 0, "each wavefront loads KD/4 rows of each operand");
   // two slabs as separate LDS objects, so that the compiler can tell the
   // in-flight loads into one from the reads of the other
-  __shared__ __align__(16) cpx<double> As0[KT][TMv], Bs0[KT][TMv];
-  __shared__ __align__(16) cpx<double> As1[KT][TMv], Bs1[KT][TMv];
-  __shared__ double Ws0[KT], Ws1[KT];
+  __shared__ __align__(16) cpx<double> As0[KD][TMv], Bs0[KD][TMv];
+  __shared__ __align__(16) cpx<double> As1[KD][TMv], Bs1[KD][TMv];
+  __shared__ double Ws0[KD], Ws1[KD];
   const int i0 = ti * TMv, j0 = tj * TMv;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -109,11 +110,11 @@ __device__ __forceinline__ void chi0_f64_tile_dl(const cpx<double>* __restrict__
       t2[a][b] = (d4){0, 0, 0, 0};
       t3[a][b] = (d4){0, 0, 0, 0};
     }
-  // rows wave*KT/4 .. of both operands of the slab at p0
+  // rows wave*KD/4 .. of both operands of the slab at p0
   auto issue = [&](cpx<double> (*As)[TMv], cpx<double> (*Bs)[TMv], int p0) {
 #pragma unroll
-    for (int r = 0; r < KT / 4; ++r) {
-      const int kk = wave * (KT / 4) + r;
+    for (int r = 0; r < KD / 4; ++r) {
+      const int kk = wave * (KD / 4) + r;
       const size_t row = (size_t)min(p0 + kk, P - 1) * neps;
       __builtin_amdgcn_global_load_lds((const void*)(M + row + ca), (lds_void*)&As[kk][0], 16, 0,
                                        0);
@@ -121,11 +122,11 @@ __device__ __forceinline__ void chi0_f64_tile_dl(const cpx<double>* __restrict__
                                        0);
     }
   };
-  auto weight = [&](int p0) { return (tid < KT && p0 + tid < P) ? w[p0 + tid] : 0.0; };
+  auto weight = [&](int p0) { return (tid < KD && p0 + tid < P) ? w[p0 + tid] : 0.0; };
   auto compute = [&](const cpx<double> (*As)[TMv], const cpx<double> (*Bs)[TMv],
                      const double* Ws) {
 #pragma unroll
-    for (int s = 0; s < KT / 4; ++s) {
+    for (int s = 0; s < KD / 4; ++s) {
       const int kk = s * 4 + lk;
       const double wk = Ws[kk];
       cpx<double> av[2], bv[2];
@@ -172,18 +173,18 @@ __device__ __forceinline__ void chi0_f64_tile_dl(const cpx<double>* __restrict__
       wn = weight(pn);
     }
     compute(Ac, Bc, Wc);
-    if (more && tid < KT) Wn[tid] = wn;
+    if (more && tid < KD) Wn[tid] = wn;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   };
   issue(As0, Bs0, 0);
   const double w0 = weight(0);
-  if (tid < KT) Ws0[tid] = w0;
+  if (tid < KD) Ws0[tid] = w0;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int p0 = 0; p0 < P; p0 += 2 * KT) {
-    step(As0, Bs0, Ws0, As1, Bs1, Ws1, p0 + KT);
-    if (p0 + KT < P) step(As1, Bs1, Ws1, As0, Bs0, Ws0, p0 + 2 * KT);
+  for (int p0 = 0; p0 < P; p0 += 2 * KD) {
+    step(As0, Bs0, Ws0, As1, Bs1, Ws1, p0 + KD);
+    if (p0 + KD < P) step(As1, Bs1, Ws1, As0, Bs0, Ws0, p0 + 2 * KD);
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
