@@ -262,6 +262,35 @@ def test_alias_box_rejected(P, ctx):
     assert ei.value.status == P.GW_EINVAL
 
 
+@pytest.mark.parametrize("n,kind", [(n, "definite") for n in (1, 63, 64, 65, 129, 200)]
+                         + [(n, "indefinite") for n in (65, 129)])
+def test_epsinv_block_counts_match_oracle(P, ctx, n, kind):
+    """eps^-1 at sizes around the 64-wide Gauss-Jordan blocks (one block, a ragged
+    last block, the look-ahead block skipped by the rank update), three
+    frequencies at once. 'definite' is chi0 <= 0 (the Gauss-Jordan path); in
+    'indefinite' one frequency has chi0 with eigenvalues above 1/v, so eps~ is not
+    positive definite and the call must take the pivoted LU path."""
+    rng = np.random.default_rng(7 * n + (kind == "indefinite"))
+    nf = 3
+    v = rng.uniform(0.5, 3.0, n)
+    chi = np.empty((nf, n, n), dtype=np.complex128)
+    for f in range(nf):
+        x = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+        chi[f] = -(x @ x.conj().T) * (0.3 + f)
+    if kind == "indefinite":
+        # a Hermitian chi0 with eigenvalues of both signs and size well above 1/v
+        y = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+        chi[1] = (y + y.conj().T) * 2.0 + 1.5 * np.eye(n)
+    want = oracle.epsilon_inverse(chi, v)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    out = torch.empty((nf, n, n), dtype=torch.complex128, device="cuda:0")
+    P.gw_epsinv(ctx, n, nf, dev(chi), dev(v), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for f in range(nf):
+        assert oracle.rel_f(got[f], want[f]) < 1e-10, (n, kind, f)
+
+
 def test_singular_eps_reported(P, ctx):
     n = 70
     chi = torch.eye(n, dtype=torch.complex128, device="cuda").reshape(1, n, n).contiguous()
