@@ -23,6 +23,10 @@ mtxel_convolution        | brute force, single plane wave, orthonormality
 mtxel_bruteforce         | closed forms on single plane waves
 chi0                     | scipy ZHERK, Hermitian/NSD, Loewner, asymptote,
                          | doubled collinear set (spinor = 2 x spinless)
+chi0_weight_real         | imaginary-axis factor at w = i omega, eta = 0;
+                         | the summed form 2a/(a^2 - w^2), a = delta + i eta
+chi0_real                | scipy ZHERK on the real and imaginary weight parts,
+                         | even in w, absorptive diagonal, static limit
 epsilon / epsilon_inverse| Sherman-Morrison closed form, eigenvalue bounds,
                          | LU solve via scipy
 head_overlap             | convolution form at G = 0, orthonormality
@@ -33,7 +37,8 @@ import numpy as np
 
 __all__ = [
     "box_offsets", "wavefunction_on_box", "mtxel_fft", "mtxel_convolution",
-    "mtxel_bruteforce", "chi0_weight", "chi0", "epsilon", "epsilon_inverse",
+    "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
+    "epsilon_inverse",
     "head_overlap", "chi0_from_system", "rel_f", "alias_free",
 ]
 
@@ -183,6 +188,37 @@ def chi0(mtxel, ev, ec, omega, prefactor=1.0):
     nv, nc, neps = m.shape
     flat = m.reshape(nv * nc, neps)
     w = chi0_weight(ev, ec, omega)
+    return np.stack([prefactor * ((np.conj(flat).T * wf[None, :]) @ flat) for wf in w])
+
+
+def chi0_weight_real(ev, ec, omega, eta):
+    """Adler-Wiser energy factor with broadening, as Sec. II writes it.
+
+    The bracket 1/(e_v - e_c - w + i eta) + 1/(e_v - e_c + w + i eta) for every
+    frequency w of `omega` (real frequencies for the real-axis polarizability;
+    a complex w = i*omega' with eta = 0 gives the imaginary-axis factor).
+    Returns complex w[nfreq][nv*nc].
+    """
+    ev = np.asarray(ev, dtype=np.float64)
+    ec = np.asarray(ec, dtype=np.float64)
+    delta = (ev[:, None] - ec[None, :]).reshape(-1)
+    out = []
+    for om in np.atleast_1d(np.asarray(omega, dtype=np.complex128)):
+        out.append(1.0 / (delta - om + 1j * eta) + 1.0 / (delta + om + 1j * eta))
+    return np.array(out)
+
+
+def chi0_real(mtxel, ev, ec, omega, eta, prefactor=1.0):
+    """P_GG'(q, w) on the real frequency axis with broadening eta (Sec. II).
+
+    (1/N_k) sum_{v,c} M*_vc(G) M_vc(G') times the complex bracket of
+    chi0_weight_real; the result is not Hermitian.  mtxel: [nv][nc][neps].
+    Returns chi0[nfreq][neps][neps] complex128.
+    """
+    m = np.asarray(mtxel, dtype=np.complex128)
+    nv, nc, neps = m.shape
+    flat = m.reshape(nv * nc, neps)
+    w = chi0_weight_real(ev, ec, omega, eta)
     return np.stack([prefactor * ((np.conj(flat).T * wf[None, :]) @ flat) for wf in w])
 
 

@@ -178,6 +178,61 @@ def test_weight_closed_form():
     assert np.all(w < 0)
 
 
+def test_real_axis_weight_forms():
+    ev = np.array([-0.2, -0.05])
+    ec = np.array([0.1, 0.3, 0.7])
+    d = (ev[:, None] - ec[None, :]).ravel()
+    # at w = i*omega and eta = 0 the bracket is the imaginary-axis factor
+    om = np.array([0.0, 0.4, 3.0])
+    w = oracle.chi0_weight_real(ev, ec, 1j * om, 0.0)
+    assert np.allclose(w, oracle.chi0_weight(ev, ec, om), rtol=1e-15, atol=0)
+    # on the real axis the two terms sum to 2a / (a^2 - w^2), a = delta + i eta
+    eta = 0.01
+    wr = np.array([0.0, 0.15, 0.5, 2.0])
+    w = oracle.chi0_weight_real(ev, ec, wr, eta)
+    a = d + 1j * eta
+    for f, o in enumerate(wr):
+        assert np.allclose(w[f], 2 * a / (a * a - o * o), rtol=1e-13, atol=0)
+    assert np.all(w.imag < 0)  # absorptive: both poles sit below the real axis
+
+
+def test_chi0_real_splits_into_hermitian_parts(tiny):
+    """Re and Im of the bracket are real weights, so P(w) = A + iB with A, B
+    Hermitian contractions; each is rebuilt with scipy ZHERK from the positive and
+    negative parts of its weight."""
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    flat = m.reshape(-1, m.shape[-1])
+    wr = [0.0, 0.12, 0.4]
+    eta = 0.02
+    x = oracle.chi0_real(m, s["ev"], s["ec"], wr, eta, prefactor=0.5)
+    w = oracle.chi0_weight_real(s["ev"], s["ec"], wr, eta)
+
+    def herk(weights):
+        out = np.zeros((flat.shape[1], flat.shape[1]), dtype=np.complex128)
+        for sign in (1.0, -1.0):
+            part = np.clip(sign * weights, 0.0, None)
+            a = np.sqrt(part)[:, None] * flat
+            up = scipy.linalg.blas.zherk(0.5 * sign, a, trans=2)
+            out += np.triu(up) + np.triu(up, 1).conj().T
+        return out
+
+    for f in range(len(wr)):
+        ref = herk(w[f].real) + 1j * herk(w[f].imag)
+        assert oracle.rel_f(x[f], ref) < 1e-14
+        # absorptive diagonal for eta > 0
+        assert np.all(np.diag(x[f]).imag < 0)
+    # even in w
+    xm = oracle.chi0_real(m, s["ev"], s["ec"], [-v for v in wr], eta, prefactor=0.5)
+    assert oracle.rel_f(xm, x) < 1e-15
+    # static limit: at w = 0 the difference from the imaginary-axis chi0 at
+    # omega = 0 is first order in eta (an imaginary part -2 eta / delta^2 per pair)
+    ref0 = oracle.chi0(m, s["ev"], s["ec"], [0.0])[0]
+    errs = [oracle.rel_f(oracle.chi0_real(m, s["ev"], s["ec"], [0.0], e)[0], ref0)
+            for e in (1e-6, 1e-9)]
+    assert errs[1] < 1e-7 and 500 < errs[0] / errs[1] < 2000
+
+
 def test_chi0_matches_zherk_and_is_hermitian_nsd(tiny):
     s = tiny
     m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
