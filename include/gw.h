@@ -149,19 +149,54 @@ gw_status gw_chi0_accumulate(gw_ctx* ctx, int nv, int nc, int neps,
                              double* chi0);
 
 /*
- * gw_epsinv -- eps_f = I - diag(vcoul) chi0_f, then eps_f^-1 by LU factorisation
- * with partial pivoting (row interchanges, largest |re|+|im| in the column,
- * lowest index on ties) followed by forward and back substitution on the
- * permuted identity, all in double (Sec. II, dielectric matrix and W = eps^-1 v).
+ * gw_chi0_accumulate_real -- the polarizability on the real frequency axis with
+ * broadening (Sec. II, the Adler-Wiser sum as written):
+ *   chi0_f[G][G'] += prefactor * sum_p b_p(omega_f) conj(M_p(G)) M_p(G'),
+ *   b_p(omega) = 1/(D_p - omega + i eta) + 1/(D_p + omega + i eta),  D_p = ev[v] - ec[c].
+ * The update is not Hermitian. It is formed as A + iB from two Hermitian
+ * contractions with the real weights Re b and Im b, each computed like
+ * gw_chi0_accumulate's.
+ *   omega (host) double[nfreq], any finite real frequencies; eta > 0.
+ *   chi0  (device) in/out complex double[nfreq][neps][neps]; the update is added.
+ *   The other arguments are as for gw_chi0_accumulate; there is no head/wings
+ *   split (the q -> 0 head is an imaginary-axis quantity here).
+ * Uses 2*nfreq*neps^2*16 bytes of context workspace for A and B.
+ * Errors: GW_EINVAL for eta <= 0, non-finite omega or prefactor, NULL arrays,
+ * unknown dtype/precision, split-BF16 with GW_C128, nfreq > 32767.
+ */
+gw_status gw_chi0_accumulate_real(gw_ctx* ctx, int nv, int nc, int neps,
+                                  const void* mtxel, gw_dtype dtype,
+                                  const double* ev, const double* ec,
+                                  int nfreq, const double* omega, double eta,
+                                  double prefactor, gw_prec prec, double* chi0);
+
+/*
+ * gw_epsinv -- eps_f = I - diag(vcoul) chi0_f and eps_f^-1, all in double
+ * (Sec. II, dielectric matrix and W = eps^-1 v).  When v > 0 and chi0 is
+ * Hermitian negative semidefinite (the imaginary axis), eps~ = I - V^1/2 chi0
+ * V^1/2 is Hermitian positive definite and is inverted by blocked Gauss-Jordan
+ * without pivoting, every pivot checked (real part >= 1/2, |imaginary part| <=
+ * 1/4 of it); if any check fails, or some v <= 0, the whole call is redone by
+ * gw_epsinv_lu's LU path.
  *
  *   chi0    (device) complex double[nfreq][neps][neps].
  *   vcoul   (device) double[neps], v(q+G) = 4 pi / (Omega |q+G|^2).
  *   epsinv  (device) out complex double[nfreq][neps][neps]; may not alias chi0.
- * Synchronises the context stream to read the singular flag: GW_ESINGULAR if
- * any pivot of any frequency was exactly zero (epsinv then holds non-finite values).
+ * Synchronises the context stream to read the flags: GW_ESINGULAR if any pivot
+ * of the LU path was exactly zero (epsinv then holds non-finite values).
  */
 gw_status gw_epsinv(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
                     const double* vcoul, double* epsinv);
+
+/*
+ * gw_epsinv_lu -- eps_f^-1 for any nonsingular eps_f (for example from
+ * gw_chi0_accumulate_real), by LU factorisation with partial pivoting (row
+ * interchanges, largest |re|+|im| in the column, lowest index on ties) and
+ * forward and back substitution on the permuted identity, in double.
+ * Arguments, ownership and errors as for gw_epsinv.
+ */
+gw_status gw_epsinv_lu(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
+                       const double* vcoul, double* epsinv);
 
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */

@@ -1,7 +1,8 @@
 """MI355X-native hot path of fully relativistic (spinor) GW, Epsilon stage.
 
 arXiv:2206.00808, Sec. II: spinor plane-wave matrix elements M_vc(q+G), the
-imaginary-axis polarizability chi0_GG'(q) and eps^-1, as hand-written HIP
+polarizability chi0_GG'(q) on the imaginary axis (and on the real axis with
+broadening) and eps^-1, as hand-written HIP
 kernels for gfx950 behind the C ABI in include/gw.h.  This package is the thin
 Python binding over that library; it raises ImportError when the library has
 not been built.
@@ -11,5 +12,6 @@ from .binding import (  # noqa: F401
     GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EALIAS, GW_ESINGULAR, GW_ENOTTRAINED,
     GW_EUNSUPPORTED, GW_EFALLBACK, GW_C128, GW_C64, GW_PREC_FP64, GW_PREC_SPLITBF16,
     GW_CLOSURE_INFER, GW_CLOSURE_TRAIN_STEP, GW_CLOSURE_FULL_FALLBACK,
-    gw_mtxel_spinor, gw_chi0_accumulate, gw_epsinv, status_string, EXPORTED, LIB_PATH,
+    gw_mtxel_spinor, gw_chi0_accumulate, gw_epsinv, gw_chi0_accumulate_real, gw_epsinv_lu,
+    status_string, EXPORTED, LIB_PATH,
 )

@@ -26,7 +26,8 @@ EXPORTED = [
     "gw_ctx_create", "gw_ctx_destroy", "gw_ctx_set_stream", "gw_last_error", "gw_status_string",
     "gw_ctx_profile", "gw_ctx_profile_only", "gw_ctx_profile_reset", "gw_ctx_profile_count",
     "gw_ctx_profile_entry",
-    "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv",
+    "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
+    "gw_epsinv_lu",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -67,6 +68,9 @@ _SIG = {
     "gw_chi0_accumulate": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _i, _vp, _i,
                                 _vp]),
     "gw_epsinv": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
+                                     _vp]),
+    "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "gw_mlp_create": (_i, [_vp, ct.POINTER(_vp), _i, _i, _i, _i, _u64]),
     "gw_mlp_destroy": (_i, [_vp]),
     "gw_mlp_save": (_i, [_vp, _vp, ct.POINTER(ct.c_size_t)]),
@@ -221,6 +225,27 @@ def gw_epsinv(ctx, neps, nfreq, chi0, vcoul, epsinv):
     """epsinv[f] = (I - diag(vcoul) chi0[f])^-1 (see include/gw.h)."""
     ctx.sync_stream()
     s = _lib.gw_epsinv(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul), _ptr(epsinv))
+    return _check(ctx, s)
+
+
+def gw_chi0_accumulate_real(ctx, nv, nc, neps, mtxel, ev, ec, omega, eta, prefactor, prec,
+                            chi0):
+    """chi0[f] += prefactor * sum_p b_p(omega_f) conj(M_p) M_p^T on the real axis
+    with broadening eta (see include/gw.h)."""
+    ctx.sync_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    dt = _dtype_code(mtxel)
+    s = _lib.gw_chi0_accumulate_real(ctx.handle, int(nv), int(nc), int(neps), _ptr(mtxel), dt,
+                                     _ptr(ev), _ptr(ec), len(om), om.ctypes.data, float(eta),
+                                     float(prefactor), int(prec), _ptr(chi0))
+    return _check(ctx, s)
+
+
+def gw_epsinv_lu(ctx, neps, nfreq, chi0, vcoul, epsinv):
+    """epsinv[f] = (I - diag(vcoul) chi0[f])^-1 by pivoted LU (see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_epsinv_lu(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul),
+                          _ptr(epsinv))
     return _check(ctx, s)
 
 

@@ -419,6 +419,71 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
   return GW_OK;
 }
 
+gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const void* mtxel,
+                                  gw_dtype dtype, const double* ev, const double* ec, int nfreq,
+                                  const double* omega, double eta, double prefactor, gw_prec prec,
+                                  double* chi0) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (nv < 0 || nc < 0 || neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (prec != GW_PREC_FP64 && prec != GW_PREC_SPLITBF16) return fail(c, GW_EINVAL, "unknown precision");
+  if (prec == GW_PREC_SPLITBF16 && dtype != GW_C64)
+    return fail(c, GW_EINVAL, "split-BF16 contraction needs GW_C64 matrix elements");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, GW_EINVAL, "eta must be finite and > 0");
+  if (nv == 0 || nc == 0 || neps == 0 || nfreq == 0) return GW_OK;
+  if (!mtxel || !ev || !ec || !omega || !chi0) return fail(c, GW_EINVAL, "NULL array argument");
+  if (!std::isfinite(prefactor)) return fail(c, GW_EINVAL, "non-finite prefactor");
+  for (int f = 0; f < nfreq; ++f)
+    if (!std::isfinite(omega[f])) return fail(c, GW_EINVAL, "omega[%d] must be finite", f);
+  if ((long long)neps * neps > (1LL << 40)) return fail(c, GW_EINVAL, "neps too large");
+  if (nfreq > 32767) return fail(c, GW_EINVAL, "nfreq above 32767");
+  (void)hipSetDevice(c->device);
+  const int P = nv * nc, nw = 2 * nfreq;
+  const size_t nn = (size_t)neps * neps;
+  const int split = chi0_split(c, P, neps, nw, prec, dtype);
+  const size_t part_bytes = (size_t)(split - 1) * nw * nn * 16;
+  const size_t xs_bytes = prec == GW_PREC_SPLITBF16 ? bf16_split_bytes(P, neps, nw) : 0;
+  gw_status st = ws_begin(c, align_up((size_t)nfreq * 8) + align_up((size_t)nw * P * 8) +
+                                 align_up((size_t)nw * nn * 16) + align_up(part_bytes) +
+                                 align_up(xs_bytes));
+  if (st != GW_OK) return st;
+  double* d_om = static_cast<double*>(ws_take(c, (size_t)nfreq * 8));
+  double* wts = static_cast<double*>(ws_take(c, (size_t)nw * P * 8));
+  double* h = static_cast<double*>(ws_take(c, (size_t)nw * nn * 16));
+  double* part = part_bytes ? static_cast<double*>(ws_take(c, part_bytes)) : nullptr;
+  void* xsplit = xs_bytes ? ws_take(c, xs_bytes) : nullptr;
+  GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
+  GW_HIP(c, hipMemsetAsync(h, 0, (size_t)nw * nn * 16, c->stream));
+  if ((st = chi0_weights_real(c, nv, nc, ev, ec, nfreq, d_om, eta, prefactor, wts)) != GW_OK)
+    return st;
+  // the two real weight sets give two Hermitian contractions A and B, and
+  // chi0 += A + i B
+  if (prec == GW_PREC_FP64)
+    st = chi0_fp64(c, P, neps, mtxel, dtype, nw, wts, -1, h, split, part);
+  else
+    st = chi0_splitbf16(c, P, neps, mtxel, nw, wts, -1, h, split, part, xsplit);
+  if (st != GW_OK) return st;
+  if ((st = chi0_combine_real(c, neps, nfreq, h, chi0)) != GW_OK) return st;
+  // omega was copied from pageable host memory: finish before returning
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  return GW_OK;
+}
+
+gw_status gw_epsinv_lu(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
+                       double* epsinv) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (neps == 0 || nfreq == 0) return GW_OK;
+  if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
+  if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv may not alias chi0");
+  if (neps > 16384) return fail(c, GW_EINVAL, "neps above 16384");
+  if (nfreq > 65535) return fail(c, GW_EINVAL, "nfreq above 65535");
+  (void)hipSetDevice(c->device);
+  return epsinv_pivoted_one(c, neps, nfreq, chi0, vcoul, epsinv);
+}
+
 gw_status gw_epsinv(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
                     double* epsinv) {
   if (!c) return GW_EINVAL;

@@ -177,6 +177,12 @@ gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double
 // The pair sum of the contraction is cut into `split` ranges when that fills
 // the last round of workgroups better; ranges 1.. write their tiles to `part`
 // (split-1 matrices per frequency), which are then added to chi0 in order.
+// real-axis weights (Re and Im of the bracket as 2*nfreq real sets) and the
+// combination chi0[f] += h[f] + i h[nfreq + f] of the two Hermitian results
+gw_status chi0_weights_real(gw_ctx* c, int nv, int nc, const double* ev, const double* ec,
+                            int nfreq, const double* d_omega, double eta, double pref,
+                            double* wts);
+gw_status chi0_combine_real(gw_ctx* c, int neps, int nfreq, const double* h, double* chi0);
 int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt);
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
                     const double* wts, int skip_head, double* chi0, int split, double* part);
@@ -196,8 +202,11 @@ gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A
                    double* C, size_t offC, int ldc, long long sC, int batch, size_t extA,
                    size_t extB, size_t extC, double beta = 1.0);
 
-// eps and its inverse (lu.hip)
+// eps and its inverse (lu.hip): Gauss-Jordan on eps~ with the pivoted fallback,
+// or LU with partial pivoting for any matrix
 gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
                      double* epsinv);
+gw_status epsinv_pivoted_one(gw_ctx* c, int N, int nfreq, const double* chi0,
+                             const double* vcoul, double* epsinv);
 
 }  // namespace gw

@@ -37,6 +37,55 @@ gw_status chi0_weights(gw_ctx* c, int nv, int nc, const double* ev, const double
   return GW_OK;
 }
 
+// Real-frequency weights with broadening eta > 0, split into two real sets:
+// w[f][p] = pref Re b and w[nfreq + f][p] = pref Im b for the bracket
+// b = 1/(d - o + i eta) + 1/(d + o + i eta), each term as (x - i eta)/(x^2 + eta^2).
+__global__ void k_weights_real(const double* __restrict__ ev, const double* __restrict__ ec,
+                               int nv, int nc, const double* __restrict__ om, int nfreq,
+                               double eta, double pref, double* __restrict__ w) {
+  const int P = nv * nc;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (p >= P || f >= nfreq) return;
+  const double d = ev[p / nc] - ec[p % nc];
+  const double xm = d - om[f], xp = d + om[f];
+  const double qm = xm * xm + eta * eta, qp = xp * xp + eta * eta;
+  w[(size_t)f * P + p] = pref * (xm / qm + xp / qp);
+  w[(size_t)(nfreq + f) * P + p] = -pref * (eta / qm + eta / qp);
+}
+
+gw_status chi0_weights_real(gw_ctx* c, int nv, int nc, const double* ev, const double* ec,
+                            int nfreq, const double* d_omega, double eta, double pref,
+                            double* wts) {
+  const int P = nv * nc;
+  ProfScope ps(c, "chi0_weights");
+  hipLaunchKernelGGL(k_weights_real, dim3((P + 255) / 256, nfreq), dim3(256), 0, c->stream, ev,
+                     ec, nv, nc, d_omega, nfreq, eta, pref, wts);
+  GW_CHECK_LAUNCH(c, "k_weights_real");
+  return GW_OK;
+}
+
+// chi0[f] += A[f] + i B[f] for the Hermitian contractions A = h[f], B = h[nfreq + f]
+__global__ void k_combine_real(const cpx<double>* __restrict__ h, size_t nn, int nfreq,
+                               cpx<double>* __restrict__ chi) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const size_t f = blockIdx.y;
+  const cpx<double> a = h[f * nn + e], b = h[(nfreq + f) * nn + e];
+  cpx<double>* o = chi + f * nn + e;
+  *o = mk(o->x + (a.x - b.y), o->y + (a.y + b.x));
+}
+
+gw_status chi0_combine_real(gw_ctx* c, int neps, int nfreq, const double* h, double* chi0) {
+  const size_t nn = (size_t)neps * neps;
+  ProfScope ps(c, "chi0_combine");
+  hipLaunchKernelGGL(k_combine_real, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                     c->stream, reinterpret_cast<const cpx<double>*>(h), nn, nfreq,
+                     reinterpret_cast<cpx<double>*>(chi0));
+  GW_CHECK_LAUNCH(c, "k_combine_real");
+  return GW_OK;
+}
+
 // ---------------------------------------------------------------- single-q contractions
 // Grid (upper-triangle tiles, frequencies, pair ranges). Range 0 adds into chi0;
 // range s >= 1 covers pairs [s pc, (s+1) pc) and stores into partial matrix s-1.

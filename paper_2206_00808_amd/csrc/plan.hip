@@ -27,8 +27,6 @@
 
 namespace gw {
 
-gw_status epsinv_pivoted_one(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
-                             double* epsinv);
 
 struct ChiQ {
   const void* M;

@@ -210,6 +210,86 @@ def test_chi0_ragged_sizes_match_oracle(P, ctx, prec, shape):
         assert oracle.rel_f(got[f], x[f]) < tol, (prec, shape, f)
 
 
+# ----------------------------------------------------------------- real frequency axis
+@pytest.mark.parametrize("prec", ["fp64", "splitbf16"])
+@pytest.mark.parametrize("shape", [(3, 37, 70), (16, 50, 200)])
+def test_chi0_real_axis_matches_oracle(P, ctx, prec, shape):
+    """Real-frequency chi0 with broadening (the Sec. II bracket with complex
+    weights) against the oracle: non-Hermitian result, frequencies of both signs
+    and one on a pole region, accumulated on top of an existing chi0."""
+    nv, nc, neps = shape
+    rng = np.random.default_rng(300 + nv + nc + neps)
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    m = ((rng.standard_normal((nv, nc, neps)) + 1j * rng.standard_normal((nv, nc, neps)))
+         / np.sqrt(2)).astype(dt)
+    ev = rng.uniform(-0.44, 0.0, nv)
+    ec = rng.uniform(0.07, 1.5, nc)
+    omega = np.array([0.0, 0.35, -0.35, 0.9])
+    eta = 0.02
+    base = (rng.standard_normal((len(omega), neps, neps))
+            + 1j * rng.standard_normal((len(omega), neps, neps)))
+    want = base + oracle.chi0_real(m.astype(np.complex128), ev, ec, omega, eta, prefactor=0.5)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    chi = dev(base)
+    code = P.GW_PREC_FP64 if prec == "fp64" else P.GW_PREC_SPLITBF16
+    P.gw_chi0_accumulate_real(ctx, nv, nc, neps, dev(m), dev(ev), dev(ec), omega, eta, 0.5, code,
+                              chi)
+    torch.cuda.synchronize()
+    got = chi.cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for f in range(len(omega)):
+        assert oracle.rel_f(got[f] - base[f], want[f] - base[f]) < tol, (prec, shape, f)
+    # the update is not Hermitian; its anti-Hermitian part is i times the
+    # contraction with Im b, which is negative on the diagonal (absorption)
+    upd = got[1] - base[1]
+    assert np.abs(upd - upd.conj().T).max() > 1e-3 * np.abs(upd).max()
+    assert np.all(np.diag(upd).imag < 0)
+
+
+def test_chi0_real_axis_from_pipeline_and_lu_inverse(P, ctx):
+    """The whole real-axis path on a synthetic system: matrix elements from the
+    library, chi0 on the real axis, eps^-1 by the pivoted LU entry point, against
+    the oracle's chi0_real and numpy's inverse of the non-Hermitian eps."""
+    s = _sys("T1")
+    from paper_2206_00808_amd import pipeline
+    d = pipeline.upload(s)
+    out = pipeline.alloc_outputs(d)
+    pipeline.run_path(ctx, d, out, stages=("mtxel",))
+    m = out["mtxel"]
+    omega = np.array([0.0, 0.2, 0.5])
+    eta = 0.01
+    neps = d["neps"]
+    chi = torch.zeros((len(omega), neps, neps), dtype=torch.complex128, device="cuda:0")
+    P.gw_chi0_accumulate_real(ctx, d["nv"], d["nc"], neps, m, d["ev"], d["ec"], omega, eta, 1.0,
+                              P.GW_PREC_FP64, chi)
+    einv = torch.empty_like(chi)
+    P.gw_epsinv_lu(ctx, neps, len(omega), chi, d["vcoul"], einv)
+    torch.cuda.synchronize()
+    mh = m.cpu().numpy().reshape(d["nv"], d["nc"], neps)
+    x = oracle.chi0_real(mh, d["ev"].cpu().numpy(), d["ec"].cpu().numpy(), omega, eta)
+    e = oracle.epsilon_inverse(x, d["vcoul"].cpu().numpy())
+    for f in range(len(omega)):
+        assert oracle.rel_f(chi[f].cpu().numpy(), x[f]) < 1e-12
+        assert oracle.rel_f(einv[f].cpu().numpy(), e[f]) < 1e-10
+
+
+def test_chi0_real_axis_rejects_bad_arguments(P, ctx):
+    m = torch.zeros((2, 3, 4), dtype=torch.complex128, device="cuda")
+    ev = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ec = torch.ones(3, dtype=torch.float64, device="cuda")
+    chi = torch.zeros((1, 4, 4), dtype=torch.complex128, device="cuda")
+    for eta in (0.0, -1.0, float("nan")):
+        with pytest.raises(P.GwError) as ei:
+            P.gw_chi0_accumulate_real(ctx, 2, 3, 4, m, ev, ec, [0.1], eta, 1.0, P.GW_PREC_FP64, chi)
+        assert ei.value.status == P.GW_EINVAL
+    with pytest.raises(P.GwError) as ei:
+        P.gw_chi0_accumulate_real(ctx, 2, 3, 4, m, ev, ec, [float("inf")], 0.1, 1.0,
+                                  P.GW_PREC_FP64, chi)
+    assert ei.value.status == P.GW_EINVAL
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(chi) == 0
+
+
 # ----------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
 def test_mixed_path_within_1e4(P, ctx, name):
