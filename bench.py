@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-real-axis", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--closure-train", type=int, default=256)
@@ -231,6 +232,49 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_real_axis(ctx, P, d, mtxel, steps, nfreq=9, eta=0.005):
+    """Real-frequency chi0 with broadening (gw_chi0_accumulate_real, FP64) on the
+    workload's matrix elements at nfreq frequencies in [0, 0.8] Ha, and its
+    inverse dielectric matrix by pivoted LU (gw_epsinv_lu)."""
+    import torch
+    omega = np.linspace(0.0, 0.8, nfreq)
+    neps = d["neps"]
+    chi = torch.zeros((nfreq, neps, neps), dtype=torch.complex128, device="cuda")
+    einv = torch.empty_like(chi)
+
+    def run_chi():
+        chi.zero_()
+        P.gw_chi0_accumulate_real(ctx, d["nv"], d["nc"], neps, mtxel, d["ev"], d["ec"], omega,
+                                  eta, 1.0, P.GW_PREC_FP64, chi)
+
+    def run_inv():
+        P.gw_epsinv_lu(ctx, neps, nfreq, chi, d["vcoul"], einv)
+
+    out = {}
+    for name, fn in (("chi0", run_chi), ("epsinv_lu", run_inv)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / steps
+    pairs = d["nv"] * d["nc"]
+    # a general (non-Hermitian) complex rank-P update: 8 N^2 P flops per frequency
+    flops = 8.0 * neps * neps * pairs * nfreq
+    out["chi0_tflops"] = flops / (out["chi0_ms"] * 1e-3) / 1e12
+    out["chi0_frac_of_fp64_peak"] = out["chi0_tflops"] / FP64_PEAK_TFLOPS
+    out["config"] = {"nfreq": nfreq, "omega_Ha": [0.0, 0.8], "eta_Ha": eta, "pairs": pairs,
+                     "neps": neps}
+    out["note"] = ("chi0 includes zeroing the output, the weights, two Hermitian contractions "
+                   "(Re and Im of the bracket) and their combination; eps^-1 by LU with "
+                   "partial pivoting on the non-Hermitian eps")
+    return out
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -405,6 +449,10 @@ def main():
                 "conduction planes on chip and reuse them across valence bands, so the rate "
                 "by this unit can exceed the HBM peak"}
     epsinv64 = o64["epsinv"]
+
+    # ---------------- real frequency axis (FP64), on the FP64 matrix elements
+    if not args.no_real_axis:
+        result["real_axis"] = bench_real_axis(ctx, P, d64, o64["mtxel"], args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:
