@@ -248,10 +248,13 @@ def bench_real_axis(ctx, P, d, mtxel, steps, nfreq=9, eta=0.005):
                                   eta, 1.0, P.GW_PREC_FP64, chi)
 
     def run_inv():
+        P.gw_epsinv(ctx, neps, nfreq, chi, d["vcoul"], einv)
+
+    def run_lu():
         P.gw_epsinv_lu(ctx, neps, nfreq, chi, d["vcoul"], einv)
 
     out = {}
-    for name, fn in (("chi0", run_chi), ("epsinv_lu", run_inv)):
+    for name, fn in (("chi0", run_chi), ("epsinv", run_inv), ("epsinv_lu", run_lu)):
         fn()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -270,8 +273,9 @@ def bench_real_axis(ctx, P, d, mtxel, steps, nfreq=9, eta=0.005):
     out["config"] = {"nfreq": nfreq, "omega_Ha": [0.0, 0.8], "eta_Ha": eta, "pairs": pairs,
                      "neps": neps}
     out["note"] = ("chi0 includes zeroing the output, the weights, two Hermitian contractions "
-                   "(Re and Im of the bracket) and their combination; eps^-1 by LU with "
-                   "partial pivoting on the non-Hermitian eps")
+                   "(Re and Im of the bracket) and their combination; epsinv is gw_epsinv "
+                   "(Gauss-Jordan kept after its residual check, else LU), epsinv_lu is LU "
+                   "with partial pivoting throughout")
     return out
 
 

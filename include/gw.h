@@ -176,7 +176,10 @@ gw_status gw_chi0_accumulate_real(gw_ctx* ctx, int nv, int nc, int neps,
  * Hermitian negative semidefinite (the imaginary axis), eps~ = I - V^1/2 chi0
  * V^1/2 is Hermitian positive definite and is inverted by blocked Gauss-Jordan
  * without pivoting, every pivot checked (real part >= 1/2, |imaginary part| <=
- * 1/4 of it); if any check fails, or some v <= 0, the whole call is redone by
+ * 1/4 of it).  If a check fails (for example eps from the real axis), the
+ * Gauss-Jordan result is kept only if max_ij |(eps X - I)_ij| <= 1e-9 (|re| +
+ * |im|, every frequency, eps formed again and multiplied on the matrix cores);
+ * otherwise, and whenever some v <= 0, the whole call is redone by
  * gw_epsinv_lu's LU path.
  *
  *   chi0    (device) complex double[nfreq][neps][neps].

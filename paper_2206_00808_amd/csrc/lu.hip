@@ -225,7 +225,7 @@ __global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* 
 // Inverse of the diagonal block D = A[K][K] (nbk <= GB = 64) by Gauss-Jordan
 // without pivoting, register resident (gj_invert_64); the block of frequency f
 // is src[f * sstride + i * ld + j] and its inverse goes to Dw[f]. A pivot that
-// is not real and >= 1/2 sets flag[1].
+// is not real and >= 1/2 sets flag[2].
 __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict__ src, int ld,
                                                   size_t sstride, int nbk,
                                                   cpx<double>* __restrict__ Dw,
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const cpx<double>* __restrict_
       const int i = ti + 32 * a, j = tj + 32 * b;
       d[a][b] = (i < nbk && j < nbk) ? src[(size_t)i * ld + j] : mk(i == j ? 1.0 : 0.0, 0.0);
     }
-  if (gj_invert_64<32>(d, nbk, rowb, colb)) flag[1] = 1;
+  if (gj_invert_64<32>(d, nbk, rowb, colb)) flag[2] = 1;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
         const int i = ti + TG * a, j = tj + TG * b;
         d[a][b] = (i < nb2 && j < nb2) ? Dn[i * GB + j] : mk(i == j ? 1.0 : 0.0, 0.0);
       }
-    if (gj_invert_64<TG>(d, nb2, rowb, colb)) flag[1] = 1;
+    if (gj_invert_64<TG>(d, nb2, rowb, colb)) flag[2] = 1;
 #pragma unroll
     for (int a = 0; a < TE; ++a)
 #pragma unroll
@@ -576,15 +576,84 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
   return GW_OK;
 }
 
+// rmax[f] = max_ij |R_f[i][j] - delta_ij| (|re| + |im|), one workgroup per
+// frequency; a non-finite entry makes the result non-finite
+__global__ void __launch_bounds__(1024) k_resid_max(const cpx<double>* __restrict__ R, int N,
+                                                    double* __restrict__ rmax) {
+  __shared__ double sm[1024];
+  const size_t nn = (size_t)N * N;
+  R += (size_t)blockIdx.x * nn;
+  double m = 0.0;
+  for (size_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    const cpx<double> r = R[e];
+    const double a = fabs(r.x - (i == j ? 1.0 : 0.0)) + fabs(r.y);
+    m = (a > m || a != a) ? a : m;
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = sm[threadIdx.x + s];
+      if (o > sm[threadIdx.x] || o != o) sm[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rmax[blockIdx.x] = sm[0];
+}
+
+// Whether X solves eps X = I for every frequency to max |eps X - I| <= tol,
+// with eps = I - diag(v) chi0 formed again.
+constexpr double kVerifyTol = 1e-9;
+static gw_status epsinv_verified(gw_ctx* c, int N, int nfreq, const double* chi0,
+                                 const double* vcoul, const double* X, bool* ok) {
+  const size_t nn = (size_t)N * N, ext = (size_t)nfreq * nn;
+  gw_status st = ws_begin(c, 2 * align_up(ext * 16) + align_up((size_t)nfreq * 8));
+  if (st != GW_OK) return st;
+  cpx<double>* E = static_cast<cpx<double>*>(ws_take(c, ext * 16));
+  double* R = static_cast<double*>(ws_take(c, ext * 16));
+  double* d_rmax = static_cast<double*>(ws_take(c, (size_t)nfreq * 8));
+  {
+    ProfScope ps(c, "eps_build");
+    hipLaunchKernelGGL(k_eps_build, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, reinterpret_cast<const cpx<double>*>(chi0), vcoul, E, N);
+    GW_CHECK_LAUNCH(c, "k_eps_build");
+  }
+  st = zgemm_nn(c, N, N, N, 1.0, reinterpret_cast<const double*>(E), 0, N, (long long)nn, X, 0, N,
+                (long long)nn, R, 0, N, (long long)nn, nfreq, ext, ext, ext, 0.0);
+  if (st != GW_OK) return st;
+  {
+    ProfScope ps(c, "eps_verify");
+    hipLaunchKernelGGL(k_resid_max, dim3(nfreq), dim3(1024), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(R), N, d_rmax);
+    GW_CHECK_LAUNCH(c, "k_resid_max");
+  }
+  std::vector<double> rmax(nfreq);
+  GW_HIP(c, hipMemcpyAsync(rmax.data(), d_rmax, (size_t)nfreq * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  *ok = true;
+  for (double r : rmax) *ok = *ok && r <= kVerifyTol;
+  return GW_OK;
+}
+
 gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const double* vcoul,
                      double* epsinv) {
   gw_status st = epsinv_gauss_jordan(c, N, nfreq, chi0, vcoul, epsinv);
   if (st != GW_OK) return st;
-  int flags[2] = {0, 0};
+  int flags[3] = {0, 0, 0};
   GW_HIP(c, hipMemcpyAsync(flags, c->d_flag, sizeof flags, hipMemcpyDeviceToHost, c->stream));
   GW_HIP(c, hipStreamSynchronize(c->stream));
-  if (!flags[1]) return GW_OK;
-  // not positive definite (or v <= 0): general LU with partial pivoting
+  // some v <= 0: the symmetric form eps~ does not exist; general LU
+  if (flags[1]) return epsinv_pivoted_one(c, N, nfreq, chi0, vcoul, epsinv);
+  if (!flags[2]) return GW_OK;
+  // a pivot was not of the Hermitian positive-definite kind (eps~ not >= I, as
+  // on the real frequency axis): Gauss-Jordan without pivoting carries no
+  // stability guarantee there, so its result is kept only if it solves
+  // eps X = I to kVerifyTol; otherwise general LU with partial pivoting
+  bool ok = false;
+  if ((st = epsinv_verified(c, N, nfreq, chi0, vcoul, epsinv, &ok)) != GW_OK) return st;
+  if (ok) return GW_OK;
   return epsinv_pivoted_one(c, N, nfreq, chi0, vcoul, epsinv);
 }
 

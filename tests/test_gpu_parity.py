@@ -264,6 +264,9 @@ def test_chi0_real_axis_from_pipeline_and_lu_inverse(P, ctx):
                               P.GW_PREC_FP64, chi)
     einv = torch.empty_like(chi)
     P.gw_epsinv_lu(ctx, neps, len(omega), chi, d["vcoul"], einv)
+    # the default entry point: Gauss-Jordan, kept after the residual check, or LU
+    einv2 = torch.empty_like(chi)
+    P.gw_epsinv(ctx, neps, len(omega), chi, d["vcoul"], einv2)
     torch.cuda.synchronize()
     mh = m.cpu().numpy().reshape(d["nv"], d["nc"], neps)
     x = oracle.chi0_real(mh, d["ev"].cpu().numpy(), d["ec"].cpu().numpy(), omega, eta)
@@ -271,6 +274,7 @@ def test_chi0_real_axis_from_pipeline_and_lu_inverse(P, ctx):
     for f in range(len(omega)):
         assert oracle.rel_f(chi[f].cpu().numpy(), x[f]) < 1e-12
         assert oracle.rel_f(einv[f].cpu().numpy(), e[f]) < 1e-10
+        assert oracle.rel_f(einv2[f].cpu().numpy(), e[f]) < 1e-10
 
 
 def test_chi0_real_axis_rejects_bad_arguments(P, ctx):
