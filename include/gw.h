@@ -177,8 +177,9 @@ gw_status gw_chi0_accumulate_real(gw_ctx* ctx, int nv, int nc, int neps,
  * V^1/2 is Hermitian positive definite and is inverted by blocked Gauss-Jordan
  * without pivoting, every pivot checked (real part >= 1/2, |imaginary part| <=
  * 1/4 of it).  If a check fails (for example eps from the real axis), the
- * Gauss-Jordan result is kept only if max_ij |(eps X - I)_ij| <= 1e-9 (|re| +
- * |im|, every frequency, eps formed again and multiplied on the matrix cores);
+ * Gauss-Jordan result is kept only if max_ij |(eps X - I)_ij| <= 1e-10 / neps
+ * (|re| + |im|, every frequency, eps formed again and multiplied on the matrix
+ * cores), which bounds the relative error of X in the infinity norm by 1e-10;
  * otherwise, and whenever some v <= 0, the whole call is redone by
  * gw_epsinv_lu's LU path.
  *

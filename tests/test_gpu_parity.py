@@ -264,10 +264,17 @@ def test_chi0_real_axis_from_pipeline_and_lu_inverse(P, ctx):
                               P.GW_PREC_FP64, chi)
     einv = torch.empty_like(chi)
     P.gw_epsinv_lu(ctx, neps, len(omega), chi, d["vcoul"], einv)
-    # the default entry point: Gauss-Jordan, kept after the residual check, or LU
+    # the default entry point: eps~ is not >= I on the real axis, so the
+    # Gauss-Jordan result goes through the residual check; for this well-conditioned
+    # eps it is kept, and the LU path does not run
     einv2 = torch.empty_like(chi)
+    ctx.profile(True)
+    ctx.profile_reset()
     P.gw_epsinv(ctx, neps, len(omega), chi, d["vcoul"], einv2)
     torch.cuda.synchronize()
+    names = set(ctx.profile_table())
+    ctx.profile(False)
+    assert "eps_verify" in names and "lu_panel" not in names, names
     mh = m.cpu().numpy().reshape(d["nv"], d["nc"], neps)
     x = oracle.chi0_real(mh, d["ev"].cpu().numpy(), d["ec"].cpu().numpy(), omega, eta)
     e = oracle.epsilon_inverse(x, d["vcoul"].cpu().numpy())
