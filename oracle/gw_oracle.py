@@ -30,6 +30,8 @@ chi0_real                | scipy ZHERK on the real and imaginary weight parts,
 epsilon / epsilon_inverse| Sherman-Morrison closed form, eigenvalue bounds,
                          | LU solve via scipy
 head_overlap             | convolution form at G = 0, orthonormality
+head_dipole              | k.p limit of head_overlap for a spin-dependent
+                         | local-potential model, Hermiticity, plane waves
 """
 from __future__ import annotations
 
@@ -39,7 +41,7 @@ __all__ = [
     "box_offsets", "wavefunction_on_box", "mtxel_fft", "mtxel_convolution",
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
-    "head_overlap", "chi0_from_system", "rel_f", "alias_free",
+    "head_overlap", "head_dipole", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -246,6 +248,27 @@ def head_overlap(cv, gv, cc, gc):
     Returns [nv][nc] complex128.
     """
     return mtxel_convolution(cv, gv, cc, gc, np.zeros((1, 3), dtype=np.int32))[:, :, 0]
+
+
+def head_dipole(cv, cc, g, cell, kred, qcart, ev, ec):
+    """M_vc(q -> 0, G = 0) from momentum matrix elements at one k-point.
+
+    Sec. II, optical absorption: with the momentum operator standing in for the
+    velocity, <v|v|c> = -i (E_c - E_v) <v|r|c>, so to first order in q
+    M_vc(q, G=0) = i q.<v|r|c> = q.P_vc / (E_v - E_c), where
+    P_vc = sum_alpha sum_G conj(c_v^alpha(G)) (k+G) c_c^alpha(G) and
+    k+G = (g + kred) * 2 pi / a (Cartesian, bohr^-1; orthorhombic cell a).
+    Valence and conduction coefficients on the same G list g at k.
+    Returns [nv][nc] complex128.
+    """
+    cv = np.asarray(cv, dtype=np.complex128)
+    cc = np.asarray(cc, dtype=np.complex128)
+    kg = (np.asarray(g, dtype=np.float64) + np.asarray(kred, dtype=np.float64)) * (
+        2.0 * np.pi / np.asarray(cell, dtype=np.float64))
+    qdot = kg @ np.asarray(qcart, dtype=np.float64)
+    p = np.einsum("vsg,g,csg->vc", np.conj(cv), qdot, cc)
+    d = np.asarray(ev, dtype=np.float64)[:, None] - np.asarray(ec, dtype=np.float64)[None, :]
+    return p / d
 
 
 def chi0_from_system(sysd, prefactor=1.0, nc=None, method="fft"):

@@ -309,6 +309,91 @@ def test_eps_spectrum_bounds_and_lu_solve():
         assert oracle.rel_f(einv[f], ref) < 1e-13
 
 
+def _spinor_model(cell, g, kred, vpot):
+    """Eigenpairs of H(k) = |k+G|^2/2 + V(G - G') (2x2 in spin) on the list g:
+    a local, spin-dependent potential, so the velocity is exactly p + k."""
+    ng = len(g)
+    kg = (g + np.asarray(kred)) * (2 * np.pi / np.asarray(cell))
+    h = np.zeros((2 * ng, 2 * ng), dtype=np.complex128)
+    for a in range(ng):
+        for b in range(ng):
+            h[2 * a:2 * a + 2, 2 * b:2 * b + 2] = vpot(tuple(g[a] - g[b]))
+    h += np.diag(np.repeat(0.5 * np.sum(kg * kg, axis=1), 2))
+    e, u = np.linalg.eigh(h)
+    # coefficients c[n][sigma][G]
+    return e, np.transpose(u.reshape(ng, 2, 2 * ng), (2, 1, 0))
+
+
+def test_head_dipole_is_the_kp_limit_of_the_overlap():
+    """In a plane-wave model with a local spin-dependent potential (no time
+    reversal, so no degeneracies), the G = 0 matrix element <u_v,k+q|u_c,k> from
+    wavefunctions diagonalised at k+q matches q.P_vc/(E_v - E_c) from k alone, with
+    an error second order in q."""
+    cell = (5.0, 5.3, 5.7)
+    g = g_sphere(cell, (0, 0, 0), 6.0)
+    rng = np.random.default_rng(11)
+    table = {}
+
+    def vpot(dg):
+        if dg == (0, 0, 0):
+            return np.array([[0.3, 0.1 - 0.05j], [0.1 + 0.05j, -0.2]])
+        key = min(dg, tuple(-x for x in dg))
+        if key not in table:
+            table[key] = 0.15 * (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)))
+        m = table[key]
+        return m if dg == key else m.conj().T
+
+    nv, nc = 2, 3
+    e0, c0 = _spinor_model(cell, g, (0, 0, 0), vpot)
+    assert np.min(np.diff(e0[:nv + nc])) > 1e-3
+    qdir = np.array([0.6, -0.3, 0.74])
+    qdir /= np.linalg.norm(qdir)
+    errs = []
+    for qn in (2e-3, 1e-3):
+        qcart = qn * qdir
+        qred = qcart * np.asarray(cell) / (2 * np.pi)
+        eq, cq = _spinor_model(cell, g, qred, vpot)
+        # fix the arbitrary phase of each band at k+q to its k counterpart
+        for n in range(nv):
+            ov = np.vdot(c0[n].ravel(), cq[n].ravel())
+            cq[n] *= np.conj(ov) / abs(ov)
+        over = oracle.head_overlap(cq[:nv], g, c0[nv:nv + nc], g)
+        dip = oracle.head_dipole(c0[:nv], c0[nv:nv + nc], g, cell, (0, 0, 0), qcart, e0[:nv],
+                                 e0[nv:nv + nc])
+        errs.append(np.abs(over - dip).max() / np.abs(dip).max())
+    assert errs[0] < 5e-3
+    # M itself is first order in q and the difference second order, so the
+    # relative difference halves with q
+    assert 1.8 < errs[0] / errs[1] < 2.2
+
+
+def test_head_dipole_hermiticity_and_plane_waves():
+    cell = (5.0, 5.3, 5.7)
+    g = g_sphere(cell, (0, 0, 0), 8.0)
+    rng = np.random.default_rng(3)
+    nv, nc = 2, 3
+    cv = _random_spinors(rng, len(g), nv, 2)
+    cc = _random_spinors(rng, len(g), nc, 2)
+    ev = np.array([-0.3, -0.1])
+    ec = np.array([0.2, 0.4, 0.9])
+    k = (0.1, -0.2, 0.05)
+    q = np.array([1e-3, -2e-3, 0.5e-3])
+    d_vc = oracle.head_dipole(cv, cc, g, cell, k, q, ev, ec) * (ev[:, None] - ec[None, :])
+    d_cv = oracle.head_dipole(cc, cv, g, cell, k, q, ec, ev) * (ec[:, None] - ev[None, :])
+    assert np.allclose(d_vc, np.conj(d_cv).T, rtol=1e-14, atol=1e-16)
+    # single plane waves: P = delta_{G1 G2} delta_{ab} (k + G1)
+    i1, i2 = 5, 9
+    a = np.zeros((1, 2, len(g)), dtype=np.complex128)
+    b = np.zeros((2, 2, len(g)), dtype=np.complex128)
+    a[0, 1, i1] = 1.0
+    b[0, 1, i1] = 1.0
+    b[1, 1, i2] = 1.0
+    m = oracle.head_dipole(a, b, g, cell, k, q, [0.0], [1.0, 1.0])
+    kg1 = (np.asarray(g[i1], dtype=np.float64) + np.asarray(k)) * 2 * np.pi / np.asarray(cell)
+    assert np.isclose(m[0, 0], -(kg1 @ q), rtol=1e-14, atol=0)
+    assert m[0, 1] == 0
+
+
 def test_generator_is_deterministic():
     a = synth.build_system(synth.CONFIGS["C1"])
     b = synth.build_system(synth.CONFIGS["C1"])
