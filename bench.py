@@ -279,6 +279,35 @@ def bench_real_axis(ctx, P, d, mtxel, steps, nfreq=9, eta=0.005):
     return out
 
 
+def bench_head_dipole(ctx, P, sysd, d, steps):
+    """The q -> 0 head from momentum matrix elements (gw_head_dipole) at the
+    workload's sizes: N_v bands and N_c bands of the conduction set's sphere at k
+    (both at one k-point), q = 1e-3 bohr^-1 along x."""
+    import torch
+    nv, nc = d["nv"], d["nc"]
+    cc = d["cc"]
+    cv = cc[:nv].contiguous()
+    g = np.asarray(sysd["gc"], dtype=np.int32)
+    mh = torch.empty(nv * nc, dtype=torch.complex128, device="cuda")
+    args = (ctx, d["nspinor"], g, cv, cc, sysd["cell"], (0.0, 0.0, 0.0), (1e-3, 0.0, 0.0),
+            d["ev"], d["ec"], mh)
+    P.gw_head_dipole(*args)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        P.gw_head_dipole(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nbytes = (nv + nc) * d["nspinor"] * g.shape[0] * 16 + nv * nc * 16
+    return {"ms": ms, "pairs": nv * nc, "ng": int(g.shape[0]),
+            "algorithmic_GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+            "note": "includes the G-list upload and the call's final synchronisation; "
+                    "algorithmic bytes = both coefficient sets once + the output"}
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -457,6 +486,7 @@ def main():
     # ---------------- real frequency axis (FP64), on the FP64 matrix elements
     if not args.no_real_axis:
         result["real_axis"] = bench_real_axis(ctx, P, d64, o64["mtxel"], args.steps)
+        result["head_dipole"] = bench_head_dipole(ctx, P, sysd, d64, args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:

@@ -149,6 +149,29 @@ gw_status gw_chi0_accumulate(gw_ctx* ctx, int nv, int nc, int neps,
                              double* chi0);
 
 /*
+ * gw_head_dipole -- the q -> 0 head M_vc(q, G=0) from momentum matrix elements at
+ * one k-point (Sec. II, optical absorption: the dipole relation with the
+ * momentum operator standing in for the velocity), to first order in q:
+ *   mhead[v*nc + c] = q.P_vc / (E_v - E_c),
+ *   P_vc = sum_s sum_G conj(c_v^s(G)) (k+G) c_c^s(G),  k+G = (g + kpt) 2 pi / cell.
+ * No wavefunctions at k+q are needed.  The result is the mhead input of
+ * gw_chi0_accumulate (valence and conduction here both at k).
+ *   g        (host) int32[ng][3] G-vectors shared by cv and cc.
+ *   cv, cc   (device) complex[nv][nspinor][ng], complex[nc][nspinor][ng] of dtype.
+ *   cell     (host) double[3] orthorhombic cell edges (bohr); kpt (host) double[3]
+ *            reduced k; qcart (host) double[3] the small q in Cartesian bohr^-1.
+ *   ev, ec   (device) double[nv], double[nc].
+ *   mhead    (device) out complex double[nv*nc]; pairs with ev == ec give
+ *            non-finite values.
+ * Errors: GW_EINVAL for nspinor not 1 or 2, negative sizes, unknown dtype, NULL
+ * arrays, a non-positive cell edge or non-finite k or q.
+ */
+gw_status gw_head_dipole(gw_ctx* ctx, int nspinor, int nv, int nc, int ng, const int* g,
+                         const void* cv, const void* cc, gw_dtype dtype, const double* cell,
+                         const double* kpt, const double* qcart, const double* ev,
+                         const double* ec, double* mhead);
+
+/*
  * gw_chi0_accumulate_real -- the polarizability on the real frequency axis with
  * broadening (Sec. II, the Adler-Wiser sum as written):
  *   chi0_f[G][G'] += prefactor * sum_p b_p(omega_f) conj(M_p(G)) M_p(G'),

@@ -27,7 +27,7 @@ EXPORTED = [
     "gw_ctx_profile", "gw_ctx_profile_only", "gw_ctx_profile_reset", "gw_ctx_profile_count",
     "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
-    "gw_epsinv_lu",
+    "gw_epsinv_lu", "gw_head_dipole",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -71,6 +71,8 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_head_dipole": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp,
+                            _vp]),
     "gw_mlp_create": (_i, [_vp, ct.POINTER(_vp), _i, _i, _i, _i, _u64]),
     "gw_mlp_destroy": (_i, [_vp]),
     "gw_mlp_save": (_i, [_vp, _vp, ct.POINTER(ct.c_size_t)]),
@@ -246,6 +248,21 @@ def gw_epsinv_lu(ctx, neps, nfreq, chi0, vcoul, epsinv):
     ctx.sync_stream()
     s = _lib.gw_epsinv_lu(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul),
                           _ptr(epsinv))
+    return _check(ctx, s)
+
+
+def gw_head_dipole(ctx, nspinor, g, cv, cc, cell, kpt, qcart, ev, ec, mhead):
+    """mhead[v*nc + c] = q.P_vc / (E_v - E_c) from momentum matrix elements (see
+    include/gw.h); g is a host int array [ng][3], cv/cc device tensors."""
+    ctx.sync_stream()
+    gh = np.ascontiguousarray(np.asarray(g, dtype=np.int32))
+    cl = np.ascontiguousarray(np.asarray(cell, dtype=np.float64))
+    kp = np.ascontiguousarray(np.asarray(kpt, dtype=np.float64))
+    qc = np.ascontiguousarray(np.asarray(qcart, dtype=np.float64))
+    nv, nc, ng = int(cv.shape[0]), int(cc.shape[0]), int(gh.shape[0])
+    s = _lib.gw_head_dipole(ctx.handle, int(nspinor), nv, nc, ng, gh.ctypes.data, _ptr(cv),
+                            _ptr(cc), _dtype_code(cv), cl.ctypes.data, kp.ctypes.data,
+                            qc.ctypes.data, _ptr(ev), _ptr(ec), _ptr(mhead))
     return _check(ctx, s)
 
 

@@ -419,6 +419,42 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
   return GW_OK;
 }
 
+gw_status gw_head_dipole(gw_ctx* c, int nspinor, int nv, int nc, int ng, const int* g,
+                         const void* cv, const void* cc, gw_dtype dtype, const double* cell,
+                         const double* kpt, const double* qcart, const double* ev,
+                         const double* ec, double* mhead) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (nspinor != 1 && nspinor != 2) return fail(c, GW_EINVAL, "nspinor must be 1 or 2");
+  if (nv < 0 || nc < 0 || ng < 0) return fail(c, GW_EINVAL, "negative size");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (nv == 0 || nc == 0) return GW_OK;
+  if (!cell || !kpt || !qcart || !ev || !ec || !mhead || (ng > 0 && (!g || !cv || !cc)))
+    return fail(c, GW_EINVAL, "NULL array argument");
+  if ((long long)nv * nc > (1LL << 31) - 1) return fail(c, GW_EINVAL, "nv*nc too large");
+  double sq[3], q0k = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    if (!(cell[i] > 0.0) || !std::isfinite(cell[i]) || !std::isfinite(kpt[i]) ||
+        !std::isfinite(qcart[i]))
+      return fail(c, GW_EINVAL, "cell must be positive and k, q finite");
+    sq[i] = 2.0 * M_PI * qcart[i] / cell[i];
+    q0k += kpt[i] * sq[i];
+  }
+  (void)hipSetDevice(c->device);
+  gw_status st = ws_begin(c, align_up((size_t)std::max(ng, 1) * 3 * sizeof(int)));
+  if (st != GW_OK) return st;
+  int* d_g = static_cast<int*>(ws_take(c, (size_t)std::max(ng, 1) * 3 * sizeof(int)));
+  if (ng > 0)
+    GW_HIP(c, hipMemcpyAsync(d_g, g, (size_t)ng * 3 * sizeof(int), hipMemcpyHostToDevice,
+                             c->stream));
+  if ((st = head_dipole(c, dtype, nspinor, nv, nc, ng, cv, cc, d_g, sq, q0k, ev, ec, mhead)) !=
+      GW_OK)
+    return st;
+  // g was copied from pageable host memory: finish before returning
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  return GW_OK;
+}
+
 gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const void* mtxel,
                                   gw_dtype dtype, const double* ev, const double* ec, int nfreq,
                                   const double* omega, double eta, double prefactor, gw_prec prec,

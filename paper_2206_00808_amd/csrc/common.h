@@ -165,6 +165,9 @@ size_t band_scratch_bytes(const int box[3], const SphereMap* sm, int nbs, size_t
 size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem);
 
 // Head overlap (head.hip)
+gw_status head_dipole(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int nc, int ng,
+                      const void* cv, const void* cc, const int* d_g, const double sq[3],
+                      double q0k, const double* ev, const double* ec, double* mhead);
 gw_status head_overlap(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int ngv, const void* cv,
                        int nc, int ngc, const void* cc, const int* d_match, int nmatch,
                        double* mhead);

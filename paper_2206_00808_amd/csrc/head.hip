@@ -66,6 +66,72 @@ gw_status head_overlap(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int ngv, con
   return GW_OK;
 }
 
+// The head from momentum matrix elements at one k-point (Sec. II, optical
+// absorption: the dipole relation with the momentum operator standing in for
+// the velocity): M_vc(q, 0) = q.P_vc / (E_v - E_c) to first order in q, with
+// P_vc = sum_s sum_G conj(c_v^s(G)) (k+G) c_c^s(G). q.(k+G) = sum_i g_i sq_i + q0k
+// with sq_i = 2 pi q_i / a_i and q0k = sum_i k_i sq_i (the host folds the cell
+// and k in). One workgroup per pair; the pair sum is reduced in a fixed order.
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_head_dipole(const cpx<Tin>* __restrict__ cv,
+                                                     const cpx<Tin>* __restrict__ cc, int ng,
+                                                     int nspinor, int nc,
+                                                     const int* __restrict__ g, double sq0,
+                                                     double sq1, double sq2, double q0k,
+                                                     const double* __restrict__ ev,
+                                                     const double* __restrict__ ec,
+                                                     cpx<double>* __restrict__ mhead) {
+  __shared__ double sr[256], si[256];
+  const int p = blockIdx.x;
+  const int v = p / nc, c = p % nc;
+  double ar = 0.0, ai = 0.0;
+  for (int s = 0; s < nspinor; ++s) {
+    const cpx<Tin>* a = cv + ((size_t)v * nspinor + s) * ng;
+    const cpx<Tin>* b = cc + ((size_t)c * nspinor + s) * ng;
+    for (int m = threadIdx.x; m < ng; m += blockDim.x) {
+      const double qd = g[3 * m] * sq0 + g[3 * m + 1] * sq1 + g[3 * m + 2] * sq2 + q0k;
+      const cpx<Tin> x = a[m], y = b[m];
+      const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+      ar += qd * (xr * yr + xi * yi);
+      ai += qd * (xr * yi - xi * yr);
+    }
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double d = ev[v] - ec[c];
+    mhead[p] = mk(sr[0] / d, si[0] / d);
+  }
+}
+
+gw_status head_dipole(gw_ctx* c, gw_dtype dt, int nspinor, int nv, int nc, int ng,
+                      const void* cv, const void* cc, const int* d_g, const double sq[3],
+                      double q0k, const double* ev, const double* ec, double* mhead) {
+  const int P = nv * nc;
+  if (P == 0) return GW_OK;
+  ProfScope ps(c, "head_dipole");
+  if (dt == GW_C128)
+    hipLaunchKernelGGL(k_head_dipole<double>, dim3(P), dim3(256), 0, c->stream,
+                       static_cast<const cpx<double>*>(cv), static_cast<const cpx<double>*>(cc),
+                       ng, nspinor, nc, d_g, sq[0], sq[1], sq[2], q0k, ev, ec,
+                       reinterpret_cast<cpx<double>*>(mhead));
+  else
+    hipLaunchKernelGGL(k_head_dipole<float>, dim3(P), dim3(256), 0, c->stream,
+                       static_cast<const cpx<float>*>(cv), static_cast<const cpx<float>*>(cc), ng,
+                       nspinor, nc, d_g, sq[0], sq[1], sq[2], q0k, ev, ec,
+                       reinterpret_cast<cpx<double>*>(mhead));
+  GW_CHECK_LAUNCH(c, "k_head_dipole");
+  return GW_OK;
+}
+
 // chi0[f][h][j] += sum_p conj(mh_p) w_f(p) X_p(j), X_p(j) = M_p(j) (j != h) or mh_p (j = h);
 // chi0[f][j][h] += the conjugate for j != h. A block takes kWingCols columns; its
 // kWingSlices thread rows split the pair sum and are added in a fixed order.

@@ -210,6 +210,60 @@ def test_chi0_ragged_sizes_match_oracle(P, ctx, prec, shape):
         assert oracle.rel_f(got[f], x[f]) < tol, (prec, shape, f)
 
 
+# ----------------------------------------------------------------- q -> 0 head from momenta
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_head_dipole_matches_oracle(P, ctx, dtype):
+    from synth.generate import _random_spinors, g_sphere
+    rng = np.random.default_rng(17)
+    cell = (5.0, 5.3, 5.7)
+    g = g_sphere(cell, (0, 0, 0), 9.0)
+    nv, nc = 5, 11
+    cv = _random_spinors(rng, len(g), nv, 2).astype(dtype)
+    cc = _random_spinors(rng, len(g), nc, 2).astype(dtype)
+    ev = np.sort(rng.uniform(-0.4, -0.01, nv))
+    ec = np.sort(rng.uniform(0.02, 0.9, nc))
+    k = (0.25, 0.0, -0.25)
+    q = np.array([1.0e-3, -0.4e-3, 0.7e-3])
+    want = oracle.head_dipole(cv.astype(np.complex128), cc.astype(np.complex128), g, cell, k, q,
+                              ev, ec).ravel()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    mh = torch.empty(nv * nc, dtype=torch.complex128, device="cuda:0")
+    P.gw_head_dipole(ctx, 2, g, dev(cv), dev(cc), cell, k, q, dev(ev), dev(ec), mh)
+    torch.cuda.synchronize()
+    assert oracle.rel_f(mh.cpu().numpy(), want) < 1e-12
+
+
+def test_head_dipole_feeds_the_chi0_head_and_wings(P, ctx):
+    """The dipole head as gw_chi0_accumulate's mhead: the head row and column of chi0
+    are the contraction with column h of M replaced by it."""
+    from synth.generate import _random_spinors, g_sphere
+    rng = np.random.default_rng(23)
+    cell = (5.0, 5.3, 5.7)
+    g = g_sphere(cell, (0, 0, 0), 9.0)
+    nv, nc, neps, h = 4, 9, 90, 0
+    cv = _random_spinors(rng, len(g), nv, 2)
+    cc = _random_spinors(rng, len(g), nc, 2)
+    ev = np.sort(rng.uniform(-0.4, -0.01, nv))
+    ec = np.sort(rng.uniform(0.02, 0.9, nc))
+    q = np.array([0.0, 2e-3, 0.0])
+    m = (rng.standard_normal((nv, nc, neps)) + 1j * rng.standard_normal((nv, nc, neps))) / 3
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    mh = torch.empty(nv * nc, dtype=torch.complex128, device="cuda:0")
+    P.gw_head_dipole(ctx, 2, g, dev(cv), dev(cc), cell, (0, 0, 0), q, dev(ev), dev(ec), mh)
+    omega = [0.0, 0.5]
+    chi = torch.zeros((2, neps, neps), dtype=torch.complex128, device="cuda:0")
+    P.gw_chi0_accumulate(ctx, nv, nc, neps, dev(m), dev(ev), dev(ec), omega, 1.0,
+                         P.GW_PREC_FP64, chi, mhead=mh, head_index=h)
+    torch.cuda.synchronize()
+    mx = m.copy()
+    mx[:, :, h] = oracle.head_dipole(cv, cc, g, cell, (0, 0, 0), q, ev, ec)
+    x = oracle.chi0(mx, ev, ec, omega)
+    got = chi.cpu().numpy()
+    for f in range(2):
+        assert oracle.rel_f(got[f], x[f]) < 1e-12
+        assert np.abs(got[f][h] - x[f][h]).max() <= 1e-12 * np.abs(x[f][h]).max()
+
+
 # ----------------------------------------------------------------- real frequency axis
 @pytest.mark.parametrize("prec", ["fp64", "splitbf16"])
 @pytest.mark.parametrize("shape", [(3, 37, 70), (16, 50, 200)])
