@@ -32,6 +32,9 @@ epsilon / epsilon_inverse| Sherman-Morrison closed form, eigenvalue bounds,
 head_overlap             | convolution form at G = 0, orthonormality
 head_dipole              | k.p limit of head_overlap for a spin-dependent
                          | local-potential model, Hermiticity, plane waves
+screened_w               | Hermitian for the symmetric form of eps (closed form)
+sigma_sx_static          | bare exchange at eps^-1 = I (closed form), real and
+                         | between the bare exchange and 0 for chi0 <= 0
 """
 from __future__ import annotations
 
@@ -41,7 +44,7 @@ __all__ = [
     "box_offsets", "wavefunction_on_box", "mtxel_fft", "mtxel_convolution",
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
-    "head_overlap", "head_dipole", "chi0_from_system", "rel_f", "alias_free",
+    "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -240,6 +243,25 @@ def epsilon_inverse(chi0_all, vcoul):
     """
     c = np.asarray(chi0_all, dtype=np.complex128)
     return np.stack([np.linalg.inv(epsilon(cf, vcoul)) for cf in c])
+
+
+def screened_w(epsinv_all, vcoul):
+    """W_GG'(q) = eps^-1_GG'(q) v(q+G')  (Sec. II)."""
+    e = np.asarray(epsinv_all, dtype=np.complex128)
+    return e * np.asarray(vcoul, dtype=np.float64)[None, None, :]
+
+
+def sigma_sx_static(mtxel, epsinv, vcoul, prefactor=1.0):
+    """Screened exchange <n|Sigma^SX|n> with the static eps^-1 (Sec. II, the SX
+    term of the self-energy with its frequency argument taken at 0):
+      -prefactor sum_{n''}^{occ} sum_{G,G'} conj(M_{n''n}(G)) M_{n''n}(G') eps^-1_GG' v(q+G'),
+    mtxel [nocc][nband][neps] holding M_{n''n} at -q-G by sphere index G
+    (the caller's ordering), epsinv [neps][neps] at omega = 0, vcoul [neps].
+    Returns complex [nband].
+    """
+    m = np.asarray(mtxel, dtype=np.complex128)
+    w = np.asarray(epsinv, dtype=np.complex128) * np.asarray(vcoul, dtype=np.float64)[None, :]
+    return -prefactor * np.einsum("ang,gh,anh->n", np.conj(m), w, m)
 
 
 def head_overlap(cv, gv, cc, gc):

@@ -394,6 +394,26 @@ def test_head_dipole_hermiticity_and_plane_waves():
     assert m[0, 1] == 0
 
 
+def test_static_screened_exchange_bounds(tiny):
+    """Sigma^SX with the static eps^-1: at eps^-1 = I it is the bare exchange
+    -sum |M(G)|^2 v(G); with chi0 <= 0 the screened W = eps^-1 v is Hermitian
+    positive semidefinite and no larger than v, so Sigma^SX is real and lies
+    between the bare exchange and 0, band by band."""
+    s = tiny
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])  # [3][5][neps]
+    v = s["vcoul"]
+    neps = m.shape[-1]
+    bare = oracle.sigma_sx_static(m, np.eye(neps), v, prefactor=0.5)
+    assert np.allclose(bare, -0.5 * np.einsum("ang,g->n", np.abs(m) ** 2, v), rtol=1e-14, atol=0)
+    x = oracle.chi0(m, s["ev"], s["ec"], [0.0])[0]
+    einv = oracle.epsilon_inverse(x[None], v)[0]
+    w = oracle.screened_w(einv[None], v)[0]
+    assert np.abs(w - w.conj().T).max() < 1e-13 * np.abs(w).max()
+    sx = oracle.sigma_sx_static(m, einv, v, prefactor=0.5)
+    assert np.abs(sx.imag).max() < 1e-12 * np.abs(sx).max()
+    assert np.all(sx.real < 0) and np.all(sx.real > bare.real)
+
+
 def test_generator_is_deterministic():
     a = synth.build_system(synth.CONFIGS["C1"])
     b = synth.build_system(synth.CONFIGS["C1"])
