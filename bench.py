@@ -308,6 +308,39 @@ def bench_head_dipole(ctx, P, sysd, d, steps):
                     "algorithmic bytes = both coefficient sets once + the output"}
 
 
+def bench_w_and_sx(ctx, P, d, mtxel, epsinv, steps):
+    """The consumers of eps^-1 at the workload's sizes: W = eps^-1 v over every
+    frequency (gw_screened_w, HBM-bound: eps^-1 read once, W written once), and the
+    static screened exchange (gw_sigma_sx) with the N_v valence bands as the occupied
+    n'' and the N_c conduction bands as n, on the omega = 0 eps^-1."""
+    import torch
+    nv, nc, neps, nfreq = d["nv"], d["nc"], d["neps"], epsinv.shape[0]
+    w = torch.empty_like(epsinv)
+    sig = torch.zeros(nc, dtype=torch.complex128, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn in (
+            ("screened_w", lambda: P.gw_screened_w(ctx, neps, nfreq, epsinv, d["vcoul"], w)),
+            ("sigma_sx", lambda: P.gw_sigma_sx(ctx, nv, nc, neps, mtxel, epsinv[0], d["vcoul"],
+                                               1.0, sig))):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms": e0.elapsed_time(e1) / steps}
+    wb = 2 * nfreq * neps * neps * 16 + neps * 8
+    out["screened_w"]["algorithmic_GB_per_s"] = wb / (out["screened_w"]["ms"] * 1e-3) / 1e9
+    fl = 8.0 * nv * nc * neps * neps
+    out["sigma_sx"]["TFLOP_per_s"] = fl / (out["sigma_sx"]["ms"] * 1e-3) / 1e12
+    out["sigma_sx"]["note"] = ("flops = the U = conj(M) eps^-1 contraction, 8 N_v N_c N_eps^2; "
+                               "includes the widening copy and the per-band reduction")
+    return out
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -487,6 +520,7 @@ def main():
     if not args.no_real_axis:
         result["real_axis"] = bench_real_axis(ctx, P, d64, o64["mtxel"], args.steps)
         result["head_dipole"] = bench_head_dipole(ctx, P, sysd, d64, args.steps)
+        result["w_and_sx"] = bench_w_and_sx(ctx, P, d64, o64["mtxel"], epsinv64, args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:

@@ -225,6 +225,36 @@ gw_status gw_epsinv(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
 gw_status gw_epsinv_lu(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
                        const double* vcoul, double* epsinv);
 
+/*
+ * gw_screened_w -- W_f[G][G'] = epsinv_f[G][G'] v(q+G') (Sec. II).
+ *   epsinv (device) complex double[nfreq][neps][neps]; vcoul (device) double[neps];
+ *   w      (device) out complex double[nfreq][neps][neps] (may be epsinv: in place).
+ * Errors: GW_EINVAL for negative sizes, NULL arrays, nfreq > 65535.
+ */
+gw_status gw_screened_w(gw_ctx* ctx, int neps, int nfreq, const double* epsinv,
+                        const double* vcoul, double* w);
+
+/*
+ * gw_sigma_sx -- the screened exchange with the static inverse dielectric matrix
+ * (Sec. II, the SX term of the self-energy with its frequency argument at 0),
+ * for one q, added to sigma:
+ *   sigma[n] -= prefactor sum_{n''}^{occ} sum_{G,G'} conj(M_{n''n}(G)) M_{n''n}(G')
+ *               epsinv[G][G'] v(q+G'),
+ * computed as U = conj(M) epsinv on the matrix cores and per-band dot products
+ * with v M, summed over n'' and G' in a fixed order.
+ *   mtxel   (device) complex[nocc][nband][neps] of dtype: M_{n''n} at -q-G by the
+ *           sphere index G (the caller's ordering, matching epsinv's).
+ *   epsinv  (device) complex double[neps][neps] at omega = 0; vcoul (device) double[neps].
+ *   prefactor  the q-point weight.
+ *   sigma   (device) in/out complex double[nband]; may not alias an input.
+ * Uses 2*nocc*nband*neps*16 bytes of context workspace.
+ * Errors: GW_EINVAL for negative sizes, unknown dtype, NULL arrays, a non-finite
+ * prefactor, nocc*nband > 65535 or neps > 16384; GW_EALIAS if sigma aliases an input.
+ */
+gw_status gw_sigma_sx(gw_ctx* ctx, int nocc, int nband, int neps, const void* mtxel,
+                      gw_dtype dtype, const double* epsinv, const double* vcoul,
+                      double prefactor, double* sigma);
+
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */
 /* ------------------------------------------------------------------------ */

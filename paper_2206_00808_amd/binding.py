@@ -27,7 +27,7 @@ EXPORTED = [
     "gw_ctx_profile", "gw_ctx_profile_only", "gw_ctx_profile_reset", "gw_ctx_profile_count",
     "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
-    "gw_epsinv_lu", "gw_head_dipole",
+    "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -71,6 +71,8 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_screened_w": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_sigma_sx": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _d, _vp]),
     "gw_head_dipole": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp,
                             _vp]),
     "gw_mlp_create": (_i, [_vp, ct.POINTER(_vp), _i, _i, _i, _i, _u64]),
@@ -263,6 +265,22 @@ def gw_head_dipole(ctx, nspinor, g, cv, cc, cell, kpt, qcart, ev, ec, mhead):
     s = _lib.gw_head_dipole(ctx.handle, int(nspinor), nv, nc, ng, gh.ctypes.data, _ptr(cv),
                             _ptr(cc), _dtype_code(cv), cl.ctypes.data, kp.ctypes.data,
                             qc.ctypes.data, _ptr(ev), _ptr(ec), _ptr(mhead))
+    return _check(ctx, s)
+
+
+def gw_screened_w(ctx, neps, nfreq, epsinv, vcoul, w):
+    """w[f] = epsinv[f] diag(vcoul) (see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_screened_w(ctx.handle, int(neps), int(nfreq), _ptr(epsinv), _ptr(vcoul), _ptr(w))
+    return _check(ctx, s)
+
+
+def gw_sigma_sx(ctx, nocc, nband, neps, mtxel, epsinv, vcoul, prefactor, sigma):
+    """sigma[n] -= prefactor sum_occ M^H epsinv diag(v) M (static SX; see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_sigma_sx(ctx.handle, int(nocc), int(nband), int(neps), _ptr(mtxel),
+                         _dtype_code(mtxel), _ptr(epsinv), _ptr(vcoul), float(prefactor),
+                         _ptr(sigma))
     return _check(ctx, s)
 
 

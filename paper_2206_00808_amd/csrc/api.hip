@@ -520,6 +520,37 @@ gw_status gw_epsinv_lu(gw_ctx* c, int neps, int nfreq, const double* chi0, const
   return epsinv_pivoted_one(c, neps, nfreq, chi0, vcoul, epsinv);
 }
 
+gw_status gw_screened_w(gw_ctx* c, int neps, int nfreq, const double* epsinv,
+                        const double* vcoul, double* w) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (neps == 0 || nfreq == 0) return GW_OK;
+  if (!epsinv || !vcoul || !w) return fail(c, GW_EINVAL, "NULL array argument");
+  if (nfreq > 65535) return fail(c, GW_EINVAL, "nfreq above 65535");
+  if ((long long)neps * neps > (1LL << 40)) return fail(c, GW_EINVAL, "neps too large");
+  (void)hipSetDevice(c->device);
+  return screened_w(c, neps, nfreq, epsinv, vcoul, w);
+}
+
+gw_status gw_sigma_sx(gw_ctx* c, int nocc, int nband, int neps, const void* mtxel,
+                      gw_dtype dtype, const double* epsinv, const double* vcoul,
+                      double prefactor, double* sigma) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (nocc < 0 || nband < 0 || neps < 0) return fail(c, GW_EINVAL, "negative size");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (nocc == 0 || nband == 0 || neps == 0) return GW_OK;
+  if (!mtxel || !epsinv || !vcoul || !sigma) return fail(c, GW_EINVAL, "NULL array argument");
+  if (!std::isfinite(prefactor)) return fail(c, GW_EINVAL, "non-finite prefactor");
+  if ((long long)nocc * nband > 65535 || neps > 16384)
+    return fail(c, GW_EINVAL, "nocc*nband above 65535 or neps above 16384");
+  if (static_cast<const void*>(sigma) == mtxel || sigma == epsinv)
+    return fail(c, GW_EALIAS, "sigma aliases an input");
+  (void)hipSetDevice(c->device);
+  return sigma_sx_static(c, nocc, nband, neps, mtxel, dtype, epsinv, vcoul, prefactor, sigma);
+}
+
 gw_status gw_epsinv(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,
                     double* epsinv) {
   if (!c) return GW_EINVAL;

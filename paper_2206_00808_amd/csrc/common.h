@@ -211,5 +211,11 @@ gw_status epsinv_run(gw_ctx* c, int neps, int nfreq, const double* chi0, const d
                      double* epsinv);
 gw_status epsinv_pivoted_one(gw_ctx* c, int N, int nfreq, const double* chi0,
                              const double* vcoul, double* epsinv);
+// consumers of eps^-1 (lu.hip): W = eps^-1 v, and the static screened exchange
+gw_status screened_w(gw_ctx* c, int N, int nfreq, const double* epsinv, const double* vcoul,
+                     double* w);
+gw_status sigma_sx_static(gw_ctx* c, int nocc, int nband, int N, const void* mtxel, gw_dtype dt,
+                          const double* epsinv, const double* vcoul, double prefactor,
+                          double* sigma);
 
 }  // namespace gw

@@ -379,6 +379,109 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
                  ti * UT + (wave >> 1) * 32, tj * UT + (wave & 1) * 32, N, A, N, 0);
 }
 
+// ---------------------------------------------------------------- consumers of eps^-1
+// W[f][G][G'] = eps^-1[f][G][G'] v(q+G')
+__global__ void k_screened_w(const cpx<double>* __restrict__ einv, const double* __restrict__ v,
+                             int N, cpx<double>* __restrict__ w) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const size_t off = (size_t)blockIdx.y * nn + e;
+  w[off] = scal(einv[off], v[e % N]);
+}
+
+// X[p][G] = conj(M[p][G]) in double (the left factor of the SX quadratic form)
+template <typename Tin>
+__global__ void k_conj_widen(const cpx<Tin>* __restrict__ m, size_t n, cpx<double>* __restrict__ x) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const cpx<Tin> a = m[e];
+  x[e] = mk((double)a.x, -(double)a.y);
+}
+
+// sigma[n] += -pref sum_{n''} sum_G' U[(n'',n)][G'] v(G') M[(n'',n)][G'], U = conj(M) eps^-1;
+// one workgroup per band n, the occupied bands and G' summed in a fixed order
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_sx_reduce(const cpx<double>* __restrict__ U,
+                                                   const cpx<Tin>* __restrict__ m,
+                                                   const double* __restrict__ v, int nocc,
+                                                   int nband, int N, double pref,
+                                                   cpx<double>* __restrict__ sigma) {
+  __shared__ double sr[256], si[256];
+  const int n = blockIdx.x;
+  double ar = 0.0, ai = 0.0;
+  for (int o = 0; o < nocc; ++o) {
+    const size_t row = ((size_t)o * nband + n) * N;
+    for (int g = threadIdx.x; g < N; g += blockDim.x) {
+      const cpx<double> u = U[row + g];
+      const cpx<Tin> b = m[row + g];
+      const double br = v[g] * (double)b.x, bi = v[g] * (double)b.y;
+      ar += u.x * br - u.y * bi;
+      ai += u.x * bi + u.y * br;
+    }
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[n] = mk(sigma[n].x - pref * sr[0], sigma[n].y - pref * si[0]);
+}
+
+gw_status screened_w(gw_ctx* c, int N, int nfreq, const double* epsinv, const double* vcoul,
+                     double* w) {
+  const size_t nn = (size_t)N * N;
+  ProfScope ps(c, "screened_w");
+  hipLaunchKernelGGL(k_screened_w, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                     c->stream, reinterpret_cast<const cpx<double>*>(epsinv), vcoul, N,
+                     reinterpret_cast<cpx<double>*>(w));
+  GW_CHECK_LAUNCH(c, "k_screened_w");
+  return GW_OK;
+}
+
+gw_status sigma_sx_static(gw_ctx* c, int nocc, int nband, int N, const void* mtxel, gw_dtype dt,
+                          const double* epsinv, const double* vcoul, double prefactor,
+                          double* sigma) {
+  const int P = nocc * nband;
+  const size_t np = (size_t)P * N;
+  gw_status st = ws_begin(c, 2 * align_up(np * 16));
+  if (st != GW_OK) return st;
+  cpx<double>* X = static_cast<cpx<double>*>(ws_take(c, np * 16));
+  double* U = static_cast<double*>(ws_take(c, np * 16));
+  {
+    ProfScope ps(c, "sx_conj");
+    if (dt == GW_C128)
+      hipLaunchKernelGGL(k_conj_widen<double>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
+                         c->stream, static_cast<const cpx<double>*>(mtxel), np, X);
+    else
+      hipLaunchKernelGGL(k_conj_widen<float>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
+                         c->stream, static_cast<const cpx<float>*>(mtxel), np, X);
+    GW_CHECK_LAUNCH(c, "k_conj_widen");
+  }
+  // U = conj(M) eps^-1 on the matrix cores
+  st = zgemm_nn(c, P, N, N, 1.0, reinterpret_cast<const double*>(X), 0, N, 0, epsinv, 0, N, 0, U,
+                0, N, 0, 1, np, (size_t)N * N, np, 0.0);
+  if (st != GW_OK) return st;
+  ProfScope ps(c, "sx_reduce");
+  if (dt == GW_C128)
+    hipLaunchKernelGGL(k_sx_reduce<double>, dim3(nband), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(U),
+                       static_cast<const cpx<double>*>(mtxel), vcoul, nocc, nband, N, prefactor,
+                       reinterpret_cast<cpx<double>*>(sigma));
+  else
+    hipLaunchKernelGGL(k_sx_reduce<float>, dim3(nband), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(U),
+                       static_cast<const cpx<float>*>(mtxel), vcoul, nocc, nband, N, prefactor,
+                       reinterpret_cast<cpx<double>*>(sigma));
+  GW_CHECK_LAUNCH(c, "k_sx_reduce");
+  return GW_OK;
+}
+
 // eps^-1 = S epst^-1 S^-1, in place.
 __global__ void k_unscale(cpx<double>* __restrict__ A, const double* __restrict__ v, int N) {
   const size_t nn = (size_t)N * N;

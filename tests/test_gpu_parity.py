@@ -504,3 +504,80 @@ def test_c2_full_size_fp64(P, ctx):
 @pytest.mark.slow
 def test_c3_full_size_mixed(P, ctx):
     _sampled_checks(P, ctx, "C3", "c64", P.GW_PREC_SPLITBF16, 2e-6, 1e-4, 1e-6)
+
+
+# ----------------------------------------------------------------- consumers of eps^-1
+def _rand_c(rng, shape, dtype=np.complex128):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / 3).astype(dtype)
+
+
+@pytest.mark.parametrize("inplace", [False, True])
+def test_screened_w_matches_oracle(P, ctx, inplace):
+    rng = np.random.default_rng(41)
+    nfreq, neps = 3, 137
+    e = _rand_c(rng, (nfreq, neps, neps))
+    v = rng.uniform(0.01, 20.0, neps)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    de = dev(e)
+    w = de if inplace else torch.empty_like(de)
+    P.gw_screened_w(ctx, neps, nfreq, de, dev(v), w)
+    torch.cuda.synchronize()
+    # one product per element, correctly rounded on both sides
+    assert np.array_equal(w.cpu().numpy(), oracle.screened_w(e, v))
+
+
+@pytest.mark.parametrize("dtype,nocc,nband,neps", [
+    (np.complex128, 5, 13, 200), (np.complex128, 1, 1, 1), (np.complex128, 3, 70, 64),
+    (np.complex64, 4, 9, 129)])
+def test_sigma_sx_matches_oracle(P, ctx, dtype, nocc, nband, neps):
+    rng = np.random.default_rng(nocc * 1000 + neps)
+    m = _rand_c(rng, (nocc, nband, neps), dtype)
+    a = _rand_c(rng, (neps, neps))
+    e = np.eye(neps) + 0.2 * (a + a.conj().T) / np.sqrt(neps)
+    v = rng.uniform(0.01, 20.0, neps)
+    s0 = _rand_c(rng, nband)
+    pref = 0.37
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    sig = dev(s0)
+    P.gw_sigma_sx(ctx, nocc, nband, neps, dev(m), dev(e), dev(v), pref, sig)
+    torch.cuda.synchronize()
+    want = s0 + oracle.sigma_sx_static(m.astype(np.complex128), e, v, pref)
+    # widened inputs, FP64 arithmetic on both sides: only the summation order differs
+    assert oracle.rel_f(sig.cpu().numpy(), want) < 1e-12
+
+
+def test_sigma_sx_from_the_gpu_chain_matches_the_oracle_chain(P, ctx):
+    """M -> chi0 -> eps^-1 on the GPU, then the static SX with the valence bands as
+    the occupied n'' and the conduction bands as n, against the same chain in the oracle."""
+    s = _sys("C1")
+    d, out = _run(P, ctx, s)
+    m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(m, s["ev"], s["ec"], s["omega"])
+    e = oracle.epsilon_inverse(x, s["vcoul"])
+    assert s["omega"][0] == 0.0
+    want = oracle.sigma_sx_static(m, e[0], s["vcoul"], 0.5)
+    nv, nc, neps = m.shape
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    sig = torch.zeros(nc, dtype=torch.complex128, device="cuda:0")
+    P.gw_sigma_sx(ctx, nv, nc, neps, dev(out["mtxel"]), dev(out["epsinv"][0]), d["vcoul"], 0.5,
+                  sig)
+    torch.cuda.synchronize()
+    assert oracle.rel_f(sig.cpu().numpy(), want) < 1e-10
+
+
+def test_sigma_sx_rejects_bad_arguments(P, ctx):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    m = dev(np.zeros((2, 3, 4), np.complex128))
+    e = dev(np.eye(4, dtype=np.complex128))
+    v = dev(np.ones(4))
+    sig = dev(np.zeros(3, np.complex128))
+    with pytest.raises(P.GwError):
+        P.gw_sigma_sx(ctx, 2, 3, 4, m, e, v, float("nan"), sig)
+    with pytest.raises(P.GwError):
+        P.gw_sigma_sx(ctx, 2, 3, 4, m, e, v, 1.0, m)
+    with pytest.raises(P.GwError):
+        P.gw_sigma_sx(ctx, 2, 3, 4, m, e, v, 1.0, None)
+    # empty sizes are a no-op
+    P.gw_sigma_sx(ctx, 0, 3, 4, m, e, v, 1.0, sig)
+    torch.cuda.synchronize()
+    assert np.abs(sig.cpu().numpy()).max() == 0.0
