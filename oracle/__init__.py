@@ -6,3 +6,5 @@ this package.  It shares no code with the HIP library and never imports it.
 from .gw_oracle import *  # noqa: F401,F403
 
 from .closure import *  # noqa: F401,F403
+
+from .symmetry import *  # noqa: F401,F403
