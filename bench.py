@@ -341,6 +341,47 @@ def bench_w_and_sx(ctx, P, d, mtxel, epsinv, steps):
     return out
 
 
+def bench_unfold(ctx, P, sysd, d, steps):
+    """Spinor unfolding (gw_unfold_spinor) of the workload's N_c conduction bands at
+    k = 0 under the 2_1 screw {C2z | (0, 0, 1/2)} of its orthorhombic cell, the
+    sphere onto itself.  The call's time includes building the index and phase
+    tables on the host and the final synchronisation; the kernel's own time comes
+    from the library's events around it."""
+    import torch
+    cc = d["cc"]
+    g = np.asarray(sysd["gc"], dtype=np.int32)
+    rot = [[-1, 0, 0], [0, -1, 0], [0, 0, 1]]
+    tau = (0.0, 0.0, 0.5)
+    out = torch.empty_like(cc)
+    call = lambda: P.gw_unfold_spinor(ctx, d["nspinor"], g, cc, g, rot, tau, sysd["cell"], out)
+    call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.profile_reset()
+    ctx.profile(True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    tab = ctx.profile_table()
+    ctx.profile(False)
+    ctx.profile_reset()
+    n, kms = tab.get("unfold", (1, float("nan")))
+    kms /= max(n, 1)
+    nb, ns, ng = cc.shape
+    nbytes = nb * ns * 2 * ng * cc.element_size() + ng * (4 + 16)
+    return {"ms_call": ms, "ms_kernel": kms, "bands": nb, "ng": ng,
+            "algorithmic_GB_per_s": nbytes / (kms * 1e-3) / 1e9,
+            "note": "algorithmic bytes = every coefficient read and written once + the "
+                    "index and phase tables; the rate uses the kernel's own time"}
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -521,6 +562,7 @@ def main():
         result["real_axis"] = bench_real_axis(ctx, P, d64, o64["mtxel"], args.steps)
         result["head_dipole"] = bench_head_dipole(ctx, P, sysd, d64, args.steps)
         result["w_and_sx"] = bench_w_and_sx(ctx, P, d64, o64["mtxel"], epsinv64, args.steps)
+        result["unfold"] = bench_unfold(ctx, P, sysd, d64, args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:

@@ -249,11 +249,43 @@ gw_status gw_screened_w(gw_ctx* ctx, int neps, int nfreq, const double* epsinv,
  *   sigma   (device) in/out complex double[nband]; may not alias an input.
  * Uses 2*nocc*nband*neps*16 bytes of context workspace.
  * Errors: GW_EINVAL for negative sizes, unknown dtype, NULL arrays, a non-finite
- * prefactor, nocc*nband > 65535 or neps > 16384; GW_EALIAS if sigma aliases an input.
+ * prefactor, nocc*nband > 65535, neps > 16384, or sigma aliasing an input.
  */
 gw_status gw_sigma_sx(gw_ctx* ctx, int nocc, int nband, int neps, const void* mtxel,
                       gw_dtype dtype, const double* epsinv, const double* vcoul,
                       double prefactor, double* sigma);
+
+/*
+ * gw_unfold_spinor -- wavefunctions at k' = S k - G0 from those at k under a
+ * space-group operation {S|tau}: r -> S r + tau (Sec. IV, symmetries with spinor
+ * wavefunctions, axis and angle extraction):
+ *   cout[b][s][i] = sum_t U[s][t] cin[b][t][j] e^{-i G.tau},
+ *   G = gout_i - G0 (the same plane wave relative to S k), gin_j = S^-1 G,
+ * with the band-independent phase e^{-i S k.tau} dropped.  U is the SU(2) matrix
+ * exp(-i theta/2 n.sigma) of the rotation part of S (S itself, or -S when
+ * det S = -1: spin is unchanged by inversion), found from the quaternion of the
+ * Cartesian rotation by Markley's form of Shepperd's method, positive branch.
+ *   nspinor 1 or 2 (1: no spin rotation); nb bands.
+ *   gin   (host) int[ng_in][3]  integer reciprocal coordinates of the sphere at k.
+ *   cin   (device) complex[nb][nspinor][ng_in] of dtype.
+ *   gout  (host) int[ng_out][3] the sphere at k' (any order).
+ *   rot   (host) int[9] S in the lattice basis, row-major, acting on fractional
+ *         coordinates of r (on integer reciprocal coordinates S acts as rot^-T).
+ *   tau   (host) double[3] fractional translation in lattice coordinates.
+ *   g0    (host) int[3] the reciprocal vector folding S k back, or NULL for 0.
+ *   cell  (host) double[3] orthorhombic lattice constants (S_cart = A S A^-1).
+ *   cout  (device) out complex[nb][nspinor][ng_out] of dtype; may not alias cin.
+ * Arithmetic in double; c64 inputs are rounded once on output.  Synchronises the
+ * context stream before returning (the index tables are staged from the host).
+ * Errors: GW_EINVAL for nspinor not 1 or 2, negative sizes, unknown dtype, NULL
+ * arrays, nb > 524280, det rot not +-1, rot not orthogonal in this cell,
+ * duplicate or out-of-range input G, an output G whose preimage is not in gin,
+ * cout aliasing cin.
+ */
+gw_status gw_unfold_spinor(gw_ctx* ctx, int nspinor, int nb, int ng_in, const int* gin,
+                           const void* cin, gw_dtype dtype, int ng_out, const int* gout,
+                           const int* rot, const double* tau, const int* g0,
+                           const double* cell, void* cout);
 
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */

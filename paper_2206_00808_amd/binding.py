@@ -28,6 +28,7 @@ EXPORTED = [
     "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
+    "gw_unfold_spinor",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -71,6 +72,8 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_unfold_spinor": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp,
+                              _vp]),
     "gw_screened_w": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "gw_sigma_sx": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _d, _vp]),
     "gw_head_dipole": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp,
@@ -281,6 +284,24 @@ def gw_sigma_sx(ctx, nocc, nband, neps, mtxel, epsinv, vcoul, prefactor, sigma):
     s = _lib.gw_sigma_sx(ctx.handle, int(nocc), int(nband), int(neps), _ptr(mtxel),
                          _dtype_code(mtxel), _ptr(epsinv), _ptr(vcoul), float(prefactor),
                          _ptr(sigma))
+    return _check(ctx, s)
+
+
+def gw_unfold_spinor(ctx, nspinor, gin, cin, gout, rot, tau, cell, cout, g0=None):
+    """cout = U cin(S^-1 (gout - g0)) e^{-i (gout - g0).tau} (see include/gw.h)."""
+    gin = _host_i32(gin).reshape(-1, 3)
+    gout = _host_i32(gout).reshape(-1, 3)
+    rot = _host_i32(rot).reshape(9)
+    tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(3))
+    cell = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(3))
+    g0a = None if g0 is None else _host_i32(g0).reshape(3)
+    nb = cin.shape[0] if hasattr(cin, "shape") else 0
+    ctx.sync_stream()
+    s = _lib.gw_unfold_spinor(ctx.handle, int(nspinor), int(nb), gin.shape[0], gin.ctypes.data,
+                              _ptr(cin), _dtype_code(cin), gout.shape[0], gout.ctypes.data,
+                              rot.ctypes.data, tau.ctypes.data,
+                              None if g0a is None else g0a.ctypes.data, cell.ctypes.data,
+                              _ptr(cout))
     return _check(ctx, s)
 
 

@@ -546,7 +546,7 @@ gw_status gw_sigma_sx(gw_ctx* c, int nocc, int nband, int neps, const void* mtxe
   if ((long long)nocc * nband > 65535 || neps > 16384)
     return fail(c, GW_EINVAL, "nocc*nband above 65535 or neps above 16384");
   if (static_cast<const void*>(sigma) == mtxel || sigma == epsinv)
-    return fail(c, GW_EALIAS, "sigma aliases an input");
+    return fail(c, GW_EINVAL, "sigma aliases an input");
   (void)hipSetDevice(c->device);
   return sigma_sx_static(c, nocc, nband, neps, mtxel, dtype, epsinv, vcoul, prefactor, sigma);
 }
