@@ -257,7 +257,7 @@ gw_status gw_sigma_sx(gw_ctx* ctx, int nocc, int nband, int neps, const void* mt
 
 /*
  * gw_unfold_spinor -- wavefunctions at k' = S k - G0 from those at k under a
- * space-group operation {S|tau}: r -> S r + tau (Sec. IV, symmetries with spinor
+ * space-group operation {S|tau}: r -> S r + tau (Sec. III, symmetries with spinor
  * wavefunctions, axis and angle extraction):
  *   cout[b][s][i] = sum_t U[s][t] cin[b][t][j] e^{-i G.tau},
  *   G = gout_i - G0 (the same plane wave relative to S k), gin_j = S^-1 G,

@@ -1,6 +1,6 @@
 """Spinor symmetry unfolding, written out from its definitions.  TEST INFRASTRUCTURE ONLY.
 
-Sec. IV (symmetries without spin, with spinor wavefunctions, axis and angle
+Sec. III (symmetries without spin, with spinor wavefunctions, axis and angle
 extraction) of arXiv:2206.00808.  Conventions:
 
 * Orthorhombic cell a = (a1, a2, a3): direct lattice matrix A = diag(a), a
@@ -43,14 +43,14 @@ PAULI = (_SX, _SY, _SZ)
 
 def rotation_lat_to_cart(s_lat, cell):
     """S_cart = A S_lat A^-1 with A the matrix of lattice vectors as columns
-    (Sec. IV, the change from the lattice basis to the Cartesian basis)."""
+    (Sec. III, the change from the lattice basis to the Cartesian basis)."""
     a = np.diag(np.asarray(cell, dtype=np.float64))
     return a @ np.asarray(s_lat, dtype=np.float64) @ np.linalg.inv(a)
 
 
 def quaternion_from_rotation(r):
     """Unit quaternion (q1, q2, q3, q4) = (n sin(theta/2), cos(theta/2)) of a proper
-    rotation R that turns vectors by theta about n (Sec. IV, Markley's variant of
+    rotation R that turns vectors by theta about n (Sec. III, Markley's variant of
     Shepperd's method).
 
     Reading: the symmetric 4x4 matrix X is built so that X = 4 q q^T for the
@@ -76,7 +76,7 @@ def quaternion_from_rotation(r):
 
 
 def su2_from_rotation(r_cart):
-    """The 2x2 spin rotation of a point operation (Sec. IV, spinor wavefunctions).
+    """The 2x2 spin rotation of a point operation (Sec. III, spinor wavefunctions).
 
     An improper operation (det = -1) is inversion times a proper rotation; spin
     is axial, so only the rotation part -S turns it.  From the quaternion, the
@@ -108,7 +108,7 @@ def rotate_g(s_lat, g):
 
 
 def unfold_spinor(c, gin, gout, s_lat, tau_lat, cell, g0=(0, 0, 0)):
-    """Coefficients at k' = S k - G0 from those at k (Sec. IV):
+    """Coefficients at k' = S k - G0 from those at k (Sec. III):
     c'(G') = U c(S^-1 G) e^{-i G.tau} with G = G' - G0 the same plane wave's vector
     relative to S k (k' + G' = S k + G; the common phase e^{-i S k . tau} dropped,
     as in the paper).

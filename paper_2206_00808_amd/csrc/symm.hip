@@ -1,6 +1,6 @@
 // Unfolding spinor wavefunctions from one k-point to a symmetry-related one.
 //
-// Sec. IV: an operation {S|tau} (r -> S r + tau) carries the Bloch state at k to
+// Sec. III: an operation {S|tau} (r -> S r + tau) carries the Bloch state at k to
 // one at S k.  Its plane-wave coefficients move to the rotated vectors and pick
 // up the translation phase, c'(S G) = c(G) e^{-i S G . tau} (the band-independent
 // phase e^{-i S k . tau} is dropped), and the two spinor components mix by the
