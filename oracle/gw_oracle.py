@@ -35,6 +35,12 @@ head_dipole              | k.p limit of head_overlap for a spin-dependent
 screened_w               | Hermitian for the symmetric form of eps (closed form)
 sigma_sx_static          | bare exchange at eps^-1 = I (closed form), real and
                          | between the bare exchange and 0 for chi0 <= 0
+gpp_modes / epsinv_gpp   | eps^-1_GPP(0) = eps^-1 on kept modes (closed form);
+                         | f-sum rule by quadrature of the broadened pole
+sigma_gpp                | SX at E = E_n'' equals sigma_sx_static on the GPP's
+                         | static eps^-1; COH from the w' > 0 integral of the
+                         | broadened pole by quadrature; static COH limit
+                         | 1/2 m^H (eps^-1 - 1) v m for wtilde >> |E - E_n''|
 """
 from __future__ import annotations
 
@@ -44,7 +50,8 @@ __all__ = [
     "box_offsets", "wavefunction_on_box", "mtxel_fft", "mtxel_convolution",
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
-    "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "chi0_from_system", "rel_f", "alias_free",
+    "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "GPP_DROP_TOL", "gpp_modes",
+    "epsinv_gpp", "sigma_gpp", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -262,6 +269,94 @@ def sigma_sx_static(mtxel, epsinv, vcoul, prefactor=1.0):
     m = np.asarray(mtxel, dtype=np.complex128)
     w = np.asarray(epsinv, dtype=np.complex128) * np.asarray(vcoul, dtype=np.float64)[None, :]
     return -prefactor * np.einsum("ang,gh,anh->n", np.conj(m), w, m)
+
+
+# Modes whose |delta - eps^-1| is at most this are left out of the plasmon-pole
+# model (their pole weight is set to zero), as are modes with Re(wtilde^2) <= 0.
+GPP_DROP_TOL = 1e-10
+
+
+def gpp_modes(epsinv, geps, cell, qred, rho_box):
+    """Hybertsen-Louie generalized plasmon-pole parameters of the static eps^-1.
+
+    The paper evaluates Sigma with this model (Sec. II, after the COH term, and
+    the computational details), which needs only the static eps^-1 and the
+    valence density; its parameters are those of the cited Hybertsen-Louie
+    model:
+      Omega^2_GG' = omega_p^2 (q+G).(q+G') / |q+G|^2 rho(G-G') / rho(0),
+      omega_p^2 = 4 pi rho(0),
+      wtilde^2_GG' = Omega^2_GG' / (delta_GG' - eps^-1_GG'(q; 0)),
+    so that eps^-1(omega) = delta + Omega^2 / (omega^2 - wtilde^2) reproduces the
+    static eps^-1 and satisfies the f-sum rule.  wtilde is the principal square
+    root.  Modes with |delta - eps^-1| <= GPP_DROP_TOL or Re(wtilde^2) <= 0 are
+    dropped (Omega^2 = 0, wtilde = 1).
+    rho_box: rho(G) on the FFT box at g mod n.  Returns (omega2, wtilde, keep).
+    """
+    e = np.asarray(epsinv, dtype=np.complex128)
+    g = np.asarray(geps, dtype=np.int64)
+    n = e.shape[0]
+    qg = 2.0 * np.pi * (g + np.asarray(qred, dtype=np.float64)[None, :]) / np.asarray(cell)
+    rho = np.asarray(rho_box, dtype=np.complex128)
+    box = np.asarray(rho.shape)
+    rho0 = rho[0, 0, 0].real
+    wp2 = 4.0 * np.pi * rho0
+    omega2 = np.zeros((n, n), dtype=np.complex128)
+    wt2 = np.zeros((n, n), dtype=np.complex128)
+    keep = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        for j in range(n):
+            d = np.mod(g[i] - g[j], box)
+            o2 = wp2 * np.dot(qg[i], qg[j]) / np.dot(qg[i], qg[i]) * rho[d[0], d[1], d[2]] / rho0
+            den = (1.0 if i == j else 0.0) - e[i, j]
+            if abs(den) <= GPP_DROP_TOL:
+                continue
+            w2 = o2 / den
+            if w2.real <= 0.0:
+                continue
+            omega2[i, j], wt2[i, j], keep[i, j] = o2, w2, True
+    wtilde = np.where(keep, np.sqrt(wt2), 1.0 + 0j)
+    return omega2, wtilde, keep
+
+
+def epsinv_gpp(omega2, wtilde, w):
+    """The plasmon-pole eps^-1(w) = delta + Omega^2 / (w^2 - wtilde^2) at real w."""
+    n = omega2.shape[0]
+    return np.eye(n, dtype=np.complex128) + omega2 / (w * w - wtilde * wtilde)
+
+
+def sigma_gpp(mtxel, en, nocc, vcoul, omega2, wtilde, energies, prefactor=1.0):
+    """Diagonal SX and COH matrix elements with the plasmon-pole eps^-1 for one q.
+
+    SX (Sec. II, Eq. sigma_sx), n'' over the first nocc (occupied) states:
+      -prefactor sum_{n''} m^H [eps^-1_GPP(E - E_n'') v] m,   m = M_{n''n}.
+    COH (Sec. II, Eq. sigma_coh), n'' over every state: with the pole's spectral
+    weight -(1/pi) Im eps^-1(w') = Omega^2/(2 wtilde) delta(w' - wtilde) for w' > 0,
+      prefactor sum_{n''} m^H [Omega^2 / (2 wtilde (E - E_n'' - wtilde)) v] m
+    (reading: the integral runs over w' > 0 and carries v(q+G') as the SX term
+    does, as in the Hybertsen-Louie form the paper cites).
+    mtxel [nn][nband][neps] (n'' by band n by G), en [nn], energies [nband][ne].
+    Each term is built as its full G x G' matrix and contracted: no reordering.
+    Returns (sx, coh), each complex [nband][ne].
+    """
+    m = np.asarray(mtxel, dtype=np.complex128)
+    en = np.asarray(en, dtype=np.float64)
+    v = np.asarray(vcoul, dtype=np.float64)
+    E = np.asarray(energies, dtype=np.float64)
+    nn, nband, _ = m.shape
+    ne = E.shape[1]
+    sx = np.zeros((nband, ne), dtype=np.complex128)
+    coh = np.zeros((nband, ne), dtype=np.complex128)
+    for b in range(nband):
+        for k in range(ne):
+            for a in range(nn):
+                d = E[b, k] - en[a]
+                x = m[a, b]
+                c = omega2 / (2.0 * wtilde * (d - wtilde)) * v[None, :]
+                coh[b, k] += np.conj(x) @ c @ x
+                if a < nocc:
+                    f = epsinv_gpp(omega2, wtilde, d) * v[None, :]
+                    sx[b, k] -= np.conj(x) @ f @ x
+    return prefactor * sx, prefactor * coh
 
 
 def head_overlap(cv, gv, cc, gc):

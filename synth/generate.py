@@ -142,6 +142,27 @@ def vcoul(cell, q, geps):
     return 4.0 * np.pi / (omega_cell * qg2)
 
 
+def charge_density(seed, cell, box, nelec, decay=2.5):
+    """Fourier components rho(G) of a synthetic valence density on the FFT box,
+    stored at g mod n: rho(0) = nelec / Omega (electrons per bohr^3), rho(-G) =
+    conj(rho(G)) (a real density), and |rho(G)| ~ 0.4 rho(0) exp(-|G|^2 / (2 decay^2))
+    with random phases.  Stands in for the DFT density the plasmon-pole model reads."""
+    rng = np.random.default_rng(seed)
+    n = np.asarray(box, dtype=np.int64)
+    axes = [np.fft.fftfreq(int(m), 1.0 / int(m)).astype(np.int64) for m in n]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+    gc = 2.0 * np.pi * g / np.asarray(cell, dtype=np.float64)
+    rho0 = nelec / float(np.prod(cell))
+    amp = 0.4 * rho0 * np.exp(-(gc ** 2).sum(-1) / (2.0 * decay ** 2))
+    z = (rng.standard_normal(amp.shape) + 1j * rng.standard_normal(amp.shape)) / np.sqrt(2.0)
+    r = amp * z
+    # Hermitise: rho(-G) = conj(rho(G)); -g mod n is the reversed index on every axis
+    neg = r[tuple(np.ix_(*[(-np.arange(int(m))) % int(m) for m in n]))]
+    r = 0.5 * (r + np.conj(neg))
+    r[0, 0, 0] = rho0
+    return np.ascontiguousarray(r.astype(np.complex128))
+
+
 def _map_coeffs(c_src, g_src, g_dst):
     """Re-express coefficients given on g_src on the sphere g_dst (zero where absent)."""
     lut = {tuple(g): i for i, g in enumerate(g_src.tolist())}
