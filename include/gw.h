@@ -287,6 +287,51 @@ gw_status gw_unfold_spinor(gw_ctx* ctx, int nspinor, int nb, int ng_in, const in
                            const int* rot, const double* tau, const int* g0,
                            const double* cell, void* cout);
 
+/*
+ * gw_gpp_modes -- Hybertsen-Louie generalized plasmon-pole parameters of the
+ * static eps^-1 (the model Sec. II and the computational details use for Sigma):
+ *   Omega^2_GG' = wp^2 (q+G).(q+G') / |q+G|^2 rho(G-G') / rho(0),  wp^2 = 4 pi rho(0),
+ *   wt^2_GG'    = Omega^2_GG' / (delta_GG' - eps^-1_GG'(q; 0)),  wt its principal root,
+ * returned as amp = Omega^2 / wt and wtilde = wt.  A mode with |delta - eps^-1|
+ * <= 1e-10 or Re wt^2 <= 0 has no pole: amp = 0, wtilde = 1.
+ *   geps  (host) int[neps][3]; cell (host) double[3] orthorhombic lattice
+ *         constants; qred (host) double[3] q in reduced coordinates (q + G != 0).
+ *   box   (host) int[3] the grid of rho; each box[a] > 2 max |geps[.][a]|.
+ *   rho   (device) complex double[box0][box1][box2]: the valence density's
+ *         Fourier components at g mod box (rho(0) = electrons per bohr^3 > 0).
+ *   epsinv (device) complex double[neps][neps] at omega = 0.
+ *   amp, wtilde (device) out complex double[neps][neps], distinct from epsinv.
+ * Synchronises the context stream (reads rho(0); stages q + G from the host).
+ * Errors: GW_EINVAL for NULL arguments, neps > 46340, a non-positive cell or box,
+ * q + G = 0, a box too small for G - G', rho(0) <= 0, overlapping outputs.
+ */
+gw_status gw_gpp_modes(gw_ctx* ctx, int neps, const int* geps, const double* cell,
+                       const double* qred, const int* box, const double* rho,
+                       const double* epsinv, double* amp, double* wtilde);
+
+/*
+ * gw_sigma_gpp -- diagonal SX and COH self-energy matrix elements for one q with
+ * the plasmon-pole eps^-1 (Sec. II, the SX and COH terms), added to the outputs:
+ *   sigma_sx[n][e]  -= prefactor sum_{n'' < nocc} m^H [(delta + Omega^2/(d^2 - wt^2)) v] m
+ *   sigma_coh[n][e] += prefactor sum_{n'' < nn}  m^H [Omega^2 / (2 wt (d - wt)) v] m
+ * with m = M_{n''n}, d = energies[n][e] - en[n''], v = v(q+G').  The COH term is
+ * the w' > 0 integral of the pole's spectral weight, with v(q+G') as in SX.
+ *   mtxel   (device) complex[nn][nband][neps] of dtype: M_{n''n}(G), the first
+ *           nocc of the nn states n'' occupied.
+ *   en      (device) double[nn] energies of the states n'' (Hartree).
+ *   vcoul   (device) double[neps]; amp, wtilde (device) from gw_gpp_modes.
+ *   nenergy 1..4 evaluation energies per band; energies (device) double[nband][nenergy].
+ *   sigma_sx, sigma_coh (device) in/out complex double[nband][nenergy], distinct.
+ * Each band's sums run in a fixed order (no atomics).  FP64 throughout; c64
+ * matrix elements are widened.  Uses up to 256 MiB of context workspace.
+ * Errors: GW_EINVAL for negative sizes, nocc > nn, unknown dtype, nenergy outside
+ * 1..4, a non-finite prefactor, NULL arrays, neps > 46340, sigma_sx == sigma_coh.
+ */
+gw_status gw_sigma_gpp(gw_ctx* ctx, int nn, int nocc, int nband, int neps, const void* mtxel,
+                       gw_dtype dtype, const double* en, const double* vcoul, const double* amp,
+                       const double* wtilde, int nenergy, const double* energies,
+                       double prefactor, double* sigma_sx, double* sigma_coh);
+
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */
 /* ------------------------------------------------------------------------ */

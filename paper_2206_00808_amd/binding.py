@@ -28,7 +28,7 @@ EXPORTED = [
     "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
-    "gw_unfold_spinor",
+    "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -72,6 +72,9 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_gpp_modes": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gw_sigma_gpp": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _i, _vp, _d, _vp,
+                          _vp]),
     "gw_unfold_spinor": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp,
                               _vp]),
     "gw_screened_w": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
@@ -302,6 +305,32 @@ def gw_unfold_spinor(ctx, nspinor, gin, cin, gout, rot, tau, cell, cout, g0=None
                               rot.ctypes.data, tau.ctypes.data,
                               None if g0a is None else g0a.ctypes.data, cell.ctypes.data,
                               _ptr(cout))
+    return _check(ctx, s)
+
+
+def gw_gpp_modes(ctx, geps, cell, qred, rho, epsinv, amp, wtilde):
+    """Plasmon-pole amp = Omega^2/wt and wtilde from the static eps^-1 (see include/gw.h).
+    rho: device complex128 tensor [n1][n2][n3] (the box is its shape)."""
+    geps = _host_i32(geps).reshape(-1, 3)
+    cell = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(3))
+    q = np.ascontiguousarray(np.asarray(qred, dtype=np.float64).reshape(3))
+    box = _host_i32(list(rho.shape))
+    ctx.sync_stream()
+    s = _lib.gw_gpp_modes(ctx.handle, geps.shape[0], geps.ctypes.data, cell.ctypes.data,
+                          q.ctypes.data, box.ctypes.data, _ptr(rho), _ptr(epsinv), _ptr(amp),
+                          _ptr(wtilde))
+    return _check(ctx, s)
+
+
+def gw_sigma_gpp(ctx, nn, nocc, nband, neps, mtxel, en, vcoul, amp, wtilde, energies, prefactor,
+                 sigma_sx, sigma_coh):
+    """Plasmon-pole SX and COH added to sigma_sx, sigma_coh [nband][ne] (see include/gw.h)."""
+    ne = energies.shape[-1]
+    ctx.sync_stream()
+    s = _lib.gw_sigma_gpp(ctx.handle, int(nn), int(nocc), int(nband), int(neps), _ptr(mtxel),
+                          _dtype_code(mtxel), _ptr(en), _ptr(vcoul), _ptr(amp), _ptr(wtilde),
+                          int(ne), _ptr(energies), float(prefactor), _ptr(sigma_sx),
+                          _ptr(sigma_coh))
     return _check(ctx, s)
 
 
