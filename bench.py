@@ -382,6 +382,57 @@ def bench_unfold(ctx, P, sysd, d, steps):
                     "index and phase tables; the rate uses the kernel's own time"}
 
 
+def bench_gpp(ctx, P, sysd, d, epsinv0, steps, nband=8, ne=3):
+    """Plasmon-pole SX + COH (gw_gpp_modes, gw_sigma_gpp) at the workload's sizes:
+    the static eps^-1 of the timed path, n'' over all N_v + N_c states (N_v
+    occupied), Sigma for the `nband` bands at the gap (N_v/2 .. N_v + nband/2),
+    three energies per band (E_n and E_n +- 0.02 Ha); synthetic M_{n''n}(G) and a
+    synthetic valence density of N_v electrons on the 48^3 box."""
+    import torch
+    import synth
+    nv, nc, neps = d["nv"], d["nc"], d["neps"]
+    nn = nv + nc
+    rng = np.random.default_rng(77)
+    m = (rng.standard_normal((nn, nband, neps)) + 1j * rng.standard_normal((nn, nband, neps)))
+    m = torch.from_numpy(m / np.sqrt(2 * neps)).to("cuda")
+    en = torch.cat([d["ev"], d["ec"]]).contiguous()
+    lo = nv - nband // 2
+    e_n = en[lo:lo + nband].cpu().numpy()
+    energies = torch.from_numpy(e_n[:, None] + np.array([-0.02, 0.0, 0.02])[None, :ne]).to("cuda")
+    rho = torch.from_numpy(synth.charge_density(78, sysd["cell"], sysd["box"], nelec=nv)).to("cuda")
+    amp = torch.empty_like(epsinv0)
+    wt = torch.empty_like(epsinv0)
+    sx = torch.zeros((nband, ne), dtype=torch.complex128, device="cuda")
+    coh = torch.zeros_like(sx)
+    geps = np.asarray(sysd["geps"], dtype=np.int32)
+    modes = lambda: P.gw_gpp_modes(ctx, geps, sysd["cell"], sysd["q"], rho, epsinv0, amp, wt)
+    sig = lambda: P.gw_sigma_gpp(ctx, nn, nv, nband, neps, m, en, d["vcoul"], amp, wt, energies,
+                                 1.0, sx, coh)
+    modes()
+    sig()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn in (("gpp_modes", modes), ("sigma_gpp", sig)):
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms": e0.elapsed_time(e1) / steps}
+    evals = float(nn) * nband * neps * neps * ne
+    flops = evals * 21.0 + float(nv) * nband * neps * neps * ne * 23.0
+    out["sigma_gpp"].update({
+        "element_evaluations_per_s": evals / (out["sigma_gpp"]["ms"] * 1e-3),
+        "TFLOP_per_s": flops / (out["sigma_gpp"]["ms"] * 1e-3) / 1e12,
+        "states": nn, "occupied": nv, "bands": nband, "energies": ne,
+        "note": "flops = 21 per COH element and energy + 23 per SX element and energy "
+                "(each also one FP64 reciprocal), counted from the formulas"})
+    out["gpp_modes"]["kept_fraction"] = float((amp != 0).float().mean().item())
+    return out
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -563,6 +614,7 @@ def main():
         result["head_dipole"] = bench_head_dipole(ctx, P, sysd, d64, args.steps)
         result["w_and_sx"] = bench_w_and_sx(ctx, P, d64, o64["mtxel"], epsinv64, args.steps)
         result["unfold"] = bench_unfold(ctx, P, sysd, d64, args.steps)
+        result["gpp"] = bench_gpp(ctx, P, sysd, d64, epsinv64[0], args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:

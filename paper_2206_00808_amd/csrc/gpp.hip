@@ -14,11 +14,13 @@
 // Sigma_n(E) = -sum_{n'' occ} m^H [SX v] m + sum_{n''} m^H [COH v] m, m = M_{n''n}.
 // Modes with |delta - eps^-1| <= 1e-10 or Re wt^2 <= 0 carry no pole (A = 0).
 //
-// k_sigma_gpp keeps a 32 x 64 tile of (A, wt) in registers (eight rows of one
-// column per thread) and streams every n'' past it: the work per element is
-// one or two complex reciprocals and a few products, so the kernel is bound by
-// the FP64 vector ALUs, not by memory.  Each thread sums its rows, then its
-// column's v M(G'), over all n'' before a single reduction per band.
+// k_sigma_gpp keeps a 16 x 64 tile of (A, wt) in registers (four rows of one
+// column per thread) and streams every n'' past it: the work per element and
+// energy is one reciprocal (two for occupied n'') and about a dozen FP64
+// operations, so the kernel is bound by the vector ALUs, not by memory.
+// conj(M(G)) A is formed once per element and n'' and reused for every energy.
+// Each thread sums its rows, then its column's v M(G'), over all n'' before a
+// single reduction per band.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -29,7 +31,7 @@ namespace gw {
 
 namespace {
 constexpr double kGppDropTol = 1e-10;
-constexpr int kTR = 32, kTC = 64, kRows = 8, kChunk = 8;
+constexpr int kTR = 16, kTC = 64, kRows = 4, kChunk = 8;
 }  // namespace
 
 __global__ void k_gpp_modes(const double* __restrict__ qg, const int* __restrict__ g, int N,
@@ -70,14 +72,17 @@ __global__ void k_gpp_modes(const double* __restrict__ qg, const int* __restrict
   wt[e] = w;
 }
 
-// 1 / (re + i im) in double
-__device__ __forceinline__ cpx<double> crcp(double re, double im) {
-  const double inv = 1.0 / (re * re + im * im);
-  return mk(re * inv, -im * inv);
+// 1 / x for x > 0 in double: the hardware reciprocal refined by two Newton
+// steps (each squares the relative error), in place of the IEEE division
+// sequence, which would dominate the element's cost
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
 }
 
 template <typename Tin, int NE>
-__global__ void __launch_bounds__(256) k_sigma_gpp(
+__global__ void __launch_bounds__(256, 3) k_sigma_gpp(
     const cpx<Tin>* __restrict__ m, int nn, int nocc, int nband, int N, int b0,
     const double* __restrict__ en, const double* __restrict__ v,
     const cpx<double>* __restrict__ amp, const cpx<double>* __restrict__ wt,
@@ -138,25 +143,38 @@ __global__ void __launch_bounds__(256) k_sigma_gpp(
       const double ea = en[a];
       const bool occ = a < nocc;
       const cpx<double> wc = wcol[s][c];
+      cpx<double> tc[NE], ts[NE];
 #pragma unroll
-      for (int k = 0; k < NE; ++k) {
-        const double d = E[k] - ea;
-        cpx<double> tc = mk(0.0, 0.0), ts = mk(0.0, 0.0);
+      for (int k = 0; k < NE; ++k) tc[k] = ts[k] = mk(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-          const cpx<double> mr = mrow[s][rg * kRows + r];
-          const cpx<double> r1 = crcp(d - W[r].x, -W[r].y);
-          const cpx<double> f1 = cmul(A[r], r1);  // A / (d - wt)
-          tc = tc + cmulc(mr, f1);
+      for (int r = 0; r < kRows; ++r) {
+        const cpx<double> mr = mrow[s][rg * kRows + r];
+        // conj(M(G)) A is the same for every energy; A/(d - wt) = A conj(d - wt) / |d - wt|^2
+        const cpx<double> B = cmulc(mr, A[r]);
+        const double wx = W[r].x, wy = W[r].y;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+          const double d = E[k] - ea;
+          const double z1 = d - wx;
+          const double y1 = rcp_nr(fma(z1, z1, wy * wy));
+          // B (z1 + i wy) = B conj(d - wt)
+          const cpx<double> b1 = mk(fma(B.x, z1, -B.y * wy), fma(B.x, wy, B.y * z1));
+          tc[k] = mk(fma(y1, b1.x, tc[k].x), fma(y1, b1.y, tc[k].y));
           if (occ) {
-            const cpx<double> r2 = crcp(d + W[r].x, W[r].y);
-            cpx<double> fs = scal(f1 - cmul(A[r], r2), 0.5);
-            if (r == diag) fs.x += 1.0;
-            ts = ts + cmulc(mr, fs);
+            const double z2 = d + wx;
+            const double y2 = rcp_nr(fma(z2, z2, wy * wy));
+            // B conj(d + wt) = B (z2 - i wy)
+            const cpx<double> b2 = mk(fma(B.x, z2, B.y * wy), fma(B.y, z2, -B.x * wy));
+            cpx<double> f = mk(0.5 * fma(y1, b1.x, -y2 * b2.x), 0.5 * fma(y1, b1.y, -y2 * b2.y));
+            if (r == diag) f = f + mk(mr.x, -mr.y);
+            ts[k] = ts[k] + f;
           }
         }
-        acoh[k] = acoh[k] + cmul(tc, wc);
-        asx[k] = asx[k] + cmul(ts, wc);
+      }
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        acoh[k] = acoh[k] + cmul(tc[k], wc);
+        asx[k] = asx[k] + cmul(ts[k], wc);
       }
     }
   }
