@@ -22,6 +22,10 @@ quaternion_from_rotation | q q^T = X / 4 for random rotations, including
 su2_from_rotation        | unitary, det 1, U^H sigma_i U = sum_j R_ij sigma_j
                          | (the spin vector turns with R); improper ops take
                          | the rotation part; q and -q give U and -U
+chi0_symmetrize          | chi0 from the irreducible points of q's little group,
+                         | weighted by their orbits and symmetrised, equals chi0
+                         | from states diagonalised at every k of the grid; the
+                         | result is invariant under every operation
 unfold_spinor            | the unfolded state is an eigenstate of a plane-wave
                          | Hamiltonian with spin-orbit coupling at S k, for
                          | symmorphic and screw operations; chi0 summed over
@@ -33,7 +37,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["rotation_lat_to_cart", "quaternion_from_rotation", "su2_from_rotation",
-           "rotate_g", "unfold_spinor"]
+           "rotate_g", "unfold_spinor", "little_group_shift", "chi0_symmetrize"]
 
 _SX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
 _SY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
@@ -134,3 +138,41 @@ def unfold_spinor(c, gin, gout, s_lat, tau_lat, cell, g0=(0, 0, 0)):
         u = su2_from_rotation(rotation_lat_to_cart(s_lat, cell))
         out = np.einsum("st,btg->bsg", u, out)
     return out
+
+
+def little_group_shift(s_lat, qred):
+    """G_S with S q = q + G_S (integer reciprocal coordinates), or None when S is
+    not in the little group of q."""
+    sq = np.linalg.inv(np.asarray(s_lat, dtype=np.float64)).T @ np.asarray(qred, dtype=np.float64)
+    gs = sq - np.asarray(qred, dtype=np.float64)
+    r = np.rint(gs)
+    return r.astype(np.int64) if np.allclose(gs, r, atol=1e-9) else None
+
+
+def chi0_symmetrize(chi, geps, ops, qred):
+    """Average chi0(q) over the little group of q (Sec. III: sums over k are
+    unfolded with the little group of q).
+
+    With the unfolding rule above, the pair (v at S(k+q) - G_S, c at S k) has
+    M_{Sk}(G) = e^{i(q+G).tau} M_k(S^-1 (G - G_S)), since S^-1 (q+G) = q + S^-1 (G - G_S)
+    and the spinor rotation cancels in conj(psi_v) psi_c.  Hence
+      chi0_{Sk}(G, G') = e^{-i(G-G').tau} chi0_k(S^-1 (G - G_S), S^-1 (G' - G_S)),
+    and the sum over a full k grid equals (1/|G_q|) sum_S T_S(sum_i w_i chi0_{k_i})
+    over irreducible points k_i with orbit sizes w_i.  This function applies
+    (1/n) sum_S T_S to chi (complex [..., N, N] on the sphere geps).
+    """
+    x = np.asarray(chi, dtype=np.complex128)
+    g = np.asarray(geps, dtype=np.int64)
+    lut = {tuple(v): i for i, v in enumerate(g.tolist())}
+    out = np.zeros_like(x)
+    for s_lat, tau in ops:
+        gs = little_group_shift(s_lat, qred)
+        if gs is None:
+            raise ValueError("operation not in the little group of q")
+        src = (g - gs[None, :]) @ np.asarray(s_lat, dtype=np.int64)  # S^-1 = S_lat^T
+        idx = np.array([lut.get(tuple(v), -1) for v in src.tolist()])
+        if np.any(idx < 0):
+            raise ValueError("the eps sphere is not closed under the operation")
+        ph = np.exp(-2j * np.pi * (g @ np.asarray(tau, dtype=np.float64)))
+        out += ph[:, None] * np.conj(ph)[None, :] * x[..., idx[:, None], idx[None, :]]
+    return out / len(ops)

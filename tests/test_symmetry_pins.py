@@ -301,3 +301,41 @@ def test_chi0_over_the_full_grid_from_unfolded_states(model):
     finally:
         sym.su2_from_rotation = real
     assert np.abs(a + b).max() < 1e-15
+
+
+def test_chi0_from_the_irreducible_wedge_symmetrised(model):
+    """chi0(q) over the 3x3x3 grid from the irreducible points of the little group
+    of q only (states diagonalised there, weighted by orbit size) and averaged over
+    the little group equals chi0 from states diagonalised at every k.  Dropping the
+    translation phase breaks it, and the result is invariant under each operation."""
+    nv, nc = 4, 4
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    geps = g_sphere(CELL, q, 3.0)
+    omega = np.array([0.0, 0.4])
+    grid = [np.array([i / 3, j / 3, l / 3]) for i in range(3) for j in range(3) for l in range(3)]
+    little = [op for op in model.ops if oracle.little_group_shift(op[0], q) is not None]
+
+    def chi_at(k):
+        e1, c1, g1 = model.states(k, nv + nc)
+        e2, c2, g2 = model.states(k + q, nv)
+        m = oracle.mtxel_convolution(c2[:nv], g2, c1[nv:], g1, geps)
+        return oracle.chi0(m, e2[:nv], e1[nv:nv + nc], omega)
+
+    def key(k):
+        kf = np.mod(k + 1e-12, 1.0)
+        return tuple(np.round(np.where(kf > 1 - 1e-9, 0.0, kf), 9))
+
+    direct = sum(chi_at(k) for k in grid)
+    seen, irr = set(), 0
+    for k in grid:
+        if key(k) in seen:
+            continue
+        orbit = {key(_kprime(s, k)) for s, _ in little}
+        seen |= orbit
+        irr = irr + len(orbit) * chi_at(k)
+    assert len(seen) == len(grid)
+    sym = oracle.chi0_symmetrize(irr, geps, little, q)
+    assert oracle.rel_f(sym, direct) < 1e-10
+    assert oracle.rel_f(oracle.chi0_symmetrize(sym, geps, little[1:2], q), sym) < 1e-13
+    no_phase = [(s, np.zeros(3)) for s, _ in little]
+    assert oracle.rel_f(oracle.chi0_symmetrize(irr, geps, no_phase, q), direct) > 1e-3
