@@ -433,6 +433,42 @@ def bench_gpp(ctx, P, sysd, d, epsinv0, steps, nband=8, ne=3):
     return out
 
 
+def bench_symmetrize(ctx, P, sysd, chi, steps):
+    """Little-group average of chi0 (gw_chi0_symmetrize) over the workload's nine
+    frequencies at N_eps: the four operations of the orthorhombic cell that keep
+    q along x (E, C2x, the mirrors normal to y and z).  The call includes building
+    the index and phase tables on the host and the final synchronisation."""
+    import torch
+    ops = [(np.diag(d), (0.0, 0.0, 0.0)) for d in ((1, 1, 1), (1, -1, -1), (1, -1, 1), (1, 1, -1))]
+    out = torch.empty_like(chi)
+    geps = np.asarray(sysd["geps"], dtype=np.int32)
+    call = lambda: P.gw_chi0_symmetrize(ctx, geps, sysd["q"], ops, chi, out)
+    call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.profile_reset()
+    ctx.profile(True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    n, kms = ctx.profile_table().get("chi0_symmetrize", (1, float("nan")))
+    ctx.profile(False)
+    ctx.profile_reset()
+    kms /= max(n, 1)
+    nf, ne, _ = chi.shape
+    nbytes = nf * ne * ne * 16 * (len(ops) + 1)
+    return {"ms_call": ms, "ms_kernel": kms, "ops": len(ops),
+            "algorithmic_GB_per_s": nbytes / (kms * 1e-3) / 1e9,
+            "note": "algorithmic bytes = chi0 read once per operation and written once"}
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -615,6 +651,7 @@ def main():
         result["w_and_sx"] = bench_w_and_sx(ctx, P, d64, o64["mtxel"], epsinv64, args.steps)
         result["unfold"] = bench_unfold(ctx, P, sysd, d64, args.steps)
         result["gpp"] = bench_gpp(ctx, P, sysd, d64, epsinv64[0], args.steps)
+        result["symmetrize"] = bench_symmetrize(ctx, P, sysd, o64["chi0"], args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:

@@ -288,6 +288,27 @@ gw_status gw_unfold_spinor(gw_ctx* ctx, int nspinor, int nb, int ng_in, const in
                            const double* cell, void* cout);
 
 /*
+ * gw_chi0_symmetrize -- chi0(q) averaged over operations of the little group of q
+ * (Sec. III: k-sums are unfolded with the little group of q).  For {S|tau} with
+ * S q = q + G_S, the pair at S k has M_{Sk}(G) = e^{i(q+G).tau} M_k(S^-1 (G - G_S)), so
+ *   chi_out[f][G][G'] = (1/nops) sum_S e^{-i(G-G').tau} chi_in[f][S^-1(G-G_S)][S^-1(G'-G_S)].
+ * chi0 summed over the irreducible points of the little group, each weighted by
+ * its orbit size, then passed through this call equals the full-grid sum.
+ *   geps (host) int[neps][3] the eps sphere at q (closed under every operation).
+ *   qred (host) double[3]; nops 1..96; rots (host) int[nops][9] S in the lattice
+ *   basis, row-major, as for gw_unfold_spinor; taus (host) double[nops][3].
+ *   chi_in (device) complex double[nfreq][neps][neps]; chi_out (device) out, same
+ *   shape, not chi_in.
+ * Synchronises the context stream (its tables are staged from the host).
+ * Errors: GW_EINVAL for negative sizes, nops outside 1..96, NULL arguments,
+ * aliasing, det S not +-1, an operation outside the little group of q, a sphere
+ * not closed under an operation, duplicate G.
+ */
+gw_status gw_chi0_symmetrize(gw_ctx* ctx, int neps, int nfreq, const int* geps,
+                             const double* qred, int nops, const int* rots, const double* taus,
+                             const double* chi_in, double* chi_out);
+
+/*
  * gw_gpp_modes -- Hybertsen-Louie generalized plasmon-pole parameters of the
  * static eps^-1 (the model Sec. II and the computational details use for Sigma):
  *   Omega^2_GG' = wp^2 (q+G).(q+G') / |q+G|^2 rho(G-G') / rho(0),  wp^2 = 4 pi rho(0),

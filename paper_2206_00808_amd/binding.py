@@ -28,7 +28,7 @@ EXPORTED = [
     "gw_ctx_profile_entry",
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
-    "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp",
+    "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -72,6 +72,7 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_chi0_symmetrize": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "gw_gpp_modes": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gw_sigma_gpp": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _i, _vp, _d, _vp,
                           _vp]),
@@ -331,6 +332,21 @@ def gw_sigma_gpp(ctx, nn, nocc, nband, neps, mtxel, en, vcoul, amp, wtilde, ener
                           _dtype_code(mtxel), _ptr(en), _ptr(vcoul), _ptr(amp), _ptr(wtilde),
                           int(ne), _ptr(energies), float(prefactor), _ptr(sigma_sx),
                           _ptr(sigma_coh))
+    return _check(ctx, s)
+
+
+def gw_chi0_symmetrize(ctx, geps, qred, ops, chi_in, chi_out):
+    """chi_out = little-group average of chi_in (see include/gw.h); ops = [(rot, tau), ...]."""
+    geps = _host_i32(geps).reshape(-1, 3)
+    q = np.ascontiguousarray(np.asarray(qred, dtype=np.float64).reshape(3))
+    rots = _host_i32([np.asarray(r).reshape(9) for r, _ in ops]).reshape(-1)
+    taus = np.ascontiguousarray(np.asarray([np.asarray(t, dtype=np.float64).reshape(3)
+                                            for _, t in ops]).reshape(-1))
+    nfreq = chi_in.shape[0] if chi_in.dim() == 3 else 1
+    ctx.sync_stream()
+    s = _lib.gw_chi0_symmetrize(ctx.handle, geps.shape[0], nfreq, geps.ctypes.data, q.ctypes.data,
+                                len(ops), rots.ctypes.data, taus.ctypes.data, _ptr(chi_in),
+                                _ptr(chi_out))
     return _check(ctx, s)
 
 

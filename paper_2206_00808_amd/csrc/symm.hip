@@ -85,6 +85,24 @@ __global__ void __launch_bounds__(256) k_unfold(const cpx<T>* __restrict__ cin, 
   }
 }
 
+// out[f][i][j] = (1/nops) sum_S p_S(i) conj(p_S(j)) in[f][idx_S(i)][idx_S(j)]
+__global__ void k_chi0_symmetrize(const cpx<double>* __restrict__ in, int N, int nops,
+                                  const int* __restrict__ idx, const cpx<double>* __restrict__ ph,
+                                  cpx<double>* __restrict__ out) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  const cpx<double>* x = in + (size_t)blockIdx.y * nn;
+  cpx<double> acc = mk(0.0, 0.0);
+  for (int s = 0; s < nops; ++s) {
+    const int a = idx[(size_t)s * N + i], b = idx[(size_t)s * N + j];
+    const cpx<double> pij = cmulc(ph[(size_t)s * N + j], ph[(size_t)s * N + i]);  // p_i conj(p_j)
+    acc = acc + cmul(pij, x[(size_t)a * N + b]);
+  }
+  out[(size_t)blockIdx.y * nn + e] = scal(acc, 1.0 / nops);
+}
+
 template <typename T, int NS>
 static void launch_unfold(gw_ctx* c, const void* cin, int ng_in, const int* src,
                           const cpx<double>* ph, int ng_out, int nb, const cpx<double> u[4],
@@ -202,6 +220,106 @@ extern "C" gw_status gw_unfold_spinor(gw_ctx* c, int nspinor, int nb, int ng_in,
     GW_CHECK_LAUNCH(c, "k_unfold");
   }
   // the index and phase tables live in host vectors: finish before returning
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  return GW_OK;
+}
+
+extern "C" gw_status gw_chi0_symmetrize(gw_ctx* c, int neps, int nfreq, const int* geps,
+                                        const double* qred, int nops, const int* rots,
+                                        const double* taus, const double* chi_in,
+                                        double* chi_out) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 0 || nfreq < 0 || nops < 0) return fail(c, GW_EINVAL, "negative size");
+  if (neps == 0 || nfreq == 0) return GW_OK;
+  if (nops == 0 || nops > 96) return fail(c, GW_EINVAL, "nops must be 1 to 96");
+  if (!geps || !qred || !rots || !taus || !chi_in || !chi_out)
+    return fail(c, GW_EINVAL, "NULL argument");
+  if (chi_in == chi_out) return fail(c, GW_EINVAL, "chi_out aliases chi_in");
+  if (nfreq > 65535 || neps > 46340) return fail(c, GW_EINVAL, "nfreq or neps too large");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(qred[a])) return fail(c, GW_EINVAL, "q must be finite");
+  std::unordered_map<long long, int> lut;
+  lut.reserve((size_t)neps * 2);
+  auto key = [](long long x, long long y, long long z) {
+    return ((x + (1LL << 20)) << 42) | ((y + (1LL << 20)) << 21) | (z + (1LL << 20));
+  };
+  for (int i = 0; i < neps; ++i) {
+    const int* g = geps + 3 * i;
+    for (int a = 0; a < 3; ++a)
+      if (g[a] < -(1 << 19) || g[a] > (1 << 19)) return fail(c, GW_EINVAL, "G out of range");
+    if (!lut.emplace(key(g[0], g[1], g[2]), i).second)
+      return fail(c, GW_EINVAL, "duplicate eps G");
+  }
+  std::vector<int> idx((size_t)nops * neps);
+  std::vector<cpx<double>> ph((size_t)nops * neps);
+  for (int s = 0; s < nops; ++s) {
+    long long m[9];
+    for (int i = 0; i < 9; ++i) m[i] = rots[9 * s + i];
+    const long long det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                          m[2] * (m[3] * m[7] - m[4] * m[6]);
+    if (det != 1 && det != -1) return fail(c, GW_EINVAL, "operation %d: det %lld", s, det);
+    const double* tau = taus + 3 * s;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(tau[a])) return fail(c, GW_EINVAL, "operation %d: tau not finite", s);
+    // S acts on reciprocal integer coordinates as S_lat^-T = adj(S_lat)^T / det;
+    // G_S = S q - q must be a reciprocal lattice vector
+    long long adj[9];
+    adj[0] = m[4] * m[8] - m[5] * m[7];
+    adj[1] = m[2] * m[7] - m[1] * m[8];
+    adj[2] = m[1] * m[5] - m[2] * m[4];
+    adj[3] = m[5] * m[6] - m[3] * m[8];
+    adj[4] = m[0] * m[8] - m[2] * m[6];
+    adj[5] = m[2] * m[3] - m[0] * m[5];
+    adj[6] = m[3] * m[7] - m[4] * m[6];
+    adj[7] = m[1] * m[6] - m[0] * m[7];
+    adj[8] = m[0] * m[4] - m[1] * m[3];
+    long long gsh[3];
+    for (int a = 0; a < 3; ++a) {
+      // (S_lat^-1)^T q: row a of S_lat^-T is column a of S_lat^-1 = adj / det
+      const double sq = (double)(adj[a] * qred[0] + adj[3 + a] * qred[1] + adj[6 + a] * qred[2]) /
+                        (double)det;
+      const double d = sq - qred[a];
+      gsh[a] = (long long)std::llround(d);
+      if (std::fabs(d - (double)gsh[a]) > 1e-9)
+        return fail(c, GW_EINVAL, "operation %d is not in the little group of q", s);
+    }
+    for (int i = 0; i < neps; ++i) {
+      const long long gq[3] = {geps[3 * i] - gsh[0], geps[3 * i + 1] - gsh[1],
+                               geps[3 * i + 2] - gsh[2]};
+      // S^-1 (G - G_S) = S_lat^T (G - G_S)
+      long long src[3];
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        src[a] = gq[0] * m[a] + gq[1] * m[3 + a] + gq[2] * m[6 + a];
+        ok &= src[a] >= -(1 << 19) && src[a] <= (1 << 19);
+      }
+      auto it = ok ? lut.find(key(src[0], src[1], src[2])) : lut.end();
+      if (it == lut.end())
+        return fail(c, GW_EINVAL, "operation %d maps eps G %d outside the sphere", s, i);
+      idx[(size_t)s * neps + i] = it->second;
+      double t = geps[3 * i] * tau[0] + geps[3 * i + 1] * tau[1] + geps[3 * i + 2] * tau[2];
+      t -= std::nearbyint(t);
+      ph[(size_t)s * neps + i] = mk(std::cos(2.0 * M_PI * t), -std::sin(2.0 * M_PI * t));
+    }
+  }
+  (void)hipSetDevice(c->device);
+  const size_t n_t = (size_t)nops * neps;
+  gw_status st = ws_begin(c, align_up(n_t * sizeof(int)) + align_up(n_t * 16));
+  if (st != GW_OK) return st;
+  int* d_idx = static_cast<int*>(ws_take(c, n_t * sizeof(int)));
+  cpx<double>* d_ph = static_cast<cpx<double>*>(ws_take(c, n_t * 16));
+  GW_HIP(c, hipMemcpyAsync(d_idx, idx.data(), n_t * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  GW_HIP(c, hipMemcpyAsync(d_ph, ph.data(), n_t * 16, hipMemcpyHostToDevice, c->stream));
+  const size_t nn = (size_t)neps * neps;
+  {
+    ProfScope ps(c, "chi0_symmetrize");
+    hipLaunchKernelGGL(k_chi0_symmetrize, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, reinterpret_cast<const cpx<double>*>(chi_in), neps, nops, d_idx,
+                       d_ph, reinterpret_cast<cpx<double>*>(chi_out));
+    GW_CHECK_LAUNCH(c, "k_chi0_symmetrize");
+  }
+  // the tables were staged from host vectors: finish before returning
   GW_HIP(c, hipStreamSynchronize(c->stream));
   return GW_OK;
 }

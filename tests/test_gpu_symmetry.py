@@ -1,6 +1,7 @@
-"""GPU parity of the spinor unfolding (gw_unfold_spinor) against the oracle, and
-chi0 over a full k grid from unfolded states on the GPU against the oracle's sum
-over states diagonalised at every k."""
+"""GPU parity of the spinor unfolding (gw_unfold_spinor) and of the little-group
+average of chi0 (gw_chi0_symmetrize) against the oracle, and chi0 over a full k
+grid on the GPU, from unfolded states or from the irreducible points alone,
+against the oracle's sum over states diagonalised at every k."""
 import numpy as np
 import pytest
 
@@ -133,3 +134,80 @@ def test_chi0_over_the_full_grid_from_gpu_unfolded_states(P, ctx, model):
     torch.cuda.synchronize()
     assert len(covered) == len(grid)
     assert oracle.rel_f(chi.cpu().numpy(), direct) < 1e-10
+
+
+def _little(model, q):
+    return [op for op in model.ops if oracle.little_group_shift(op[0], q) is not None]
+
+
+def test_chi0_symmetrize_matches_oracle(P, ctx, model):
+    rng = np.random.default_rng(4)
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    geps = g_sphere(CELL, q, 8.0)
+    n = len(geps)
+    x = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
+    little = _little(model, q)
+    out = torch.empty((3, n, n), dtype=torch.complex128, device="cuda:0")
+    P.gw_chi0_symmetrize(ctx, geps, q, little, _dev(x), out)
+    torch.cuda.synchronize()
+    want = oracle.chi0_symmetrize(x, geps, little, q)
+    assert np.abs(out.cpu().numpy() - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_chi0_symmetrize_rejects_bad_arguments(P, ctx, model):
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    geps = g_sphere(CELL, q, 3.0)
+    n = len(geps)
+    x = _dev(np.zeros((1, n, n), np.complex128))
+    y = torch.empty_like(x)
+    outside = [op for op in model.ops if oracle.little_group_shift(op[0], q) is None]
+    with pytest.raises(P.GwError):
+        P.gw_chi0_symmetrize(ctx, geps, q, outside[:1], x, y)
+    with pytest.raises(P.GwError):
+        P.gw_chi0_symmetrize(ctx, geps, q, _little(model, q), x, x)
+    with pytest.raises(P.GwError):  # a sphere that is not closed under C4
+        P.gw_chi0_symmetrize(ctx, geps[:-3], q, _little(model, q), _dev(np.zeros((1, n - 3, n - 3),
+                             np.complex128)), torch.empty((1, n - 3, n - 3), dtype=torch.complex128,
+                                                          device="cuda:0"))
+
+
+def test_chi0_from_irreducible_points_on_the_gpu(P, ctx, model):
+    """Only the irreducible points of q's little group: states diagonalised there
+    (CPU inputs), matrix elements and chi0 on the GPU weighted by orbit size, then
+    gw_chi0_symmetrize; against the oracle's chi0 over states at every k of the grid."""
+    nv, nc = 4, 4
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    geps = g_sphere(CELL, q, 3.0)
+    omega = [0.0, 0.4]
+    grid = [np.array([i / 3, j / 3, l / 3]) for i in range(3) for j in range(3) for l in range(3)]
+    little = _little(model, q)
+    direct = 0
+    for k in grid:
+        e1, c1, g1 = model.states(k, nv + nc)
+        e2, c2, g2 = model.states(k + q, nv)
+        m = oracle.mtxel_convolution(c2[:nv], g2, c1[nv:], g1, geps)
+        direct = direct + oracle.chi0(m, e2[:nv], e1[nv:nv + nc], np.asarray(omega))
+
+    def key(k):
+        kf = np.mod(k + 1e-12, 1.0)
+        return tuple(np.round(np.where(kf > 1 - 1e-9, 0.0, kf), 9))
+
+    chi = torch.zeros((2, len(geps), len(geps)), dtype=torch.complex128, device="cuda:0")
+    seen, nirr = set(), 0
+    for k in grid:
+        if key(k) in seen:
+            continue
+        orbit = {key(_kprime(s, k)) for s, _ in little}
+        seen |= orbit
+        nirr += 1
+        ec_, cc_, gc_ = model.states(k, nv + nc)
+        ev_, cv_, gv_ = model.states(k + q, nv)
+        m = torch.empty((nv, nc, len(geps)), dtype=torch.complex128, device="cuda:0")
+        P.gw_mtxel_spinor(ctx, (16, 16, 16), 2, gv_, _dev(cv_), gc_, _dev(cc_[nv:]), geps, m)
+        P.gw_chi0_accumulate(ctx, nv, nc, len(geps), m, _dev(ev_[:nv]), _dev(ec_[nv:nv + nc]),
+                             omega, float(len(orbit)), P.GW_PREC_FP64, chi)
+    out = torch.empty_like(chi)
+    P.gw_chi0_symmetrize(ctx, geps, q, little, chi, out)
+    torch.cuda.synchronize()
+    assert len(seen) == len(grid) and nirr < len(grid)
+    assert oracle.rel_f(out.cpu().numpy(), direct) < 1e-10
