@@ -300,21 +300,16 @@ def gpp_modes(epsinv, geps, cell, qred, rho_box):
     box = np.asarray(rho.shape)
     rho0 = rho[0, 0, 0].real
     wp2 = 4.0 * np.pi * rho0
-    omega2 = np.zeros((n, n), dtype=np.complex128)
-    wt2 = np.zeros((n, n), dtype=np.complex128)
-    keep = np.zeros((n, n), dtype=bool)
-    for i in range(n):
-        for j in range(n):
-            d = np.mod(g[i] - g[j], box)
-            o2 = wp2 * np.dot(qg[i], qg[j]) / np.dot(qg[i], qg[i]) * rho[d[0], d[1], d[2]] / rho0
-            den = (1.0 if i == j else 0.0) - e[i, j]
-            if abs(den) <= GPP_DROP_TOL:
-                continue
-            w2 = o2 / den
-            if w2.real <= 0.0:
-                continue
-            omega2[i, j], wt2[i, j], keep[i, j] = o2, w2, True
-    wtilde = np.where(keep, np.sqrt(wt2), 1.0 + 0j)
+    # every (G, G') at once: rho at (G - G') mod box, the dot products, the division
+    d = np.mod(g[:, None, :] - g[None, :, :], box)
+    rho_d = rho[d[..., 0], d[..., 1], d[..., 2]]
+    o2 = wp2 * (qg @ qg.T) / (qg * qg).sum(1)[:, None] * rho_d / rho0
+    den = np.eye(n) - e
+    big = np.abs(den) > GPP_DROP_TOL
+    wt2 = np.where(big, o2 / np.where(big, den, 1.0), 0.0)
+    keep = big & (wt2.real > 0.0)
+    omega2 = np.where(keep, o2, 0.0)
+    wtilde = np.where(keep, np.sqrt(np.where(keep, wt2, 1.0)), 1.0 + 0j)
     return omega2, wtilde, keep
 
 
