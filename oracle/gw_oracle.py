@@ -37,6 +37,11 @@ sigma_sx_static          | bare exchange at eps^-1 = I (closed form), real and
                          | between the bare exchange and 0 for chi0 <= 0
 gpp_modes / epsinv_gpp   | eps^-1_GPP(0) = eps^-1 on kept modes (closed form);
                          | f-sum rule by quadrature of the broadened pole
+bse_kernel               | real-space double sums over the grid with the
+                         | Coulomb and W kernels built from their Fourier
+                         | series; collinear spinors give the spinless kernels
+                         | in the same-spin blocks and 0 across spin flips;
+                         | K^X Hermitian PSD, D + K^X + K^D Hermitian
 sigma_gpp                | SX at E = E_n'' equals sigma_sx_static on the GPP's
                          | static eps^-1; COH from the w' > 0 integral of the
                          | broadened pole by quadrature; static COH limit
@@ -51,7 +56,7 @@ __all__ = [
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
     "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "GPP_DROP_TOL", "gpp_modes",
-    "epsinv_gpp", "sigma_gpp", "chi0_from_system", "rel_f", "alias_free",
+    "epsinv_gpp", "sigma_gpp", "bse_kernel", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -352,6 +357,28 @@ def sigma_gpp(mtxel, en, nocc, vcoul, omega2, wtilde, energies, prefactor=1.0):
                     f = epsinv_gpp(omega2, wtilde, d) * v[None, :]
                     sx[b, k] -= np.conj(x) @ f @ x
     return prefactor * sx, prefactor * coh
+
+
+def bse_kernel(mvc, mcc, mvv, vx, w):
+    """Exchange and direct kernels of the Bethe-Salpeter equation in the
+    Tamm-Dancoff form for one k-point (Sec. II, the K^X and K^D integrals, whose
+    spin dependence is the spin trace inside M_nn'):
+      K^X_{vc,v'c'} =  sum_G     conj(M_vc(G)) v_x(G) M_v'c'(G),
+      K^D_{vc,v'c'} = -sum_{G,G'} conj(M_cc'(G)) W_GG' M_vv'(G').
+    Reading: the factors -i and i of the printed integrals are those of the
+    Green's-function form; in the eigenvalue problem the exchange enters
+    repulsive and the screened direct term attractive, as here.  v_x is the bare
+    Coulomb potential with its long-range G = 0 term set to 0 by the caller.
+    mvc [nv][nc][N], mcc [nc][nc][N], mvv [nv][nv][N], W [N][N].
+    Returns (kx, kd), each [nv*nc][nv*nc] with pair index v*nc + c.
+    """
+    mvc = np.asarray(mvc, dtype=np.complex128)
+    nv, nc, n = mvc.shape
+    flat = mvc.reshape(nv * nc, n)
+    kx = (np.conj(flat) * np.asarray(vx, dtype=np.float64)[None, :]) @ flat.T
+    kd = -np.einsum("cdg,gh,vuh->vcud", np.conj(np.asarray(mcc, dtype=np.complex128)),
+                    np.asarray(w, dtype=np.complex128), np.asarray(mvv, dtype=np.complex128))
+    return kx, kd.reshape(nv * nc, nv * nc)
 
 
 def head_overlap(cv, gv, cc, gc):
