@@ -353,6 +353,30 @@ gw_status gw_sigma_gpp(gw_ctx* ctx, int nn, int nocc, int nband, int neps, const
                        const double* wtilde, int nenergy, const double* energies,
                        double prefactor, double* sigma_sx, double* sigma_coh);
 
+/*
+ * gw_bse_kernel -- exchange and direct kernels of the Bethe-Salpeter equation in
+ * the Tamm-Dancoff form for one k-point (Sec. II, K^X and K^D, whose spin
+ * dependence is the spin trace inside M_nn'):
+ *   kx[(v,c)][(v',c')] =  sum_G     conj(M_vc(G)) vx(G) M_v'c'(G)
+ *   kd[(v,c)][(v',c')] = -sum_{G,G'} conj(M_cc'(G)) W_GG' M_vv'(G')
+ * with pair index v*nc + c.  Exchange is repulsive and the screened direct term
+ * attractive; the -i and i of the Green's-function form are absorbed.
+ *   mvc (device) complex[nv][nc][neps], mcc [nc][nc][neps], mvv [nv][nv][neps]
+ *       of dtype, as gw_mtxel_spinor writes them (left set, right set, G).
+ *   vx  (device) double[neps] the bare Coulomb potential, its long-range G = 0
+ *       entry set to 0 by the caller.
+ *   w   (device) complex double[neps][neps] the screened interaction W = eps^-1 v.
+ *   kx, kd (device) out complex double[nv*nc][nv*nc], overwritten; distinct, and
+ *       neither may alias an input.
+ * FP64 matrix-core GEMMs; c64 inputs are widened.  Uses about
+ * 16 (2 nv nc N + 2 nc^2 N + nv^2 N + nc^2 nv^2) bytes of context workspace.
+ * Errors: GW_EINVAL for negative sizes, unknown dtype, NULL arrays, aliasing,
+ * nv*nc or neps above 46340; GW_ENOMEM if the workspace cannot be allocated.
+ */
+gw_status gw_bse_kernel(gw_ctx* ctx, int nv, int nc, int neps, const void* mvc, const void* mcc,
+                        const void* mvv, gw_dtype dtype, const double* vx, const double* w,
+                        double* kx, double* kd);
+
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */
 /* ------------------------------------------------------------------------ */

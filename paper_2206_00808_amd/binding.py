@@ -29,6 +29,7 @@ EXPORTED = [
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
+    "gw_bse_kernel",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -72,6 +73,7 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_bse_kernel": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "gw_chi0_symmetrize": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "gw_gpp_modes": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gw_sigma_gpp": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _i, _vp, _d, _vp,
@@ -347,6 +349,20 @@ def gw_chi0_symmetrize(ctx, geps, qred, ops, chi_in, chi_out):
     s = _lib.gw_chi0_symmetrize(ctx.handle, geps.shape[0], nfreq, geps.ctypes.data, q.ctypes.data,
                                 len(ops), rots.ctypes.data, taus.ctypes.data, _ptr(chi_in),
                                 _ptr(chi_out))
+    return _check(ctx, s)
+
+
+def gw_bse_kernel(ctx, mvc, mcc, mvv, vx, w, kx, kd):
+    """BSE exchange and direct kernels for one k-point (see include/gw.h)."""
+    nv, nc, neps = mvc.shape
+    dt = _dtype_code(mvc)
+    if _dtype_code(mcc) != dt or _dtype_code(mvv) != dt:
+        raise TypeError("mvc, mcc and mvv must share one complex dtype")
+    if tuple(mcc.shape) != (nc, nc, neps) or tuple(mvv.shape) != (nv, nv, neps):
+        raise ValueError("mcc must be [nc][nc][neps] and mvv [nv][nv][neps]")
+    ctx.sync_stream()
+    s = _lib.gw_bse_kernel(ctx.handle, nv, nc, neps, _ptr(mvc), _ptr(mcc), _ptr(mvv), dt, _ptr(vx),
+                           _ptr(w), _ptr(kx), _ptr(kd))
     return _check(ctx, s)
 
 

@@ -1,0 +1,106 @@
+"""GPU parity of the BSE exchange and direct kernels (gw_bse_kernel) against the
+oracle, on random matrix elements and on matrix elements from the GPU path."""
+import numpy as np
+import pytest
+
+import oracle
+from synth.generate import _random_spinors, g_sphere
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2206_00808_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rc(rng, shape, dtype=np.complex128):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / 3).astype(dtype)
+
+
+def _run(P, ctx, mvc, mcc, mvv, vx, w):
+    nv, nc, _ = mvc.shape
+    kx = torch.empty((nv * nc, nv * nc), dtype=torch.complex128, device="cuda:0")
+    kd = torch.empty_like(kx)
+    P.gw_bse_kernel(ctx, _dev(mvc), _dev(mcc), _dev(mvv), _dev(vx), _dev(w), kx, kd)
+    torch.cuda.synchronize()
+    return kx.cpu().numpy(), kd.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype,nv,nc,n", [(np.complex128, 3, 5, 70), (np.complex128, 4, 7, 130),
+                                           (np.complex128, 1, 1, 1), (np.complex64, 5, 9, 97)])
+def test_bse_kernel_matches_oracle(P, ctx, dtype, nv, nc, n):
+    rng = np.random.default_rng(nv * 100 + n)
+    mvc, mcc, mvv = _rc(rng, (nv, nc, n), dtype), _rc(rng, (nc, nc, n), dtype), _rc(rng, (nv, nv, n), dtype)
+    vx = rng.uniform(0.0, 4.0, n)
+    w = _rc(rng, (n, n))
+    kx, kd = _run(P, ctx, mvc, mcc, mvv, vx, w)
+    wx, wd = oracle.bse_kernel(mvc.astype(np.complex128), mcc.astype(np.complex128),
+                               mvv.astype(np.complex128), vx, w)
+    assert np.abs(kx - wx).max() < 1e-13 * np.abs(wx).max()
+    assert np.abs(kd - wd).max() < 1e-13 * np.abs(wd).max()
+
+
+def test_bse_kernel_from_gpu_matrix_elements(P, ctx):
+    """M_vc, M_cc' and M_vv' at q = 0 from gw_mtxel_spinor, then the kernels; against
+    the oracle's matrix elements and kernels.  v_x drops G = 0; W is Hermitian and
+    real in real space, so D + K^X + K^D is Hermitian."""
+    rng = np.random.default_rng(9)
+    cell = (7.5, 7.75, 9.5)
+    g = g_sphere(cell, (0, 0, 0), 8.0)
+    geps = g_sphere(cell, (0, 0, 0), 3.0)
+    nv, nc, n = 4, 6, len(geps)
+    c = _random_spinors(rng, len(g), nv + nc, 2)
+    cv, cc = c[:nv], c[nv:]
+    box = (16, 16, 16)
+    assert oracle.alias_free(g, g, geps, box)
+
+    def gpu_m(a, b):
+        m = torch.empty((len(a), len(b), n), dtype=torch.complex128, device="cuda:0")
+        P.gw_mtxel_spinor(ctx, box, 2, g, _dev(a), g, _dev(b), geps, m)
+        return m
+
+    qg2 = ((2 * np.pi * geps / np.asarray(cell)) ** 2).sum(1)
+    vx = np.where(qg2 > 0, 4 * np.pi / (np.prod(cell) * np.where(qg2 > 0, qg2, 1.0)), 0.0)
+    lut = {tuple(v): i for i, v in enumerate(geps.tolist())}
+    minus = np.array([lut[tuple(-x for x in v)] for v in geps.tolist()])
+    a = _rc(rng, (n, n))
+    w = a @ a.conj().T / n
+    w = 0.5 * (w + np.conj(w[np.ix_(minus, minus)]))
+    kx = torch.empty((nv * nc, nv * nc), dtype=torch.complex128, device="cuda:0")
+    kd = torch.empty_like(kx)
+    P.gw_bse_kernel(ctx, gpu_m(cv, cc), gpu_m(cc, cc), gpu_m(cv, cv), _dev(vx), _dev(w), kx, kd)
+    torch.cuda.synchronize()
+    wx, wd = oracle.bse_kernel(oracle.mtxel_convolution(cv, g, cc, g, geps),
+                               oracle.mtxel_convolution(cc, g, cc, g, geps),
+                               oracle.mtxel_convolution(cv, g, cv, g, geps), vx, w)
+    kx, kd = kx.cpu().numpy(), kd.cpu().numpy()
+    assert np.abs(kx - wx).max() < 1e-12 * np.abs(wx).max()
+    assert np.abs(kd - wd).max() < 1e-12 * np.abs(wd).max()
+    h = np.diag(rng.uniform(0.1, 0.5, nv * nc)) + kx + kd
+    assert np.abs(h - h.conj().T).max() < 1e-12 * np.abs(h).max()
+
+
+def test_bse_kernel_rejects_bad_arguments(P, ctx):
+    rng = np.random.default_rng(2)
+    mvc, mcc, mvv = _dev(_rc(rng, (2, 3, 5))), _dev(_rc(rng, (3, 3, 5))), _dev(_rc(rng, (2, 2, 5)))
+    vx, w = _dev(np.ones(5)), _dev(_rc(rng, (5, 5)))
+    kx = torch.empty((6, 6), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(P.GwError):
+        P.gw_bse_kernel(ctx, mvc, mcc, mvv, vx, w, kx, kx)
+    with pytest.raises(P.GwError):
+        P.gw_bse_kernel(ctx, mvc, mcc, mvv, vx, w, kx, w)
+    with pytest.raises(ValueError):
+        P.gw_bse_kernel(ctx, mvc, mvv, mcc, vx, w, kx, torch.empty_like(kx))
