@@ -469,6 +469,38 @@ def bench_symmetrize(ctx, P, sysd, chi, steps):
             "note": "algorithmic bytes = chi0 read once per operation and written once"}
 
 
+def bench_bse(ctx, P, d, epsinv0, steps, nc=64):
+    """BSE exchange and direct kernels (gw_bse_kernel) for the workload's N_v valence
+    bands and its lowest `nc` conduction bands on the N_eps sphere: synthetic
+    matrix elements, W = eps^-1 v from the timed path's static eps^-1."""
+    import torch
+    nv, neps = d["nv"], d["neps"]
+    g = torch.Generator(device="cuda").manual_seed(91)
+    rnd = lambda *s: torch.randn(*s, dtype=torch.complex128, device="cuda", generator=g) / neps
+    mvc, mcc, mvv = rnd(nv, nc, neps), rnd(nc, nc, neps), rnd(nv, nv, neps)
+    w = torch.empty_like(epsinv0)
+    P.gw_screened_w(ctx, neps, 1, epsinv0, d["vcoul"], w)
+    vx = d["vcoul"].clone()
+    p = nv * nc
+    kx = torch.empty((p, p), dtype=torch.complex128, device="cuda")
+    kd = torch.empty_like(kx)
+    call = lambda: P.gw_bse_kernel(ctx, mvc, mcc, mvv, vx, w, kx, kd)
+    call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops = 8.0 * (p * p * neps + nc * nc * neps * neps + nc * nc * nv * nv * neps)
+    return {"ms": ms, "nv": nv, "nc": nc, "neps": neps, "TFLOP_per_s": flops / (ms * 1e-3) / 1e12,
+            "note": "flops = the three complex GEMMs (K^X, conj(M_cc) W, and its product with "
+                    "M_vv^T); the time includes widening, transposes and the reordering"}
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -652,6 +684,7 @@ def main():
         result["unfold"] = bench_unfold(ctx, P, sysd, d64, args.steps)
         result["gpp"] = bench_gpp(ctx, P, sysd, d64, epsinv64[0], args.steps)
         result["symmetrize"] = bench_symmetrize(ctx, P, sysd, o64["chi0"], args.steps)
+        result["bse_kernel"] = bench_bse(ctx, P, d64, epsinv64[0], args.steps)
 
     # ---------------- mixed path
     if not args.no_mixed:
