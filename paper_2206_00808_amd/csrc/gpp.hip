@@ -202,23 +202,38 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
   }
 }
 
-// sigma_coh[n][k] += pref * 0.5 * sum_tiles coh;  sigma_sx[n][k] -= pref * sum_tiles sx
+// sigma_coh[n][k] += pref * 0.5 * sum_tiles coh;  sigma_sx[n][k] -= pref * sum_tiles sx.
+// One workgroup per (band, energy): strided partial sums, then a fixed-order tree.
 template <int NE>
-__global__ void k_gpp_reduce(const cpx<double>* __restrict__ part, int ntiles, int nbc, int b0,
-                             double pref, cpx<double>* __restrict__ sx,
-                             cpx<double>* __restrict__ coh) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nbc * NE) return;
-  const int nb = idx / NE, k = idx % NE;
-  cpx<double> c = mk(0.0, 0.0), s = mk(0.0, 0.0);
-  for (int tl = 0; tl < ntiles; ++tl) {
+__global__ void __launch_bounds__(256) k_gpp_reduce(const cpx<double>* __restrict__ part,
+                                                    int ntiles, int b0, double pref,
+                                                    cpx<double>* __restrict__ sx,
+                                                    cpx<double>* __restrict__ coh) {
+  __shared__ double red[4][256];
+  const int nb = blockIdx.x / NE, k = blockIdx.x % NE, t = threadIdx.x;
+  double cr = 0.0, ci = 0.0, sr = 0.0, si = 0.0;
+  for (int tl = t; tl < ntiles; tl += 256) {
     const cpx<double>* p = part + ((size_t)nb * ntiles + tl) * 2 * NE;
-    c = c + p[2 * k];
-    s = s + p[2 * k + 1];
+    cr += p[2 * k].x;
+    ci += p[2 * k].y;
+    sr += p[2 * k + 1].x;
+    si += p[2 * k + 1].y;
   }
-  const size_t o = (size_t)(b0 + nb) * NE + k;
-  coh[o] = coh[o] + scal(c, 0.5 * pref);
-  sx[o] = sx[o] - scal(s, pref);
+  red[0][t] = cr;
+  red[1][t] = ci;
+  red[2][t] = sr;
+  red[3][t] = si;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const size_t o = (size_t)(b0 + nb) * NE + k;
+    coh[o] = coh[o] + scal(mk(red[0][0], red[1][0]), 0.5 * pref);
+    sx[o] = sx[o] - scal(mk(red[2][0], red[3][0]), pref);
+  }
 }
 
 template <typename Tin, int NE>
@@ -246,9 +261,8 @@ static gw_status sigma_gpp_run(gw_ctx* c, int nn, int nocc, int nband, int N, co
       GW_CHECK_LAUNCH(c, "k_sigma_gpp");
     }
     ProfScope ps(c, "sigma_gpp_reduce");
-    hipLaunchKernelGGL(k_gpp_reduce<NE>, dim3((nb * NE + 255) / 256), dim3(256), 0, c->stream,
-                       part, ntiles, nb, b0, pref, reinterpret_cast<cpx<double>*>(sx),
-                       reinterpret_cast<cpx<double>*>(coh));
+    hipLaunchKernelGGL(k_gpp_reduce<NE>, dim3(nb * NE), dim3(256), 0, c->stream, part, ntiles, b0,
+                       pref, reinterpret_cast<cpx<double>*>(sx), reinterpret_cast<cpx<double>*>(coh));
     GW_CHECK_LAUNCH(c, "k_gpp_reduce");
   }
   return GW_OK;
