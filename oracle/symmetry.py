@@ -22,6 +22,10 @@ quaternion_from_rotation | q q^T = X / 4 for random rotations, including
 su2_from_rotation        | unitary, det 1, U^H sigma_i U = sum_j R_ij sigma_j
                          | (the spin vector turns with R); improper ops take
                          | the rotation part; q and -q give U and -U
+kgrid_orbits             | the orbits partition the grid, every point is its
+                         | representative moved by the recorded operation and
+                         | G0, the weights sum to the grid size, and chi0 from
+                         | the representatives equals the full-grid chi0
 chi0_symmetrize          | chi0 from the irreducible points of q's little group,
                          | weighted by their orbits and symmetrised, equals chi0
                          | from states diagonalised at every k of the grid; the
@@ -37,7 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["rotation_lat_to_cart", "quaternion_from_rotation", "su2_from_rotation",
-           "rotate_g", "unfold_spinor", "little_group_shift", "chi0_symmetrize"]
+           "rotate_g", "unfold_spinor", "little_group_shift", "chi0_symmetrize", "kgrid_orbits"]
 
 _SX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
 _SY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
@@ -176,3 +180,38 @@ def chi0_symmetrize(chi, geps, ops, qred):
         ph = np.exp(-2j * np.pi * (g @ np.asarray(tau, dtype=np.float64)))
         out += ph[:, None] * np.conj(ph)[None, :] * x[..., idx[:, None], idx[None, :]]
     return out / len(ops)
+
+
+def kgrid_orbits(n, ops):
+    """Orbits of the unshifted grid k = (i1/n1, i2/n2, i3/n3) under the point
+    parts of `ops` (Sec. III: the k-sum over the irreducible wedge of the little
+    group of q).  Points are indexed (i1 n2 + i2) n3 + i3; the representative of
+    an orbit is its first point in that order.  Returns rep[i], op[i] (an
+    operation with S k_rep = k_i + G0), g0[i] (that integer G0) and weight[i]
+    (orbit size at representatives, 0 elsewhere).
+    """
+    n = np.asarray(n, dtype=np.int64)
+    npts = int(np.prod(n))
+    idx = np.stack(np.meshgrid(*[np.arange(m) for m in n], indexing="ij"), -1).reshape(-1, 3)
+    k = idx / n[None, :]
+    rep = np.full(npts, -1, dtype=np.int64)
+    opi = np.zeros(npts, dtype=np.int64)
+    g0 = np.zeros((npts, 3), dtype=np.int64)
+    weight = np.zeros(npts, dtype=np.int64)
+    for i in range(npts):
+        if rep[i] >= 0:
+            continue
+        for j, (s_lat, _) in enumerate(ops):
+            sk = np.linalg.inv(np.asarray(s_lat, dtype=np.float64)).T @ k[i]
+            cell = np.floor(sk + 1e-9)
+            frac = sk - cell
+            t = np.rint(frac * n)
+            if np.abs(frac * n - t).max() > 1e-6:
+                raise ValueError("the grid is not closed under an operation")
+            t = np.mod(t, n).astype(np.int64)
+            m = int((t[0] * n[1] + t[1]) * n[2] + t[2])
+            if rep[m] < 0:
+                rep[m], opi[m] = i, j
+                g0[m] = np.rint(sk - k[m]).astype(np.int64)
+                weight[i] += 1
+    return rep, opi, g0, weight

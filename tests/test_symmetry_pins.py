@@ -334,8 +334,31 @@ def test_chi0_from_the_irreducible_wedge_symmetrised(model):
         seen |= orbit
         irr = irr + len(orbit) * chi_at(k)
     assert len(seen) == len(grid)
+    # the same sum over the representatives and weights kgrid_orbits returns
+    rep, _, _, w = oracle.kgrid_orbits((3, 3, 3), little)
+    irr2 = sum(int(w[i]) * chi_at(np.array([i // 9, (i // 3) % 3, i % 3]) / 3.0)
+               for i in np.nonzero(w)[0])
+    assert oracle.rel_f(oracle.chi0_symmetrize(irr2, geps, little, q), direct) < 1e-10
     sym = oracle.chi0_symmetrize(irr, geps, little, q)
     assert oracle.rel_f(sym, direct) < 1e-10
     assert oracle.rel_f(oracle.chi0_symmetrize(sym, geps, little[1:2], q), sym) < 1e-13
     no_phase = [(s, np.zeros(3)) for s, _ in little]
     assert oracle.rel_f(oracle.chi0_symmetrize(irr, geps, no_phase, q), direct) > 1e-3
+
+
+def test_kgrid_orbits_partition_the_grid(model):
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    little = [op for op in model.ops if oracle.little_group_shift(op[0], q) is not None]
+    for n, ops in (((3, 3, 3), little), ((4, 4, 2), model.ops), ((4, 4, 3), little[:4])):
+        rep, op, g0, w = oracle.kgrid_orbits(n, ops)
+        npts = int(np.prod(n))
+        assert w.sum() == npts and np.all(w[rep[w > 0]] > 0)
+        idx = np.stack(np.meshgrid(*[np.arange(m) for m in n], indexing="ij"), -1).reshape(-1, 3)
+        k = idx / np.asarray(n)
+        for i in range(npts):
+            s = ops[op[i]][0]
+            assert np.allclose(_kprime(s, k[rep[i]]), k[i] + g0[i], atol=1e-12)
+            assert w[rep[i]] == np.sum(rep == rep[i])
+    # the 16-element group folds the 4x4x2 grid; the trivial group leaves it
+    assert (oracle.kgrid_orbits((4, 4, 2), model.ops)[3] > 0).sum() < 32
+    assert (oracle.kgrid_orbits((2, 2, 2), model.ops[:1])[3] > 0).sum() == 8
