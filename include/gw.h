@@ -304,6 +304,30 @@ gw_status gw_unfold_spinor(gw_ctx* ctx, int nspinor, int nb, int ng_in, const in
  * aliasing, det S not +-1, an operation outside the little group of q, a sphere
  * not closed under an operation, duplicate G.
  */
+/*
+ * gw_little_group -- host bookkeeping, no context and no device work: which of
+ * nops operations (rots as for gw_unfold_spinor) keep q, S q = q + G_S (Sec. III,
+ * the little group of q).  in_group[s] = 1 or 0; gshift[s][3] = G_S (0 when not
+ * in the group).  GW_EINVAL for NULL arrays or det S not +-1.
+ */
+gw_status gw_little_group(int nops, const int* rots, const double* qred, int* in_group,
+                          int* gshift);
+
+/*
+ * gw_kgrid_orbits -- host bookkeeping, no context and no device work: orbits of
+ * the unshifted grid k = (i1/n1, i2/n2, i3/n3), point index (i1 n2 + i2) n3 + i3,
+ * under nops operations (normally the little group of q).  For every point i:
+ * rep[i] the index of its orbit's first point, op[i] an operation with
+ * S k_rep = k_i + G0, g0[i][3] that G0; weight[i] the orbit size at
+ * representatives and 0 elsewhere; *nirr the number of orbits.  The k-sum over
+ * the grid is then sum over representatives of weight * (its term), averaged
+ * over the group by gw_chi0_symmetrize.  GW_EINVAL for non-positive sizes, more
+ * than 2^26 points, NULL arrays, det S not +-1, or a grid not closed under an
+ * operation.  Arrays: rep, op, weight int[n1 n2 n3]; g0 int[n1 n2 n3][3].
+ */
+gw_status gw_kgrid_orbits(int n1, int n2, int n3, int nops, const int* rots, int* rep, int* op,
+                          int* g0, int* weight, int* nirr);
+
 gw_status gw_chi0_symmetrize(gw_ctx* ctx, int neps, int nfreq, const int* geps,
                              const double* qred, int nops, const int* rots, const double* taus,
                              const double* chi_in, double* chi_out);

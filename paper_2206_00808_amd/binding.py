@@ -29,7 +29,7 @@ EXPORTED = [
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
-    "gw_bse_kernel",
+    "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -73,6 +73,8 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_little_group": (_i, [_i, _vp, _vp, _vp, _vp]),
+    "gw_kgrid_orbits": (_i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gw_bse_kernel": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "gw_chi0_symmetrize": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
     "gw_gpp_modes": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -364,6 +366,43 @@ def gw_bse_kernel(ctx, mvc, mcc, mvv, vx, w, kx, kd):
     s = _lib.gw_bse_kernel(ctx.handle, nv, nc, neps, _ptr(mvc), _ptr(mcc), _ptr(mvv), dt, _ptr(vx),
                            _ptr(w), _ptr(kx), _ptr(kd))
     return _check(ctx, s)
+
+
+def _host_rots(ops):
+    return _host_i32([np.asarray(op[0] if isinstance(op, tuple) else op).reshape(9)
+                      for op in ops]).reshape(-1)
+
+
+def gw_little_group(ops, qred):
+    """(in_group bool[nops], gshift int[nops][3]) for S q = q + G_S (see include/gw.h).
+    Host only: needs no device and no context."""
+    rots = _host_rots(ops)
+    q = np.ascontiguousarray(np.asarray(qred, dtype=np.float64).reshape(3))
+    ing = np.zeros(len(ops), dtype=np.int32)
+    gs = np.zeros((len(ops), 3), dtype=np.int32)
+    s = _lib.gw_little_group(len(ops), rots.ctypes.data, q.ctypes.data, ing.ctypes.data,
+                             gs.ctypes.data)
+    if s != GW_OK:
+        raise GwError(s, "gw_little_group: bad operation")
+    return ing.astype(bool), gs
+
+
+def gw_kgrid_orbits(n, ops):
+    """(rep, op, g0, weight, nirr) for the unshifted grid n under ops (see include/gw.h).
+    Host only: needs no device and no context."""
+    rots = _host_rots(ops)
+    npts = int(n[0]) * int(n[1]) * int(n[2])
+    rep = np.zeros(npts, dtype=np.int32)
+    op = np.zeros(npts, dtype=np.int32)
+    g0 = np.zeros((npts, 3), dtype=np.int32)
+    w = np.zeros(npts, dtype=np.int32)
+    nirr = ct.c_int()
+    s = _lib.gw_kgrid_orbits(int(n[0]), int(n[1]), int(n[2]), len(ops), rots.ctypes.data,
+                             rep.ctypes.data, op.ctypes.data, g0.ctypes.data, w.ctypes.data,
+                             ct.byref(nirr))
+    if s != GW_OK:
+        raise GwError(s, "gw_kgrid_orbits: bad grid or operation")
+    return rep, op, g0, w, nirr.value
 
 
 def raw():

@@ -172,15 +172,15 @@ def test_chi0_symmetrize_rejects_bad_arguments(P, ctx, model):
 
 
 def test_chi0_from_irreducible_points_on_the_gpu(P, ctx, model):
-    """Only the irreducible points of q's little group: states diagonalised there
-    (CPU inputs), matrix elements and chi0 on the GPU weighted by orbit size, then
-    gw_chi0_symmetrize; against the oracle's chi0 over states at every k of the grid."""
+    """Only the irreducible points of q's little group, found by the library's host
+    bookkeeping: states diagonalised there (CPU inputs), matrix elements and chi0
+    on the GPU weighted by orbit size, then gw_chi0_symmetrize; against the
+    oracle's chi0 over states at every k of the grid."""
     nv, nc = 4, 4
     q = np.array([0.0, 0.0, 1.0 / 3.0])
     geps = g_sphere(CELL, q, 3.0)
     omega = [0.0, 0.4]
     grid = [np.array([i / 3, j / 3, l / 3]) for i in range(3) for j in range(3) for l in range(3)]
-    little = _little(model, q)
     direct = 0
     for k in grid:
         e1, c1, g1 = model.states(k, nv + nc)
@@ -188,26 +188,22 @@ def test_chi0_from_irreducible_points_on_the_gpu(P, ctx, model):
         m = oracle.mtxel_convolution(c2[:nv], g2, c1[nv:], g1, geps)
         direct = direct + oracle.chi0(m, e2[:nv], e1[nv:nv + nc], np.asarray(omega))
 
-    def key(k):
-        kf = np.mod(k + 1e-12, 1.0)
-        return tuple(np.round(np.where(kf > 1 - 1e-9, 0.0, kf), 9))
-
     chi = torch.zeros((2, len(geps), len(geps)), dtype=torch.complex128, device="cuda:0")
-    seen, nirr = set(), 0
-    for k in grid:
-        if key(k) in seen:
-            continue
-        orbit = {key(_kprime(s, k)) for s, _ in little}
-        seen |= orbit
-        nirr += 1
+    # the library's own bookkeeping: the little group of q and the grid's orbits
+    ing, _ = P.gw_little_group(model.ops, q)
+    little = [op for op, keep in zip(model.ops, ing) if keep]
+    rep, _, _, weight, nirr = P.gw_kgrid_orbits((3, 3, 3), little)
+    for i in np.nonzero(weight)[0]:
+        k = np.array([i // 9, (i // 3) % 3, i % 3]) / 3.0
         ec_, cc_, gc_ = model.states(k, nv + nc)
         ev_, cv_, gv_ = model.states(k + q, nv)
         m = torch.empty((nv, nc, len(geps)), dtype=torch.complex128, device="cuda:0")
         P.gw_mtxel_spinor(ctx, (16, 16, 16), 2, gv_, _dev(cv_), gc_, _dev(cc_[nv:]), geps, m)
         P.gw_chi0_accumulate(ctx, nv, nc, len(geps), m, _dev(ev_[:nv]), _dev(ec_[nv:nv + nc]),
-                             omega, float(len(orbit)), P.GW_PREC_FP64, chi)
+                             omega, float(weight[i]), P.GW_PREC_FP64, chi)
+    seen = set(rep.tolist())
     out = torch.empty_like(chi)
     P.gw_chi0_symmetrize(ctx, geps, q, little, chi, out)
     torch.cuda.synchronize()
-    assert len(seen) == len(grid) and nirr < len(grid)
+    assert len(seen) == nirr < len(grid) and weight.sum() == len(grid)
     assert oracle.rel_f(out.cpu().numpy(), direct) < 1e-10
