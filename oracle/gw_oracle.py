@@ -32,6 +32,9 @@ epsilon / epsilon_inverse| Sherman-Morrison closed form, eigenvalue bounds,
 head_overlap             | convolution form at G = 0, orthonormality
 head_dipole              | k.p limit of head_overlap for a spin-dependent
                          | local-potential model, Hermiticity, plane waves
+epsinv_lowrank           | exact inverse at nb = N; rank-one chi0 exact at nb = 1
+                         | (Sherman-Morrison); at omega = 0 the error is the
+                         | discarded eigenvalues' 1/lambda - 1 (closed form)
 screened_w               | Hermitian for the symmetric form of eps (closed form)
 sigma_sx_static          | bare exchange at eps^-1 = I (closed form), real and
                          | between the bare exchange and 0 for chi0 <= 0
@@ -56,7 +59,7 @@ __all__ = [
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
     "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "GPP_DROP_TOL", "gpp_modes",
-    "epsinv_gpp", "sigma_gpp", "bse_kernel", "chi0_from_system", "rel_f", "alias_free",
+    "epsinv_gpp", "sigma_gpp", "bse_kernel", "epsinv_lowrank", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -255,6 +258,31 @@ def epsilon_inverse(chi0_all, vcoul):
     """
     c = np.asarray(chi0_all, dtype=np.complex128)
     return np.stack([np.linalg.inv(epsilon(cf, vcoul)) for cf in c])
+
+
+def epsinv_lowrank(chi0_all, vcoul, nb):
+    """eps^-1 in a reduced basis of static eigenvectors (Sec. IV, Bi2Se3: the
+    full-frequency calculation keeps 200 eigenvectors, about a tenth of the
+    spectrum).  With V = diag(v), epst(w) = I - V^1/2 chi0(w) V^1/2 (Hermitian; eps
+    is similar to it), U the eigenvectors of epst(0) with the nb largest
+    eigenvalues (numpy.linalg.eigh), and epst_B(w) = U^H epst(w) U:
+      epst^-1(w) ~= I + U (epst_B(w)^-1 - I) U^H,   eps^-1 = V^1/2 epst^-1 V^-1/2.
+    Outside span(U) the screening is left out (epst^-1 acts as I there).
+    Returns (epsinv [nfreq][N][N], eigenvalues of epst(0) in ascending order).
+    """
+    c = np.asarray(chi0_all, dtype=np.complex128)
+    v = np.asarray(vcoul, dtype=np.float64)
+    sv = np.sqrt(v)
+    n = c.shape[-1]
+    epst = np.eye(n)[None] - sv[None, :, None] * c * sv[None, None, :]
+    lam, vec = np.linalg.eigh(epst[0])
+    u = vec[:, n - nb:]
+    out = []
+    for e in epst:
+        eb = u.conj().T @ e @ u
+        et = np.eye(n) + u @ (np.linalg.inv(eb) - np.eye(nb)) @ u.conj().T
+        out.append(sv[:, None] * et / sv[None, :])
+    return np.stack(out), lam
 
 
 def screened_w(epsinv_all, vcoul):

@@ -434,3 +434,47 @@ def test_q0_head_construction_scales_with_q():
     assert np.abs(h).max() < 20 * qn and np.abs(h).max() > 1e-3 * qn
     m = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
     assert np.allclose(m[:, :, s["head_index"]], h, atol=1e-15)
+
+
+# ----------------------------------------------------------------- low-rank eps^-1
+def _lr_system(seed, n=40, nf=3, rank=None):
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(0.2, 3.0, n)
+    r = n if rank is None else rank
+    m = (rng.standard_normal((r, n)) + 1j * rng.standard_normal((r, n))) * 0.3
+    chi = np.stack([-(np.conj(m).T @ m) / (1.0 + f) for f in range(nf)])
+    return chi, v
+
+
+def test_lowrank_full_basis_is_the_exact_inverse():
+    chi, v = _lr_system(1)
+    lr, _ = oracle.epsinv_lowrank(chi, v, chi.shape[-1])
+    ex = oracle.epsilon_inverse(chi, v)
+    assert np.abs(lr - ex).max() < 1e-12 * np.abs(ex).max()
+
+
+def test_lowrank_rank_one_chi_is_exact_with_one_vector():
+    """chi0(w) = -a(w) x x^H: epst - I has rank one, so one eigenvector carries all
+    of it and the Sherman-Morrison inverse follows exactly."""
+    rng = np.random.default_rng(2)
+    n = 30
+    v = rng.uniform(0.2, 3.0, n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    chi = np.stack([-a * np.outer(np.conj(x), x) for a in (0.7, 0.3, 0.05)])
+    lr, _ = oracle.epsinv_lowrank(chi, v, 1)
+    ex = oracle.epsilon_inverse(chi, v)
+    assert np.abs(lr - ex).max() < 1e-12 * np.abs(ex).max()
+
+
+def test_lowrank_static_error_is_the_discarded_spectrum():
+    """At w = 0: epst^-1 - approx = sum over discarded eigenpairs of (1/lambda - 1) u u^H,
+    whose 2-norm is max |1/lambda - 1| over the discarded eigenvalues."""
+    chi, v = _lr_system(3)
+    n, nb = chi.shape[-1], 12
+    lr, lam = oracle.epsinv_lowrank(chi, v, nb)
+    ex = oracle.epsilon_inverse(chi, v)
+    sv = np.sqrt(v)
+    d = (lr[0] - ex[0]) * sv[None, :] / sv[:, None]  # back to the symmetric form
+    want = np.max(np.abs(1.0 / lam[:n - nb] - 1.0))
+    assert abs(np.linalg.norm(d, 2) - want) < 1e-10 * want
+    assert np.all(lam >= 1.0 - 1e-12)
