@@ -226,6 +226,27 @@ gw_status gw_epsinv_lu(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
                        const double* vcoul, double* epsinv);
 
 /*
+ * gw_epsinv_lowrank -- eps^-1 in a reduced basis of nb static eigenvectors
+ * (Sec. IV, Bi2Se3: the full-frequency calculation keeps 200 eigenvectors,
+ * about a tenth of the spectrum).  With epst(w) = I - V^1/2 chi0(w) V^1/2 and U the
+ * eigenvectors of epst(0) with the nb largest eigenvalues:
+ *   epst^-1(w) ~= I + U ((U^H epst(w) U)^-1 - I) U^H,  eps^-1 = V^1/2 epst^-1 V^-1/2.
+ * The eigenvectors come from a cyclic Jacobi method on the GPU (converged to an
+ * off-diagonal norm of 1e-14 of the matrix's); nb = neps gives the exact inverse.
+ *   chi0  (device) complex double[nfreq][neps][neps], Hermitian, frequency 0 first.
+ *   vcoul (device) double[neps], every entry > 0.
+ *   epsinv (device) out complex double[nfreq][neps][neps], not chi0.
+ *   eigenvalues (device) out double[neps] of epst(0) in ascending order, or NULL.
+ * Allocates its own buffers (about 16 (nfreq + 2) neps^2 bytes) and synchronises
+ * the context stream.
+ * Errors: GW_EINVAL for negative sizes, nb outside 1..neps, neps > 8192, NULL
+ * arrays, aliasing, vcoul <= 0, non-finite input; GW_ENOMEM; GW_ESINGULAR from
+ * the small inverses.
+ */
+gw_status gw_epsinv_lowrank(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
+                            const double* vcoul, int nb, double* epsinv, double* eigenvalues);
+
+/*
  * gw_screened_w -- W_f[G][G'] = epsinv_f[G][G'] v(q+G') (Sec. II).
  *   epsinv (device) complex double[nfreq][neps][neps]; vcoul (device) double[neps];
  *   w      (device) out complex double[nfreq][neps][neps] (may be epsinv: in place).

@@ -14,6 +14,6 @@ from .binding import (  # noqa: F401
     GW_CLOSURE_INFER, GW_CLOSURE_TRAIN_STEP, GW_CLOSURE_FULL_FALLBACK,
     gw_mtxel_spinor, gw_chi0_accumulate, gw_epsinv, gw_chi0_accumulate_real, gw_epsinv_lu,
     gw_head_dipole, gw_screened_w, gw_sigma_sx, gw_unfold_spinor, gw_gpp_modes, gw_sigma_gpp, gw_chi0_symmetrize, gw_bse_kernel,
-    gw_little_group, gw_kgrid_orbits,
+    gw_little_group, gw_kgrid_orbits, gw_epsinv_lowrank,
     status_string, EXPORTED, LIB_PATH,
 )

@@ -29,7 +29,7 @@ EXPORTED = [
     "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
-    "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits",
+    "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits", "gw_epsinv_lowrank",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -73,6 +73,7 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_epsinv_lowrank": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "gw_little_group": (_i, [_i, _vp, _vp, _vp, _vp]),
     "gw_kgrid_orbits": (_i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gw_bse_kernel": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp]),
@@ -403,6 +404,14 @@ def gw_kgrid_orbits(n, ops):
     if s != GW_OK:
         raise GwError(s, "gw_kgrid_orbits: bad grid or operation")
     return rep, op, g0, w, nirr.value
+
+
+def gw_epsinv_lowrank(ctx, neps, nfreq, chi0, vcoul, nb, epsinv, eigenvalues=None):
+    """eps^-1 in a basis of nb static eigenvectors (see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_epsinv_lowrank(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul), int(nb),
+                               _ptr(epsinv), _ptr(eigenvalues))
+    return _check(ctx, s)
 
 
 def raw():

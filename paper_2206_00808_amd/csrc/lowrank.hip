@@ -1,0 +1,361 @@
+// eps^-1 in a reduced basis of static eigenvectors.
+//
+// Sec. IV (Bi2Se3, full frequency) keeps 200 eigenvectors of the static
+// dielectric matrix, about a tenth of the spectrum, and treats every frequency
+// in that basis.  With V = diag(v) and the Hermitian epst(w) = I - V^1/2 chi0(w) V^1/2
+// (eps is similar to it), U the eigenvectors of epst(0) with the nb largest
+// eigenvalues and epst_B(w) = U^H epst(w) U:
+//   epst^-1(w) ~= I + U (epst_B(w)^-1 - I) U^H,   eps^-1 = V^1/2 epst^-1 V^-1/2.
+//
+// The eigenvectors come from a cyclic two-sided Jacobi method on the GPU:
+// each sweep runs N - 1 rounds of N/2 disjoint plane rotations in round-robin
+// order (every pair once per sweep), each round as three kernels (rotation
+// parameters; row update of A and of the eigenvector rows; column update of A).
+// Sweeps repeat until the off-diagonal Frobenius norm is below 1e-14 of the
+// matrix's.  The projections and the small inverses run on the FP64 GEMM and
+// the library's Hermitian inverse (Gauss-Jordan with its checks).
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace gw {
+
+namespace {
+struct JacRot {
+  int p, q, skip, pad;
+  double c, s, er, ei;  // J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]], e^{i phi} = er + i ei
+};
+}  // namespace
+
+__global__ void k_lr_epst(const cpx<double>* __restrict__ chi, const double* __restrict__ v,
+                          int N, cpx<double>* __restrict__ E) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  const double s = sqrt(v[i]) * sqrt(v[j]);
+  const cpx<double> x = chi[(size_t)blockIdx.y * nn + e];
+  E[(size_t)blockIdx.y * nn + e] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
+}
+
+// round r of the round-robin schedule over m (even) indices: pair 0 is (r, m-1),
+// pair k > 0 is ((r + k) mod (m-1), (r - k) mod (m-1)); indices >= N are padding
+__global__ void k_jac_params(const cpx<double>* __restrict__ A, int N, int m, int r,
+                             JacRot* __restrict__ rot) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m / 2) return;
+  int p, q;
+  if (k == 0) {
+    p = r;
+    q = m - 1;
+  } else {
+    p = (r + k) % (m - 1);
+    q = (r - k + (m - 1)) % (m - 1);
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+  JacRot o;
+  o.p = p;
+  o.q = q;
+  o.pad = 0;
+  o.skip = 1;
+  o.c = 1.0;
+  o.s = 0.0;
+  o.er = 1.0;
+  o.ei = 0.0;
+  if (q < N) {
+    const cpx<double> b = A[(size_t)p * N + q];
+    const double ab = hypot(b.x, b.y);
+    if (ab > 0.0) {
+      const double a = A[(size_t)p * N + p].x, d = A[(size_t)q * N + q].x;
+      // real symmetric [[a, |b|], [|b|, d]]: t = tan(theta), the smaller root
+      const double tau = (d - a) / (2.0 * ab);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      o.c = 1.0 / sqrt(1.0 + t * t);
+      o.s = t * o.c;
+      o.er = b.x / ab;
+      o.ei = b.y / ab;
+      o.skip = 0;
+    }
+  }
+  rot[k] = o;
+}
+
+// A <- J^H A on rows p, q and Vt <- J^T Vt (eigenvectors stored as rows)
+__global__ void k_jac_rows(cpx<double>* __restrict__ A, cpx<double>* __restrict__ Vt, int N,
+                           const JacRot* __restrict__ rot) {
+  const JacRot o = rot[blockIdx.x];
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (o.skip || j >= N) return;
+  const cpx<double> e = mk(o.er, o.ei), ec = mk(o.er, -o.ei);
+  {
+    const cpx<double> ap = A[(size_t)o.p * N + j], aq = A[(size_t)o.q * N + j];
+    // new p = c ap - s e^{i phi} aq;  new q = s ap + c e^{i phi} aq
+    const cpx<double> eq = cmul(e, aq);
+    A[(size_t)o.p * N + j] = scal(ap, o.c) - scal(eq, o.s);
+    A[(size_t)o.q * N + j] = scal(ap, o.s) + scal(eq, o.c);
+  }
+  {
+    const cpx<double> vp = Vt[(size_t)o.p * N + j], vq = Vt[(size_t)o.q * N + j];
+    // (V J)^T: new p = c vp - s e^{-i phi} vq;  new q = s vp + c e^{-i phi} vq
+    const cpx<double> eq = cmul(ec, vq);
+    Vt[(size_t)o.p * N + j] = scal(vp, o.c) - scal(eq, o.s);
+    Vt[(size_t)o.q * N + j] = scal(vp, o.s) + scal(eq, o.c);
+  }
+}
+
+// A <- A J on columns p, q
+__global__ void k_jac_cols(cpx<double>* __restrict__ A, int N, const JacRot* __restrict__ rot) {
+  const JacRot o = rot[blockIdx.x];
+  const int i = blockIdx.y * blockDim.x + threadIdx.x;
+  if (o.skip || i >= N) return;
+  const cpx<double> ec = mk(o.er, -o.ei);
+  const cpx<double> ap = A[(size_t)i * N + o.p], aq = A[(size_t)i * N + o.q];
+  // new p = c ap - s e^{-i phi} aq;  new q = s ap + c e^{-i phi} aq
+  const cpx<double> eq = cmul(ec, aq);
+  A[(size_t)i * N + o.p] = scal(ap, o.c) - scal(eq, o.s);
+  A[(size_t)i * N + o.q] = scal(ap, o.s) + scal(eq, o.c);
+}
+
+// partial sums of |A_ij|^2 off the diagonal and over all entries, fixed order
+__global__ void __launch_bounds__(256) k_lr_norms(const cpx<double>* __restrict__ A, int N,
+                                                  double* __restrict__ part) {
+  __shared__ double so[256], sa[256];
+  const size_t nn = (size_t)N * N;
+  double off = 0.0, all = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (size_t)gridDim.x * 256) {
+    const cpx<double> x = A[e];
+    const double m2 = x.x * x.x + x.y * x.y;
+    all += m2;
+    if (e / N != e % N) off += m2;
+  }
+  so[threadIdx.x] = off;
+  sa[threadIdx.x] = all;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      so[threadIdx.x] += so[threadIdx.x + h];
+      sa[threadIdx.x] += sa[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = so[0];
+    part[2 * blockIdx.x + 1] = sa[0];
+  }
+}
+
+// rank of eigenvalue i in descending order (ties by index); eigenvalues ascending out
+__global__ void k_lr_rank(const cpx<double>* __restrict__ A, int N, int* __restrict__ rank,
+                          double* __restrict__ lam_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double li = A[(size_t)i * N + i].x;
+  int r = 0;
+  for (int j = 0; j < N; ++j) {
+    const double lj = A[(size_t)j * N + j].x;
+    r += (lj > li || (lj == li && j < i)) ? 1 : 0;
+  }
+  rank[i] = r;
+  if (lam_out) lam_out[N - 1 - r] = li;
+}
+
+// U[g][rank i] = Vt[i][g] and Uh[rank i][g] = conj(Vt[i][g]) for the nb leading i
+__global__ void k_lr_select(const cpx<double>* __restrict__ Vt, const int* __restrict__ rank,
+                            int N, int nb, cpx<double>* __restrict__ U,
+                            cpx<double>* __restrict__ Uh) {
+  const int i = blockIdx.x;
+  const int r = rank[i];
+  if (r >= nb) return;
+  for (int g = threadIdx.x; g < N; g += blockDim.x) {
+    const cpx<double> x = Vt[(size_t)i * N + g];
+    U[(size_t)g * nb + r] = x;
+    Uh[(size_t)r * N + g] = mk(x.x, -x.y);
+  }
+}
+
+// x[f] <- sign * x[f] + add * I   (nb x nb blocks)
+__global__ void k_lr_shift(cpx<double>* __restrict__ x, int nb, double sign, double add) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t bb = (size_t)nb * nb;
+  if (e >= bb) return;
+  cpx<double>* y = x + (size_t)blockIdx.y * bb + e;
+  const bool diag = (e / nb) == (e % nb);
+  *y = mk(sign * y->x + (diag ? add : 0.0), sign * y->y);
+}
+
+__global__ void k_lr_fill(cpx<double>* __restrict__ out, int N, double* __restrict__ ones,
+                          int nb) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nn) out[(size_t)blockIdx.y * nn + e] = mk((e / N) == (e % N) ? 1.0 : 0.0, 0.0);
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) ones[k] = 1.0;
+}
+
+__global__ void k_lr_unscale(cpx<double>* __restrict__ out, const double* __restrict__ v, int N) {
+  const size_t nn = (size_t)N * N;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  cpx<double>* y = out + (size_t)blockIdx.y * nn + e;
+  *y = scal(*y, sqrt(v[i]) / sqrt(v[j]));
+}
+
+static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
+                             const double* vcoul, int nb, double* epsinv, double* lam,
+                             char* base) {
+  const size_t nn = (size_t)N * N, nub = (size_t)N * nb, bb = (size_t)nb * nb;
+  const int m = N + (N & 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += align_up(bytes);
+    return p;
+  };
+  auto* E = reinterpret_cast<cpx<double>*>(take(nfreq * nn * 16));
+  auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* U = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* Y = reinterpret_cast<cpx<double>*>(take(nfreq * nub * 16));
+  auto* B = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* Bi = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
+  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
+  auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
+  const unsigned gnn = (unsigned)((nn + 255) / 256);
+  {
+    ProfScope ps(c, "lowrank_prep");
+    hipLaunchKernelGGL(k_lr_epst, dim3(gnn, nfreq), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(chi0), vcoul, N, E);
+    GW_HIP(c, hipMemcpyAsync(A, E, nn * 16, hipMemcpyDeviceToDevice, c->stream));
+    // Vt = I; also the identity that the final products accumulate onto, and ones
+    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, 1), dim3(256), 0, c->stream, Vt, N, ones, nb);
+    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, nfreq), dim3(256), 0, c->stream,
+                       reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
+    GW_CHECK_LAUNCH(c, "low-rank preparation");
+  }
+  // cyclic Jacobi on epst(0)
+  const int nblk = (int)std::min<size_t>(1024, (nn + 255) / 256);
+  std::vector<double> hp(2 * (size_t)nblk);
+  const dim3 gp((m / 2 + 127) / 128), gr(m / 2, (N + 255) / 256);
+  bool done = false;
+  for (int sweep = 0; sweep < 40 && !done; ++sweep) {
+    {
+      ProfScope ps(c, "jacobi_sweep");
+      for (int r = 0; r < m - 1; ++r) {
+        hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, c->stream, A, N, m, r, rot);
+        hipLaunchKernelGGL(k_jac_rows, gr, dim3(256), 0, c->stream, A, Vt, N, rot);
+        hipLaunchKernelGGL(k_jac_cols, gr, dim3(256), 0, c->stream, A, N, rot);
+      }
+      GW_CHECK_LAUNCH(c, "jacobi round");
+    }
+    hipLaunchKernelGGL(k_lr_norms, dim3(nblk), dim3(256), 0, c->stream, A, N, part);
+    GW_CHECK_LAUNCH(c, "k_lr_norms");
+    GW_HIP(c, hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    GW_HIP(c, hipStreamSynchronize(c->stream));
+    double so = 0.0, sa = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      so += hp[2 * b];
+      sa += hp[2 * b + 1];
+    }
+    if (!std::isfinite(so) || !std::isfinite(sa))
+      return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
+    done = so <= 1e-28 * sa;
+  }
+  if (!done) return fail(c, GW_EINVAL, "Jacobi eigen-decomposition of epst(0) did not converge");
+  {
+    ProfScope ps(c, "lowrank_basis");
+    hipLaunchKernelGGL(k_lr_rank, dim3((N + 255) / 256), dim3(256), 0, c->stream, A, N, rank, lam);
+    hipLaunchKernelGGL(k_lr_select, dim3(N), dim3(256), 0, c->stream, Vt, rank, N, nb, U, Uh);
+    GW_CHECK_LAUNCH(c, "low-rank basis");
+  }
+  const long long snn = (long long)nn, snb = (long long)nub, sbb = (long long)bb;
+  // Y_f = E_f U;  B_f = U^H Y_f
+  gw_status st = zgemm_nn(c, N, nb, N, 1.0, reinterpret_cast<const double*>(E), 0, N, snn,
+                          reinterpret_cast<const double*>(U), 0, nb, 0,
+                          reinterpret_cast<double*>(Y), 0, nb, snb, nfreq, nfreq * nn, nub,
+                          nfreq * nub, 0.0);
+  if (st != GW_OK) return st;
+  st = zgemm_nn(c, nb, nb, N, 1.0, reinterpret_cast<const double*>(Uh), 0, N, 0,
+                reinterpret_cast<const double*>(Y), 0, nb, snb, reinterpret_cast<double*>(B), 0,
+                nb, sbb, nfreq, nub, nfreq * nub, nfreq * bb, 0.0);
+  if (st != GW_OK) return st;
+  // B_f^-1 by the Hermitian inverse of I - 1 * (I - B_f)
+  {
+    ProfScope ps(c, "lowrank_small");
+    hipLaunchKernelGGL(k_lr_shift, dim3((unsigned)((bb + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, B, nb, -1.0, 1.0);
+    GW_CHECK_LAUNCH(c, "k_lr_shift");
+  }
+  st = epsinv_run(c, nb, nfreq, reinterpret_cast<const double*>(B), ones,
+                  reinterpret_cast<double*>(Bi));
+  if (st != GW_OK) return st;
+  {
+    ProfScope ps(c, "lowrank_small");
+    hipLaunchKernelGGL(k_lr_shift, dim3((unsigned)((bb + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, Bi, nb, 1.0, -1.0);
+    GW_CHECK_LAUNCH(c, "k_lr_shift");
+  }
+  // Y_f = U (B_f^-1 - I);  out_f = I + Y_f U^H
+  st = zgemm_nn(c, N, nb, nb, 1.0, reinterpret_cast<const double*>(U), 0, nb, 0,
+                reinterpret_cast<const double*>(Bi), 0, nb, sbb, reinterpret_cast<double*>(Y), 0,
+                nb, snb, nfreq, nub, nfreq * bb, nfreq * nub, 0.0);
+  if (st != GW_OK) return st;
+  st = zgemm_nn(c, N, N, nb, 1.0, reinterpret_cast<const double*>(Y), 0, nb, snb,
+                reinterpret_cast<const double*>(Uh), 0, N, 0, epsinv, 0, N, snn, nfreq,
+                nfreq * nub, nub, nfreq * nn, 1.0);
+  if (st != GW_OK) return st;
+  ProfScope ps(c, "lowrank_unscale");
+  hipLaunchKernelGGL(k_lr_unscale, dim3(gnn, nfreq), dim3(256), 0, c->stream,
+                     reinterpret_cast<cpx<double>*>(epsinv), vcoul, N);
+  GW_CHECK_LAUNCH(c, "k_lr_unscale");
+  return GW_OK;
+}
+
+}  // namespace gw
+
+using namespace gw;
+
+extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const double* chi0,
+                                       const double* vcoul, int nb, double* epsinv,
+                                       double* eigenvalues) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 0 || nfreq < 0) return fail(c, GW_EINVAL, "negative size");
+  if (neps == 0 || nfreq == 0) return GW_OK;
+  if (nb < 1 || nb > neps) return fail(c, GW_EINVAL, "nb must be 1 to neps");
+  if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
+  if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv aliases chi0");
+  if (neps > 8192 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 8192 or nfreq too large");
+  (void)hipSetDevice(c->device);
+  // v > 0 is required for V^1/2: checked on a host copy
+  std::vector<double> hv((size_t)neps);
+  GW_HIP(c, hipMemcpyAsync(hv.data(), vcoul, (size_t)neps * 8, hipMemcpyDeviceToHost, c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  for (double x : hv)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(c, GW_EINVAL, "vcoul must be positive");
+  const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb, bb = (size_t)nb * nb;
+  const int m = neps + (neps & 1);
+  const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up(nn * 16) + 2 * align_up(nub * 16) +
+                       align_up(nfreq * nub * 16) + 2 * align_up(nfreq * bb * 16) +
+                       align_up((size_t)(m / 2) * 48) + align_up(2 * 1024 * 8) +
+                       align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
+  // its own buffers: the small inverse below uses the context workspace
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) return fail(c, GW_ENOMEM, "low-rank buffers of %zu bytes", bytes);
+  gw_status st = lowrank_run(c, neps, nfreq, chi0, vcoul, nb, epsinv, eigenvalues,
+                             static_cast<char*>(base));
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(base);
+  if (st != GW_OK) return st;
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamSynchronize");
+  return GW_OK;
+}

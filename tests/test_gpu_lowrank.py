@@ -1,0 +1,75 @@
+"""GPU parity of eps^-1 in a reduced basis of static eigenvectors
+(gw_epsinv_lowrank) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2206_00808_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _chi(seed, n, nf, rank):
+    """chi0(w) = -M^H diag(1/(1 + w_p f)) M: rank `rank` at every frequency, so
+    epst(0) has `rank` eigenvalues above 1 and the rest at 1 (a clean gap)."""
+    rng = np.random.default_rng(seed)
+    m = (rng.standard_normal((rank, n)) + 1j * rng.standard_normal((rank, n))) * 0.3
+    wp = rng.uniform(0.5, 2.0, rank)
+    chi = np.stack([-(np.conj(m).T * (1.0 / (1.0 + wp * f))[None, :]) @ m for f in range(nf)])
+    v = rng.uniform(0.2, 3.0, n)
+    return chi, v
+
+
+def _run(P, ctx, chi, v, nb, lam=False):
+    nf, n, _ = chi.shape
+    out = torch.empty((nf, n, n), dtype=torch.complex128, device="cuda:0")
+    ev = torch.empty(n, dtype=torch.float64, device="cuda:0") if lam else None
+    P.gw_epsinv_lowrank(ctx, n, nf, _dev(chi), _dev(v), nb, out, ev)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (ev.cpu().numpy() if lam else None)
+
+
+@pytest.mark.parametrize("n,nf,rank,nb", [(40, 3, 10, 10), (37, 2, 37, 37), (130, 4, 25, 25),
+                                          (64, 1, 64, 64), (1, 1, 1, 1)])
+def test_lowrank_matches_oracle(P, ctx, n, nf, rank, nb):
+    chi, v = _chi(n + rank, n, nf, rank)
+    got, lam = _run(P, ctx, chi, v, nb, lam=True)
+    want, wlam = oracle.epsinv_lowrank(chi, v, nb)
+    for f in range(nf):
+        assert oracle.rel_f(got[f], want[f]) < 1e-10
+    assert np.abs(lam - wlam).max() < 1e-12 * np.abs(wlam).max()
+    if nb == n:  # the full basis is the exact inverse
+        ex = oracle.epsilon_inverse(chi, v)
+        assert oracle.rel_f(got[0], ex[0]) < 1e-10
+
+
+def test_lowrank_rejects_bad_arguments(P, ctx):
+    chi, v = _chi(1, 8, 1, 3)
+    out = torch.empty((1, 8, 8), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(P.GwError):
+        P.gw_epsinv_lowrank(ctx, 8, 1, _dev(chi), _dev(v), 0, out)
+    with pytest.raises(P.GwError):
+        P.gw_epsinv_lowrank(ctx, 8, 1, _dev(chi), _dev(v), 9, out)
+    bad = v.copy()
+    bad[3] = 0.0
+    with pytest.raises(P.GwError):
+        P.gw_epsinv_lowrank(ctx, 8, 1, _dev(chi), _dev(bad), 3, out)
+    c = _dev(chi)
+    with pytest.raises(P.GwError):
+        P.gw_epsinv_lowrank(ctx, 8, 1, c, _dev(v), 3, c)
