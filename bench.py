@@ -501,6 +501,41 @@ def bench_bse(ctx, P, d, epsinv0, steps, nc=64):
                     "M_vv^T); the time includes widening, transposes and the reordering"}
 
 
+def bench_lowrank(ctx, P, d, chi, epsinv_full, reps=2):
+    """eps^-1 in a basis of N_eps/10 static eigenvectors (gw_epsinv_lowrank) for the
+    workload's nine frequencies, against the full inverse of the timed path: time
+    and the relative Frobenius difference per frequency."""
+    import torch
+    nf, neps, _ = chi.shape
+    nb = max(1, neps // 10)
+    out = torch.empty_like(chi)
+    lam = torch.empty(neps, dtype=torch.float64, device="cuda")
+    call = lambda: P.gw_epsinv_lowrank(ctx, neps, nf, chi, d["vcoul"], nb, out, lam)
+    call()
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    tab = ctx.profile_table()
+    ctx.profile(False)
+    ctx.profile_reset()
+    jac = tab.get("jacobi_sweep", (0, 0.0))
+    diff = (out - epsinv_full).reshape(nf, -1)
+    rel = (torch.linalg.vector_norm(diff, dim=1) /
+           torch.linalg.vector_norm(epsinv_full.reshape(nf, -1), dim=1)).cpu().numpy()
+    lam_h = lam.cpu().numpy()
+    return {"ms": ms, "nb": nb, "jacobi_ms": jac[1] / reps, "jacobi_sweeps": jac[0] / reps,
+            "rel_diff_vs_full_inverse": [float(x) for x in rel],
+            "kept_eigenvalue_min": float(lam_h[neps - nb]),
+            "discarded_eigenvalue_max": float(lam_h[neps - nb - 1]),
+            "note": "wall time of the call (it synchronises); the Jacobi sweeps dominate, "
+                    "each N_eps - 1 rounds of two small kernels replayed from a graph"}
+
+
 def _one_blas_thread():
     try:
         from threadpoolctl import threadpool_limits
@@ -685,6 +720,7 @@ def main():
         result["gpp"] = bench_gpp(ctx, P, sysd, d64, epsinv64[0], args.steps)
         result["symmetrize"] = bench_symmetrize(ctx, P, sysd, o64["chi0"], args.steps)
         result["bse_kernel"] = bench_bse(ctx, P, d64, epsinv64[0], args.steps)
+        result["lowrank"] = bench_lowrank(ctx, P, d64, o64["chi0"], epsinv64)
 
     # ---------------- mixed path
     if not args.no_mixed:

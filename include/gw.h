@@ -239,7 +239,7 @@ gw_status gw_epsinv_lu(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
  *   eigenvalues (device) out double[neps] of epst(0) in ascending order, or NULL.
  * Allocates its own buffers (about 16 (nfreq + 2) neps^2 bytes) and synchronises
  * the context stream.
- * Errors: GW_EINVAL for negative sizes, nb outside 1..neps, neps > 8192, NULL
+ * Errors: GW_EINVAL for negative sizes, nb outside 1..neps, neps > 4096, NULL
  * arrays, aliasing, vcoul <= 0, non-finite input; GW_ENOMEM; GW_ESINGULAR from
  * the small inverses.
  */

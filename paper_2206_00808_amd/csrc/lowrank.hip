@@ -9,11 +9,13 @@
 //
 // The eigenvectors come from a cyclic two-sided Jacobi method on the GPU:
 // each sweep runs N - 1 rounds of N/2 disjoint plane rotations in round-robin
-// order (every pair once per sweep), each round as three kernels (rotation
-// parameters; row update of A and of the eigenvector rows; column update of A).
-// Sweeps repeat until the off-diagonal Frobenius norm is below 1e-14 of the
-// matrix's.  The projections and the small inverses run on the FP64 GEMM and
-// the library's Hermitian inverse (Gauss-Jordan with its checks).
+// order (every pair once per sweep), each round as two kernels (rotation
+// parameters; then one workgroup per pair rewriting its two rows of J^H A J and
+// of the eigenvector rows, see k_jac_round).
+// One sweep is captured into a HIP graph and replayed; sweeps repeat until the
+// off-diagonal Frobenius norm is below 1e-14 of the matrix's.  The projections
+// and the small inverses run on the FP64 GEMM and the library's Hermitian
+// inverse (Gauss-Jordan with its checks).
 #include <cmath>
 #include <vector>
 
@@ -42,7 +44,7 @@ __global__ void k_lr_epst(const cpx<double>* __restrict__ chi, const double* __r
 // round r of the round-robin schedule over m (even) indices: pair 0 is (r, m-1),
 // pair k > 0 is ((r + k) mod (m-1), (r - k) mod (m-1)); indices >= N are padding
 __global__ void k_jac_params(const cpx<double>* __restrict__ A, int N, int m, int r,
-                             JacRot* __restrict__ rot) {
+                             JacRot* __restrict__ rot, int* __restrict__ pairof) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m / 2) return;
   int p, q;
@@ -83,42 +85,61 @@ __global__ void k_jac_params(const cpx<double>* __restrict__ A, int N, int m, in
     }
   }
   rot[k] = o;
+  if (p < N) pairof[p] = k;
+  if (q < N) pairof[q] = k;
 }
 
-// A <- J^H A on rows p, q and Vt <- J^T Vt (eigenvectors stored as rows)
-__global__ void k_jac_rows(cpx<double>* __restrict__ A, cpx<double>* __restrict__ Vt, int N,
-                           const JacRot* __restrict__ rot) {
+// One round, one workgroup per pair (p, q): rows p and q of A' = J^H A J.  The
+// row rotation needs only rows p and q of A; the column rotation then mixes,
+// inside each of those rows, the two entries of every pair of the round, so the
+// whole update stays within the two rows (held in LDS).  Vt <- J^T Vt (the
+// eigenvectors as rows) needs the row rotation only.
+__global__ void __launch_bounds__(256) k_jac_round(cpx<double>* __restrict__ A,
+                                                   cpx<double>* __restrict__ Vt, int N,
+                                                   const JacRot* __restrict__ rot,
+                                                   const int* __restrict__ pairof) {
+  extern __shared__ cpx<double> rows[];  // [2][N]
+  cpx<double>* bp = rows;
+  cpx<double>* bq = rows + N;
   const JacRot o = rot[blockIdx.x];
-  const int j = blockIdx.y * blockDim.x + threadIdx.x;
-  if (o.skip || j >= N) return;
+  const bool hasq = o.q < N;
   const cpx<double> e = mk(o.er, o.ei), ec = mk(o.er, -o.ei);
-  {
-    const cpx<double> ap = A[(size_t)o.p * N + j], aq = A[(size_t)o.q * N + j];
-    // new p = c ap - s e^{i phi} aq;  new q = s ap + c e^{i phi} aq
-    const cpx<double> eq = cmul(e, aq);
-    A[(size_t)o.p * N + j] = scal(ap, o.c) - scal(eq, o.s);
-    A[(size_t)o.q * N + j] = scal(ap, o.s) + scal(eq, o.c);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const cpx<double> ap = A[(size_t)o.p * N + j];
+    const cpx<double> aq = hasq ? A[(size_t)o.q * N + j] : mk(0.0, 0.0);
+    if (o.skip) {
+      bp[j] = ap;
+      bq[j] = aq;
+    } else {
+      // J^H rows: new p = c ap - s e^{i phi} aq;  new q = s ap + c e^{i phi} aq
+      const cpx<double> eq = cmul(e, aq);
+      bp[j] = scal(ap, o.c) - scal(eq, o.s);
+      bq[j] = scal(ap, o.s) + scal(eq, o.c);
+      // (V J)^T rows: new p = c vp - s e^{-i phi} vq;  new q = s vp + c e^{-i phi} vq
+      const cpx<double> vp = Vt[(size_t)o.p * N + j], vq = Vt[(size_t)o.q * N + j];
+      const cpx<double> ev = cmul(ec, vq);
+      Vt[(size_t)o.p * N + j] = scal(vp, o.c) - scal(ev, o.s);
+      Vt[(size_t)o.q * N + j] = scal(vp, o.s) + scal(ev, o.c);
+    }
   }
-  {
-    const cpx<double> vp = Vt[(size_t)o.p * N + j], vq = Vt[(size_t)o.q * N + j];
-    // (V J)^T: new p = c vp - s e^{-i phi} vq;  new q = s vp + c e^{-i phi} vq
-    const cpx<double> eq = cmul(ec, vq);
-    Vt[(size_t)o.p * N + j] = scal(vp, o.c) - scal(eq, o.s);
-    Vt[(size_t)o.q * N + j] = scal(vp, o.s) + scal(eq, o.c);
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const JacRot w = rot[pairof[j]];
+    cpx<double> np = bp[j], nq = bq[j];
+    if (!w.skip) {
+      // columns: new col p' = c a_p' - s e^{-i phi} a_q';  new col q' = s a_p' + c e^{-i phi} a_q'
+      const cpx<double> wc = mk(w.er, -w.ei);
+      if (j == w.p) {
+        np = scal(bp[w.p], w.c) - scal(cmul(wc, bp[w.q]), w.s);
+        nq = scal(bq[w.p], w.c) - scal(cmul(wc, bq[w.q]), w.s);
+      } else {
+        np = scal(bp[w.p], w.s) + scal(cmul(wc, bp[w.q]), w.c);
+        nq = scal(bq[w.p], w.s) + scal(cmul(wc, bq[w.q]), w.c);
+      }
+    }
+    A[(size_t)o.p * N + j] = np;
+    if (hasq) A[(size_t)o.q * N + j] = nq;
   }
-}
-
-// A <- A J on columns p, q
-__global__ void k_jac_cols(cpx<double>* __restrict__ A, int N, const JacRot* __restrict__ rot) {
-  const JacRot o = rot[blockIdx.x];
-  const int i = blockIdx.y * blockDim.x + threadIdx.x;
-  if (o.skip || i >= N) return;
-  const cpx<double> ec = mk(o.er, -o.ei);
-  const cpx<double> ap = A[(size_t)i * N + o.p], aq = A[(size_t)i * N + o.q];
-  // new p = c ap - s e^{-i phi} aq;  new q = s ap + c e^{-i phi} aq
-  const cpx<double> eq = cmul(ec, aq);
-  A[(size_t)i * N + o.p] = scal(ap, o.c) - scal(eq, o.s);
-  A[(size_t)i * N + o.q] = scal(ap, o.s) + scal(eq, o.c);
 }
 
 // partial sums of |A_ij|^2 off the diagonal and over all entries, fixed order
@@ -228,6 +249,7 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
   auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
   auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
   auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
+  auto* pairof = reinterpret_cast<int*>(take((size_t)N * 4));
   auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
   const unsigned gnn = (unsigned)((nn + 255) / 256);
   {
@@ -241,20 +263,40 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
                        reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
     GW_CHECK_LAUNCH(c, "low-rank preparation");
   }
-  // cyclic Jacobi on epst(0)
+  // cyclic Jacobi on epst(0): one sweep (2 (m - 1) small launches) is captured
+  // once into a graph on a private stream and replayed until converged
   const int nblk = (int)std::min<size_t>(1024, (nn + 255) / 256);
   std::vector<double> hp(2 * (size_t)nblk);
-  const dim3 gp((m / 2 + 127) / 128), gr(m / 2, (N + 255) / 256);
+  const dim3 gp((m / 2 + 127) / 128);
+  struct SweepGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~SweepGraph() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (g) (void)hipGraphDestroy(g);
+      if (cap) (void)hipStreamDestroy(cap);
+    }
+  } sg;
+  GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
+  GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
+  for (int r = 0; r < m - 1; ++r) {
+    hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, sg.cap, A, N, m, r, rot, pairof);
+    hipLaunchKernelGGL(k_jac_round, dim3(m / 2), dim3(256), (size_t)2 * N * 16, sg.cap, A, Vt, N,
+                       rot, pairof);
+  }
+  {
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(sg.cap, &sg.g);
+    if (le != hipSuccess) return hip_fail(c, le, "jacobi sweep capture");
+    if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+  }
+  GW_HIP(c, hipGraphInstantiate(&sg.exec, sg.g, nullptr, nullptr, 0));
   bool done = false;
   for (int sweep = 0; sweep < 40 && !done; ++sweep) {
     {
       ProfScope ps(c, "jacobi_sweep");
-      for (int r = 0; r < m - 1; ++r) {
-        hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, c->stream, A, N, m, r, rot);
-        hipLaunchKernelGGL(k_jac_rows, gr, dim3(256), 0, c->stream, A, Vt, N, rot);
-        hipLaunchKernelGGL(k_jac_cols, gr, dim3(256), 0, c->stream, A, N, rot);
-      }
-      GW_CHECK_LAUNCH(c, "jacobi round");
+      GW_HIP(c, hipGraphLaunch(sg.exec, c->stream));
     }
     hipLaunchKernelGGL(k_lr_norms, dim3(nblk), dim3(256), 0, c->stream, A, N, part);
     GW_CHECK_LAUNCH(c, "k_lr_norms");
@@ -333,7 +375,7 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   if (nb < 1 || nb > neps) return fail(c, GW_EINVAL, "nb must be 1 to neps");
   if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
   if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv aliases chi0");
-  if (neps > 8192 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 8192 or nfreq too large");
+  if (neps > 4096 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 4096 or nfreq too large");
   (void)hipSetDevice(c->device);
   // v > 0 is required for V^1/2: checked on a host copy
   std::vector<double> hv((size_t)neps);
@@ -346,7 +388,7 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up(nn * 16) + 2 * align_up(nub * 16) +
                        align_up(nfreq * nub * 16) + 2 * align_up(nfreq * bb * 16) +
                        align_up((size_t)(m / 2) * 48) + align_up(2 * 1024 * 8) +
-                       align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
+                       2 * align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
   // its own buffers: the small inverse below uses the context workspace
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, bytes);
