@@ -146,21 +146,50 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
       cpx<double> tc[NE], ts[NE];
 #pragma unroll
       for (int k = 0; k < NE; ++k) tc[k] = ts[k] = mk(0.0, 0.0);
+      if (!occ) {
+        // empty n'': COH only.  The NE reciprocals of |d - wt|^2 come from one
+        // hardware reciprocal of their product (prefix products, then back-substitution)
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) {
-        const cpx<double> mr = mrow[s][rg * kRows + r];
-        // conj(M(G)) A is the same for every energy; A/(d - wt) = A conj(d - wt) / |d - wt|^2
-        const cpx<double> B = cmulc(mr, A[r]);
-        const double wx = W[r].x, wy = W[r].y;
+        for (int r = 0; r < kRows; ++r) {
+          const cpx<double> mr = mrow[s][rg * kRows + r];
+          // conj(M(G)) A is the same for every energy; A/(d - wt) = A conj(d - wt) / |d - wt|^2
+          const cpx<double> B = cmulc(mr, A[r]);
+          const double wx = W[r].x, wy = W[r].y, wy2 = wy * wy;
+          double z1[NE], x[NE], pre[NE], inv[NE];
 #pragma unroll
-        for (int k = 0; k < NE; ++k) {
-          const double d = E[k] - ea;
-          const double z1 = d - wx;
-          const double y1 = rcp_nr(fma(z1, z1, wy * wy));
-          // B (z1 + i wy) = B conj(d - wt)
-          const cpx<double> b1 = mk(fma(B.x, z1, -B.y * wy), fma(B.x, wy, B.y * z1));
-          tc[k] = mk(fma(y1, b1.x, tc[k].x), fma(y1, b1.y, tc[k].y));
-          if (occ) {
+          for (int k = 0; k < NE; ++k) {
+            z1[k] = (E[k] - ea) - wx;
+            x[k] = fma(z1[k], z1[k], wy2);
+            pre[k] = k == 0 ? x[0] : pre[k - 1] * x[k];
+          }
+          double rr = rcp_nr(pre[NE - 1]);
+#pragma unroll
+          for (int k = NE - 1; k > 0; --k) {
+            inv[k] = rr * pre[k - 1];
+            rr *= x[k];
+          }
+          inv[0] = rr;
+#pragma unroll
+          for (int k = 0; k < NE; ++k) {
+            // B (z1 + i wy) = B conj(d - wt)
+            const cpx<double> b1 = mk(fma(B.x, z1[k], -B.y * wy), fma(B.x, wy, B.y * z1[k]));
+            tc[k] = mk(fma(inv[k], b1.x, tc[k].x), fma(inv[k], b1.y, tc[k].y));
+          }
+        }
+      } else {
+        // occupied n'': COH and SX, one refined reciprocal per denominator
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const cpx<double> mr = mrow[s][rg * kRows + r];
+          const cpx<double> B = cmulc(mr, A[r]);
+          const double wx = W[r].x, wy = W[r].y;
+#pragma unroll
+          for (int k = 0; k < NE; ++k) {
+            const double d = E[k] - ea;
+            const double z1 = d - wx;
+            const double y1 = rcp_nr(fma(z1, z1, wy * wy));
+            const cpx<double> b1 = mk(fma(B.x, z1, -B.y * wy), fma(B.x, wy, B.y * z1));
+            tc[k] = mk(fma(y1, b1.x, tc[k].x), fma(y1, b1.y, tc[k].y));
             const double z2 = d + wx;
             const double y2 = rcp_nr(fma(z2, z2, wy * wy));
             // B conj(d + wt) = B (z2 - i wy)
