@@ -146,8 +146,36 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
       cpx<double> tc[NE], ts[NE];
 #pragma unroll
       for (int k = 0; k < NE; ++k) tc[k] = ts[k] = mk(0.0, 0.0);
-      if (!occ) {
-        // empty n'': COH only.  The NE reciprocals of |d - wt|^2 come from one
+      if (!occ && NE <= 3) {
+        // empty n'': COH only.  The kRows * NE reciprocals of |d - wt|^2 come from one
+        // hardware reciprocal of their product (prefix products, then back-substitution)
+        double z1[kRows][NE], x[kRows][NE], pre[kRows * NE];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+#pragma unroll
+          for (int k = 0; k < NE; ++k) {
+            z1[r][k] = (E[k] - ea) - W[r].x;
+            x[r][k] = fma(z1[r][k], z1[r][k], W[r].y * W[r].y);
+            const int i = r * NE + k;
+            pre[i] = i == 0 ? x[0][0] : pre[i - 1] * x[r][k];
+          }
+        double rr = rcp_nr(pre[kRows * NE - 1]);
+#pragma unroll
+        for (int r = kRows - 1; r >= 0; --r)
+#pragma unroll
+          for (int k = NE - 1; k >= 0; --k) {
+            const int i = r * NE + k;
+            const double inv = i == 0 ? rr : rr * pre[i - 1];
+            rr *= x[r][k];
+            const cpx<double> mr = mrow[s][rg * kRows + r];
+            // conj(M(G)) A conj(d - wt) / |d - wt|^2 = A conj(M) / (d - wt)
+            const cpx<double> B = cmulc(mr, A[r]);
+            const double wy = W[r].y;
+            const cpx<double> b1 = mk(fma(B.x, z1[r][k], -B.y * wy), fma(B.x, wy, B.y * z1[r][k]));
+            tc[k] = mk(fma(inv, b1.x, tc[k].x), fma(inv, b1.y, tc[k].y));
+          }
+      } else if (!occ) {
+        // empty n'', four energies: the NE reciprocals of |d - wt|^2 come from one
         // hardware reciprocal of their product (prefix products, then back-substitution)
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
