@@ -2,8 +2,8 @@
 //
 // A small network predicts chi0_full - chi0_trunc for one (q, omega = 0) matrix
 // from per-(G <= G') features; chi0_trunc plus the Hermitised prediction is the
-// corrected matrix, and the full band sum remains the fallback and the judge
-// of its error.  The nearest idea in the paper is the static remainder used for
+// corrected matrix, and the full band sum remains the fallback and the
+// reference for its error.  The nearest idea in the paper is the static remainder used for
 // the Coulomb-hole sum over empty states (Computational Details).
 //
 //   features  |q+G|, |q+G'|, (q+G).(q+G')/10, Re chi_t/s, Im chi_t/s, 10 gap, 2 emax
