@@ -35,6 +35,8 @@ head_dipole              | k.p limit of head_overlap for a spin-dependent
 epsinv_lowrank           | exact inverse at nb = N; rank-one chi0 exact at nb = 1
                          | (Sherman-Morrison); at omega = 0 the error is the
                          | discarded eigenvalues' 1/lambda - 1 (closed form)
+epsinv_projected         | equals epsinv_lowrank (chi0 projected after the sum)
+                         | for the same basis; exact when chi0's range is nb-dim
 screened_w               | Hermitian for the symmetric form of eps (closed form)
 sigma_sx_static          | bare exchange at eps^-1 = I (closed form), real and
                          | between the bare exchange and 0 for chi0 <= 0
@@ -59,7 +61,7 @@ __all__ = [
     "mtxel_bruteforce", "chi0_weight", "chi0", "chi0_weight_real", "chi0_real", "epsilon",
     "epsilon_inverse",
     "head_overlap", "head_dipole", "screened_w", "sigma_sx_static", "GPP_DROP_TOL", "gpp_modes",
-    "epsinv_gpp", "sigma_gpp", "bse_kernel", "epsinv_lowrank", "chi0_from_system", "rel_f", "alias_free",
+    "epsinv_gpp", "sigma_gpp", "bse_kernel", "epsinv_lowrank", "epsinv_projected", "chi0_from_system", "rel_f", "alias_free",
 ]
 
 
@@ -283,6 +285,27 @@ def epsinv_lowrank(chi0_all, vcoul, nb):
         et = np.eye(n) + u @ (np.linalg.inv(eb) - np.eye(nb)) @ u.conj().T
         out.append(sv[:, None] * et / sv[None, :])
     return np.stack(out), lam
+
+
+def epsinv_projected(mtxel, ev, ec, omega, vcoul, u, prefactor=1.0):
+    """The same reduced-basis eps^-1 with chi0 built in the basis: with
+    M_B = M diag(sqrt v) U, chi_B(w) = sum_p w_p(w) conj(M_B,p) M_B,p^T equals
+    U^H V^1/2 chi0(w) V^1/2 U, and
+      epst^-1(w) ~= I + U ((I - chi_B(w))^-1 - I) U^H,  eps^-1 = V^1/2 epst^-1 V^-1/2.
+    u: [N][nb] orthonormal columns.  Returns [nfreq][N][N]."""
+    m = np.asarray(mtxel, dtype=np.complex128)
+    nv, nc, n = m.shape
+    v = np.asarray(vcoul, dtype=np.float64)
+    sv = np.sqrt(v)
+    u = np.asarray(u, dtype=np.complex128)
+    nb = u.shape[1]
+    mb = ((m.reshape(nv * nc, n) * sv[None, :]) @ u).reshape(nv, nc, nb)
+    chib = chi0(mb, ev, ec, omega, prefactor)
+    out = []
+    for cb in chib:
+        et = np.eye(n) + u @ (np.linalg.inv(np.eye(nb) - cb) - np.eye(nb)) @ u.conj().T
+        out.append(sv[:, None] * et / sv[None, :])
+    return np.stack(out)
 
 
 def screened_w(epsinv_all, vcoul):

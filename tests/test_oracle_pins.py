@@ -478,3 +478,30 @@ def test_lowrank_static_error_is_the_discarded_spectrum():
     want = np.max(np.abs(1.0 / lam[:n - nb] - 1.0))
     assert abs(np.linalg.norm(d, 2) - want) < 1e-10 * want
     assert np.all(lam >= 1.0 - 1e-12)
+
+
+def test_projected_chi0_route_equals_the_projected_inverse():
+    """Building chi0 in the basis (M projected first) gives the same reduced-basis
+    eps^-1 as projecting the full chi0; when every M_p lies in an nb-dimensional
+    space the reduced basis is exact."""
+    rng = np.random.default_rng(8)
+    nv, nc, n, nb = 3, 7, 36, 9
+    m = (rng.standard_normal((nv, nc, n)) + 1j * rng.standard_normal((nv, nc, n))) / 3
+    ev = np.sort(rng.uniform(-0.5, -0.05, nv))
+    ec = np.sort(rng.uniform(0.05, 0.9, nc))
+    om = np.array([0.0, 0.3, 1.1])
+    v = rng.uniform(0.2, 3.0, n)
+    chi = oracle.chi0(m, ev, ec, om)
+    lr, _ = oracle.epsinv_lowrank(chi, v, nb)
+    sv = np.sqrt(v)
+    u = np.linalg.eigh(np.eye(n) - sv[:, None] * chi[0] * sv[None, :])[1][:, n - nb:]
+    pr = oracle.epsinv_projected(m, ev, ec, om, v, u)
+    assert np.abs(pr - lr).max() < 1e-12 * np.abs(lr).max()
+    # M_p = coefficients x a fixed nb-row basis / sqrt(v): chi0(w) has an nb-dim range
+    basis = (rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))) / sv[None, :]
+    m2 = (rng.standard_normal((nv, nc, nb)) + 1j * rng.standard_normal((nv, nc, nb))) @ basis / 4
+    chi2 = oracle.chi0(m2, ev, ec, om)
+    u2 = np.linalg.eigh(np.eye(n) - sv[:, None] * chi2[0] * sv[None, :])[1][:, n - nb:]
+    ex = oracle.epsilon_inverse(chi2, v)
+    pr2 = oracle.epsinv_projected(m2, ev, ec, om, v, u2)
+    assert np.abs(pr2 - ex).max() < 1e-10 * np.abs(ex).max()
