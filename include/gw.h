@@ -247,6 +247,34 @@ gw_status gw_epsinv_lowrank(gw_ctx* ctx, int neps, int nfreq, const double* chi0
                             const double* vcoul, int nb, double* epsinv, double* eigenvalues);
 
 /*
+ * The reduced basis in three steps, for chi0 built directly in it (the use the
+ * scheme is for: P nb^2 instead of P N^2 work and nb^2 memory per frequency):
+ *
+ * gw_lowrank_basis -- U (device out complex double[neps][nb], columns the
+ *   eigenvectors of epst(0) = I - V^1/2 chi0(0) V^1/2 with the nb largest
+ *   eigenvalues, descending) from the static chi0 (device complex double
+ *   [neps][neps], Hermitian) by the Jacobi method of gw_epsinv_lowrank;
+ *   eigenvalues (device out double[neps], ascending) or NULL.  Allocates its own
+ *   buffers and synchronises the context stream.  GW_EINVAL for nb outside
+ *   1..neps, neps > 4096, NULL arrays, vcoul <= 0, non-finite input.
+ * gw_mtxel_project -- out[p][b] = sum_G M[p][G] sqrt(v(G)) U[G][b] (device out
+ *   complex double[npairs][nb]) for matrix elements of dtype (device
+ *   [npairs][neps]); gw_chi0_accumulate on it with neps := nb gives
+ *   chi_B(w) = U^H V^1/2 chi0(w) V^1/2 U.  GW_EINVAL for bad sizes or aliasing.
+ * gw_epsinv_from_basis -- eps^-1(w) from chi_B (device complex double
+ *   [nfreq][nb][nb]): epst^-1 ~= I + U ((I - chi_B)^-1 - I) U^H, eps^-1 =
+ *   V^1/2 epst^-1 V^-1/2 (device out complex double[nfreq][neps][neps]).
+ *   Allocates its own buffers and synchronises.  GW_EINVAL for bad sizes, NULL
+ *   arrays, aliasing, vcoul <= 0; GW_ESINGULAR from the small inverses.
+ */
+gw_status gw_lowrank_basis(gw_ctx* ctx, int neps, const double* chi0_static,
+                           const double* vcoul, int nb, double* basis, double* eigenvalues);
+gw_status gw_mtxel_project(gw_ctx* ctx, int npairs, int neps, const void* mtxel, gw_dtype dtype,
+                           const double* vcoul, int nb, const double* basis, double* out);
+gw_status gw_epsinv_from_basis(gw_ctx* ctx, int neps, int nb, int nfreq, const double* chi_b,
+                               const double* vcoul, const double* basis, double* epsinv);
+
+/*
  * gw_screened_w -- W_f[G][G'] = epsinv_f[G][G'] v(q+G') (Sec. II).
  *   epsinv (device) complex double[nfreq][neps][neps]; vcoul (device) double[neps];
  *   w      (device) out complex double[nfreq][neps][neps] (may be epsinv: in place).

@@ -30,6 +30,7 @@ EXPORTED = [
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
     "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits", "gw_epsinv_lowrank",
+    "gw_lowrank_basis", "gw_mtxel_project", "gw_epsinv_from_basis",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -73,6 +74,9 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_lowrank_basis": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp]),
+    "gw_mtxel_project": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp]),
+    "gw_epsinv_from_basis": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "gw_epsinv_lowrank": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "gw_little_group": (_i, [_i, _vp, _vp, _vp, _vp]),
     "gw_kgrid_orbits": (_i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -411,6 +415,33 @@ def gw_epsinv_lowrank(ctx, neps, nfreq, chi0, vcoul, nb, epsinv, eigenvalues=Non
     ctx.sync_stream()
     s = _lib.gw_epsinv_lowrank(ctx.handle, int(neps), int(nfreq), _ptr(chi0), _ptr(vcoul), int(nb),
                                _ptr(epsinv), _ptr(eigenvalues))
+    return _check(ctx, s)
+
+
+def gw_lowrank_basis(ctx, neps, chi0_static, vcoul, nb, basis, eigenvalues=None):
+    """U [neps][nb]: the leading eigenvectors of epst(0) (see include/gw.h)."""
+    ctx.sync_stream()
+    s = _lib.gw_lowrank_basis(ctx.handle, int(neps), _ptr(chi0_static), _ptr(vcoul), int(nb),
+                              _ptr(basis), _ptr(eigenvalues))
+    return _check(ctx, s)
+
+
+def gw_mtxel_project(ctx, mtxel, vcoul, basis, out):
+    """out [npairs][nb] = M diag(sqrt v) U (see include/gw.h)."""
+    neps = mtxel.shape[-1]
+    npairs = mtxel.numel() // neps
+    ctx.sync_stream()
+    s = _lib.gw_mtxel_project(ctx.handle, npairs, neps, _ptr(mtxel), _dtype_code(mtxel),
+                              _ptr(vcoul), basis.shape[1], _ptr(basis), _ptr(out))
+    return _check(ctx, s)
+
+
+def gw_epsinv_from_basis(ctx, chi_b, vcoul, basis, epsinv):
+    """eps^-1 from the projected chi_B [nfreq][nb][nb] (see include/gw.h)."""
+    neps, nb = basis.shape
+    ctx.sync_stream()
+    s = _lib.gw_epsinv_from_basis(ctx.handle, int(neps), int(nb), chi_b.shape[0], _ptr(chi_b),
+                                  _ptr(vcoul), _ptr(basis), _ptr(epsinv))
     return _check(ctx, s)
 
 

@@ -227,41 +227,41 @@ __global__ void k_lr_unscale(cpx<double>* __restrict__ out, const double* __rest
   *y = scal(*y, sqrt(v[i]) / sqrt(v[j]));
 }
 
-static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
-                             const double* vcoul, int nb, double* epsinv, double* lam,
-                             char* base) {
-  const size_t nn = (size_t)N * N, nub = (size_t)N * nb, bb = (size_t)nb * nb;
+// X[p][g] = M[p][g] sqrt(v[g]), widened to double
+template <typename Tin>
+__global__ void k_proj_prep(const cpx<Tin>* __restrict__ m, size_t rows, int N,
+                            const double* __restrict__ v, cpx<double>* __restrict__ x) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * (size_t)N) return;
+  const cpx<Tin> a = m[e];
+  const double s = sqrt(v[e % N]);
+  x[e] = mk(s * (double)a.x, s * (double)a.y);
+}
+
+// Uh[r][g] = conj(U[g][r])
+__global__ void k_lr_conjt(const cpx<double>* __restrict__ U, int N, int nb,
+                           cpx<double>* __restrict__ Uh) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)N * nb) return;
+  const int g = (int)(e / nb), r = (int)(e % nb);
+  const cpx<double> x = U[e];
+  Uh[(size_t)r * N + g] = mk(x.x, -x.y);
+}
+
+// Eigenvectors of the Hermitian A (destroyed) by cyclic Jacobi; U[g][r] and
+// Uh[r][g] receive the eigenvectors of the nb largest eigenvalues in descending
+// order, lam (may be NULL) all eigenvalues ascending.
+static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<double>* Vt,
+                              JacRot* rot, int* pairof, double* part, int* rank,
+                              cpx<double>* U, cpx<double>* Uh, double* lam) {
+  const size_t nn = (size_t)N * N;
   const int m = N + (N & 1);
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    char* p = base + off;
-    off += align_up(bytes);
-    return p;
-  };
-  auto* E = reinterpret_cast<cpx<double>*>(take(nfreq * nn * 16));
-  auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* U = reinterpret_cast<cpx<double>*>(take(nub * 16));
-  auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
-  auto* Y = reinterpret_cast<cpx<double>*>(take(nfreq * nub * 16));
-  auto* B = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
-  auto* Bi = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
-  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
-  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
-  auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
-  auto* pairof = reinterpret_cast<int*>(take((size_t)N * 4));
-  auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
-  const unsigned gnn = (unsigned)((nn + 255) / 256);
   {
     ProfScope ps(c, "lowrank_prep");
-    hipLaunchKernelGGL(k_lr_epst, dim3(gnn, nfreq), dim3(256), 0, c->stream,
-                       reinterpret_cast<const cpx<double>*>(chi0), vcoul, N, E);
-    GW_HIP(c, hipMemcpyAsync(A, E, nn * 16, hipMemcpyDeviceToDevice, c->stream));
-    // Vt = I; also the identity that the final products accumulate onto, and ones
-    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, 1), dim3(256), 0, c->stream, Vt, N, ones, nb);
-    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, nfreq), dim3(256), 0, c->stream,
-                       reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
-    GW_CHECK_LAUNCH(c, "low-rank preparation");
+    double* dummy_ones = part;  // k_lr_fill's ones output is unused here (nb = 0)
+    hipLaunchKernelGGL(k_lr_fill, dim3((unsigned)((nn + 255) / 256), 1), dim3(256), 0, c->stream,
+                       Vt, N, dummy_ones, 0);
+    GW_CHECK_LAUNCH(c, "k_lr_fill");
   }
   // cyclic Jacobi on epst(0): one sweep (2 (m - 1) small launches) is captured
   // once into a graph on a private stream and replayed until converged
@@ -318,26 +318,21 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
     hipLaunchKernelGGL(k_lr_select, dim3(N), dim3(256), 0, c->stream, Vt, rank, N, nb, U, Uh);
     GW_CHECK_LAUNCH(c, "low-rank basis");
   }
+  return GW_OK;
+}
+
+// Given chi_B[f] (nb x nb, the projected V^1/2 chi0 V^1/2) and the basis U (N x nb)
+// with Uh = U^H: epsinv[f] (pre-filled with I) += U ((I - chi_B)^-1 - I) U^H, then
+// eps^-1 = V^1/2 epst^-1 V^-1/2.  chiB is kept; Bi, Y are scratch.
+static gw_status lowrank_apply(gw_ctx* c, int N, int nb, int nfreq, cpx<double>* chiB,
+                               cpx<double>* Bi, const double* ones, const cpx<double>* U,
+                               const cpx<double>* Uh, cpx<double>* Y, const double* vcoul,
+                               double* epsinv) {
+  const size_t nn = (size_t)N * N, nub = (size_t)N * nb, bb = (size_t)nb * nb;
   const long long snn = (long long)nn, snb = (long long)nub, sbb = (long long)bb;
-  // Y_f = E_f U;  B_f = U^H Y_f
-  gw_status st = zgemm_nn(c, N, nb, N, 1.0, reinterpret_cast<const double*>(E), 0, N, snn,
-                          reinterpret_cast<const double*>(U), 0, nb, 0,
-                          reinterpret_cast<double*>(Y), 0, nb, snb, nfreq, nfreq * nn, nub,
-                          nfreq * nub, 0.0);
-  if (st != GW_OK) return st;
-  st = zgemm_nn(c, nb, nb, N, 1.0, reinterpret_cast<const double*>(Uh), 0, N, 0,
-                reinterpret_cast<const double*>(Y), 0, nb, snb, reinterpret_cast<double*>(B), 0,
-                nb, sbb, nfreq, nub, nfreq * nub, nfreq * bb, 0.0);
-  if (st != GW_OK) return st;
-  // B_f^-1 by the Hermitian inverse of I - 1 * (I - B_f)
-  {
-    ProfScope ps(c, "lowrank_small");
-    hipLaunchKernelGGL(k_lr_shift, dim3((unsigned)((bb + 255) / 256), nfreq), dim3(256), 0,
-                       c->stream, B, nb, -1.0, 1.0);
-    GW_CHECK_LAUNCH(c, "k_lr_shift");
-  }
-  st = epsinv_run(c, nb, nfreq, reinterpret_cast<const double*>(B), ones,
-                  reinterpret_cast<double*>(Bi));
+  const unsigned gnn = (unsigned)((nn + 255) / 256);
+  gw_status st = epsinv_run(c, nb, nfreq, reinterpret_cast<const double*>(chiB), ones,
+                            reinterpret_cast<double*>(Bi));
   if (st != GW_OK) return st;
   {
     ProfScope ps(c, "lowrank_small");
@@ -359,6 +354,64 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
                      reinterpret_cast<cpx<double>*>(epsinv), vcoul, N);
   GW_CHECK_LAUNCH(c, "k_lr_unscale");
   return GW_OK;
+}
+
+static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
+                             const double* vcoul, int nb, double* epsinv, double* lam,
+                             char* base) {
+  const size_t nn = (size_t)N * N, nub = (size_t)N * nb, bb = (size_t)nb * nb;
+  const int m = N + (N & 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += align_up(bytes);
+    return p;
+  };
+  auto* E = reinterpret_cast<cpx<double>*>(take(nfreq * nn * 16));
+  auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* U = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* Y = reinterpret_cast<cpx<double>*>(take(nfreq * nub * 16));
+  auto* B = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* Bi = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
+  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
+  auto* pairof = reinterpret_cast<int*>(take((size_t)N * 4));
+  auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
+  const unsigned gnn = (unsigned)((nn + 255) / 256);
+  {
+    ProfScope ps(c, "lowrank_prep");
+    hipLaunchKernelGGL(k_lr_epst, dim3(gnn, nfreq), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(chi0), vcoul, N, E);
+    GW_HIP(c, hipMemcpyAsync(A, E, nn * 16, hipMemcpyDeviceToDevice, c->stream));
+    // Vt = I; also the identity that the final products accumulate onto, and ones
+    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, 1), dim3(256), 0, c->stream, Vt, N, ones, nb);
+    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, nfreq), dim3(256), 0, c->stream,
+                       reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
+    GW_CHECK_LAUNCH(c, "low-rank preparation");
+  }
+  gw_status st = jacobi_basis(c, N, nb, A, Vt, rot, pairof, part, rank, U, Uh, lam);
+  if (st != GW_OK) return st;
+  const long long snn = (long long)nn, snb = (long long)nub, sbb = (long long)bb;
+  // Y_f = E_f U;  B_f = U^H Y_f
+  st = zgemm_nn(c, N, nb, N, 1.0, reinterpret_cast<const double*>(E), 0, N, snn,
+                reinterpret_cast<const double*>(U), 0, nb, 0, reinterpret_cast<double*>(Y), 0, nb,
+                snb, nfreq, nfreq * nn, nub, nfreq * nub, 0.0);
+  if (st != GW_OK) return st;
+  st = zgemm_nn(c, nb, nb, N, 1.0, reinterpret_cast<const double*>(Uh), 0, N, 0,
+                reinterpret_cast<const double*>(Y), 0, nb, snb, reinterpret_cast<double*>(B), 0,
+                nb, sbb, nfreq, nub, nfreq * nub, nfreq * bb, 0.0);
+  if (st != GW_OK) return st;
+  // chi_B = I - B_f, then the reduced-basis inverse
+  {
+    ProfScope ps(c, "lowrank_small");
+    hipLaunchKernelGGL(k_lr_shift, dim3((unsigned)((bb + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, B, nb, -1.0, 1.0);
+    GW_CHECK_LAUNCH(c, "k_lr_shift");
+  }
+  return lowrank_apply(c, N, nb, nfreq, B, Bi, ones, U, Uh, Y, vcoul, epsinv);
 }
 
 }  // namespace gw
@@ -396,6 +449,147 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   gw_status st = lowrank_run(c, neps, nfreq, chi0, vcoul, nb, epsinv, eigenvalues,
                              static_cast<char*>(base));
   hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(base);
+  if (st != GW_OK) return st;
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamSynchronize");
+  return GW_OK;
+}
+
+static gw_status check_v_positive(gw_ctx* c, const double* vcoul, int n) {
+  std::vector<double> hv((size_t)n);
+  GW_HIP(c, hipMemcpyAsync(hv.data(), vcoul, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  for (double x : hv)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(c, GW_EINVAL, "vcoul must be positive");
+  return GW_OK;
+}
+
+extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_static,
+                                      const double* vcoul, int nb, double* basis,
+                                      double* eigenvalues) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 1 || nb < 1 || nb > neps) return fail(c, GW_EINVAL, "need 1 <= nb <= neps");
+  if (neps > 4096) return fail(c, GW_EINVAL, "neps above 4096");
+  if (!chi0_static || !vcoul || !basis) return fail(c, GW_EINVAL, "NULL array argument");
+  (void)hipSetDevice(c->device);
+  gw_status st = check_v_positive(c, vcoul, neps);
+  if (st != GW_OK) return st;
+  const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb;
+  const int m = neps + (neps & 1);
+  const size_t bytes = 2 * align_up(nn * 16) + align_up(nub * 16) + align_up((size_t)(m / 2) * 48) +
+                       align_up(2 * 1024 * 8) + 2 * align_up((size_t)neps * 4) + 4096;
+  char* base = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
+    return fail(c, GW_ENOMEM, "basis buffers of %zu bytes", bytes);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
+  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* rank = reinterpret_cast<int*>(take((size_t)neps * 4));
+  auto* pairof = reinterpret_cast<int*>(take((size_t)neps * 4));
+  {
+    ProfScope ps(c, "lowrank_prep");
+    hipLaunchKernelGGL(k_lr_epst, dim3((unsigned)((nn + 255) / 256), 1), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(chi0_static), vcoul, neps, A);
+    st = hipGetLastError() == hipSuccess ? GW_OK : GW_EDEVICE;
+  }
+  if (st == GW_OK)
+    st = jacobi_basis(c, neps, nb, A, Vt, rot, pairof, part, rank,
+                      reinterpret_cast<cpx<double>*>(basis), Uh, eigenvalues);
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(base);
+  if (st != GW_OK) return st == GW_EDEVICE ? fail(c, st, "k_lr_epst launch") : st;
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamSynchronize");
+  return GW_OK;
+}
+
+extern "C" gw_status gw_mtxel_project(gw_ctx* c, int npairs, int neps, const void* mtxel,
+                                      gw_dtype dtype, const double* vcoul, int nb,
+                                      const double* basis, double* out) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (npairs < 0 || neps < 1 || nb < 1 || nb > neps) return fail(c, GW_EINVAL, "bad sizes");
+  if (dtype != GW_C128 && dtype != GW_C64) return fail(c, GW_EINVAL, "unknown dtype");
+  if (npairs == 0) return GW_OK;
+  if (!mtxel || !vcoul || !basis || !out) return fail(c, GW_EINVAL, "NULL array argument");
+  if (out == mtxel || out == basis) return fail(c, GW_EINVAL, "out aliases an input");
+  (void)hipSetDevice(c->device);
+  const size_t nx = (size_t)npairs * neps;
+  gw_status st = ws_begin(c, align_up(nx * 16));
+  if (st != GW_OK) return st;
+  auto* X = static_cast<cpx<double>*>(ws_take(c, nx * 16));
+  {
+    ProfScope ps(c, "mtxel_project_prep");
+    if (dtype == GW_C128)
+      hipLaunchKernelGGL(k_proj_prep<double>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0,
+                         c->stream, static_cast<const cpx<double>*>(mtxel), (size_t)npairs, neps,
+                         vcoul, X);
+    else
+      hipLaunchKernelGGL(k_proj_prep<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0,
+                         c->stream, static_cast<const cpx<float>*>(mtxel), (size_t)npairs, neps,
+                         vcoul, X);
+    GW_CHECK_LAUNCH(c, "k_proj_prep");
+  }
+  // out = X U  (npairs x nb)
+  return zgemm_nn(c, npairs, nb, neps, 1.0, reinterpret_cast<const double*>(X), 0, neps, 0, basis,
+                  0, nb, 0, out, 0, nb, 0, 1, nx, (size_t)neps * nb, (size_t)npairs * nb, 0.0);
+}
+
+extern "C" gw_status gw_epsinv_from_basis(gw_ctx* c, int neps, int nb, int nfreq,
+                                          const double* chi_b, const double* vcoul,
+                                          const double* basis, double* epsinv) {
+  if (!c) return GW_EINVAL;
+  c->err.clear();
+  if (neps < 1 || nb < 1 || nb > neps || nfreq < 0) return fail(c, GW_EINVAL, "bad sizes");
+  if (nfreq == 0) return GW_OK;
+  if (!chi_b || !vcoul || !basis || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
+  if (epsinv == chi_b || epsinv == basis) return fail(c, GW_EINVAL, "epsinv aliases an input");
+  if (neps > 46340 || nfreq > 65535) return fail(c, GW_EINVAL, "neps or nfreq too large");
+  (void)hipSetDevice(c->device);
+  gw_status st = check_v_positive(c, vcoul, neps);
+  if (st != GW_OK) return st;
+  const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb, bb = (size_t)nb * nb;
+  // own buffers: the small inverse uses the context workspace
+  const size_t bytes = align_up(nub * 16) + align_up(nfreq * bb * 16) * 2 +
+                       align_up(nfreq * nub * 16) + align_up((size_t)nb * 8) + 4096;
+  char* base = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
+    return fail(c, GW_ENOMEM, "buffers of %zu bytes", bytes);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
+  auto* chiB = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* Bi = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
+  auto* Y = reinterpret_cast<cpx<double>*>(take(nfreq * nub * 16));
+  auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
+  st = GW_OK;
+  {
+    ProfScope ps(c, "lowrank_prep");
+    hipLaunchKernelGGL(k_lr_conjt, dim3((unsigned)((nub + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(basis), neps, nb, Uh);
+    hipLaunchKernelGGL(k_lr_fill, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
+                       c->stream, reinterpret_cast<cpx<double>*>(epsinv), neps, ones, nb);
+    if (hipMemcpyAsync(chiB, chi_b, nfreq * bb * 16, hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess ||
+        hipGetLastError() != hipSuccess)
+      st = fail(c, GW_EDEVICE, "low-rank preparation");
+  }
+  if (st == GW_OK)
+    st = lowrank_apply(c, neps, nb, nfreq, chiB, Bi, ones,
+                       reinterpret_cast<const cpx<double>*>(basis), Uh, Y, vcoul, epsinv);
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
   (void)hipFree(base);
   if (st != GW_OK) return st;
   if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamSynchronize");
