@@ -501,10 +501,11 @@ def bench_bse(ctx, P, d, epsinv0, steps, nc=64):
                     "M_vv^T); the time includes widening, transposes and the reordering"}
 
 
-def bench_lowrank(ctx, P, d, chi, epsinv_full, reps=2):
+def bench_lowrank(ctx, P, d, chi, epsinv_full, mtxel, reps=2):
     """eps^-1 in a basis of N_eps/10 static eigenvectors (gw_epsinv_lowrank) for the
     workload's nine frequencies, against the full inverse of the timed path: time
-    and the relative Frobenius difference per frequency."""
+    and the relative Frobenius difference per frequency; then the same with chi0
+    built in the basis (each step timed once)."""
     import torch
     nf, neps, _ = chi.shape
     nb = max(1, neps // 10)
@@ -528,7 +529,34 @@ def bench_lowrank(ctx, P, d, chi, epsinv_full, reps=2):
     rel = (torch.linalg.vector_norm(diff, dim=1) /
            torch.linalg.vector_norm(epsinv_full.reshape(nf, -1), dim=1)).cpu().numpy()
     lam_h = lam.cpu().numpy()
-    return {"ms": ms, "nb": nb, "jacobi_ms": jac[1] / reps, "jacobi_sweeps": jac[0] / reps,
+    # chi0 built in the basis: basis from the static chi0, projected matrix
+    # elements, chi_B at every frequency, eps^-1 from chi_B
+    import paper_2206_00808_amd as P2
+    nv, nc = d["nv"], d["nc"]
+    u = torch.empty((neps, nb), dtype=torch.complex128, device="cuda")
+    mb = torch.empty((nv, nc, nb), dtype=torch.complex128, device="cuda")
+    chib = torch.empty((nf, nb, nb), dtype=torch.complex128, device="cuda")
+    proj_out = torch.empty_like(chi)
+    steps_ms = {}
+    ev = torch.cuda.Event(enable_timing=True)
+    ev2 = torch.cuda.Event(enable_timing=True)
+    for name, fn in (
+            ("basis", lambda: P2.gw_lowrank_basis(ctx, neps, chi[0], d["vcoul"], nb, u)),
+            ("project", lambda: P2.gw_mtxel_project(ctx, mtxel, d["vcoul"], u, mb)),
+            ("chi0_in_basis", lambda: (chib.zero_(), P2.gw_chi0_accumulate(
+                ctx, nv, nc, nb, mb, d["ev"], d["ec"], d["omega"], 1.0, P2.GW_PREC_FP64, chib))),
+            ("epsinv_from_basis", lambda: P2.gw_epsinv_from_basis(ctx, chib, d["vcoul"], u,
+                                                                   proj_out))):
+        torch.cuda.synchronize()
+        ev.record()
+        fn()
+        ev2.record()
+        torch.cuda.synchronize()
+        steps_ms[name] = ev.elapsed_time(ev2)
+    pdiff = (proj_out - out).reshape(nf, -1)
+    prel = float((torch.linalg.vector_norm(pdiff) / torch.linalg.vector_norm(out)).item())
+    return {"ms": ms, "nb": nb, "chi0_in_basis_route_ms": steps_ms,
+            "chi0_in_basis_vs_projected_epst_rel": prel, "jacobi_ms": jac[1] / reps, "jacobi_sweeps": jac[0] / reps,
             "rel_diff_vs_full_inverse": [float(x) for x in rel],
             "kept_eigenvalue_min": float(lam_h[neps - nb]),
             "discarded_eigenvalue_max": float(lam_h[neps - nb - 1]),
@@ -720,7 +748,7 @@ def main():
         result["gpp"] = bench_gpp(ctx, P, sysd, d64, epsinv64[0], args.steps)
         result["symmetrize"] = bench_symmetrize(ctx, P, sysd, o64["chi0"], args.steps)
         result["bse_kernel"] = bench_bse(ctx, P, d64, epsinv64[0], args.steps)
-        result["lowrank"] = bench_lowrank(ctx, P, d64, o64["chi0"], epsinv64)
+        result["lowrank"] = bench_lowrank(ctx, P, d64, o64["chi0"], epsinv64, o64["mtxel"])
 
     # ---------------- mixed path
     if not args.no_mixed:
