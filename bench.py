@@ -561,7 +561,7 @@ def bench_lowrank(ctx, P, d, chi, epsinv_full, mtxel, reps=2):
             "kept_eigenvalue_min": float(lam_h[neps - nb]),
             "discarded_eigenvalue_max": float(lam_h[neps - nb - 1]),
             "note": "wall time of the call (it synchronises); the Jacobi sweeps dominate, "
-                    "each N_eps - 1 rounds of two small kernels replayed from a graph"}
+                    "each N_eps - 1 rounds of one kernel replayed from a graph"}
 
 
 def _one_blas_thread():

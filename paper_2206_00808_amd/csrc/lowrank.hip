@@ -142,6 +142,104 @@ __global__ void __launch_bounds__(256) k_jac_round(cpx<double>* __restrict__ A,
   }
 }
 
+// The whole round in one kernel, reading A_in and writing A_out (the two buffers
+// alternate between rounds): every workgroup first forms the rotation of every
+// pair of the round from A_in into LDS (so no separate parameter kernel and no
+// grid-wide wait), then rewrites its own pair's two rows as k_jac_round does.
+__global__ void __launch_bounds__(256) k_jac_round_pp(const cpx<double>* __restrict__ Ain,
+                                                      cpx<double>* __restrict__ Aout,
+                                                      cpx<double>* __restrict__ Vt, int N, int m,
+                                                      int r) {
+  extern __shared__ char smem[];
+  JacRot* rot = reinterpret_cast<JacRot*>(smem);
+  int* pairof = reinterpret_cast<int*>(rot + m / 2);
+  cpx<double>* bp = reinterpret_cast<cpx<double>*>(pairof + ((N + 3) & ~3));
+  cpx<double>* bq = bp + N;
+  for (int k = threadIdx.x; k < m / 2; k += blockDim.x) {
+    int p, q;
+    if (k == 0) {
+      p = r;
+      q = m - 1;
+    } else {
+      p = (r + k) % (m - 1);
+      q = (r - k + (m - 1)) % (m - 1);
+    }
+    if (p > q) {
+      const int t = p;
+      p = q;
+      q = t;
+    }
+    JacRot o;
+    o.p = p;
+    o.q = q;
+    o.pad = 0;
+    o.skip = 1;
+    o.c = 1.0;
+    o.s = 0.0;
+    o.er = 1.0;
+    o.ei = 0.0;
+    if (q < N) {
+      const cpx<double> b = Ain[(size_t)p * N + q];
+      const double ab = hypot(b.x, b.y);
+      if (ab > 0.0) {
+        const double a = Ain[(size_t)p * N + p].x, d = Ain[(size_t)q * N + q].x;
+        const double tau = (d - a) / (2.0 * ab);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        o.c = 1.0 / sqrt(1.0 + t * t);
+        o.s = t * o.c;
+        o.er = b.x / ab;
+        o.ei = b.y / ab;
+        o.skip = 0;
+      }
+    }
+    rot[k] = o;
+    if (p < N) pairof[p] = k;
+    if (q < N) pairof[q] = k;
+  }
+  __syncthreads();
+  const JacRot o = rot[blockIdx.x];
+  const bool hasq = o.q < N;
+  const cpx<double> e = mk(o.er, o.ei), ec = mk(o.er, -o.ei);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const cpx<double> ap = Ain[(size_t)o.p * N + j];
+    const cpx<double> aq = hasq ? Ain[(size_t)o.q * N + j] : mk(0.0, 0.0);
+    if (o.skip) {
+      bp[j] = ap;
+      bq[j] = aq;
+    } else {
+      const cpx<double> eq = cmul(e, aq);
+      bp[j] = scal(ap, o.c) - scal(eq, o.s);
+      bq[j] = scal(ap, o.s) + scal(eq, o.c);
+      const cpx<double> vp = Vt[(size_t)o.p * N + j], vq = Vt[(size_t)o.q * N + j];
+      const cpx<double> ev = cmul(ec, vq);
+      Vt[(size_t)o.p * N + j] = scal(vp, o.c) - scal(ev, o.s);
+      Vt[(size_t)o.q * N + j] = scal(vp, o.s) + scal(ev, o.c);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const JacRot w = rot[pairof[j]];
+    cpx<double> np = bp[j], nq = bq[j];
+    if (!w.skip) {
+      const cpx<double> wc = mk(w.er, -w.ei);
+      if (j == w.p) {
+        np = scal(bp[w.p], w.c) - scal(cmul(wc, bp[w.q]), w.s);
+        nq = scal(bq[w.p], w.c) - scal(cmul(wc, bq[w.q]), w.s);
+      } else {
+        np = scal(bp[w.p], w.s) + scal(cmul(wc, bp[w.q]), w.c);
+        nq = scal(bq[w.p], w.s) + scal(cmul(wc, bq[w.q]), w.c);
+      }
+    }
+    Aout[(size_t)o.p * N + j] = np;
+    if (hasq) Aout[(size_t)o.q * N + j] = nq;
+  }
+}
+
+__global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<double>* __restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
 // partial sums of |A_ij|^2 off the diagonal and over all entries, fixed order
 __global__ void __launch_bounds__(256) k_lr_norms(const cpx<double>* __restrict__ A, int N,
                                                   double* __restrict__ part) {
@@ -251,8 +349,8 @@ __global__ void k_lr_conjt(const cpx<double>* __restrict__ U, int N, int nb,
 // Eigenvectors of the Hermitian A (destroyed) by cyclic Jacobi; U[g][r] and
 // Uh[r][g] receive the eigenvectors of the nb largest eigenvalues in descending
 // order, lam (may be NULL) all eigenvalues ascending.
-static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<double>* Vt,
-                              JacRot* rot, int* pairof, double* part, int* rank,
+static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<double>* A2,
+                              cpx<double>* Vt, JacRot* rot, int* pairof, double* part, int* rank,
                               cpx<double>* U, cpx<double>* Uh, double* lam) {
   const size_t nn = (size_t)N * N;
   const int m = N + (N & 1);
@@ -267,7 +365,6 @@ static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<doub
   // once into a graph on a private stream and replayed until converged
   const int nblk = (int)std::min<size_t>(1024, (nn + 255) / 256);
   std::vector<double> hp(2 * (size_t)nblk);
-  const dim3 gp((m / 2 + 127) / 128);
   struct SweepGraph {
     hipStream_t cap = nullptr;
     hipGraph_t g = nullptr;
@@ -280,10 +377,28 @@ static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<doub
   } sg;
   GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
   GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
-  for (int r = 0; r < m - 1; ++r) {
-    hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, sg.cap, A, N, m, r, rot, pairof);
-    hipLaunchKernelGGL(k_jac_round, dim3(m / 2), dim3(256), (size_t)2 * N * 16, sg.cap, A, Vt, N,
-                       rot, pairof);
+  // one kernel per round while every pair's rotation and the two rows fit in
+  // 64 KiB of LDS (N up to about 1090): rounds alternate A -> A2 -> A ..., and an
+  // odd number of rounds ends with a copy back.  Larger N: a parameter kernel,
+  // then the two-row update in place.
+  const size_t lds_pp = (size_t)(m / 2) * sizeof(JacRot) + (size_t)((N + 3) & ~3) * 4 +
+                        (size_t)2 * N * 16;
+  if (lds_pp <= 65536) {
+    for (int r = 0; r < m - 1; ++r) {
+      const bool even = (r & 1) == 0;
+      hipLaunchKernelGGL(k_jac_round_pp, dim3(m / 2), dim3(256), lds_pp, sg.cap, even ? A : A2,
+                         even ? A2 : A, Vt, N, m, r);
+    }
+    if ((m - 1) & 1)
+      hipLaunchKernelGGL(k_lr_copy, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, sg.cap, A2,
+                         nn, A);
+  } else {
+    const dim3 gp((m / 2 + 127) / 128);
+    for (int r = 0; r < m - 1; ++r) {
+      hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, sg.cap, A, N, m, r, rot, pairof);
+      hipLaunchKernelGGL(k_jac_round, dim3(m / 2), dim3(256), (size_t)2 * N * 16, sg.cap, A, Vt,
+                         N, rot, pairof);
+    }
   }
   {
     const hipError_t le = hipGetLastError();
@@ -369,6 +484,7 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
   };
   auto* E = reinterpret_cast<cpx<double>*>(take(nfreq * nn * 16));
   auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* A2 = reinterpret_cast<cpx<double>*>(take(nn * 16));
   auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
   auto* U = reinterpret_cast<cpx<double>*>(take(nub * 16));
   auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
@@ -392,7 +508,7 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
                        reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
     GW_CHECK_LAUNCH(c, "low-rank preparation");
   }
-  gw_status st = jacobi_basis(c, N, nb, A, Vt, rot, pairof, part, rank, U, Uh, lam);
+  gw_status st = jacobi_basis(c, N, nb, A, A2, Vt, rot, pairof, part, rank, U, Uh, lam);
   if (st != GW_OK) return st;
   const long long snn = (long long)nn, snb = (long long)nub, sbb = (long long)bb;
   // Y_f = E_f U;  B_f = U^H Y_f
@@ -428,7 +544,7 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   if (nb < 1 || nb > neps) return fail(c, GW_EINVAL, "nb must be 1 to neps");
   if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
   if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv aliases chi0");
-  if (neps > 4096 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 4096 or nfreq too large");
+  if (neps > 2048 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 2048 or nfreq too large");
   (void)hipSetDevice(c->device);
   // v > 0 is required for V^1/2: checked on a host copy
   std::vector<double> hv((size_t)neps);
@@ -438,7 +554,7 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
     if (!(x > 0.0) || !std::isfinite(x)) return fail(c, GW_EINVAL, "vcoul must be positive");
   const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb, bb = (size_t)nb * nb;
   const int m = neps + (neps & 1);
-  const size_t bytes = align_up(nfreq * nn * 16) + 2 * align_up(nn * 16) + 2 * align_up(nub * 16) +
+  const size_t bytes = align_up(nfreq * nn * 16) + 3 * align_up(nn * 16) + 2 * align_up(nub * 16) +
                        align_up(nfreq * nub * 16) + 2 * align_up(nfreq * bb * 16) +
                        align_up((size_t)(m / 2) * 48) + align_up(2 * 1024 * 8) +
                        2 * align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
@@ -470,14 +586,14 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
   if (!c) return GW_EINVAL;
   c->err.clear();
   if (neps < 1 || nb < 1 || nb > neps) return fail(c, GW_EINVAL, "need 1 <= nb <= neps");
-  if (neps > 4096) return fail(c, GW_EINVAL, "neps above 4096");
+  if (neps > 2048) return fail(c, GW_EINVAL, "neps above 2048");
   if (!chi0_static || !vcoul || !basis) return fail(c, GW_EINVAL, "NULL array argument");
   (void)hipSetDevice(c->device);
   gw_status st = check_v_positive(c, vcoul, neps);
   if (st != GW_OK) return st;
   const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb;
   const int m = neps + (neps & 1);
-  const size_t bytes = 2 * align_up(nn * 16) + align_up(nub * 16) + align_up((size_t)(m / 2) * 48) +
+  const size_t bytes = 3 * align_up(nn * 16) + align_up(nub * 16) + align_up((size_t)(m / 2) * 48) +
                        align_up(2 * 1024 * 8) + 2 * align_up((size_t)neps * 4) + 4096;
   char* base = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
@@ -489,6 +605,7 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
     return p;
   };
   auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* A2 = reinterpret_cast<cpx<double>*>(take(nn * 16));
   auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
   auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
   auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
@@ -502,7 +619,7 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
     st = hipGetLastError() == hipSuccess ? GW_OK : GW_EDEVICE;
   }
   if (st == GW_OK)
-    st = jacobi_basis(c, neps, nb, A, Vt, rot, pairof, part, rank,
+    st = jacobi_basis(c, neps, nb, A, A2, Vt, rot, pairof, part, rank,
                       reinterpret_cast<cpx<double>*>(basis), Uh, eigenvalues);
   const hipError_t e2 = hipStreamSynchronize(c->stream);
   (void)hipFree(base);

@@ -46,8 +46,10 @@ def _run(P, ctx, chi, v, nb, lam=False):
 
 
 @pytest.mark.parametrize("n,nf,rank,nb", [(40, 3, 10, 10), (37, 2, 37, 37), (130, 4, 25, 25),
-                                          (64, 1, 64, 64), (1, 1, 1, 1)])
+                                          (64, 1, 64, 64), (1, 1, 1, 1), (1201, 1, 30, 30)])
 def test_lowrank_matches_oracle(P, ctx, n, nf, rank, nb):
+    """Up to N ~ 1090 each Jacobi round is one kernel; N = 1201 (odd) takes the
+    two-kernel rounds."""
     chi, v = _chi(n + rank, n, nf, rank)
     got, lam = _run(P, ctx, chi, v, nb, lam=True)
     want, wlam = oracle.epsinv_lowrank(chi, v, nb)
