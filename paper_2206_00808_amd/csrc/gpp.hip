@@ -104,6 +104,9 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
     W[r] = in ? wt[(size_t)row * N + col] : mk(1.0, 0.0);
   }
   const int diag = (col >= row0 && col < row0 + kRows && col < N) ? col - row0 : -1;
+  double WY2[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) WY2[r] = W[r].y * W[r].y;
   double E[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) E[k] = energies[(size_t)n * NE + k];
@@ -155,25 +158,27 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
 #pragma unroll
           for (int k = 0; k < NE; ++k) {
             z1[r][k] = (E[k] - ea) - W[r].x;
-            x[r][k] = fma(z1[r][k], z1[r][k], W[r].y * W[r].y);
+            x[r][k] = fma(z1[r][k], z1[r][k], WY2[r]);
             const int i = r * NE + k;
             pre[i] = i == 0 ? x[0][0] : pre[i - 1] * x[r][k];
           }
         double rr = rcp_nr(pre[kRows * NE - 1]);
 #pragma unroll
-        for (int r = kRows - 1; r >= 0; --r)
+        for (int r = kRows - 1; r >= 0; --r) {
+          const cpx<double> mr = mrow[s][rg * kRows + r];
+          // conj(M(G)) A conj(d - wt) / |d - wt|^2 = A conj(M) / (d - wt); the products
+          // of B with Im wt are the same for every energy
+          const cpx<double> B = cmulc(mr, A[r]);
+          const double byw = B.y * W[r].y, bxw = B.x * W[r].y;
 #pragma unroll
           for (int k = NE - 1; k >= 0; --k) {
             const int i = r * NE + k;
             const double inv = i == 0 ? rr : rr * pre[i - 1];
             rr *= x[r][k];
-            const cpx<double> mr = mrow[s][rg * kRows + r];
-            // conj(M(G)) A conj(d - wt) / |d - wt|^2 = A conj(M) / (d - wt)
-            const cpx<double> B = cmulc(mr, A[r]);
-            const double wy = W[r].y;
-            const cpx<double> b1 = mk(fma(B.x, z1[r][k], -B.y * wy), fma(B.x, wy, B.y * z1[r][k]));
+            const cpx<double> b1 = mk(fma(B.x, z1[r][k], -byw), fma(B.y, z1[r][k], bxw));
             tc[k] = mk(fma(inv, b1.x, tc[k].x), fma(inv, b1.y, tc[k].y));
           }
+        }
       } else if (!occ) {
         // empty n'', four energies: the NE reciprocals of |d - wt|^2 come from one
         // hardware reciprocal of their product (prefix products, then back-substitution)
