@@ -31,7 +31,7 @@ namespace gw {
 
 namespace {
 constexpr double kGppDropTol = 1e-10;
-constexpr int kTR = 16, kTC = 64, kRows = 4, kChunk = 8;
+constexpr int kTR = 16, kTC = 64, kRows = 4, kChunk = 32;
 }  // namespace
 
 __global__ void k_gpp_modes(const double* __restrict__ qg, const int* __restrict__ g, int N,
