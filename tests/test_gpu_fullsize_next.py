@@ -105,3 +105,30 @@ def test_sigma_gpp_full_size_sampled_states(P, ctx, c2):
     wsx, wcoh = oracle.sigma_gpp(m, en, nocc, c2["vcoul"], o2, wto, energies)
     for got, want in ((sx, wsx), (coh, wcoh)):
         assert np.abs(got.cpu().numpy() - want).max() < 1e-10 * np.abs(want).max()
+
+
+def test_lowrank_full_size(P, ctx, c2):
+    """N_eps = 1000 (one Jacobi kernel per round), 100 eigenvectors, 3 frequencies:
+    V^1/2 chi0(w) V^1/2 = -Q diag(l_i / (1 + a_i w)) Q^H with a random unitary Q, 100
+    modes l in [1, 5] and 900 in [0, 0.1] (a clear gap, so the basis is unique),
+    the same input on both sides."""
+    rng = np.random.default_rng(16)
+    n, nb = len(c2["geps"]), 100
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam0 = np.concatenate([rng.uniform(1.0, 5.0, nb), rng.uniform(0.0, 0.1, n - nb)])
+    a = rng.uniform(0.2, 2.0, n)
+    v = c2["vcoul"]
+    sv = np.sqrt(v)
+    chi = np.stack([-(q * (lam0 / (1.0 + a * w))[None, :]) @ q.conj().T / sv[:, None] / sv[None, :]
+                    for w in (0.0, 0.5, 3.0)])
+    out = torch.empty(chi.shape, dtype=torch.complex128, device="cuda:0")
+    lam = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    P.gw_epsinv_lowrank(ctx, n, 3, _dev(chi), _dev(v), nb, out, lam)
+    torch.cuda.synchronize()
+    want, wlam = oracle.epsinv_lowrank(chi, v, nb)
+    gap = (wlam[n - nb] - wlam[n - nb - 1]) / wlam[-1]
+    assert gap > 0.1
+    assert np.abs(lam.cpu().numpy() - wlam).max() < 1e-12 * wlam.max()
+    got = out.cpu().numpy()
+    for f in range(3):
+        assert oracle.rel_f(got[f], want[f]) < 1e-9
