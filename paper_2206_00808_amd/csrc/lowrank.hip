@@ -240,6 +240,221 @@ __global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<dou
   if (e < n) dst[e] = src[e];
 }
 
+// ---------------------------------------------------------------- block Jacobi
+// For larger N the rotations act on pairs of 16-wide blocks: a round pairs the
+// nblk blocks in round-robin order; each pair's 32 x 32 Hermitian sub-matrix is
+// diagonalised in LDS by a few inner sweeps of the same scalar rotations, and the
+// accumulated 32 x 32 unitary W then updates the pair's block rows (W^H A), the
+// eigenvector rows (W^T Vt) and, in a second pass, the pair's block columns (A W).
+// The matrix is padded to a multiple of 32 with zero rows and columns, which no
+// rotation ever touches (their off-diagonal entries stay 0).
+constexpr int kBJ = 16;           // block width
+constexpr int kBJ2 = 2 * kBJ;     // sub-problem size
+constexpr int kBJInner = 2;       // inner sweeps per round
+
+__device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) {
+  int a, b;
+  if (k == 0) {
+    a = r;
+    b = nblk - 1;
+  } else {
+    a = (r + k) % (nblk - 1);
+    b = (r - k + (nblk - 1)) % (nblk - 1);
+  }
+  *I = a < b ? a : b;
+  *J = a < b ? b : a;
+}
+
+// Qt[k] (32 x 32, rows = columns of W) for pair k of round r
+__global__ void __launch_bounds__(256) k_bj_solve(const cpx<double>* __restrict__ A, int Np,
+                                                  int nblk, int r, cpx<double>* __restrict__ Qt) {
+  __shared__ cpx<double> S[kBJ2][kBJ2 + 1];
+  __shared__ cpx<double> W[kBJ2][kBJ2 + 1];  // W^T: row x = column x of W
+  __shared__ JacRot prm[kBJ];
+  int I, J;
+  bj_pair(nblk, r, blockIdx.x, &I, &J);
+  const int t = threadIdx.x;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) {
+    const int x = e / kBJ2, y = e % kBJ2;
+    const int gx = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
+    const int gy = (y < kBJ ? I * kBJ + y : J * kBJ + y - kBJ);
+    S[x][y] = A[(size_t)gx * Np + gy];
+    W[x][y] = mk(x == y ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < kBJInner; ++sweep)
+    for (int rr = 0; rr < kBJ2 - 1; ++rr) {
+      if (t < kBJ) {
+        int p, q;
+        if (t == 0) {
+          p = rr;
+          q = kBJ2 - 1;
+        } else {
+          p = (rr + t) % (kBJ2 - 1);
+          q = (rr - t + (kBJ2 - 1)) % (kBJ2 - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        JacRot o;
+        o.p = p;
+        o.q = q;
+        o.pad = 0;
+        o.skip = 1;
+        o.c = 1.0;
+        o.s = 0.0;
+        o.er = 1.0;
+        o.ei = 0.0;
+        const cpx<double> b = S[p][q];
+        const double ab = hypot(b.x, b.y);
+        if (ab > 0.0) {
+          const double a = S[p][p].x, d = S[q][q].x;
+          const double tau = (d - a) / (2.0 * ab);
+          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          o.c = 1.0 / sqrt(1.0 + tt * tt);
+          o.s = tt * o.c;
+          o.er = b.x / ab;
+          o.ei = b.y / ab;
+          o.skip = 0;
+        }
+        prm[t] = o;
+      }
+      __syncthreads();
+      // rows of S (J^H S) and of W^T (J^T W^T), one (pair, column) per work item
+      for (int e = t; e < kBJ * kBJ2; e += blockDim.x) {
+        const JacRot o = prm[e / kBJ2];
+        const int j = e % kBJ2;
+        if (o.skip) continue;
+        const cpx<double> ev = mk(o.er, o.ei), ec = mk(o.er, -o.ei);
+        const cpx<double> ap = S[o.p][j], aq = S[o.q][j];
+        const cpx<double> eq = cmul(ev, aq);
+        S[o.p][j] = scal(ap, o.c) - scal(eq, o.s);
+        S[o.q][j] = scal(ap, o.s) + scal(eq, o.c);
+        const cpx<double> wp = W[o.p][j], wq = W[o.q][j];
+        const cpx<double> ew = cmul(ec, wq);
+        W[o.p][j] = scal(wp, o.c) - scal(ew, o.s);
+        W[o.q][j] = scal(wp, o.s) + scal(ew, o.c);
+      }
+      __syncthreads();
+      // columns of S (S J), one (pair, row) per work item
+      for (int e = t; e < kBJ * kBJ2; e += blockDim.x) {
+        const JacRot o = prm[e / kBJ2];
+        const int i = e % kBJ2;
+        if (o.skip) continue;
+        const cpx<double> ec = mk(o.er, -o.ei);
+        const cpx<double> ap = S[i][o.p], aq = S[i][o.q];
+        const cpx<double> eq = cmul(ec, aq);
+        S[i][o.p] = scal(ap, o.c) - scal(eq, o.s);
+        S[i][o.q] = scal(ap, o.s) + scal(eq, o.c);
+      }
+      __syncthreads();
+    }
+  cpx<double>* out = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) out[e] = W[e / kBJ2][e % kBJ2];
+}
+
+// T[rows of pair k][chunk] = W^H A[rows][chunk];  Vt[rows][chunk] = W^T Vt[rows][chunk]
+__global__ void __launch_bounds__(256) k_bj_rowmix(const cpx<double>* __restrict__ A,
+                                                   cpx<double>* __restrict__ T,
+                                                   cpx<double>* __restrict__ Vt, int Np, int nblk,
+                                                   int r, const cpx<double>* __restrict__ Qt) {
+  __shared__ cpx<double> w[kBJ2][kBJ2 + 1];
+  __shared__ cpx<double> a[kBJ2][64];
+  __shared__ cpx<double> v[kBJ2][64];
+  int I, J;
+  bj_pair(nblk, r, blockIdx.x, &I, &J);
+  const int t = threadIdx.x, c0 = blockIdx.y * 64;
+  const cpx<double>* q = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) w[e / kBJ2][e % kBJ2] = q[e];
+  for (int e = t; e < kBJ2 * 64; e += blockDim.x) {
+    const int x = e / 64, j = c0 + e % 64;
+    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
+    a[x][e % 64] = j < Np ? A[(size_t)g * Np + j] : mk(0.0, 0.0);
+    v[x][e % 64] = j < Np ? Vt[(size_t)g * Np + j] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = t; e < kBJ2 * 64; e += blockDim.x) {
+    const int x = e / 64, jj = e % 64, j = c0 + jj;
+    if (j >= Np) continue;
+    cpx<double> sa = mk(0.0, 0.0), sv = mk(0.0, 0.0);
+    for (int y = 0; y < kBJ2; ++y) {
+      // (W^H)[x][y] = conj(W[y][x]) = conj(Wt[x][y]);  (W^T)[x][y] = Wt[x][y]
+      sa = sa + cmulc(w[x][y], a[y][jj]);
+      sv = sv + cmul(w[x][y], v[y][jj]);
+    }
+    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
+    T[(size_t)g * Np + j] = sa;
+    Vt[(size_t)g * Np + j] = sv;
+  }
+}
+
+// A[chunk][cols of pair k] = T[chunk][cols] W
+__global__ void __launch_bounds__(256) k_bj_colmix(const cpx<double>* __restrict__ T,
+                                                   cpx<double>* __restrict__ A, int Np, int nblk,
+                                                   int r, const cpx<double>* __restrict__ Qt) {
+  __shared__ cpx<double> w[kBJ2][kBJ2 + 1];
+  __shared__ cpx<double> tt[64][kBJ2 + 1];
+  int I, J;
+  bj_pair(nblk, r, blockIdx.x, &I, &J);
+  const int t = threadIdx.x, r0 = blockIdx.y * 64;
+  const cpx<double>* q = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) w[e / kBJ2][e % kBJ2] = q[e];
+  for (int e = t; e < 64 * kBJ2; e += blockDim.x) {
+    const int i = r0 + e / kBJ2, y = e % kBJ2;
+    const int g = (y < kBJ ? I * kBJ + y : J * kBJ + y - kBJ);
+    tt[e / kBJ2][y] = i < Np ? T[(size_t)i * Np + g] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * kBJ2; e += blockDim.x) {
+    const int ii = e / kBJ2, x = e % kBJ2, i = r0 + ii;
+    if (i >= Np) continue;
+    cpx<double> s = mk(0.0, 0.0);
+    // (T W)[i][x] = sum_y T[i][y] W[y][x] = sum_y T[i][y] Wt[x][y]
+    for (int y = 0; y < kBJ2; ++y) s = s + cmul(tt[ii][y], w[x][y]);
+    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
+    A[(size_t)i * Np + g] = s;
+  }
+}
+
+// zero-padded copy: dst (Np x Np) from src (N x N)
+__global__ void k_bj_pad(const cpx<double>* __restrict__ src, int N, int Np,
+                         cpx<double>* __restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)Np * Np) return;
+  const int i = (int)(e / Np), j = (int)(e % Np);
+  dst[e] = (i < N && j < N) ? src[(size_t)i * N + j] : mk(0.0, 0.0);
+}
+
+// rank among the first N diagonal entries of the padded matrix (descending, ties by index)
+__global__ void k_bj_rank(const cpx<double>* __restrict__ A, int Np, int N, int* __restrict__ rank,
+                          double* __restrict__ lam_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double li = A[(size_t)i * Np + i].x;
+  int r = 0;
+  for (int j = 0; j < N; ++j) {
+    const double lj = A[(size_t)j * Np + j].x;
+    r += (lj > li || (lj == li && j < i)) ? 1 : 0;
+  }
+  rank[i] = r;
+  if (lam_out) lam_out[N - 1 - r] = li;
+}
+
+__global__ void k_bj_select(const cpx<double>* __restrict__ Vt, int Np, const int* __restrict__ rank,
+                            int N, int nb, cpx<double>* __restrict__ U,
+                            cpx<double>* __restrict__ Uh) {
+  const int i = blockIdx.x;
+  const int r = rank[i];
+  if (r >= nb) return;
+  for (int g = threadIdx.x; g < N; g += blockDim.x) {
+    const cpx<double> x = Vt[(size_t)i * Np + g];
+    U[(size_t)g * nb + r] = x;
+    Uh[(size_t)r * N + g] = mk(x.x, -x.y);
+  }
+}
+
 // partial sums of |A_ij|^2 off the diagonal and over all entries, fixed order
 __global__ void __launch_bounds__(256) k_lr_norms(const cpx<double>* __restrict__ A, int N,
                                                   double* __restrict__ part) {
@@ -349,9 +564,105 @@ __global__ void k_lr_conjt(const cpx<double>* __restrict__ U, int N, int nb,
 // Eigenvectors of the Hermitian A (destroyed) by cyclic Jacobi; U[g][r] and
 // Uh[r][g] receive the eigenvectors of the nb largest eigenvalues in descending
 // order, lam (may be NULL) all eigenvalues ascending.
+// Block-Jacobi form of jacobi_basis for larger N (own padded buffers).
+static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>* A,
+                                    cpx<double>* U, cpx<double>* Uh, double* lam) {
+  const int Np = (N + kBJ2 - 1) / kBJ2 * kBJ2;
+  const int nblk = Np / kBJ, npairs = nblk / 2;
+  const size_t nnp = (size_t)Np * Np;
+  const size_t bytes = 3 * align_up(nnp * 16) + align_up((size_t)npairs * kBJ2 * kBJ2 * 16) +
+                       align_up(2 * 1024 * 8) + align_up((size_t)N * 4) + 1024;
+  char* base = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
+    return fail(c, GW_ENOMEM, "block-Jacobi buffers of %zu bytes", bytes);
+  struct Free {
+    char* p;
+    gw_ctx* c;
+    ~Free() {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(p);
+    }
+  } guard{base, c};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  auto* Ap = reinterpret_cast<cpx<double>*>(take(nnp * 16));
+  auto* Tp = reinterpret_cast<cpx<double>*>(take(nnp * 16));
+  auto* Vp = reinterpret_cast<cpx<double>*>(take(nnp * 16));
+  auto* Qt = reinterpret_cast<cpx<double>*>(take((size_t)npairs * kBJ2 * kBJ2 * 16));
+  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
+  const unsigned gnp = (unsigned)((nnp + 255) / 256);
+  {
+    ProfScope ps(c, "lowrank_prep");
+    hipLaunchKernelGGL(k_bj_pad, dim3(gnp), dim3(256), 0, c->stream, A, N, Np, Ap);
+    hipLaunchKernelGGL(k_lr_fill, dim3(gnp, 1), dim3(256), 0, c->stream, Vp, Np, part, 0);
+    GW_CHECK_LAUNCH(c, "block-Jacobi preparation");
+  }
+  struct SweepGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~SweepGraph() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (g) (void)hipGraphDestroy(g);
+      if (cap) (void)hipStreamDestroy(cap);
+    }
+  } sg;
+  GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
+  GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
+  const dim3 gmix(npairs, (Np + 63) / 64);
+  for (int r = 0; r < nblk - 1; ++r) {
+    hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(256), 0, sg.cap, Ap, Np, nblk, r, Qt);
+    hipLaunchKernelGGL(k_bj_rowmix, gmix, dim3(256), 0, sg.cap, Ap, Tp, Vp, Np, nblk, r, Qt);
+    hipLaunchKernelGGL(k_bj_colmix, gmix, dim3(256), 0, sg.cap, Tp, Ap, Np, nblk, r, Qt);
+  }
+  {
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(sg.cap, &sg.g);
+    if (le != hipSuccess) return hip_fail(c, le, "block-Jacobi sweep capture");
+    if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+  }
+  GW_HIP(c, hipGraphInstantiate(&sg.exec, sg.g, nullptr, nullptr, 0));
+  const int nrb = (int)std::min<size_t>(1024, (nnp + 255) / 256);
+  std::vector<double> hp(2 * (size_t)nrb);
+  bool done = false;
+  for (int sweep = 0; sweep < 40 && !done; ++sweep) {
+    {
+      ProfScope ps(c, "jacobi_sweep");
+      GW_HIP(c, hipGraphLaunch(sg.exec, c->stream));
+    }
+    hipLaunchKernelGGL(k_lr_norms, dim3(nrb), dim3(256), 0, c->stream, Ap, Np, part);
+    GW_CHECK_LAUNCH(c, "k_lr_norms");
+    GW_HIP(c, hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    GW_HIP(c, hipStreamSynchronize(c->stream));
+    double so = 0.0, sa = 0.0;
+    for (int b = 0; b < nrb; ++b) {
+      so += hp[2 * b];
+      sa += hp[2 * b + 1];
+    }
+    if (!std::isfinite(so) || !std::isfinite(sa))
+      return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
+    done = so <= 1e-28 * sa;
+  }
+  if (!done) return fail(c, GW_EINVAL, "block-Jacobi eigen-decomposition did not converge");
+  ProfScope ps(c, "lowrank_basis");
+  hipLaunchKernelGGL(k_bj_rank, dim3((N + 255) / 256), dim3(256), 0, c->stream, Ap, Np, N, rank,
+                     lam);
+  hipLaunchKernelGGL(k_bj_select, dim3(N), dim3(256), 0, c->stream, Vp, Np, rank, N, nb, U, Uh);
+  GW_CHECK_LAUNCH(c, "block-Jacobi basis");
+  return GW_OK;
+}
+
+constexpr int kBlockJacobiMin = 128;  // from this N on, block Jacobi
+
 static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<double>* A2,
                               cpx<double>* Vt, JacRot* rot, int* pairof, double* part, int* rank,
                               cpx<double>* U, cpx<double>* Uh, double* lam) {
+  if (N >= kBlockJacobiMin) return jacobi_basis_block(c, N, nb, A, U, Uh, lam);
   const size_t nn = (size_t)N * N;
   const int m = N + (N & 1);
   {
