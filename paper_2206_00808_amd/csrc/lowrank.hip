@@ -250,7 +250,7 @@ __global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<dou
 // rotation ever touches (their off-diagonal entries stay 0).
 constexpr int kBJ = 16;           // block width
 constexpr int kBJ2 = 2 * kBJ;     // sub-problem size
-constexpr int kBJInner = 2;       // inner sweeps per round
+constexpr int kBJInner = 1;       // inner sweeps per round
 
 __device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) {
   int a, b;
