@@ -239,7 +239,7 @@ gw_status gw_epsinv_lu(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
  *   eigenvalues (device) out double[neps] of epst(0) in ascending order, or NULL.
  * Allocates its own buffers (about 16 (nfreq + 2) neps^2 bytes) and synchronises
  * the context stream.
- * Errors: GW_EINVAL for negative sizes, nb outside 1..neps, neps > 2048, NULL
+ * Errors: GW_EINVAL for negative sizes, nb outside 1..neps, neps > 8192, NULL
  * arrays, aliasing, vcoul <= 0, non-finite input; GW_ENOMEM; GW_ESINGULAR from
  * the small inverses.
  */
@@ -256,7 +256,7 @@ gw_status gw_epsinv_lowrank(gw_ctx* ctx, int neps, int nfreq, const double* chi0
  *   [neps][neps], Hermitian) by the Jacobi method of gw_epsinv_lowrank;
  *   eigenvalues (device out double[neps], ascending) or NULL.  Allocates its own
  *   buffers and synchronises the context stream.  GW_EINVAL for nb outside
- *   1..neps, neps > 2048, NULL arrays, vcoul <= 0, non-finite input.
+ *   1..neps, neps > 8192, NULL arrays, vcoul <= 0, non-finite input.
  * gw_mtxel_project -- out[p][b] = sum_G M[p][G] sqrt(v(G)) U[G][b] (device out
  *   complex double[npairs][nb]) for matrix elements of dtype (device
  *   [npairs][neps]); gw_chi0_accumulate on it with neps := nb gives

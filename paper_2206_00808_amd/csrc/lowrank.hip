@@ -855,7 +855,7 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   if (nb < 1 || nb > neps) return fail(c, GW_EINVAL, "nb must be 1 to neps");
   if (!chi0 || !vcoul || !epsinv) return fail(c, GW_EINVAL, "NULL array argument");
   if (chi0 == epsinv) return fail(c, GW_EINVAL, "epsinv aliases chi0");
-  if (neps > 2048 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 2048 or nfreq too large");
+  if (neps > 8192 || nfreq > 65535) return fail(c, GW_EINVAL, "neps above 8192 or nfreq too large");
   (void)hipSetDevice(c->device);
   // v > 0 is required for V^1/2: checked on a host copy
   std::vector<double> hv((size_t)neps);
@@ -897,7 +897,7 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
   if (!c) return GW_EINVAL;
   c->err.clear();
   if (neps < 1 || nb < 1 || nb > neps) return fail(c, GW_EINVAL, "need 1 <= nb <= neps");
-  if (neps > 2048) return fail(c, GW_EINVAL, "neps above 2048");
+  if (neps > 8192) return fail(c, GW_EINVAL, "neps above 8192");
   if (!chi0_static || !vcoul || !basis) return fail(c, GW_EINVAL, "NULL array argument");
   (void)hipSetDevice(c->device);
   gw_status st = check_v_positive(c, vcoul, neps);
