@@ -251,6 +251,7 @@ __global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<dou
 constexpr int kBJ = 16;           // block width
 constexpr int kBJ2 = 2 * kBJ;     // sub-problem size
 constexpr int kBJInner = 1;       // inner sweeps per round
+constexpr int kRC = 32;           // columns per row-update workgroup
 
 __device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) {
   int a, b;
@@ -361,22 +362,22 @@ __global__ void __launch_bounds__(256) k_bj_rowmix(const cpx<double>* __restrict
                                                    cpx<double>* __restrict__ Vt, int Np, int nblk,
                                                    int r, const cpx<double>* __restrict__ Qt) {
   __shared__ cpx<double> w[kBJ2][kBJ2 + 1];
-  __shared__ cpx<double> a[kBJ2][64];
-  __shared__ cpx<double> v[kBJ2][64];
+  __shared__ cpx<double> a[kBJ2][kRC];
+  __shared__ cpx<double> v[kBJ2][kRC];
   int I, J;
   bj_pair(nblk, r, blockIdx.x, &I, &J);
-  const int t = threadIdx.x, c0 = blockIdx.y * 64;
+  const int t = threadIdx.x, c0 = blockIdx.y * kRC;
   const cpx<double>* q = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
   for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) w[e / kBJ2][e % kBJ2] = q[e];
-  for (int e = t; e < kBJ2 * 64; e += blockDim.x) {
-    const int x = e / 64, j = c0 + e % 64;
+  for (int e = t; e < kBJ2 * kRC; e += blockDim.x) {
+    const int x = e / kRC, j = c0 + e % kRC;
     const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
-    a[x][e % 64] = j < Np ? A[(size_t)g * Np + j] : mk(0.0, 0.0);
-    v[x][e % 64] = j < Np ? Vt[(size_t)g * Np + j] : mk(0.0, 0.0);
+    a[x][e % kRC] = j < Np ? A[(size_t)g * Np + j] : mk(0.0, 0.0);
+    v[x][e % kRC] = j < Np ? Vt[(size_t)g * Np + j] : mk(0.0, 0.0);
   }
   __syncthreads();
-  for (int e = t; e < kBJ2 * 64; e += blockDim.x) {
-    const int x = e / 64, jj = e % 64, j = c0 + jj;
+  for (int e = t; e < kBJ2 * kRC; e += blockDim.x) {
+    const int x = e / kRC, jj = e % kRC, j = c0 + jj;
     if (j >= Np) continue;
     cpx<double> sa = mk(0.0, 0.0), sv = mk(0.0, 0.0);
     for (int y = 0; y < kBJ2; ++y) {
@@ -614,10 +615,10 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   } sg;
   GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
   GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
-  const dim3 gmix(npairs, (Np + 63) / 64);
+  const dim3 growmix(npairs, (Np + kRC - 1) / kRC), gmix(npairs, (Np + 63) / 64);
   for (int r = 0; r < nblk - 1; ++r) {
     hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(256), 0, sg.cap, Ap, Np, nblk, r, Qt);
-    hipLaunchKernelGGL(k_bj_rowmix, gmix, dim3(256), 0, sg.cap, Ap, Tp, Vp, Np, nblk, r, Qt);
+    hipLaunchKernelGGL(k_bj_rowmix, growmix, dim3(256), 0, sg.cap, Ap, Tp, Vp, Np, nblk, r, Qt);
     hipLaunchKernelGGL(k_bj_colmix, gmix, dim3(256), 0, sg.cap, Tp, Ap, Np, nblk, r, Qt);
   }
   {
