@@ -723,6 +723,13 @@ def main():
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                     "launches_per_step": dl, "avg_launch_ms": dms / dl}
     roof["traffic"] = measured_traffic(dname, args.config)
+    # the nominal peaks confirmed on this device (an FP64 MFMA loop, an FP64 FMA
+    # loop, a 1 GiB copy), reported beside the published figures
+    result["measured_peaks"] = {
+        "fp64_mfma_TFLOP_per_s": P.gw_peak_probe(ctx, 0),
+        "fp64_vector_TFLOP_per_s": P.gw_peak_probe(ctx, 1),
+        "copy_GB_per_s": P.gw_peak_probe(ctx, 2),
+        "published": {"fp64_TFLOP_per_s": 78.6, "hbm_GB_per_s": HBM_PEAK_GBS}}
     result["roofline"] = roof
     bb, pb = fft_stage_bytes(d64, 16)
     fft_ms = sum(kt64.get(k, (0, 0))[1] for k in ("band_xpass", "band_plane", "pair_plane",

@@ -450,6 +450,17 @@ gw_status gw_bse_kernel(gw_ctx* ctx, int nv, int nc, int neps, const void* mvc, 
                         const void* mvv, gw_dtype dtype, const double* vx, const double* w,
                         double* kx, double* kd);
 
+/*
+ * gw_peak_probe -- measured peak of the device, to set beside the nominal
+ * roofline figures: kind 0 an FP64 matrix-core loop (TFLOP/s, v_mfma 16x16x4
+ * FP64, eight independent chains per wavefront), kind 1 an FP64 vector FMA loop
+ * (TFLOP/s), kind 2 a 1 GiB device-to-device copy (GB/s, bytes read + written).
+ * Best of three timed runs after one warm-up; synchronises.  Allocates 8 MiB
+ * (and 2 GiB for kind 2) for the duration of the call.
+ * Errors: GW_EINVAL for a NULL result or another kind; GW_ENOMEM.
+ */
+gw_status gw_peak_probe(gw_ctx* ctx, int kind, double* result);
+
 /* ------------------------------------------------------------------------ */
 /* Learned closure of the truncated conduction-band sum.                      */
 /* ------------------------------------------------------------------------ */

@@ -15,6 +15,6 @@ from .binding import (  # noqa: F401
     gw_mtxel_spinor, gw_chi0_accumulate, gw_epsinv, gw_chi0_accumulate_real, gw_epsinv_lu,
     gw_head_dipole, gw_screened_w, gw_sigma_sx, gw_unfold_spinor, gw_gpp_modes, gw_sigma_gpp, gw_chi0_symmetrize, gw_bse_kernel,
     gw_little_group, gw_kgrid_orbits, gw_epsinv_lowrank,
-    gw_lowrank_basis, gw_mtxel_project, gw_epsinv_from_basis,
+    gw_lowrank_basis, gw_mtxel_project, gw_epsinv_from_basis, gw_peak_probe,
     status_string, EXPORTED, LIB_PATH,
 )

@@ -30,7 +30,7 @@ EXPORTED = [
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
     "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits", "gw_epsinv_lowrank",
-    "gw_lowrank_basis", "gw_mtxel_project", "gw_epsinv_from_basis",
+    "gw_lowrank_basis", "gw_mtxel_project", "gw_epsinv_from_basis", "gw_peak_probe",
     "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
@@ -38,6 +38,13 @@ EXPORTED = [
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2206_00808_amd.build.build() "
                       "(or __graft_entry__.build()) first")
+
+# torch's HIP runtime is loaded before this library, so that a process that
+# creates a context before touching torch still sees its devices through torch
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    pass
 
 _lib = ct.CDLL(LIB_PATH)
 
@@ -74,6 +81,7 @@ _SIG = {
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
     "gw_epsinv_lu": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "gw_peak_probe": (_i, [_vp, _i, _vp]),
     "gw_lowrank_basis": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp]),
     "gw_mtxel_project": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp]),
     "gw_epsinv_from_basis": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]),
@@ -443,6 +451,15 @@ def gw_epsinv_from_basis(ctx, chi_b, vcoul, basis, epsinv):
     s = _lib.gw_epsinv_from_basis(ctx.handle, int(neps), int(nb), chi_b.shape[0], _ptr(chi_b),
                                   _ptr(vcoul), _ptr(basis), _ptr(epsinv))
     return _check(ctx, s)
+
+
+def gw_peak_probe(ctx, kind):
+    """Measured FP64 MFMA TFLOP/s (0), FP64 vector TFLOP/s (1) or copy GB/s (2)."""
+    r = ct.c_double()
+    ctx.sync_stream()
+    s = _lib.gw_peak_probe(ctx.handle, int(kind), ct.byref(r))
+    _check(ctx, s)
+    return r.value
 
 
 def raw():
