@@ -32,6 +32,7 @@ namespace gw {
 namespace {
 constexpr double kGppDropTol = 1e-10;
 constexpr int kTR = 16, kTC = 64, kRows = 4, kChunk = 32;
+constexpr int kRB = 4;  // rows sharing one reciprocal (kRows / kRB reciprocals per energy set)
 }  // namespace
 
 __global__ void k_gpp_modes(const double* __restrict__ qg, const int* __restrict__ g, int N,
@@ -150,33 +151,37 @@ __global__ void __launch_bounds__(256, 3) k_sigma_gpp(
 #pragma unroll
       for (int k = 0; k < NE; ++k) tc[k] = ts[k] = mk(0.0, 0.0);
       if (!occ && NE <= 3) {
-        // empty n'': COH only.  The kRows * NE reciprocals of |d - wt|^2 come from one
-        // hardware reciprocal of their product (prefix products, then back-substitution)
-        double z1[kRows][NE], x[kRows][NE], pre[kRows * NE];
+        // empty n'': COH only.  The reciprocals of |d - wt|^2 for kRB rows and every
+        // energy come from one hardware reciprocal of their product (prefix
+        // products, then back-substitution)
 #pragma unroll
-        for (int r = 0; r < kRows; ++r)
+        for (int g0 = 0; g0 < kRows; g0 += kRB) {
+          double z1[kRB][NE], x[kRB][NE], pre[kRB * NE];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) {
-            z1[r][k] = (E[k] - ea) - W[r].x;
-            x[r][k] = fma(z1[r][k], z1[r][k], WY2[r]);
-            const int i = r * NE + k;
-            pre[i] = i == 0 ? x[0][0] : pre[i - 1] * x[r][k];
-          }
-        double rr = rcp_nr(pre[kRows * NE - 1]);
+          for (int r = 0; r < kRB; ++r)
 #pragma unroll
-        for (int r = kRows - 1; r >= 0; --r) {
-          const cpx<double> mr = mrow[s][rg * kRows + r];
-          // conj(M(G)) A conj(d - wt) / |d - wt|^2 = A conj(M) / (d - wt); the products
-          // of B with Im wt are the same for every energy
-          const cpx<double> B = cmulc(mr, A[r]);
-          const double byw = B.y * W[r].y, bxw = B.x * W[r].y;
+            for (int k = 0; k < NE; ++k) {
+              z1[r][k] = (E[k] - ea) - W[g0 + r].x;
+              x[r][k] = fma(z1[r][k], z1[r][k], WY2[g0 + r]);
+              const int i = r * NE + k;
+              pre[i] = i == 0 ? x[0][0] : pre[i - 1] * x[r][k];
+            }
+          double rr = rcp_nr(pre[kRB * NE - 1]);
 #pragma unroll
-          for (int k = NE - 1; k >= 0; --k) {
-            const int i = r * NE + k;
-            const double inv = i == 0 ? rr : rr * pre[i - 1];
-            rr *= x[r][k];
-            const cpx<double> b1 = mk(fma(B.x, z1[r][k], -byw), fma(B.y, z1[r][k], bxw));
-            tc[k] = mk(fma(inv, b1.x, tc[k].x), fma(inv, b1.y, tc[k].y));
+          for (int r = kRB - 1; r >= 0; --r) {
+            const cpx<double> mr = mrow[s][rg * kRows + g0 + r];
+            // conj(M(G)) A conj(d - wt) / |d - wt|^2 = A conj(M) / (d - wt); the
+            // products of B with Im wt are the same for every energy
+            const cpx<double> B = cmulc(mr, A[g0 + r]);
+            const double byw = B.y * W[g0 + r].y, bxw = B.x * W[g0 + r].y;
+#pragma unroll
+            for (int k = NE - 1; k >= 0; --k) {
+              const int i = r * NE + k;
+              const double inv = i == 0 ? rr : rr * pre[i - 1];
+              rr *= x[r][k];
+              const cpx<double> b1 = mk(fma(B.x, z1[r][k], -byw), fma(B.y, z1[r][k], bxw));
+              tc[k] = mk(fma(inv, b1.x, tc[k].x), fma(inv, b1.y, tc[k].y));
+            }
           }
         }
       } else if (!occ) {
