@@ -267,7 +267,7 @@ __device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) 
 }
 
 // Qt[k] (32 x 32, rows = columns of W) for pair k of round r
-__global__ void __launch_bounds__(256) k_bj_solve(const cpx<double>* __restrict__ A, int Np,
+__global__ void __launch_bounds__(512) k_bj_solve(const cpx<double>* __restrict__ A, int Np,
                                                   int nblk, int r, cpx<double>* __restrict__ Qt) {
   __shared__ cpx<double> S[kBJ2][kBJ2 + 1];
   __shared__ cpx<double> W[kBJ2][kBJ2 + 1];  // W^T: row x = column x of W
@@ -617,7 +617,7 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
   const dim3 growmix(npairs, (Np + kRC - 1) / kRC), gmix(npairs, (Np + 63) / 64);
   for (int r = 0; r < nblk - 1; ++r) {
-    hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(256), 0, sg.cap, Ap, Np, nblk, r, Qt);
+    hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(512), 0, sg.cap, Ap, Np, nblk, r, Qt);
     hipLaunchKernelGGL(k_bj_rowmix, growmix, dim3(256), 0, sg.cap, Ap, Tp, Vp, Np, nblk, r, Qt);
     hipLaunchKernelGGL(k_bj_colmix, gmix, dim3(256), 0, sg.cap, Tp, Ap, Np, nblk, r, Qt);
   }
