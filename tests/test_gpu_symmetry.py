@@ -154,6 +154,19 @@ def test_chi0_symmetrize_matches_oracle(P, ctx, model):
     assert np.abs(out.cpu().numpy() - want).max() < 1e-14 * np.abs(want).max()
 
 
+def test_empty_calls_are_no_ops(P, ctx, model):
+    gin = g_sphere(CELL, (0, 0, 0), 20.0)
+    c = torch.zeros((0, 2, len(gin)), dtype=torch.complex128, device="cuda:0")
+    out = torch.zeros((0, 2, len(gin)), dtype=torch.complex128, device="cuda:0")
+    s, tau = model.ops[1]
+    P.gw_unfold_spinor(ctx, 2, gin, c, gin, s, tau, CELL, out)  # no bands
+    q = np.array([0.0, 0.0, 1.0 / 3.0])
+    geps = g_sphere(CELL, q, 3.0)
+    x = torch.zeros((0, len(geps), len(geps)), dtype=torch.complex128, device="cuda:0")
+    P.gw_chi0_symmetrize(ctx, geps, q, _little(model, q), x, torch.empty_like(x))  # no frequencies
+    torch.cuda.synchronize()
+
+
 def test_chi0_symmetrize_rejects_bad_arguments(P, ctx, model):
     q = np.array([0.0, 0.0, 1.0 / 3.0])
     geps = g_sphere(CELL, q, 3.0)
