@@ -26,12 +26,13 @@ __global__ void k_conj_scale(const cpx<Tin>* __restrict__ m, size_t rows, int N,
   out[e] = mk(s * (double)a.x, -s * (double)a.y);
 }
 
-// out[g][r] = m[r][g], widened to double; 32 x 32 tiles through LDS
+// out[g][r] = m[r][g], widened to double; 32 x 32 tiles through LDS, row tiles
+// on the grid's x dimension (the row count nv^2 may pass 65535 tiles), G tiles on y
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_transpose(const cpx<Tin>* __restrict__ m, int rows,
                                                    int N, cpx<double>* __restrict__ out) {
   __shared__ cpx<double> t[32][33];
-  const int g0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int g0 = blockIdx.y * 32, r0 = blockIdx.x * 32;
   for (int i = threadIdx.y; i < 32; i += 8) {
     const int r = r0 + i, g = g0 + threadIdx.x;
     if (r < rows && g < N) {
@@ -78,11 +79,11 @@ static gw_status bse_run(gw_ctx* c, int nv, int nc, int N, const void* mvc, cons
     ProfScope ps(c, "bse_prep");
     hipLaunchKernelGGL(k_conj_scale<Tin>, dim3((unsigned)((nX + 255) / 256)), dim3(256), 0,
                        c->stream, static_cast<const cpx<Tin>*>(mvc), P, N, vx, X);
-    hipLaunchKernelGGL(k_transpose<Tin>, dim3((N + 31) / 32, (unsigned)((P + 31) / 32)), tb, 0,
+    hipLaunchKernelGGL(k_transpose<Tin>, dim3((unsigned)((P + 31) / 32), (N + 31) / 32), tb, 0,
                        c->stream, static_cast<const cpx<Tin>*>(mvc), (int)P, N, Mt);
     hipLaunchKernelGGL(k_conj_scale<Tin>, dim3((unsigned)((nT + 255) / 256)), dim3(256), 0,
                        c->stream, static_cast<const cpx<Tin>*>(mcc), C2, N, nullptr, Cc);
-    hipLaunchKernelGGL(k_transpose<Tin>, dim3((N + 31) / 32, (unsigned)((V2 + 31) / 32)), tb, 0,
+    hipLaunchKernelGGL(k_transpose<Tin>, dim3((unsigned)((V2 + 31) / 32), (N + 31) / 32), tb, 0,
                        c->stream, static_cast<const cpx<Tin>*>(mvv), (int)V2, N, MvT);
     GW_CHECK_LAUNCH(c, "bse operand preparation");
   }

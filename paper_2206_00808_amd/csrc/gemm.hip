@@ -322,12 +322,18 @@ gw_status zgemm_nn(gw_ctx* c, int m, int n, int k, double alpha, const double* A
     return fail(c, GW_EINVAL, "zgemm operand out of range (m=%d n=%d k=%d batch=%d)", m, n, k,
                 batch);
   ProfScope ps(c, "zgemm");
-  dim3 g((n + ZTM - 1) / ZTM, (m + ZTM - 1) / ZTM, batch);
-  hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, m, n, k, alpha, beta,
-                     reinterpret_cast<const cpx<double>*>(A) + offA, lda, sA,
-                     reinterpret_cast<const cpx<double>*>(B) + offB, ldb, sB,
-                     reinterpret_cast<cpx<double>*>(C) + offC, ldc, sC);
-  GW_CHECK_LAUNCH(c, "k_zgemm_nn");
+  // the grid's y dimension counts row tiles and is limited to 65535, so taller
+  // operands run as several launches over consecutive row ranges
+  constexpr int kRowsPerLaunch = 65535 * ZTM;
+  for (long long r0 = 0; r0 < m; r0 += kRowsPerLaunch) {
+    const int mr = (int)std::min<long long>(kRowsPerLaunch, m - r0);
+    dim3 g((n + ZTM - 1) / ZTM, (mr + ZTM - 1) / ZTM, batch);
+    hipLaunchKernelGGL(k_zgemm_nn, g, dim3(256), 0, c->stream, mr, n, k, alpha, beta,
+                       reinterpret_cast<const cpx<double>*>(A) + offA + (size_t)r0 * lda, lda, sA,
+                       reinterpret_cast<const cpx<double>*>(B) + offB, ldb, sB,
+                       reinterpret_cast<cpx<double>*>(C) + offC + (size_t)r0 * ldc, ldc, sC);
+    GW_CHECK_LAUNCH(c, "k_zgemm_nn");
+  }
   return GW_OK;
 }
 

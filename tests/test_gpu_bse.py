@@ -53,6 +53,21 @@ def test_bse_kernel_matches_oracle(P, ctx, dtype, nv, nc, n):
     assert np.abs(kd - wd).max() < 1e-13 * np.abs(wd).max()
 
 
+@pytest.mark.parametrize("nv,nc", [(1, 2100), (1500, 1)])
+def test_bse_kernel_tall_operands(P, ctx, nv, nc):
+    """nc^2 = 4.41e6 rows in conj(M_cc') W pass 65535 row tiles of 64 and run as
+    two GEMM launches; nv^2 = 2.25e6 rows of M_vv' pass 65535 transpose tiles of 32."""
+    rng = np.random.default_rng(nv + nc)
+    n = 2
+    mvc, mcc, mvv = _rc(rng, (nv, nc, n)), _rc(rng, (nc, nc, n)), _rc(rng, (nv, nv, n))
+    vx = rng.uniform(0.5, 2.0, n)
+    w = _rc(rng, (n, n))
+    kx, kd = _run(P, ctx, mvc, mcc, mvv, vx, w)
+    wx, wd = oracle.bse_kernel(mvc, mcc, mvv, vx, w)
+    assert np.abs(kx - wx).max() < 1e-13 * np.abs(wx).max()
+    assert np.abs(kd - wd).max() < 1e-13 * np.abs(wd).max()
+
+
 def test_bse_kernel_from_gpu_matrix_elements(P, ctx):
     """M_vc, M_cc' and M_vv' at q = 0 from gw_mtxel_spinor, then the kernels; against
     the oracle's matrix elements and kernels.  v_x drops G = 0; W is Hermitian and
