@@ -244,14 +244,14 @@ __global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<dou
 // For larger N the rotations act on pairs of 16-wide blocks: a round pairs the
 // nblk blocks in round-robin order; each pair's 32 x 32 Hermitian sub-matrix is
 // diagonalised in LDS by a few inner sweeps of the same scalar rotations, and the
-// accumulated 32 x 32 unitary W then updates the pair's block rows (W^H A), the
-// eigenvector rows (W^T Vt) and, in a second pass, the pair's block columns (A W).
+// accumulated 32 x 32 unitaries then update A in one pass: the tile on the rows
+// of pair P and the columns of pair Q becomes W_P^H A W_Q, and the eigenvector
+// rows of pair P become W_P^T Vt.
 // The matrix is padded to a multiple of 32 with zero rows and columns, which no
 // rotation ever touches (their off-diagonal entries stay 0).
 constexpr int kBJ = 16;           // block width
 constexpr int kBJ2 = 2 * kBJ;     // sub-problem size
 constexpr int kBJInner = 1;       // inner sweeps per round
-constexpr int kRC = 32;           // columns per row-update workgroup
 
 __device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) {
   int a, b;
@@ -356,67 +356,84 @@ __global__ void __launch_bounds__(512) k_bj_solve(const cpx<double>* __restrict_
   for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) out[e] = W[e / kBJ2][e % kBJ2];
 }
 
-// T[rows of pair k][chunk] = W^H A[rows][chunk];  Vt[rows][chunk] = W^T Vt[rows][chunk]
-__global__ void __launch_bounds__(256) k_bj_rowmix(const cpx<double>* __restrict__ A,
-                                                   cpx<double>* __restrict__ T,
-                                                   cpx<double>* __restrict__ Vt, int Np, int nblk,
-                                                   int r, const cpx<double>* __restrict__ Qt) {
-  __shared__ cpx<double> w[kBJ2][kBJ2 + 1];
-  __shared__ cpx<double> a[kBJ2][kRC];
-  __shared__ cpx<double> v[kBJ2][kRC];
-  int I, J;
+// One round's update of A and of the eigenvector rows in a single pass, in place:
+//   - blockIdx.y < npairs: the 32 x 32 tile of A on the rows of pair P =
+//     blockIdx.x and the columns of pair Q = blockIdx.y becomes W_P^H A[P][Q] W_Q
+//     (every tile belongs to one workgroup, which reads it before writing it);
+//   - blockIdx.y >= npairs: 32 columns of the eigenvector rows of pair P become
+//     W_P^T V[P][cols].
+// Qt holds W transposed per pair: Qt[x][y] = W[y][x].
+__global__ void __launch_bounds__(256) k_bj_mix(cpx<double>* __restrict__ A,
+                                                cpx<double>* __restrict__ Vt, int Np, int nblk,
+                                                int r, const cpx<double>* __restrict__ Qt) {
+  __shared__ cpx<double> wp[kBJ2][kBJ2 + 1];
+  __shared__ cpx<double> wq[kBJ2][kBJ2 + 1];  // wq[y][z] = W_Q[y][z]
+  __shared__ cpx<double> a[kBJ2][kBJ2 + 1];
+  constexpr int kPer = kBJ2 * kBJ2 / 256;
+  const int npairs = nblk / 2, t = threadIdx.x;
+  const bool vpart = (int)blockIdx.y >= npairs;
+  int I, J, I2 = 0, J2 = 0;
   bj_pair(nblk, r, blockIdx.x, &I, &J);
-  const int t = threadIdx.x, c0 = blockIdx.y * kRC;
-  const cpx<double>* q = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
-  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) w[e / kBJ2][e % kBJ2] = q[e];
-  for (int e = t; e < kBJ2 * kRC; e += blockDim.x) {
-    const int x = e / kRC, j = c0 + e % kRC;
-    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
-    a[x][e % kRC] = j < Np ? A[(size_t)g * Np + j] : mk(0.0, 0.0);
-    v[x][e % kRC] = j < Np ? Vt[(size_t)g * Np + j] : mk(0.0, 0.0);
+  const cpx<double>* qp = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) wp[e / kBJ2][e % kBJ2] = qp[e];
+  if (!vpart) {
+    bj_pair(nblk, r, blockIdx.y, &I2, &J2);
+    const cpx<double>* qq = Qt + (size_t)blockIdx.y * kBJ2 * kBJ2;
+    for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) wq[e % kBJ2][e / kBJ2] = qq[e];
+  }
+  const int c0 = vpart ? ((int)blockIdx.y - npairs) * kBJ2 : 0;
+  auto grow = [](int x, int i, int j) { return x < kBJ ? i * kBJ + x : j * kBJ + x - kBJ; };
+  auto gcol = [&](int z) { return vpart ? c0 + z : grow(z, I2, J2); };
+  cpx<double>* M = vpart ? Vt : A;
+  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) {
+    const int y = e / kBJ2, z = e % kBJ2;
+    a[y][z] = M[(size_t)grow(y, I, J) * Np + gcol(z)];
   }
   __syncthreads();
-  for (int e = t; e < kBJ2 * kRC; e += blockDim.x) {
-    const int x = e / kRC, jj = e % kRC, j = c0 + jj;
-    if (j >= Np) continue;
-    cpx<double> sa = mk(0.0, 0.0), sv = mk(0.0, 0.0);
+  // thread t holds rows x0 + 8k of column z of each product (four independent sums)
+  const int x0 = t / kBJ2, zt = t % kBJ2;
+  cpx<double> s[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) s[k] = mk(0.0, 0.0);
+  // (W^H)[x][y] = conj(Qt[x][y]);  (W^T)[x][y] = Qt[x][y]
+  if (vpart) {
     for (int y = 0; y < kBJ2; ++y) {
-      // (W^H)[x][y] = conj(W[y][x]) = conj(Wt[x][y]);  (W^T)[x][y] = Wt[x][y]
-      sa = sa + cmulc(w[x][y], a[y][jj]);
-      sv = sv + cmul(w[x][y], v[y][jj]);
+      const cpx<double> b = a[y][zt];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmul(wp[x0 + 8 * k][y], b);
     }
-    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
-    T[(size_t)g * Np + j] = sa;
-    Vt[(size_t)g * Np + j] = sv;
+  } else {
+    for (int y = 0; y < kBJ2; ++y) {
+      const cpx<double> b = a[y][zt];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmulc(wp[x0 + 8 * k][y], b);
+    }
   }
-}
-
-// A[chunk][cols of pair k] = T[chunk][cols] W
-__global__ void __launch_bounds__(256) k_bj_colmix(const cpx<double>* __restrict__ T,
-                                                   cpx<double>* __restrict__ A, int Np, int nblk,
-                                                   int r, const cpx<double>* __restrict__ Qt) {
-  __shared__ cpx<double> w[kBJ2][kBJ2 + 1];
-  __shared__ cpx<double> tt[64][kBJ2 + 1];
-  int I, J;
-  bj_pair(nblk, r, blockIdx.x, &I, &J);
-  const int t = threadIdx.x, r0 = blockIdx.y * 64;
-  const cpx<double>* q = Qt + (size_t)blockIdx.x * kBJ2 * kBJ2;
-  for (int e = t; e < kBJ2 * kBJ2; e += blockDim.x) w[e / kBJ2][e % kBJ2] = q[e];
-  for (int e = t; e < 64 * kBJ2; e += blockDim.x) {
-    const int i = r0 + e / kBJ2, y = e % kBJ2;
-    const int g = (y < kBJ ? I * kBJ + y : J * kBJ + y - kBJ);
-    tt[e / kBJ2][y] = i < Np ? T[(size_t)i * Np + g] : mk(0.0, 0.0);
+  if (vpart) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = t + 256 * k, x = e / kBJ2, z = e % kBJ2;
+      Vt[(size_t)grow(x, I, J) * Np + c0 + z] = s[k];
+    }
+    return;
+  }
+  __syncthreads();  // every read of the tile is done
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int e = t + 256 * k;
+    a[e / kBJ2][e % kBJ2] = s[k];
   }
   __syncthreads();
-  for (int e = t; e < 64 * kBJ2; e += blockDim.x) {
-    const int ii = e / kBJ2, x = e % kBJ2, i = r0 + ii;
-    if (i >= Np) continue;
-    cpx<double> s = mk(0.0, 0.0);
-    // (T W)[i][x] = sum_y T[i][y] W[y][x] = sum_y T[i][y] Wt[x][y]
-    for (int y = 0; y < kBJ2; ++y) s = s + cmul(tt[ii][y], w[x][y]);
-    const int g = (x < kBJ ? I * kBJ + x : J * kBJ + x - kBJ);
-    A[(size_t)i * Np + g] = s;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) s[k] = mk(0.0, 0.0);
+  for (int y = 0; y < kBJ2; ++y) {
+    const cpx<double> b = wq[y][zt];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmul(a[x0 + 8 * k][y], b);
   }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    A[(size_t)grow(x0 + 8 * k, I, J) * Np + grow(zt, I2, J2)] = s[k];
 }
 
 // zero-padded copy: dst (Np x Np) from src (N x N)
@@ -571,7 +588,7 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   const int Np = (N + kBJ2 - 1) / kBJ2 * kBJ2;
   const int nblk = Np / kBJ, npairs = nblk / 2;
   const size_t nnp = (size_t)Np * Np;
-  const size_t bytes = 3 * align_up(nnp * 16) + align_up((size_t)npairs * kBJ2 * kBJ2 * 16) +
+  const size_t bytes = 2 * align_up(nnp * 16) + align_up((size_t)npairs * kBJ2 * kBJ2 * 16) +
                        align_up(2 * 1024 * 8) + align_up((size_t)N * 4) + 1024;
   char* base = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
@@ -591,7 +608,6 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
     return p;
   };
   auto* Ap = reinterpret_cast<cpx<double>*>(take(nnp * 16));
-  auto* Tp = reinterpret_cast<cpx<double>*>(take(nnp * 16));
   auto* Vp = reinterpret_cast<cpx<double>*>(take(nnp * 16));
   auto* Qt = reinterpret_cast<cpx<double>*>(take((size_t)npairs * kBJ2 * kBJ2 * 16));
   auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
@@ -615,11 +631,10 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   } sg;
   GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
   GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
-  const dim3 growmix(npairs, (Np + kRC - 1) / kRC), gmix(npairs, (Np + 63) / 64);
   for (int r = 0; r < nblk - 1; ++r) {
     hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(512), 0, sg.cap, Ap, Np, nblk, r, Qt);
-    hipLaunchKernelGGL(k_bj_rowmix, growmix, dim3(256), 0, sg.cap, Ap, Tp, Vp, Np, nblk, r, Qt);
-    hipLaunchKernelGGL(k_bj_colmix, gmix, dim3(256), 0, sg.cap, Tp, Ap, Np, nblk, r, Qt);
+    hipLaunchKernelGGL(k_bj_mix, dim3(npairs, 2 * npairs), dim3(256), 0, sg.cap, Ap, Vp, Np, nblk,
+                       r, Qt);
   }
   {
     const hipError_t le = hipGetLastError();
