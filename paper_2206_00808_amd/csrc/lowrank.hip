@@ -267,6 +267,19 @@ __device__ __forceinline__ void bj_pair(int nblk, int r, int k, int* I, int* J) 
 }
 
 // Qt[k] (32 x 32, rows = columns of W) for pair k of round r
+// Reciprocal and reciprocal square root from the hardware estimates refined by
+// two Newton steps (about one ulp); finite, positive, normal arguments only.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+
 __global__ void __launch_bounds__(512) k_bj_solve(const cpx<double>* __restrict__ A, int Np,
                                                   int nblk, int r, cpx<double>* __restrict__ Qt) {
   __shared__ cpx<double> S[kBJ2][kBJ2 + 1];
@@ -309,15 +322,27 @@ __global__ void __launch_bounds__(512) k_bj_solve(const cpx<double>* __restrict_
         o.er = 1.0;
         o.ei = 0.0;
         const cpx<double> b = S[p][q];
-        const double ab = hypot(b.x, b.y);
-        if (ab > 0.0) {
+        const double n2 = b.x * b.x + b.y * b.y;
+        // below 1e-300 the entry is far under the convergence threshold; skipping
+        // it also keeps the reciprocal square root away from subnormal input
+        if (n2 > 1e-300) {
           const double a = S[p][p].x, d = S[q][q].x;
-          const double tau = (d - a) / (2.0 * ab);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          o.c = 1.0 / sqrt(1.0 + tt * tt);
+          const double rab = rsq_nr(n2);  // 1/|b|
+          const double tau = 0.5 * (d - a) * rab;
+          const double at = fabs(tau);
+          // tt = sign(tau) / (|tau| + sqrt(1 + tau^2)), the smaller root
+          double tt;
+          if (at < 1e100) {
+            const double u = fma(tau, tau, 1.0);
+            tt = rcp_nr(at + u * rsq_nr(u));
+          } else {
+            tt = 0.5 * rcp_nr(at);
+          }
+          if (tau < 0.0) tt = -tt;
+          o.c = rsq_nr(fma(tt, tt, 1.0));
           o.s = tt * o.c;
-          o.er = b.x / ab;
-          o.ei = b.y / ab;
+          o.er = b.x * rab;
+          o.ei = b.y * rab;
           o.skip = 0;
         }
         prm[t] = o;
