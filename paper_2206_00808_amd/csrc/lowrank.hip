@@ -240,6 +240,8 @@ __global__ void k_lr_copy(const cpx<double>* __restrict__ src, size_t n, cpx<dou
   if (e < n) dst[e] = src[e];
 }
 
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- block Jacobi
 // For larger N the rotations act on pairs of 16-wide blocks: a round pairs the
 // nblk blocks in round-robin order; each pair's 32 x 32 Hermitian sub-matrix is
@@ -394,7 +396,6 @@ __global__ void __launch_bounds__(256) k_bj_mix(cpx<double>* __restrict__ A,
   __shared__ cpx<double> wp[kBJ2][kBJ2 + 1];
   __shared__ cpx<double> wq[kBJ2][kBJ2 + 1];  // wq[y][z] = W_Q[y][z]
   __shared__ cpx<double> a[kBJ2][kBJ2 + 1];
-  constexpr int kPer = kBJ2 * kBJ2 / 256;
   const int npairs = nblk / 2, t = threadIdx.x;
   const bool vpart = (int)blockIdx.y >= npairs;
   int I, J, I2 = 0, J2 = 0;
@@ -415,50 +416,46 @@ __global__ void __launch_bounds__(256) k_bj_mix(cpx<double>* __restrict__ A,
     a[y][z] = M[(size_t)grow(y, I, J) * Np + gcol(z)];
   }
   __syncthreads();
-  // thread t holds rows x0 + 8k of column z of each product (four independent sums)
-  const int x0 = t / kBJ2, zt = t % kBJ2;
-  cpx<double> s[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) s[k] = mk(0.0, 0.0);
-  // (W^H)[x][y] = conj(Qt[x][y]);  (W^T)[x][y] = Qt[x][y]
-  if (vpart) {
-    for (int y = 0; y < kBJ2; ++y) {
-      const cpx<double> b = a[y][zt];
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmul(wp[x0 + 8 * k][y], b);
-    }
-  } else {
-    for (int y = 0; y < kBJ2; ++y) {
-      const cpx<double> b = a[y][zt];
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmulc(wp[x0 + 8 * k][y], b);
-    }
+  // Both 32 x 32 complex products run on the FP64 matrix cores: each wavefront
+  // owns one 16 x 16 quadrant, three real v_mfma_f64_16x16x4_f64 products per
+  // complex one (Re = t1 - t2, Im = t3 - t1 - t2), operand fragments read from
+  // LDS (A operand: row l16, k lk; B operand: k lk, column l16; result element
+  // e of a lane at row lk + 4e, column l16).
+  const int lane = t & 63, wave = t >> 6, l16 = lane & 15, lk = lane >> 4;
+  const int xq = (wave >> 1) * 16, zq = (wave & 1) * 16;
+  const double sgn = vpart ? 1.0 : -1.0;  // W^T for the eigenvector rows, W^H for A
+  v4f64 t1 = {0, 0, 0, 0}, t2 = t1, t3 = t1;
+  for (int k0 = 0; k0 < kBJ2; k0 += 4) {
+    const cpx<double> fa = wp[xq + l16][k0 + lk], fb = a[k0 + lk][zq + l16];
+    const double ar = fa.x, ai = sgn * fa.y;
+    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, fb.x, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, fb.y, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, fb.x + fb.y, t3, 0, 0, 0);
   }
   if (vpart) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int e = t + 256 * k, x = e / kBJ2, z = e % kBJ2;
-      Vt[(size_t)grow(x, I, J) * Np + c0 + z] = s[k];
-    }
+    for (int e = 0; e < 4; ++e)
+      Vt[(size_t)grow(xq + lk + 4 * e, I, J) * Np + c0 + zq + l16] =
+          mk(t1[e] - t2[e], (t3[e] - t1[e]) - t2[e]);
     return;
   }
-  __syncthreads();  // every read of the tile is done
+  __syncthreads();  // every fragment read of the tile is done
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int e = t + 256 * k;
-    a[e / kBJ2][e % kBJ2] = s[k];
-  }
+  for (int e = 0; e < 4; ++e) a[xq + lk + 4 * e][zq + l16] = mk(t1[e] - t2[e], (t3[e] - t1[e]) - t2[e]);
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) s[k] = mk(0.0, 0.0);
-  for (int y = 0; y < kBJ2; ++y) {
-    const cpx<double> b = wq[y][zt];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) s[k] = s[k] + cmul(a[x0 + 8 * k][y], b);
+  t1 = (v4f64){0, 0, 0, 0};
+  t2 = t1;
+  t3 = t1;
+  for (int k0 = 0; k0 < kBJ2; k0 += 4) {
+    const cpx<double> fa = a[xq + l16][k0 + lk], fb = wq[k0 + lk][zq + l16];
+    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x, fb.x, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.y, fb.y, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x + fa.y, fb.x + fb.y, t3, 0, 0, 0);
   }
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    A[(size_t)grow(x0 + 8 * k, I, J) * Np + grow(zt, I2, J2)] = s[k];
+  for (int e = 0; e < 4; ++e)
+    A[(size_t)grow(xq + lk + 4 * e, I, J) * Np + grow(zq + l16, I2, J2)] =
+        mk(t1[e] - t2[e], (t3[e] - t1[e]) - t2[e]);
 }
 
 // zero-padded copy: dst (Np x Np) from src (N x N)
