@@ -329,7 +329,8 @@ __global__ void __launch_bounds__(512) k_bj_solve(const cpx<double>* __restrict_
         // it also keeps the reciprocal square root away from subnormal input
         if (n2 > 1e-300) {
           const double a = S[p][p].x, d = S[q][q].x;
-          const double rab = rsq_nr(n2);  // 1/|b|
+          // 1/|b|; squares past 1e300 (|b| above 1e150) take the IEEE route
+          const double rab = n2 < 1e300 ? rsq_nr(n2) : 1.0 / hypot(b.x, b.y);
           const double tau = 0.5 * (d - a) * rab;
           const double at = fabs(tau);
           // tt = sign(tau) / (|tau| + sqrt(1 + tau^2)), the smaller root
