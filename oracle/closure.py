@@ -15,9 +15,12 @@ heuristic, so this oracle is its written-out algorithm:
   update     Adam with bias correction
   result     chi_out = chi_t + s * Hermitise(y): (G,G') gets y, (G',G) its conjugate
 
-parity unpinned: nothing in the paper fixes what the network should output.
-Its gradients are pinned by central finite differences, and its Adam step by
-the closed form of the first step.
+What the network should output is not fixed by the paper: the full band sum
+is the judge of its error.  The functions themselves are pinned independently:
+the forward pass and the gradients by torch's float64 autograd of the same SiLU
+network (and the gradients also by central finite differences), the Adam update
+by torch.optim.Adam over several steps, and the feature table by a hand-built
+three-vector case.
 """
 from __future__ import annotations
 
