@@ -481,6 +481,10 @@ gw_status gw_mlp_destroy(gw_mlp* net);
  * host_buf = NULL to query *nbytes. */
 gw_status gw_mlp_save(const gw_mlp* net, void* host_buf, size_t* nbytes);
 gw_status gw_mlp_load(gw_mlp* net, const void* host_buf, size_t nbytes);
+/* Largest rel_F against the full sum at which gw_chi0_closure keeps a
+ * prediction (INFER with chi0_full); default 1e-4.  GW_EINVAL if tol < 0 or
+ * non-finite. */
+gw_status gw_mlp_set_tolerance(gw_mlp* net, double tol);
 
 /*
  * gw_chi0_closure -- predict the remainder chi0_full - chi0_trunc of one
@@ -494,9 +498,13 @@ gw_status gw_mlp_load(gw_mlp* net, const void* host_buf, size_t nbytes);
  *   lr          Adam learning rate (TRAIN_STEP).
  *   loss        (host) out float: the MSE before the step, or NULL.
  *   chi0_out    (device) out complex double[neps][neps] (INFER, FULL_FALLBACK).
- * In INFER mode, if the corrected matrix is not negative semidefinite (a
- * double-precision Cholesky of -chi0_out fails) and chi0_full is given, the
- * full sum is written instead and GW_EFALLBACK is returned.
+ * In INFER mode with chi0_full given, the full sum judges the prediction:
+ * rel_F = ||chi0_out - chi0_full||_F / ||chi0_full||_F is reduced on the device
+ * in a fixed order, and if it exceeds the network's tolerance
+ * (gw_mlp_set_tolerance, default 1e-4) or the corrected matrix is not negative
+ * semidefinite (a double-precision Cholesky of -chi0_out fails), the full sum is
+ * written instead and GW_EFALLBACK is returned.  That check synchronises the
+ * context stream.  Without chi0_full the prediction is returned unjudged.
  */
 gw_status gw_chi0_closure(gw_ctx* ctx, gw_mlp* net, int mode, int neps,
                           const double* qG, const double* chi0_trunc, double gap,

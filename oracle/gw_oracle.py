@@ -81,7 +81,15 @@ def alias_free(gv, gc, geps, box):
     return bool(np.all(np.asarray(box) > m))
 
 
-def wavefunction_on_box(c, g, box):
+def _ifftn(a, axes, workers):
+    """numpy's inverse FFT, or scipy's with `workers` threads (the same transform)."""
+    if workers is None:
+        return np.fft.ifftn(a, axes=axes)
+    import scipy.fft
+    return scipy.fft.ifftn(a, axes=axes, workers=workers)
+
+
+def wavefunction_on_box(c, g, box, workers=None):
     """Periodic part of every spinor component on the real-space grid.
 
     Sec. II (matrix elements via FFT): the spinor components phi_{nk,alpha}(r)
@@ -96,21 +104,22 @@ def wavefunction_on_box(c, g, box):
     field = np.zeros((nb, ns) + box, dtype=np.complex128)
     o = box_offsets(g, box)
     field[:, :, o[:, 0], o[:, 1], o[:, 2]] = c
-    return np.fft.ifftn(field, axes=(2, 3, 4)) * float(np.prod(box))
+    return _ifftn(field, (2, 3, 4), workers) * float(np.prod(box))
 
 
-def mtxel_fft(cv, gv, cc, gc, geps, box):
+def mtxel_fft(cv, gv, cc, gc, geps, box, workers=None):
     """M_vc(G) by the route of Eq. (matrix_el): per spin component, the
     inverse-transform of the real-space product, then the sum over spin.
 
     Sec. II, Eq. (matrix_el) and the M_nn'(k,q,G) definition before it:
     for each spin alpha, rho_alpha(r) = conj(phi_{v,k+q,alpha}(r)) phi_{c,k,alpha}(r)
     is transformed with the exp(+i G.r)/N kernel and only then summed over
-    alpha.  Returns M[nv][nc][neps] complex128.
+    alpha.  Returns M[nv][nc][neps] complex128.  `workers` threads the FFTs
+    (scipy.fft) and changes nothing else.
     """
     box = tuple(int(x) for x in box)
-    uv = wavefunction_on_box(cv, gv, box)
-    uc = wavefunction_on_box(cc, gc, box)
+    uv = wavefunction_on_box(cv, gv, box, workers)
+    uc = wavefunction_on_box(cc, gc, box, workers)
     nv, ns = uv.shape[:2]
     nc = uc.shape[0]
     o = box_offsets(geps, box)
@@ -120,7 +129,7 @@ def mtxel_fft(cv, gv, cc, gc, geps, box):
             acc = np.zeros(len(geps), dtype=np.complex128)
             for s in range(ns):
                 rho = np.conj(uv[v, s]) * uc[c, s]
-                t = np.fft.ifftn(rho)
+                t = _ifftn(rho, (0, 1, 2), workers)
                 acc += t[o[:, 0], o[:, 1], o[:, 2]]
             out[v, c] = acc
     return out

@@ -31,7 +31,8 @@ EXPORTED = [
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
     "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits", "gw_epsinv_lowrank",
     "gw_lowrank_basis", "gw_mtxel_project", "gw_epsinv_from_basis", "gw_peak_probe",
-    "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_chi0_closure",
+    "gw_mlp_create", "gw_mlp_destroy", "gw_mlp_save", "gw_mlp_load", "gw_mlp_set_tolerance",
+    "gw_chi0_closure",
     "gw_plan_create", "gw_plan_compile", "gw_plan_launch", "gw_plan_destroy", "gw_plan_describe",
 ]
 
@@ -103,6 +104,7 @@ _SIG = {
     "gw_mlp_destroy": (_i, [_vp]),
     "gw_mlp_save": (_i, [_vp, _vp, ct.POINTER(ct.c_size_t)]),
     "gw_mlp_load": (_i, [_vp, _vp, ct.c_size_t]),
+    "gw_mlp_set_tolerance": (_i, [_vp, _d]),
     "gw_chi0_closure": (_i, [_vp, _vp, _i, _i, _vp, _vp, _d, _d, _vp, ct.c_float,
                              ct.POINTER(ct.c_float), _vp]),
     "gw_plan_create": (_i, [_vp, ct.POINTER(_vp), _ip, _i, _i, _i, _i, _vp, _d, _i,
@@ -559,6 +561,10 @@ class Mlp:
     def load(self, blob):
         buf = ct.create_string_buffer(blob, len(blob))
         _check(self.ctx, _lib.gw_mlp_load(self.handle, buf, len(blob)))
+
+    def set_tolerance(self, tol):
+        """Largest rel_F against the full sum at which a judged prediction is kept."""
+        _check(self.ctx, _lib.gw_mlp_set_tolerance(self.handle, float(tol)))
 
     def close(self):
         if getattr(self, "handle", None) and getattr(self.ctx, "handle", None):

@@ -75,14 +75,18 @@ def _rel(x, ref):
 
 def evaluate(ctx, net, items):
     """Per system: relative Frobenius errors against the full sum, for chi0 and
-    eps^-1, of the truncated sum and of the corrected sum; and whether the
-    corrected matrix fell back to the full sum."""
+    eps^-1, of the truncated sum and of the network's prediction (inferred
+    without the full sum); then the judged call (with the full sum), whether it
+    fell back to the full sum and the error of what it returned."""
     rows = []
     for it in items:
         out = torch.empty_like(it["chi_f"])
+        B.gw_chi0_closure(ctx, net, B.GW_CLOSURE_INFER, it["neps"], it["qg"], it["chi_t"],
+                          it["gap"], it["emax"], chi0_out=out)
+        judged = torch.empty_like(it["chi_f"])
         st, _ = B.gw_chi0_closure(ctx, net, B.GW_CLOSURE_INFER, it["neps"], it["qg"],
                                   it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
-                                  chi0_out=out)
+                                  chi0_out=judged)
         n = it["neps"]
         inv = {}
         for key, chi in (("t", it["chi_t"]), ("c", out), ("f", it["chi_f"])):
@@ -92,6 +96,7 @@ def evaluate(ctx, net, items):
         torch.cuda.synchronize()
         rows.append(dict(
             name=it["name"], neps=n, fallback=st == B.GW_EFALLBACK,
+            chi_judged=_rel(judged, it["chi_f"]),
             chi_trunc=_rel(it["chi_t"], it["chi_f"]), chi_closure=_rel(out, it["chi_f"]),
             epsinv_trunc=_rel(inv["t"], inv["f"]), epsinv_closure=_rel(inv["c"], inv["f"]),
         ))

@@ -55,6 +55,59 @@ void* ws_take(gw_ctx* c, size_t bytes) {
   return p;
 }
 
+static void pin_release(gw_ctx* c) {
+  for (auto& r : c->pin_recs) (void)hipEventDestroy(r.ev);
+  c->pin_recs.clear();
+  if (c->pin) (void)hipHostFree(c->pin);
+  c->pin = nullptr;
+  c->pin_cap = 0;
+  c->pin_off = 0;
+}
+
+gw_status stage_h2d(gw_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return GW_OK;
+  const size_t need = align_up(bytes);
+  if (need > c->pin_cap) {
+    // grow: every earlier copy must have read its range before the free
+    for (auto& r : c->pin_recs) {
+      const hipError_t e = hipEventSynchronize(r.ev);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    }
+    pin_release(c);
+    const size_t cap = std::max<size_t>(64u << 10, 2 * need);
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, cap, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(c, GW_ENOMEM, "pinned staging of %zu bytes: %s", cap,
+                                     hipGetErrorString(e));
+    c->pin = static_cast<char*>(p);
+    c->pin_cap = cap;
+    c->pin_off = 0;
+  }
+  if (c->pin_off + need > c->pin_cap) c->pin_off = 0;
+  const size_t a = c->pin_off, b = a + need;
+  // wait for (almost always long finished) copies that still read [a, b)
+  for (size_t i = 0; i < c->pin_recs.size();) {
+    PinRec& r = c->pin_recs[i];
+    if (r.a < b && a < r.b) {
+      const hipError_t e = hipEventSynchronize(r.ev);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+      (void)hipEventDestroy(r.ev);
+      c->pin_recs.erase(c->pin_recs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  std::memcpy(c->pin + a, src, bytes);
+  GW_HIP(c, hipMemcpyAsync(dst, c->pin + a, bytes, hipMemcpyHostToDevice, c->stream));
+  hipEvent_t ev;
+  GW_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  const hipError_t e = hipEventRecord(ev, c->stream);
+  if (e != hipSuccess) { (void)hipEventDestroy(ev); return hip_fail(c, e, "hipEventRecord"); }
+  c->pin_recs.push_back(PinRec{a, b, ev});
+  c->pin_off = b;
+  return GW_OK;
+}
+
 static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
   const unsigned char* p = static_cast<const unsigned char*>(data);
   for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ull; }
@@ -142,6 +195,86 @@ static bool factorable(int n) {
 
 static bool g_ok(const int32_t* g, int n) { return n == 0 || g != nullptr; }
 
+// FP64 G = 0 overlaps of the small-q head (head.hip), from the G vectors the
+// two spheres share
+static gw_status mtxel_head(gw_ctx* c, gw_dtype dtype, int nspinor, int nv, int ngv,
+                            const int32_t* gv, const void* cv, int nc, int ngc,
+                            const int32_t* gc, const void* cc, double* mhead) {
+  std::vector<int> match;
+  std::map<std::tuple<int, int, int>, int> lut;
+  for (int i = 0; i < ngc; ++i) lut[std::make_tuple(gc[3 * i], gc[3 * i + 1], gc[3 * i + 2])] = i;
+  for (int i = 0; i < ngv; ++i) {
+    auto it = lut.find(std::make_tuple(gv[3 * i], gv[3 * i + 1], gv[3 * i + 2]));
+    if (it != lut.end()) { match.push_back(i); match.push_back(it->second); }
+  }
+  const int nm = (int)match.size() / 2;
+  if (nm == 0) {
+    GW_HIP(c, hipMemsetAsync(mhead, 0, (size_t)nv * nc * 16, c->stream));
+    return GW_OK;
+  }
+  gw_status st = ws_begin(c, align_up(match.size() * sizeof(int)));
+  if (st != GW_OK) return st;
+  int* dmatch = static_cast<int*>(ws_take(c, match.size() * sizeof(int)));
+  if ((st = stage_h2d(c, dmatch, match.data(), match.size() * sizeof(int))) != GW_OK) return st;
+  return head_overlap(c, dtype, nspinor, nv, ngv, cv, nc, ngc, cc, dmatch, nm, mhead);
+}
+
+// Matrix elements on boxes with a built xy-plane pair kernel (fft_xy.hip):
+// valence bands as full fields in [v][s][z][y][x] order, conduction bands as
+// compact z-transformed slabs, pairs in chunks of at most 4 GiB of intermediate.
+static gw_status mtxel_xy(gw_ctx* c, const int box[3], int nspinor, int nv, int ngv,
+                          const void* cv, int nc, int ngc, const void* cc, gw_dtype dtype,
+                          const SphereMap* sv, const SphereMap* sc, const SphereMap* se,
+                          void* mtxel, int head_index, double* mhead, const int32_t* gv,
+                          const int32_t* gc) {
+  const size_t elem = dtype == GW_C128 ? 16 : 8;
+  const size_t nbox = (size_t)box[0] * box[1] * box[2];
+  const size_t uv_bytes = (size_t)nv * nspinor * nbox * elem;
+  const size_t uc_bytes = band_zc_bytes(box, sc, nc * nspinor, elem);
+  const size_t band_per = band_scratch_bytes(box, sv, 1, elem);
+  const int band_chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nv * nspinor,
+                                                                   (512ull << 20) / band_per));
+  const size_t band_bytes = band_per * band_chunk;
+  const size_t pair_per = pair_xy_scratch_bytes(box, se, 1, elem);
+  int max_pairs = (int)std::max<size_t>(1, (4ull << 30) / pair_per);
+  if (max_pairs > 65535) max_pairs = 65535;
+  const int vt = std::min(nv, max_pairs);
+  const int ct = std::max(1, std::min(nc, max_pairs / vt));
+  // the valence fields in (x, y, z) order pass through the pair scratch
+  const size_t pair_bytes = std::max(pair_per * (size_t)vt * ct, uv_bytes);
+  gw_status st = ws_begin(c, align_up(uv_bytes) + align_up(uc_bytes) + align_up(band_bytes) +
+                                 align_up(pair_bytes));
+  if (st != GW_OK) return st;
+  void* uv = ws_take(c, uv_bytes);
+  void* uc = ws_take(c, uc_bytes);
+  void* bscr = ws_take(c, band_bytes);
+  void* pscr = ws_take(c, pair_bytes);
+  const bool dbl = dtype == GW_C128;
+  st = dbl ? band_to_grid<double>(c, box, nv * nspinor, ngv, cv, sv, pscr, bscr, band_bytes)
+           : band_to_grid<float>(c, box, nv * nspinor, ngv, cv, sv, pscr, bscr, band_bytes);
+  if (st != GW_OK) return st;
+  st = dbl ? grid_to_zyx<double>(c, box, nv * nspinor, pscr, uv)
+           : grid_to_zyx<float>(c, box, nv * nspinor, pscr, uv);
+  if (st != GW_OK) return st;
+  st = dbl ? band_zc<double>(c, box, nc * nspinor, ngc, cc, sc, uc)
+           : band_zc<float>(c, box, nc * nspinor, ngc, cc, sc, uc);
+  if (st != GW_OK) return st;
+  for (int v0 = 0; v0 < nv; v0 += vt) {
+    const int nvt = std::min(vt, nv - v0);
+    for (int c0 = 0; c0 < nc; c0 += ct) {
+      const int nct = std::min(ct, nc - c0);
+      st = dbl ? pair_to_eps_xy<double>(c, box, nspinor, uv, uc, sc, v0, nvt, c0, nct, nc, se,
+                                        mtxel, pscr)
+               : pair_to_eps_xy<float>(c, box, nspinor, uv, uc, sc, v0, nvt, c0, nct, nc, se,
+                                       mtxel, pscr);
+      if (st != GW_OK) return st;
+    }
+  }
+  if (mhead)
+    return mtxel_head(c, dtype, nspinor, nv, ngv, gv, cv, nc, ngc, gc, cc, mhead);
+  return GW_OK;
+}
+
 }  // namespace gw
 
 using namespace gw;
@@ -196,6 +329,7 @@ gw_status gw_ctx_destroy(gw_ctx* c) {
   for (auto& kv : c->twiddles) (void)hipFree(kv.second);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_flag) (void)hipFree(c->d_flag);
+  pin_release(c);
   delete c;
   return GW_OK;
 }
@@ -288,6 +422,9 @@ gw_status gw_mtxel_spinor(gw_ctx* c, const int box[3], int nspinor, int nv, int 
   const size_t elem = dtype == GW_C128 ? 16 : 8;
   const size_t nbox = (size_t)box[0] * box[1] * box[2];
   const size_t uv_bytes = (size_t)nv * nspinor * nbox * elem;
+  if (!pair_compact_shape(box) && pair_xy_shape(box))
+    return mtxel_xy(c, box, nspinor, nv, ngv, cv, nc, ngc, cc, dtype, sv, sc, se, mtxel,
+                    head_index, mhead, gv, gc);
   // conduction bands: compact x-transformed slabs when the pair kernels build
   // their planes themselves, full real-space fields otherwise
   const bool compact = pair_compact_shape(box);
@@ -357,15 +494,13 @@ gw_status gw_mtxel_spinor(gw_ctx* c, const int box[3], int nspinor, int nv, int 
   if (mhead) {
     const int nm = (int)match.size() / 2;
     if (nm > 0) {
-      GW_HIP(c, hipMemcpyAsync(dmatch, match.data(), match.size() * sizeof(int),
-                               hipMemcpyHostToDevice, c->stream));
+      if ((st = stage_h2d(c, dmatch, match.data(), match.size() * sizeof(int))) != GW_OK)
+        return st;
       if ((st = head_overlap(c, dtype, nspinor, nv, ngv, cv, nc, ngc, cc, dmatch, nm, mhead)) != GW_OK)
         return st;
     } else {
       GW_HIP(c, hipMemsetAsync(mhead, 0, (size_t)nv * nc * 16, c->stream));
     }
-    // the pageable copy above must complete before the host vector dies
-    GW_HIP(c, hipStreamSynchronize(c->stream));
   }
   return GW_OK;
 }
@@ -389,6 +524,7 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
       return fail(c, GW_EINVAL, "omega[%d] must be finite and >= 0", f);
   if (head_index >= neps) return fail(c, GW_EINVAL, "head_index >= neps");
   if ((long long)neps * neps > (1LL << 40)) return fail(c, GW_EINVAL, "neps too large");
+  if ((long long)nv * nc > (1LL << 31) / 2) return fail(c, GW_EINVAL, "too many pairs");
   (void)hipSetDevice(c->device);
   const int P = nv * nc;
   const bool use_head = mhead != nullptr && head_index >= 0;
@@ -402,7 +538,7 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
   double* wts = static_cast<double*>(ws_take(c, (size_t)nfreq * P * 8));
   double* part = part_bytes ? static_cast<double*>(ws_take(c, part_bytes)) : nullptr;
   void* xsplit = xs_bytes ? ws_take(c, xs_bytes) : nullptr;
-  GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
+  if ((st = stage_h2d(c, d_om, omega, (size_t)nfreq * 8)) != GW_OK) return st;
   if ((st = chi0_weights(c, nv, nc, ev, ec, nfreq, d_om, prefactor, wts)) != GW_OK) return st;
   const int skip = use_head ? head_index : -1;
   if (prec == GW_PREC_FP64)
@@ -414,8 +550,6 @@ gw_status gw_chi0_accumulate(gw_ctx* c, int nv, int nc, int neps, const void* mt
     if ((st = chi0_wings(c, P, neps, mtxel, dtype, mhead, head_index, nfreq, wts, chi0)) != GW_OK)
       return st;
   }
-  // omega was copied from pageable host memory: finish before returning
-  GW_HIP(c, hipStreamSynchronize(c->stream));
   return GW_OK;
 }
 
@@ -444,15 +578,8 @@ gw_status gw_head_dipole(gw_ctx* c, int nspinor, int nv, int nc, int ng, const i
   gw_status st = ws_begin(c, align_up((size_t)std::max(ng, 1) * 3 * sizeof(int)));
   if (st != GW_OK) return st;
   int* d_g = static_cast<int*>(ws_take(c, (size_t)std::max(ng, 1) * 3 * sizeof(int)));
-  if (ng > 0)
-    GW_HIP(c, hipMemcpyAsync(d_g, g, (size_t)ng * 3 * sizeof(int), hipMemcpyHostToDevice,
-                             c->stream));
-  if ((st = head_dipole(c, dtype, nspinor, nv, nc, ng, cv, cc, d_g, sq, q0k, ev, ec, mhead)) !=
-      GW_OK)
-    return st;
-  // g was copied from pageable host memory: finish before returning
-  GW_HIP(c, hipStreamSynchronize(c->stream));
-  return GW_OK;
+  if ((st = stage_h2d(c, d_g, g, (size_t)ng * 3 * sizeof(int))) != GW_OK) return st;
+  return head_dipole(c, dtype, nspinor, nv, nc, ng, cv, cc, d_g, sq, q0k, ev, ec, mhead);
 }
 
 gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const void* mtxel,
@@ -474,6 +601,7 @@ gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const voi
     if (!std::isfinite(omega[f])) return fail(c, GW_EINVAL, "omega[%d] must be finite", f);
   if ((long long)neps * neps > (1LL << 40)) return fail(c, GW_EINVAL, "neps too large");
   if (nfreq > 32767) return fail(c, GW_EINVAL, "nfreq above 32767");
+  if ((long long)nv * nc > (1LL << 31) / 2) return fail(c, GW_EINVAL, "too many pairs");
   (void)hipSetDevice(c->device);
   const int P = nv * nc, nw = 2 * nfreq;
   const size_t nn = (size_t)neps * neps;
@@ -489,7 +617,7 @@ gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const voi
   double* h = static_cast<double*>(ws_take(c, (size_t)nw * nn * 16));
   double* part = part_bytes ? static_cast<double*>(ws_take(c, part_bytes)) : nullptr;
   void* xsplit = xs_bytes ? ws_take(c, xs_bytes) : nullptr;
-  GW_HIP(c, hipMemcpyAsync(d_om, omega, (size_t)nfreq * 8, hipMemcpyHostToDevice, c->stream));
+  if ((st = stage_h2d(c, d_om, omega, (size_t)nfreq * 8)) != GW_OK) return st;
   GW_HIP(c, hipMemsetAsync(h, 0, (size_t)nw * nn * 16, c->stream));
   if ((st = chi0_weights_real(c, nv, nc, ev, ec, nfreq, d_om, eta, prefactor, wts)) != GW_OK)
     return st;
@@ -500,10 +628,7 @@ gw_status gw_chi0_accumulate_real(gw_ctx* c, int nv, int nc, int neps, const voi
   else
     st = chi0_splitbf16(c, P, neps, mtxel, nw, wts, -1, h, split, part, xsplit);
   if (st != GW_OK) return st;
-  if ((st = chi0_combine_real(c, neps, nfreq, h, chi0)) != GW_OK) return st;
-  // omega was copied from pageable host memory: finish before returning
-  GW_HIP(c, hipStreamSynchronize(c->stream));
-  return GW_OK;
+  return chi0_combine_real(c, neps, nfreq, h, chi0);
 }
 
 gw_status gw_epsinv_lu(gw_ctx* c, int neps, int nfreq, const double* chi0, const double* vcoul,

@@ -374,6 +374,7 @@ struct gw_mlp {
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   long long step = 0;
   bool ready = false;                  // trained or loaded
+  double tol = 1e-4;                   // INFER with chi0_full: largest accepted rel_F
   char* act = nullptr;                 // activations and scratch
   size_t act_cap = 0;
 };
@@ -411,7 +412,7 @@ static gw_status bgemm(gw_ctx* c, int M, int N, int K, const float* A, int lda, 
 struct ClBufs {
   float *X, *Y, *dY, *dZa, *dZb, *T, *part, *bpart;
   std::vector<float*> Z, H;
-  double *lpart, *loss, *scale;
+  double *lpart, *loss, *scale, *rpart, *rsum;
   cpx<double>* chol;
   cpx<double>* R;
   cpx<double>* Lw;
@@ -419,6 +420,7 @@ struct ClBufs {
 
 static constexpr int kSplits = 32;
 static constexpr int kRowChunks = 64;
+static constexpr int kRelBlocks = 256;  // workgroups of the fixed-order rel_F reduction
 
 static gw_status cl_buffers(gw_mlp* net, int N, long long npad, ClBufs* b) {
   gw_ctx* c = net->ctx;
@@ -441,6 +443,8 @@ static gw_status cl_buffers(gw_mlp* net, int N, long long npad, ClBufs* b) {
   parts.push_back({reinterpret_cast<void**>(&b->lpart), (size_t)((npad + 255) / 256) * 8});
   parts.push_back({reinterpret_cast<void**>(&b->loss), 8});
   parts.push_back({reinterpret_cast<void**>(&b->scale), 8});
+  parts.push_back({reinterpret_cast<void**>(&b->rpart), 2 * kRelBlocks * 8});
+  parts.push_back({reinterpret_cast<void**>(&b->rsum), 2 * 8});
   parts.push_back({reinterpret_cast<void**>(&b->chol), (size_t)N * N * 16});
   parts.push_back({reinterpret_cast<void**>(&b->R), (size_t)CB * N * 16});
   parts.push_back({reinterpret_cast<void**>(&b->Lw), (size_t)CB * CB * 16});
@@ -526,6 +530,60 @@ static gw_status cl_backward(gw_mlp* net, long long npad, ClBufs& b) {
     dz = nd;
     ldz = din;
   }
+  return GW_OK;
+}
+
+// Per workgroup, in a fixed order: the sums of |a - b|^2 and of |b|^2 over
+// the elements i = blockIdx.x * 256 + threadIdx.x + k * gridDim.x * 256, into
+// part[blockIdx.x] and part[gridDim.x + blockIdx.x].
+__global__ void __launch_bounds__(256) k_relf_part(const cpx<double>* __restrict__ a,
+                                                   const cpx<double>* __restrict__ b, size_t n,
+                                                   double* __restrict__ part) {
+  __shared__ double sd[256], sr[256];
+  double d = 0.0, r = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const cpx<double> x = a[i], y = b[i];
+    const double ex = x.x - y.x, ey = x.y - y.y;
+    d += ex * ex + ey * ey;
+    r += y.x * y.x + y.y * y.y;
+  }
+  sd[threadIdx.x] = d;
+  sr[threadIdx.x] = r;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      sd[threadIdx.x] += sd[threadIdx.x + k];
+      sr[threadIdx.x] += sr[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sd[0];
+    part[gridDim.x + blockIdx.x] = sr[0];
+  }
+}
+
+// rel_F(a, b) = ||a - b||_F / ||b||_F over N x N complex doubles, reduced on the
+// device in a fixed order (the same inputs give the same bits); synchronises.
+static gw_status cl_rel_f(gw_ctx* c, int N, const double* a, const double* b, ClBufs& bf,
+                          double* rel) {
+  const size_t nn = (size_t)N * N;
+  {
+    ProfScope ps(c, "closure_judge");
+    hipLaunchKernelGGL(k_relf_part, dim3(kRelBlocks), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(a),
+                       reinterpret_cast<const cpx<double>*>(b), nn, bf.rpart);
+    GW_CHECK_LAUNCH(c, "k_relf_part");
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, c->stream, bf.rpart, kRelBlocks, bf.rsum);
+    GW_CHECK_LAUNCH(c, "k_sum_f64");
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, c->stream, bf.rpart + kRelBlocks,
+                       kRelBlocks, bf.rsum + 1);
+    GW_CHECK_LAUNCH(c, "k_sum_f64");
+  }
+  double h[2] = {0.0, 0.0};
+  GW_HIP(c, hipMemcpyAsync(h, bf.rsum, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  GW_HIP(c, hipStreamSynchronize(c->stream));
+  *rel = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] > 0.0 ? INFINITY : 0.0);
   return GW_OK;
 }
 
@@ -624,6 +682,14 @@ gw_status gw_mlp_create(gw_ctx* c, gw_mlp** out, int nin, int width, int depth, 
   }
   c->mlps.insert(n);
   *out = n;
+  return GW_OK;
+}
+
+gw_status gw_mlp_set_tolerance(gw_mlp* n, double tol) {
+  if (!n) return GW_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol))
+    return fail(n->ctx, GW_EINVAL, "the closure tolerance must be finite and >= 0");
+  n->tol = tol;
   return GW_OK;
 }
 
@@ -762,8 +828,12 @@ gw_status gw_chi0_closure(gw_ctx* c, gw_mlp* net, int mode, int N, const double*
     GW_CHECK_LAUNCH(c, "k_cl_apply");
   }
   if (chi0_full) {
-    bool fails = false;
-    if ((st = cl_cholesky_fails(c, N, chi0_out, b, &fails)) != GW_OK) return st;
+    // the full sum judges the prediction: it is kept only if it is within the
+    // network's tolerance of the full sum and negative semidefinite
+    double rel = 0.0;
+    if ((st = cl_rel_f(c, N, chi0_out, chi0_full, b, &rel)) != GW_OK) return st;
+    bool fails = !(rel <= net->tol);
+    if (!fails && (st = cl_cholesky_fails(c, N, chi0_out, b, &fails)) != GW_OK) return st;
     if (fails) {
       GW_HIP(c, hipMemcpyAsync(chi0_out, chi0_full, nn * 16, hipMemcpyDeviceToDevice, c->stream));
       return GW_EFALLBACK;

@@ -78,6 +78,11 @@ struct ProfAcc {
   double ms = 0.0;
 };
 
+struct PinRec {
+  size_t a, b;     // byte range of the staging ring read by one copy
+  hipEvent_t ev;   // recorded after that copy
+};
+
 }  // namespace gw
 
 struct gw_ctx {
@@ -104,6 +109,14 @@ struct gw_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, gw::ProfAcc> prof;
   std::vector<std::string> prof_names;
+  // pinned host staging ring for small host arrays (frequencies, G lists)
+  // copied to the device by calls that return before the device finishes:
+  // each copy records an event, and a region is rewritten only after the
+  // copies that read it have completed
+  char* pin = nullptr;
+  size_t pin_cap = 0;
+  size_t pin_off = 0;
+  std::vector<gw::PinRec> pin_recs;
 };
 
 namespace gw {
@@ -117,6 +130,10 @@ gw_status hip_fail(gw_ctx* c, hipError_t e, const char* what);
 gw_status ws_begin(gw_ctx* c, size_t total_bytes);
 void* ws_take(gw_ctx* c, size_t bytes);
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+// Copy `bytes` of host memory to device memory `dst` on the context stream
+// through the pinned staging ring; the host buffer may be reused as soon as this
+// returns, and the call does not wait for the device.
+gw_status stage_h2d(gw_ctx* c, void* dst, const void* src, size_t bytes);
 
 // Device tables.
 gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], SphereMap** out);
@@ -160,6 +177,22 @@ template <typename T>
 gw_status band_compact(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
                        const SphereMap* sm, void* out);
 bool pair_compact_shape(const int box[3]);
+// Boxes whose xy-planes have a built pair kernel (fft_xy.hip): conduction bands
+// as compact z-transformed slabs [c][s][z][jy][jx] on sphere sc, valence bands
+// as full fields in [v][s][z][y][x] order, pair intermediate
+// T[pair][z][jy][jx] on the eps sphere's (x, y) extent.
+bool pair_xy_shape(const int box[3]);
+size_t band_zc_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
+size_t pair_xy_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem);
+template <typename T>
+gw_status band_zc(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                  const SphereMap* sm, void* out);
+template <typename T>
+gw_status grid_to_zyx(gw_ctx* c, const int box[3], int nbs, const void* u, void* w);
+template <typename T>
+gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* uvz,
+                         const void* tcz, const SphereMap* sc, int v0, int nvt, int c0, int nct,
+                         int nc_total, const SphereMap* em, void* mtxel, void* scratch);
 size_t band_compact_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
 size_t band_scratch_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem);
 size_t pair_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem);

@@ -368,11 +368,6 @@ __global__ void __launch_bounds__(kThreads) k_pair_x(
 // registers over the B columns (thread t takes k2 = t, t+A, ...).  Output
 // k = k2 + B*k1.  One LDS round trip per transform instead of one per radix.
 
-// frequency of transform index k on an axis of length n, kept if |f| <= g
-__device__ __forceinline__ int kept(int k, int n, int g) {
-  const int f = (2 * k <= n) ? k : k - n;
-  return (f >= -g && f <= g) ? f + g : -1;
-}
 
 template <int N>
 __host__ __device__ constexpr int ex_pitch() { return N + 1; }
@@ -591,17 +586,6 @@ __global__ void __launch_bounds__(kThreads) k_band_plane_rf(
 // layout is the one k_pair_plane_rf writes. Barriers order LDS only, so the
 // prefetch stays in flight across them; the twiddles live in LDS for the
 // same reason (a global load issued after the prefetch would wait for it).
-__device__ __forceinline__ void lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-constexpr int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
 
 constexpr int cs_split(int n) { return n == 48 ? 8 : split_n1(n); }
 

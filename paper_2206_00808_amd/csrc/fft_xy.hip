@@ -1,0 +1,553 @@
+// Spinor matrix elements on boxes with large planes (e.g. 60 x 60 x 160, the
+// layered-cell workload), Sec. II, Eq. (matrix_el):
+//   rho_vc(r) = sum_s conj(u_v^s(r)) u_c^s(r),
+//   M_vc(G)   = (1/N) sum_j rho_vc(r_j) exp(+2 pi i g.j/n),  G on the eps sphere.
+//
+// The transform is taken x first, then y, on the xy-plane of each z, and
+// along z last. One workgroup owns one z and CT conduction bands and walks
+// every valence band of the launch:
+//   - the conduction xy-planes are built on chip from compact z-transformed
+//     slabs (k_band_zc: [c][s][z][jy][jx], the conduction sphere's (x, y)
+//     extent only) and stay in registers for the whole valence loop;
+//   - the valence xy-planes at that z ([v][s][z][y][x]) are read from the
+//     caches: with the grid numbered z-major and renumbered per XCD, the
+//     workgroups of one XCD share a z, and all valence planes of one z fit its
+//     L2 (3.2 MB in float, 6.4 MB in double for 56 bands);
+//   - the spin-summed product, the x transform (keeping |g_x| <= g_eps,x) and
+//     the y transform (keeping |g_y| <= g_eps,y) leave (2 g_x + 1)(2 g_y + 1)
+//     values per pair and z, written to T[pair][z][jy][jx];
+//   - k_pair_zp transforms T along z, keeps |g_z| <= g_eps,z, scales by 1/N
+//     and scatters onto the eps sphere.
+// The yz-plane of such a box (9,600 points) would not fit on chip beside a
+// valence stream, and the valence yz-planes of one x (17 MB in double) would
+// not fit an L2; the xy-plane (3,600 points) does both.
+#include <algorithm>
+
+#include "common.h"
+#include "regfft.h"
+
+namespace gw {
+
+namespace {
+
+constexpr int kZThreads = 128;
+
+// lanes per x pencil in the pair kernel: A1 lanes of B1 values each
+constexpr int xy_split(int n) { return n == 60 ? 6 : n == 16 ? 4 : split_n1(n); }
+
+template <typename T, int N1, int N2>
+struct XyShape {
+  static constexpr int A1 = xy_split(N1), B1 = N1 / A1, L1 = pow2_at_least(A1);
+  static constexpr int NTH = ((N2 * L1 + 63) / 64) * 64;  // one lane group per row y
+  static constexpr int XP = N1 + 1;                        // exchange row pitch
+  static constexpr int A2 = xy_split(N2), B2 = N2 / A2, L2 = pow2_at_least(A2);
+  static_assert(64 % L1 == 0 && 64 % L2 == 0, "a pencil must sit in one wavefront");
+  static_assert(NTH <= 1024, "block too large");
+};
+
+// conduction planes per workgroup and valence bands per y pass
+template <typename T> struct XyTile;
+template <> struct XyTile<double> { static constexpr int CT = 1, VB = 4; };
+template <> struct XyTile<float> { static constexpr int CT = 2, VB = 2; };
+
+__device__ __forceinline__ int mod_pos(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- conduction slabs
+// z transform of every compact (jx, jy) column of one band-spin's sphere:
+// out[bs][z][jy * ex + jx] = sum_gz c(gx, gy, gz) exp(+2 pi i gz z / N3).
+// A lanes per column hold B values each (index n = t + A m): a B-point DFT in
+// registers, the twiddle, one exchange through the column's LDS row, and
+// A-point DFTs; every output is written.
+template <typename T, int N3>
+__global__ void __launch_bounds__(kZThreads) k_band_zc(const cpx<T>* __restrict__ coef, int ng,
+                                                       const int* __restrict__ cube, int ex,
+                                                       int ey, int ez, int gz,
+                                                       const cpx<T>* __restrict__ twz,
+                                                       cpx<T>* __restrict__ out) {
+  constexpr int A = split_n1(N3), B = N3 / A, L = pow2_at_least(A), CPB = kZThreads / L;
+  __shared__ cpx<T> X[CPB][N3 + 1];
+  __shared__ cpx<T> tw[N3];
+  const int bs = blockIdx.y, tid = threadIdx.x;
+  for (int i = tid; i < N3; i += kZThreads) tw[i] = twz[i];
+  __syncthreads();
+  const int ncol = ex * ey;
+  const int cq = tid / L, t = tid % L;
+  const int col = blockIdx.x * CPB + cq;
+  if (col >= ncol || t >= A) return;
+  const int jy = col / ex, jx = col - jy * ex;
+  const cpx<T>* cf = coef + (size_t)bs * ng;
+  const int* cz = cube + ((size_t)jx * ey + jy) * ez;
+  cpx<T> a[B];
+#pragma unroll
+  for (int m = 0; m < B; ++m) {
+    const int n = t + A * m;
+    const int g = 2 * n <= N3 ? n : n - N3;
+    int idx = -1;
+    if (g >= -gz && g <= gz) idx = cz[g + gz];
+    a[m] = idx >= 0 ? cf[idx] : mk<T>(0, 0);
+  }
+  reg_dft<T, B>(a);
+#pragma unroll
+  for (int k2 = 1; k2 < B; ++k2) a[k2] = cmul(a[k2], tw[t * k2]);
+  cpx<T>* Xr = X[cq];
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) Xr[k2 * A + t] = a[k2];
+  // the column's lanes share a wavefront, whose LDS accesses complete in order
+  __builtin_amdgcn_wave_barrier();
+  cpx<T>* o = out + (size_t)bs * N3 * ncol + col;
+#pragma unroll
+  for (int s = 0; s < (B + A - 1) / A; ++s) {
+    const int k2 = t + A * s;
+    if (k2 < B) {
+      cpx<T> u[A];
+#pragma unroll
+      for (int n = 0; n < A; ++n) u[n] = Xr[k2 * A + n];
+      reg_dft<T, A>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) o[(size_t)(k2 + B * k1) * ncol] = u[k1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- valence layout
+// u[bs][x][y][z] -> w[bs][z][y][x], 32 x 32 (x, z) tiles through LDS for each
+// (bs, y); grid (z tiles, x tiles, bs * n2).
+template <typename T>
+__global__ void __launch_bounds__(256) k_to_zyx(const cpx<T>* __restrict__ u, int n1, int n2,
+                                                int n3, cpx<T>* __restrict__ w) {
+  __shared__ cpx<T> tile[32][33];
+  const int z0 = blockIdx.x * 32, x0 = blockIdx.y * 32;
+  const size_t bsy = blockIdx.z;
+  const size_t bs = bsy / n2;
+  const int y = (int)(bsy % n2);
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int x = x0 + r, z = z0 + tx;
+    if (x < n1 && z < n3) tile[r][tx] = u[((bs * n1 + x) * n2 + y) * n3 + z];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int z = z0 + r, x = x0 + tx;
+    if (x < n1 && z < n3) w[((bs * n3 + z) * n2 + y) * n1 + x] = tile[tx][r];
+  }
+}
+
+// ---------------------------------------------------------------- pair planes
+// Workgroup (z, conduction group cg): conduction bands c0 + cg*CT + ct, every
+// valence band v0 .. v0 + nvt - 1. Lane group y (L1 lanes, A1 of them active)
+// owns row y of the xy-plane; lane t holds x = t + A1 m, m < B1.
+//
+// Conduction build, per band and spin: the compact slab Q[jy][jx] at z goes to
+// LDS; its y transform Yw[y][jx] = sum_gy Q W_N2^(gy y) is a direct sum (the
+// slab has few columns); then for x = t + A1 m,
+//   C[t + A1 m] = sum_r exp(+2 pi i r m / B1) b_r,
+//   b_r = sum_{gx = r mod B1} Yw[y][gx] W_N1^(gx t),
+// a B1-point DFT of per-lane sums, which leaves the plane in the layout the
+// valence rows are read in.
+//
+// Valence loop, VB bands per y pass: the lane's row slice of both spins is
+// loaded, the product with each conduction plane is formed in registers, and
+// its x transform is the two-factor scheme: B1-point DFTs in registers, the
+// twiddle W_N1^(t k2), an exchange through the row's own LDS line (the row's
+// lanes share a wavefront), A1-point DFTs; kept outputs go to Xk[j][ct][y][jkx].
+// After a block barrier, the y transforms of the VB * CT * (2 gx + 1) kept
+// columns run the same way with A2 lanes per column and write
+// T[pair][z][jky][jkx], pair = (c - c0) * nvt + (v - v0).
+template <typename T, int NS, int N1, int N2>
+__global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH)) k_pair_xy(
+    const cpx<T>* __restrict__ uvz, const cpx<T>* __restrict__ tcz, int exw, int eyw, int gxw,
+    int gyw, int v0, int nvt, int c0, int nct, int n3, int gx, int gy,
+    const cpx<T>* __restrict__ twx, const cpx<T>* __restrict__ twy, cpx<T>* __restrict__ tout) {
+  using S = XyShape<T, N1, N2>;
+  constexpr int CT = XyTile<T>::CT, VB = XyTile<T>::VB;
+  constexpr int NP = N1 * N2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* tw1 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw2 = tw1 + N1;
+  cpx<T>* Xr0 = tw2 + N2;              // N2 exchange rows of pitch XP
+  cpx<T>* R = Xr0 + N2 * S::XP;        // build: Q, Yw; valence loop: Xk
+  const int ekx = 2 * gx + 1, eky = 2 * gy + 1, XKP = ekx | 1;
+  const int ncg = (nct + CT - 1) / CT;
+  const long long lin = xcd_linear(blockIdx.x, (long long)n3 * ncg);
+  if (lin < 0) return;
+  const int z = (int)(lin / ncg), cg = (int)(lin % ncg);
+  const int tid = threadIdx.x;
+  const int y = tid / S::L1, t = tid % S::L1;
+  const bool act = y < N2 && t < S::A1;
+  for (int i = tid; i < N1; i += S::NTH) tw1[i] = twx[i];
+  for (int i = tid; i < N2; i += S::NTH) tw2[i] = twy[i];
+  const int ncw = exw * eyw, YP = exw | 1;
+  cpx<T>* Q = R;
+  cpx<T>* Yw = R + ncw;
+
+  // ---- conduction planes, built from their compact slabs
+  cpx<T> cr[CT][NS][S::B1];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int cl = cg * CT + ct;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (cl < nct) {
+        const cpx<T>* src = tcz + (((size_t)(c0 + cl) * NS + s) * n3 + z) * ncw;
+        for (int i = tid; i < ncw; i += S::NTH) Q[i] = src[i];
+      }
+      lds_sync();  // Q in place (and the twiddles, the first time)
+      if (cl < nct) {
+        for (int o = tid; o < N2 * exw; o += S::NTH) {
+          const int yy = o / exw, jx = o - yy * exw;
+          cpx<T> acc = mk<T>(0, 0);
+          for (int jy = 0; jy < eyw; ++jy) {
+            const cpx<T> w = tw2[mod_pos((jy - gyw) * yy, N2)];
+            acc = acc + cmul(Q[jy * exw + jx], w);
+          }
+          Yw[yy * YP + jx] = acc;
+        }
+      }
+      lds_sync();  // Yw complete
+      if (act) {
+        cpx<T> b[S::B1];
+#pragma unroll
+        for (int r = 0; r < S::B1; ++r) {
+          b[r] = mk<T>(0, 0);
+          if (cl < nct) {
+            // gx = r (mod B1), from the smallest such gx >= -gxw
+            for (int g = -gxw + mod_pos(r + gxw, S::B1); g <= gxw; g += S::B1)
+              b[r] = b[r] + cmul(Yw[y * YP + g + gxw], tw1[mod_pos(g * t, N1)]);
+          }
+        }
+        reg_dft<T, S::B1>(b);
+#pragma unroll
+        for (int m = 0; m < S::B1; ++m) cr[ct][s][m] = b[m];
+      }
+      lds_sync();  // Q and Yw consumed before the next slab
+    }
+  }
+
+  // ---- valence loop
+  cpx<T>* Xr = Xr0 + (act ? y : 0) * S::XP;
+  cpx<T>* Xk = R;
+  const size_t vstride = (size_t)n3 * NP;  // one spinor component of one band
+  const int nvalid = min(CT, nct - cg * CT);
+  for (int g0 = 0; g0 < nvt; g0 += VB) {
+    const int nb = min(VB, nvt - g0);
+    for (int j = 0; j < nb; ++j) {
+      if (act) {
+        const cpx<T>* pv = uvz + (size_t)(v0 + g0 + j) * NS * vstride + (size_t)z * NP +
+                           (size_t)y * N1 + t;
+        // spin-summed products with every conduction plane, one spin's row
+        // slice of the valence band in registers at a time
+        cpx<T> pa[CT][S::B1];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          cpx<T> vr[S::B1];
+#pragma unroll
+          for (int m = 0; m < S::B1; ++m) vr[m] = pv[s * vstride + S::A1 * m];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int m = 0; m < S::B1; ++m)
+              pa[ct][m] = s == 0 ? cmulc(vr[m], cr[ct][0][m]) : pa[ct][m] + cmulc(vr[m], cr[ct][s][m]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          if (ct < nvalid) {
+            cpx<T>* a = pa[ct];
+            reg_dft<T, S::B1>(a);
+            // the twiddles are read from LDS each time (an opaque copy of t keeps
+            // the compiler from holding all of them in registers across the loop);
+            // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
+            int tl = t;
+            asm volatile("" : "+v"(tl));
+#pragma unroll
+            for (int k2 = 1; k2 < S::B1; ++k2) a[k2] = cmul(a[k2], tw1[tl * k2]);
+#pragma unroll
+            for (int k2 = 0; k2 < S::B1; ++k2) Xr[k2 * S::A1 + t] = a[k2];
+            __builtin_amdgcn_wave_barrier();
+            cpx<T>* xk = Xk + ((size_t)(j * CT + ct) * N2 + y) * XKP;
+#pragma unroll
+            for (int s2 = 0; s2 < (S::B1 + S::A1 - 1) / S::A1; ++s2) {
+              const int k2 = t + S::A1 * s2;
+              if (k2 < S::B1) {
+                cpx<T> u[S::A1];
+#pragma unroll
+                for (int n = 0; n < S::A1; ++n) u[n] = Xr[k2 * S::A1 + n];
+                reg_dft<T, S::A1>(u);
+#pragma unroll
+                for (int k1 = 0; k1 < S::A1; ++k1) {
+                  const int jk = kept(k2 + S::B1 * k1, N1, gx);
+                  if (jk >= 0) xk[jk] = u[k1];
+                }
+              }
+            }
+            // the next product's exchange writes follow these reads in order
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+      }
+    }
+    lds_sync();  // every kept x column of the group is in Xk
+    // y transforms of the kept columns (j, ct, jkx)
+    const int pp = tid / S::L2, tt = tid % S::L2;
+    const int tot = nb * nvalid * ekx;
+    for (int q0 = 0; q0 < tot; q0 += S::NTH / S::L2) {
+      const int q = q0 + pp;
+      if (q < tot && tt < S::A2) {
+        const int jc = q / ekx, jk = q - jc * ekx;
+        const int j = jc / nvalid, ct = jc - j * nvalid;
+        cpx<T>* col = Xk + (size_t)(j * CT + ct) * N2 * XKP + jk;
+        cpx<T> a[S::B2];
+#pragma unroll
+        for (int m = 0; m < S::B2; ++m) a[m] = col[(tt + S::A2 * m) * XKP];
+        reg_dft<T, S::B2>(a);
+        int tl = tt;
+        asm volatile("" : "+v"(tl));
+#pragma unroll
+        for (int k2 = 1; k2 < S::B2; ++k2) a[k2] = cmul(a[k2], tw2[tl * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + tt) * XKP] = a[k2];
+        __builtin_amdgcn_wave_barrier();
+        const size_t pl = (size_t)(cg * CT + ct) * nvt + g0 + j;
+        cpx<T>* dst = tout + (pl * n3 + z) * (size_t)(ekx * eky) + jk;
+#pragma unroll
+        for (int s2 = 0; s2 < (S::B2 + S::A2 - 1) / S::A2; ++s2) {
+          const int k2 = tt + S::A2 * s2;
+          if (k2 < S::B2) {
+            cpx<T> u[S::A2];
+#pragma unroll
+            for (int n = 0; n < S::A2; ++n) u[n] = col[(k2 * S::A2 + n) * XKP];
+            reg_dft<T, S::A2>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < S::A2; ++k1) {
+              const int jky = kept(k2 + S::B2 * k1, N2, gy);
+              if (jky >= 0) dst[(size_t)jky * ekx] = u[k1];
+            }
+          }
+        }
+      }
+    }
+    lds_sync();  // Xk consumed before the next group writes it
+  }
+}
+
+// ---------------------------------------------------------------- z pass
+// For each pair and kept (jkx, jky) column of T, the z transform with A lanes
+// of B values, keeping |g_z| <= gz, scaled by 1/N and scattered onto the eps
+// sphere through its compact cube map emap[jx][jy][jz].
+template <typename T, int N3>
+__global__ void __launch_bounds__(kZThreads) k_pair_zp(
+    const cpx<T>* __restrict__ tin, int ekx, int eky, int ekz, int gz,
+    const int* __restrict__ emap, const cpx<T>* __restrict__ twz, T invN, int v0, int nvt,
+    int c0, int nc_total, int neps, cpx<T>* __restrict__ M) {
+  constexpr int A = split_n1(N3), B = N3 / A, L = pow2_at_least(A), CPB = kZThreads / L;
+  __shared__ cpx<T> X[CPB][N3 + 1];
+  __shared__ cpx<T> tw[N3];
+  const int pr = blockIdx.y, tid = threadIdx.x;
+  for (int i = tid; i < N3; i += kZThreads) tw[i] = twz[i];
+  __syncthreads();
+  const int ncol = ekx * eky;
+  const int cq = tid / L, t = tid % L;
+  const int col = blockIdx.x * CPB + cq;
+  if (col >= ncol || t >= A) return;
+  const cpx<T>* src = tin + (size_t)pr * N3 * ncol + col;
+  cpx<T> a[B];
+#pragma unroll
+  for (int m = 0; m < B; ++m) a[m] = src[(size_t)(t + A * m) * ncol];
+  reg_dft<T, B>(a);
+#pragma unroll
+  for (int k2 = 1; k2 < B; ++k2) a[k2] = cmul(a[k2], tw[t * k2]);
+  cpx<T>* Xr = X[cq];
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) Xr[k2 * A + t] = a[k2];
+  __builtin_amdgcn_wave_barrier();
+  const int v = v0 + pr % nvt, c = c0 + pr / nvt;
+  cpx<T>* dst = M + ((size_t)v * nc_total + c) * neps;
+  const int jky = col / ekx, jkx = col - jky * ekx;
+  const int* em = emap + ((size_t)jkx * eky + jky) * ekz;
+#pragma unroll
+  for (int s = 0; s < (B + A - 1) / A; ++s) {
+    const int k2 = t + A * s;
+    if (k2 < B) {
+      cpx<T> u[A];
+#pragma unroll
+      for (int n = 0; n < A; ++n) u[n] = Xr[k2 * A + n];
+      reg_dft<T, A>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int jz = kept(k2 + B * k1, N3, gz);
+        if (jz >= 0) {
+          const int idx = em[jz];
+          if (idx >= 0) dst[idx] = scal(u[k1], invN);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+// (n1, n2) xy-plane shapes and z lengths built for this path
+#define GW_XY_SHAPES(X) X(60, 60) X(16, 16)
+#define GW_XY_ZLEN(X) X(160) X(40)
+
+bool pair_xy_shape(const int box[3]) {
+  bool plane = false, zlen = false;
+#define X(A, B) if (box[0] == A && box[1] == B) plane = true;
+  GW_XY_SHAPES(X)
+#undef X
+#define X(N) if (box[2] == N) zlen = true;
+  GW_XY_ZLEN(X)
+#undef X
+  return plane && zlen;
+}
+
+size_t band_zc_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem) {
+  return (size_t)nbs * box[2] * sm->ext[0] * sm->ext[1] * elem;
+}
+
+size_t pair_xy_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem) {
+  return (size_t)npairs * box[2] * em->ext[0] * em->ext[1] * elem;
+}
+
+template <typename K>
+static hipError_t allow_lds_xy(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+gw_status band_zc(gw_ctx* c, const int box[3], int nbs, int ng, const void* coef,
+                  const SphereMap* sm, void* out) {
+  const void* twz;
+  gw_status st;
+  if ((st = twiddle_table(c, box[2], sizeof(T) == 8, &twz)) != GW_OK) return st;
+  const int ncol = sm->ext[0] * sm->ext[1];
+  ProfScope ps(c, "band_zc");
+  bool done = false;
+#define X(N)                                                                                  \
+  if (!done && box[2] == N) {                                                                 \
+    done = true;                                                                              \
+    constexpr int CPB = kZThreads / pow2_at_least(split_n1(N));                               \
+    for (int b0 = 0; b0 < nbs; b0 += 65535) {                                                 \
+      const int nb = std::min(65535, nbs - b0);                                               \
+      hipLaunchKernelGGL((k_band_zc<T, N>), dim3((ncol + CPB - 1) / CPB, nb), dim3(kZThreads), \
+                         0, c->stream, static_cast<const cpx<T>*>(coef) + (size_t)b0 * ng, ng, \
+                         sm->d_cube, sm->ext[0], sm->ext[1], sm->ext[2], sm->gmax[2],         \
+                         static_cast<const cpx<T>*>(twz),                                     \
+                         static_cast<cpx<T>*>(out) + (size_t)b0 * N * ncol);                   \
+    }                                                                                         \
+  }
+  GW_XY_ZLEN(X)
+#undef X
+  if (!done) return fail(c, GW_EUNSUPPORTED, "no z-slab kernel for n3 = %d", box[2]);
+  GW_CHECK_LAUNCH(c, "k_band_zc");
+  return GW_OK;
+}
+
+template <typename T>
+gw_status grid_to_zyx(gw_ctx* c, const int box[3], int nbs, const void* u, void* w) {
+  const int n1 = box[0], n2 = box[1], n3 = box[2];
+  ProfScope ps(c, "band_zyx");
+  const int per = std::max(1, 65535 / n2);  // band-spins per launch (grid z <= 65535)
+  for (int b0 = 0; b0 < nbs; b0 += per) {
+    const int nb = std::min(per, nbs - b0);
+    const size_t off = (size_t)b0 * n1 * n2 * n3;
+    hipLaunchKernelGGL(k_to_zyx<T>, dim3((n3 + 31) / 32, (n1 + 31) / 32, nb * n2), dim3(256), 0,
+                       c->stream, static_cast<const cpx<T>*>(u) + off, n1, n2, n3,
+                       static_cast<cpx<T>*>(w) + off);
+  }
+  GW_CHECK_LAUNCH(c, "k_to_zyx");
+  return GW_OK;
+}
+
+template <typename T>
+gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* uvz,
+                         const void* tcz, const SphereMap* sc, int v0, int nvt, int c0, int nct,
+                         int nc_total, const SphereMap* em, void* mtxel, void* scratch) {
+  const int n1 = box[0], n2 = box[1], n3 = box[2];
+  const void *twx, *twy, *twz;
+  const bool dbl = sizeof(T) == 8;
+  gw_status st;
+  if ((st = twiddle_table(c, n1, dbl, &twx)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n2, dbl, &twy)) != GW_OK) return st;
+  if ((st = twiddle_table(c, n3, dbl, &twz)) != GW_OK) return st;
+  if (nvt <= 0 || nct <= 0) return GW_OK;
+  const int gx = em->gmax[0], gy = em->gmax[1];
+  const int ekx = em->ext[0], eky = em->ext[1];
+  cpx<T>* tbuf = static_cast<cpx<T>*>(scratch);
+  bool done = false;
+  {
+    ProfScope ps(c, "pair_plane");
+#define X(A, B)                                                                                 \
+  if (!done && n1 == A && n2 == B) {                                                            \
+    done = true;                                                                                \
+    using S = XyShape<T, A, B>;                                                                 \
+    constexpr int CT = XyTile<T>::CT, VB = XyTile<T>::VB;                                       \
+    const int ncw = sc->ext[0] * sc->ext[1];                                                    \
+    const size_t build = (size_t)ncw + (size_t)B * (sc->ext[0] | 1);                            \
+    const size_t xk = (size_t)VB * CT * B * (ekx | 1);                                          \
+    const size_t lds = ((size_t)A + B + (size_t)B * S::XP + std::max(build, xk)) * sizeof(cpx<T>); \
+    const int ncg = (nct + CT - 1) / CT;                                                        \
+    const long long tot = (long long)n3 * ncg;                                                  \
+    const unsigned grid = (unsigned)(((tot + kXcd - 1) / kXcd) * kXcd);                         \
+    if (nspinor == 2) {                                                                         \
+      if (!c->capturing) GW_HIP(c, allow_lds_xy(k_pair_xy<T, 2, A, B>, lds));                   \
+      hipLaunchKernelGGL((k_pair_xy<T, 2, A, B>), dim3(grid), dim3(S::NTH), lds, c->stream,     \
+                         static_cast<const cpx<T>*>(uvz), static_cast<const cpx<T>*>(tcz),       \
+                         sc->ext[0], sc->ext[1], sc->gmax[0], sc->gmax[1], v0, nvt, c0, nct, n3, \
+                         gx, gy, static_cast<const cpx<T>*>(twx),                               \
+                         static_cast<const cpx<T>*>(twy), tbuf);                                 \
+    } else {                                                                                    \
+      if (!c->capturing) GW_HIP(c, allow_lds_xy(k_pair_xy<T, 1, A, B>, lds));                   \
+      hipLaunchKernelGGL((k_pair_xy<T, 1, A, B>), dim3(grid), dim3(S::NTH), lds, c->stream,     \
+                         static_cast<const cpx<T>*>(uvz), static_cast<const cpx<T>*>(tcz),       \
+                         sc->ext[0], sc->ext[1], sc->gmax[0], sc->gmax[1], v0, nvt, c0, nct, n3, \
+                         gx, gy, static_cast<const cpx<T>*>(twx),                               \
+                         static_cast<const cpx<T>*>(twy), tbuf);                                 \
+    }                                                                                           \
+  }
+    GW_XY_SHAPES(X)
+#undef X
+    if (!done) return fail(c, GW_EUNSUPPORTED, "no xy-plane kernel for %d x %d", n1, n2);
+    GW_CHECK_LAUNCH(c, "k_pair_xy");
+  }
+  {
+    ProfScope ps(c, "pair_xpass");
+    const T invN = (T)(1.0 / ((double)n1 * n2 * n3));
+    const int npairs = nvt * nct;
+    done = false;
+#define X(N)                                                                                   \
+  if (!done && n3 == N) {                                                                      \
+    done = true;                                                                               \
+    constexpr int CPB = kZThreads / pow2_at_least(split_n1(N));                                \
+    hipLaunchKernelGGL((k_pair_zp<T, N>), dim3((ekx * eky + CPB - 1) / CPB, npairs),           \
+                       dim3(kZThreads), 0, c->stream, tbuf, ekx, eky, em->ext[2], em->gmax[2], \
+                       em->d_cube, static_cast<const cpx<T>*>(twz), invN, v0, nvt, c0,         \
+                       nc_total, em->n, static_cast<cpx<T>*>(mtxel));                          \
+  }
+    GW_XY_ZLEN(X)
+#undef X
+    if (!done) return fail(c, GW_EUNSUPPORTED, "no z-pass kernel for n3 = %d", n3);
+    GW_CHECK_LAUNCH(c, "k_pair_zp");
+  }
+  return GW_OK;
+}
+
+template gw_status band_zc<double>(gw_ctx*, const int*, int, int, const void*, const SphereMap*,
+                                   void*);
+template gw_status band_zc<float>(gw_ctx*, const int*, int, int, const void*, const SphereMap*,
+                                  void*);
+template gw_status grid_to_zyx<double>(gw_ctx*, const int*, int, const void*, void*);
+template gw_status grid_to_zyx<float>(gw_ctx*, const int*, int, const void*, void*);
+template gw_status pair_to_eps_xy<double>(gw_ctx*, const int*, int, const void*, const void*,
+                                          const SphereMap*, int, int, int, int, int,
+                                          const SphereMap*, void*, void*);
+template gw_status pair_to_eps_xy<float>(gw_ctx*, const int*, int, const void*, const void*,
+                                         const SphereMap*, int, int, int, int, int,
+                                         const SphereMap*, void*, void*);
+
+}  // namespace gw

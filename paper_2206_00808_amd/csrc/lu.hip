@@ -207,19 +207,47 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 
-// epst = I - S chi0 S with S = diag(sqrt(v)); flag[1] = 1 if some v <= 0 or non-finite.
-__global__ void k_epst_build(const cpx<double>* __restrict__ chi, const double* __restrict__ v,
-                             cpx<double>* __restrict__ A, int N, int* __restrict__ flag) {
+// epst = I - S chi0 S with S = diag(sqrt(v)), one 32x32 tile per workgroup
+// (grid: tiles x tiles x nfreq). flag[1] = 1 if some v <= 0 or non-finite;
+// flag[3] = 1 if chi0 is not Hermitian: |chi_ij - conj(chi_ji)| above
+// kHermRel (|chi_ij| + |chi_ji|) for some pair, checked against the mirror
+// tile staged through LDS. The Gauss-Jordan pivot test alone cannot tell a
+// Hermitian positive-definite epst from a non-Hermitian one whose pivots
+// happen to look the same.
+constexpr double kHermRel = 1e-12;
+constexpr int ET = 32;
+__global__ void __launch_bounds__(256) k_epst_build(const cpx<double>* __restrict__ chi,
+                                                    const double* __restrict__ v,
+                                                    cpx<double>* __restrict__ A, int N,
+                                                    int* __restrict__ flag) {
+  __shared__ cpx<double> mir[ET][ET + 1];
   const size_t nn = (size_t)N * N;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn) return;
-  const int i = (int)(idx / N), j = (int)(idx % N);
-  const double vi = v[i], vj = v[j];
-  if (!(vi > 0.0) || !(vi < INFINITY)) flag[1] = 1;
-  const double s = sqrt(vi) * sqrt(vj);
-  const size_t off = (size_t)blockIdx.y * nn + idx;
-  const cpx<double> x = chi[off];
-  A[off] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
+  const int ti = blockIdx.y, tj = blockIdx.x;
+  chi += (size_t)blockIdx.z * nn;
+  A += (size_t)blockIdx.z * nn;
+  const int c = threadIdx.x % ET, r0 = threadIdx.x / ET;  // 8 rows per pass
+  // mirror tile (tj, ti), read row-wise and stored transposed
+  for (int r = r0; r < ET; r += 256 / ET) {
+    const int i = tj * ET + r, j = ti * ET + c;
+    if (i < N && j < N) mir[c][r] = chi[(size_t)i * N + j];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int r = r0; r < ET; r += 256 / ET) {
+    const int i = ti * ET + r, j = tj * ET + c;
+    if (i >= N || j >= N) continue;
+    const double vi = v[i], vj = v[j];
+    if (j == 0 && (!(vi > 0.0) || !(vi < INFINITY))) flag[1] = 1;
+    const cpx<double> x = chi[(size_t)i * N + j];
+    const cpx<double> y = mir[r][c];  // chi[j][i]
+    const double dr = x.x - y.x, di = x.y + y.y;
+    const double lim = kHermRel * (fabs(x.x) + fabs(x.y) + fabs(y.x) + fabs(y.y));
+    // a non-finite entry also routes the result through the residual check
+    bad = bad || !(fabs(dr) <= lim && fabs(di) <= lim);
+    const double s = sqrt(vi) * sqrt(vj);
+    A[(size_t)i * N + j] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
+  }
+  if (bad) flag[3] = 1;
 }
 
 // Inverse of the diagonal block D = A[K][K] (nbk <= GB = 64) by Gauss-Jordan
@@ -616,9 +644,9 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
   }
   {
     ProfScope ps(c, "eps_build");
-    hipLaunchKernelGGL(k_epst_build, dim3((unsigned)((nn + 255) / 256), nfreq), dim3(256), 0,
-                       c->stream, reinterpret_cast<const cpx<double>*>(chi0), vcoul, A, N,
-                       c->d_flag);
+    const unsigned nt = (unsigned)((N + ET - 1) / ET);
+    hipLaunchKernelGGL(k_epst_build, dim3(nt, nt, nfreq), dim3(256), 0, c->stream,
+                       reinterpret_cast<const cpx<double>*>(chi0), vcoul, A, N, c->d_flag);
     GW_CHECK_LAUNCH(c, "k_epst_build");
   }
   {
@@ -746,14 +774,14 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
                      double* epsinv) {
   gw_status st = epsinv_gauss_jordan(c, N, nfreq, chi0, vcoul, epsinv);
   if (st != GW_OK) return st;
-  int flags[3] = {0, 0, 0};
+  int flags[4] = {0, 0, 0, 0};
   GW_HIP(c, hipMemcpyAsync(flags, c->d_flag, sizeof flags, hipMemcpyDeviceToHost, c->stream));
   GW_HIP(c, hipStreamSynchronize(c->stream));
   // some v <= 0: the symmetric form eps~ does not exist; general LU
   if (flags[1]) return epsinv_pivoted_one(c, N, nfreq, chi0, vcoul, epsinv);
-  if (!flags[2]) return GW_OK;
-  // a pivot was not of the Hermitian positive-definite kind (eps~ not >= I, as
-  // on the real frequency axis): Gauss-Jordan without pivoting carries no
+  if (!flags[2] && !flags[3]) return GW_OK;
+  // chi0 not Hermitian (as on the real frequency axis), or a pivot not of the
+  // Hermitian positive-definite kind: Gauss-Jordan without pivoting carries no
   // stability guarantee there, so its result is kept only if it solves
   // eps X = I to within kVerifyRel / N per entry; otherwise general LU with
   // partial pivoting

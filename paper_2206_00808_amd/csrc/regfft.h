@@ -156,6 +156,27 @@ __host__ __device__ __forceinline__ void reg_dft(cpx<T>* a) {
   }
 }
 
+// frequency of transform index k on an axis of length n, kept if |f| <= g
+// (returns f + g, the index in the compact range), else -1
+__device__ __forceinline__ int kept(int k, int n, int g) {
+  const int f = (2 * k <= n) ? k : k - n;
+  return (f >= -g && f <= g) ? f + g : -1;
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight are
+// not waited for, so a register prefetch can stay outstanding across it.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
 // threads per pencil for the two-factor transform of length N (N = N1 * N2)
 constexpr int split_n1(int n) {
   return n == 160 ? 8 : n == 30 ? 5 : n == 60 ? 4 : n % 4 == 0 ? 4 : n % 2 == 0 ? 2 : 1;

@@ -73,6 +73,10 @@ CONFIGS = {
     # runtime-length transform kernels.
     "T3": SystemConfig("T3", 14, (10.0, 10.4, 10.8), (18, 20, 25), 8.0, 3.5,
                        5, 30, (0.25, 0.0, -0.25), (0.0, 2.0)),
+    # An elongated box whose transforms run x and y on xy-planes and z last
+    # (the layout of the layered-cell workload, at a size the oracle handles).
+    "T4": SystemConfig("T4", 15, (7.5, 7.75, 18.0), (16, 16, 40), 9.0, 3.0,
+                       5, 21, (0.1, 0.0, 0.05), (0.0, 1.5)),
 }
 
 

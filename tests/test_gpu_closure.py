@@ -131,13 +131,31 @@ def test_fallback_when_not_negative_semidefinite(P, ctx, data):
                                        chi0_out=out)
     assert stt == P.GW_EFALLBACK
     assert torch.equal(out, it["chi_f"])
-    # a zero network keeps the truncated sum, which is negative definite: no fallback
+    # a zero network keeps the truncated sum, which is negative definite but far
+    # from the full sum: the full sum judges it and the default 1e-4 rejects it
     net0, _ = _net_with(P, ctx, np.zeros_like(flat))
+    stt, _ = P.binding.gw_chi0_closure(ctx, net0, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
+                                       it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
+                                       chi0_out=out)
+    assert stt == P.GW_EFALLBACK
+    assert torch.equal(out, it["chi_f"])
+    # with a tolerance above its error the same prediction is kept
+    err = float(torch.linalg.vector_norm(it["chi_t"] - it["chi_f"]) /
+                torch.linalg.vector_norm(it["chi_f"]))
+    net0.set_tolerance(1.01 * err)
     stt, _ = P.binding.gw_chi0_closure(ctx, net0, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
                                        it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
                                        chi0_out=out)
     assert stt == P.GW_OK
     assert torch.allclose(out, it["chi_t"], rtol=0, atol=1e-14)
+    # and just below its error it is not
+    net0.set_tolerance(0.99 * err)
+    stt, _ = P.binding.gw_chi0_closure(ctx, net0, P.GW_CLOSURE_INFER, it["neps"], it["qg"],
+                                       it["chi_t"], it["gap"], it["emax"], chi0_full=it["chi_f"],
+                                       chi0_out=out)
+    assert stt == P.GW_EFALLBACK
+    with pytest.raises(P.GwError):
+        net0.set_tolerance(-1.0)
 
 
 def test_untrained_network_refuses_inference(P, ctx, data):
@@ -161,7 +179,10 @@ def test_training_gains_over_truncation(P, ctx, data):
     assert losses[-1] < 0.5 * losses[0]
     rows = evaluate(ctx, net, items[16:])
     trunc = np.mean([r["chi_trunc"] for r in rows])
-    corr = np.mean([r["chi_closure"] for r in rows if not r["fallback"]] or [0.0])
+    corr = np.mean([r["chi_closure"] for r in rows])
     print("held-out chi0 rel error: truncated %.3f, closure %.3f" % (trunc, corr),
           [(r["chi_trunc"], r["chi_closure"], r["fallback"]) for r in rows])
     assert corr < 0.8 * trunc
+    # what a judged call returns is within the default tolerance of the full sum
+    # (the prediction when it is that close, the full sum otherwise)
+    assert all(r["chi_judged"] <= 1e-4 for r in rows)

@@ -45,7 +45,7 @@ def _max_rel(x, ref):
 
 
 # ----------------------------------------------------------------- matrix elements
-@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3", "T4"])
 def test_mtxel_fp64_matches_definition(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s)
@@ -53,7 +53,7 @@ def test_mtxel_fp64_matches_definition(P, ctx, name):
     assert _max_rel(out["mtxel"], ref) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["C1", "T2", "T3"])
+@pytest.mark.parametrize("name", ["C1", "T2", "T3", "T4"])
 def test_mtxel_fp32_matches_definition(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
@@ -61,8 +61,9 @@ def test_mtxel_fp32_matches_definition(P, ctx, name):
     assert _max_rel(out["mtxel"], ref) < 2e-6
 
 
-def test_single_plane_wave_pairs_give_deltas(P, ctx):
-    s = _sys("T2")
+@pytest.mark.parametrize("name", ["T2", "T4"])
+def test_single_plane_wave_pairs_give_deltas(P, ctx, name):
+    s = _sys(name)
     gv, gc, geps = s["gv"], s["gc"], s["geps"]
     cv = np.zeros((2, 2, len(gv)), complex)
     cc = np.zeros((3, 2, len(gc)), complex)
@@ -82,8 +83,9 @@ def test_single_plane_wave_pairs_give_deltas(P, ctx):
     assert np.abs(out["mtxel"] - want).max() < 1e-14
 
 
-def test_zero_down_equals_spinless(P, ctx):
-    s = _sys("T1")
+@pytest.mark.parametrize("name", ["T1", "T4"])
+def test_zero_down_equals_spinless(P, ctx, name):
+    s = _sys(name)
     z = dict(s, cv=s["cv"].copy(), cc=s["cc"].copy())
     z["cv"][:, 1] = 0
     z["cc"][:, 1] = 0
@@ -111,7 +113,7 @@ def test_orthonormal_head_vanishes_at_q0(P, ctx):
 
 
 # ----------------------------------------------------------------- chi0 and eps^-1, FP64
-@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3", "T4"])
 def test_chi0_and_epsinv_fp64(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s)
@@ -356,7 +358,7 @@ def test_chi0_real_axis_rejects_bad_arguments(P, ctx):
 
 
 # ----------------------------------------------------------------- mixed precision
-@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3"])
+@pytest.mark.parametrize("name", ["C1", "T1", "T2", "T3", "T4"])
 def test_mixed_path_within_1e4(P, ctx, name):
     s = _sys(name)
     _, out = _run(P, ctx, s, dtype="c64", prec=P.GW_PREC_SPLITBF16)
@@ -494,11 +496,6 @@ def _sampled_checks(P, ctx, name, dtype, prec, tol_m, tol_chi, tol_inv, seed=0):
         eps = np.eye(neps) - s["vcoul"][:, None] * x[f]
         r = eps @ einv[f] - np.eye(neps)
         assert np.linalg.norm(r) / np.sqrt(neps) < tol_inv
-
-
-@pytest.mark.slow
-def test_c2_full_size_fp64(P, ctx):
-    _sampled_checks(P, ctx, "C2", "c128", P.GW_PREC_FP64, 1e-12, 1e-10, 1e-10)
 
 
 @pytest.mark.slow

@@ -505,3 +505,14 @@ def test_projected_chi0_route_equals_the_projected_inverse():
     ex = oracle.epsilon_inverse(chi2, v)
     pr2 = oracle.epsinv_projected(m2, ev, ec, om, v, u2)
     assert np.abs(pr2 - ex).max() < 1e-10 * np.abs(ex).max()
+
+
+def test_threaded_fft_route_equals_the_plain_one():
+    """The threaded scipy FFT (the CPU baseline's setting) computes the same M."""
+    s = synth.build_system(synth.CONFIGS["T4"])
+    a = oracle.mtxel_fft(s["cv"][:2], s["gv"], s["cc"][:3], s["gc"], s["geps"], s["box"])
+    b = oracle.mtxel_fft(s["cv"][:2], s["gv"], s["cc"][:3], s["gc"], s["geps"], s["box"],
+                         workers=2)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+    ref = oracle.mtxel_convolution(s["cv"][:2], s["gv"], s["cc"][:3], s["gc"], s["geps"])
+    assert np.abs(b - ref).max() <= 1e-13 * np.abs(ref).max()
