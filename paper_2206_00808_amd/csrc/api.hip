@@ -327,6 +327,7 @@ gw_status gw_ctx_destroy(gw_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& kv : c->spheres) (void)hipFree(kv.second.d_cube);
   for (auto& kv : c->twiddles) (void)hipFree(kv.second);
+  for (auto& kv : c->tile_orders) (void)hipFree(kv.second);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_flag) (void)hipFree(c->d_flag);
   pin_release(c);

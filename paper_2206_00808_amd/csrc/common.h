@@ -97,6 +97,7 @@ struct gw_ctx {
   // cached device tables
   std::map<std::string, gw::SphereMap> spheres;
   std::map<std::pair<int, int>, void*> twiddles;  // (n, is_double) -> device table
+  std::map<long long, void*> tile_orders;         // (tiles, block shape) -> chi0 tile order (int2)
   int* d_flag = nullptr;                          // device status flags
   bool capturing = false;                         // inside a graph capture: no attribute calls
   // networks and plans created on this context (freed with it)
@@ -220,8 +221,10 @@ gw_status chi0_weights_real(gw_ctx* c, int nv, int nc, const double* ev, const d
                             double* wts);
 gw_status chi0_combine_real(gw_ctx* c, int neps, int nfreq, const double* h, double* chi0);
 int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt);
+// no_alloc: use no device table that would be allocated on first use
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
-                    const double* wts, int skip_head, double* chi0, int split, double* part);
+                    const double* wts, int skip_head, double* chi0, int split, double* part,
+                    bool no_alloc = false);
 // The split-BF16 contraction first splits its operands into `xsplit`
 // (bf16_split_bytes(P, neps, nfreq) bytes of device workspace).
 size_t bf16_split_bytes(int P, int neps, int nfreq);

@@ -32,8 +32,11 @@ namespace {
 
 constexpr int kZThreads = 128;
 
-// lanes per x pencil in the pair kernel: A1 lanes of B1 values each
-constexpr int xy_split(int n) { return n == 60 ? 6 : n == 16 ? 4 : split_n1(n); }
+// lanes per pencil in the pair kernel: A lanes of B values each (n = A B).
+// Many lanes with few values keep the registers per lane low (the conduction
+// planes and the next valence band stay resident); the second factor is then
+// evaluated only at the kept frequencies (kept_out).
+constexpr int xy_split(int n) { return n == 60 ? 15 : n == 16 ? 4 : split_n1(n); }
 
 template <typename T, int N1, int N2>
 struct XyShape {
@@ -44,6 +47,43 @@ struct XyShape {
   static_assert(64 % L1 == 0 && 64 % L2 == 0, "a pencil must sit in one wavefront");
   static_assert(NTH <= 1024, "block too large");
 };
+
+// One kept output of the second factor of a two-factor transform of length
+// N = A B: for the signed frequency f (k = f mod N = k2 + B k1),
+//   X(k) = sum_{t < A} W_A^(t k1) line[(k2 A + t) es],
+// where line holds the twiddled first-factor results of the pencil. Evaluated
+// by Horner's rule in w = W_A^(k1) = W_N^(B k1), read from the length-N table.
+template <typename T, int A, int B>
+__device__ __forceinline__ cpx<T> kept_out(const cpx<T>* line, int es, int f,
+                                           const cpx<T>* twN) {
+  constexpr int N = A * B;
+  const int k = f < 0 ? f + N : f;
+  const int k2 = k % B, k1 = k / B;
+  const cpx<T> w = twN[(B * k1) % N];
+  const cpx<T>* p = line + k2 * A * es;
+  cpx<T> x = p[(A - 1) * es];
+  // x <- x w + p[t], four fused multiply-adds per step
+#pragma unroll
+  for (int t = A - 2; t >= 0; --t) {
+    const cpx<T> q = p[t * es];
+    x = mk(fma(x.x, w.x, fma(-x.y, w.y, q.x)), fma(x.x, w.y, fma(x.y, w.x, q.y)));
+  }
+  return x;
+}
+
+// sum_s conj(v_s) c_s over NS spinor components, as fused multiply-adds
+template <typename T, int NS>
+__device__ __forceinline__ cpx<T> spin_dot(const cpx<T> (&v)[NS], const cpx<T> (&c)[NS]) {
+  T re = v[0].x * c[0].x, im = v[0].x * c[0].y;
+  re = fma(v[0].y, c[0].y, re);
+  im = fma(-v[0].y, c[0].x, im);
+#pragma unroll
+  for (int s = 1; s < NS; ++s) {
+    re = fma(v[s].x, c[s].x, fma(v[s].y, c[s].y, re));
+    im = fma(v[s].x, c[s].y, fma(-v[s].y, c[s].x, im));
+  }
+  return mk(re, im);
+}
 
 // conduction planes per workgroup and valence bands per y pass
 template <typename T> struct XyTile;
@@ -159,7 +199,7 @@ __global__ void __launch_bounds__(256) k_to_zyx(const cpx<T>* __restrict__ u, in
 // columns run the same way with A2 lanes per column and write
 // T[pair][z][jky][jkx], pair = (c - c0) * nvt + (v - v0).
 template <typename T, int NS, int N1, int N2>
-__global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH)) k_pair_xy(
+__global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
     const cpx<T>* __restrict__ uvz, const cpx<T>* __restrict__ tcz, int exw, int eyw, int gxw,
     int gyw, int v0, int nvt, int c0, int nct, int n3, int gx, int gy,
     const cpx<T>* __restrict__ twx, const cpx<T>* __restrict__ twy, cpx<T>* __restrict__ tout) {
@@ -186,7 +226,7 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH)) k_pair_xy(
   cpx<T>* Yw = R + ncw;
 
   // ---- conduction planes, built from their compact slabs
-  cpx<T> cr[CT][NS][S::B1];
+  cpx<T> cr[CT][S::B1][NS];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int cl = cg * CT + ct;
@@ -222,68 +262,59 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH)) k_pair_xy(
         }
         reg_dft<T, S::B1>(b);
 #pragma unroll
-        for (int m = 0; m < S::B1; ++m) cr[ct][s][m] = b[m];
+        for (int m = 0; m < S::B1; ++m) cr[ct][m][s] = b[m];
       }
       lds_sync();  // Q and Yw consumed before the next slab
     }
   }
 
-  // ---- valence loop
+  // ---- valence loop; the next band's row slice is loaded while the current
+  // band is transformed (barriers order LDS only, so the loads stay in flight)
   cpx<T>* Xr = Xr0 + (act ? y : 0) * S::XP;
   cpx<T>* Xk = R;
   const size_t vstride = (size_t)n3 * NP;  // one spinor component of one band
   const int nvalid = min(CT, nct - cg * CT);
+  const cpx<T>* pv0 = uvz + (size_t)z * NP + (size_t)(act ? y : 0) * N1 + (act ? t : 0);
+  // one row-slice buffer: each band's slice is consumed by the products before
+  // the next band's loads are issued into the same registers
+  cpx<T> vn[S::B1][NS];
+  auto fetch = [&](int vl) {
+    const cpx<T>* pv = pv0 + (size_t)(v0 + vl) * NS * vstride;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < S::B1; ++m) vn[m][s] = pv[s * vstride + S::A1 * m];
+  };
+  if (act) fetch(0);
   for (int g0 = 0; g0 < nvt; g0 += VB) {
     const int nb = min(VB, nvt - g0);
     for (int j = 0; j < nb; ++j) {
       if (act) {
-        const cpx<T>* pv = uvz + (size_t)(v0 + g0 + j) * NS * vstride + (size_t)z * NP +
-                           (size_t)y * N1 + t;
-        // spin-summed products with every conduction plane, one spin's row
-        // slice of the valence band in registers at a time
+        // products of the band's row slice with every conduction plane
         cpx<T> pa[CT][S::B1];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          cpx<T> vr[S::B1];
+        for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int m = 0; m < S::B1; ++m) vr[m] = pv[s * vstride + S::A1 * m];
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int m = 0; m < S::B1; ++m)
-              pa[ct][m] = s == 0 ? cmulc(vr[m], cr[ct][0][m]) : pa[ct][m] + cmulc(vr[m], cr[ct][s][m]);
-        }
+          for (int m = 0; m < S::B1; ++m) pa[ct][m] = spin_dot<T, NS>(vn[m], cr[ct][m]);
+        // the last band fetches itself again (unconditional loads keep the
+        // buffer in one set of registers)
+        fetch(min(g0 + j + 1, nvt - 1));
+        // x transforms, kept outputs to Xk
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
           if (ct < nvalid) {
             cpx<T>* a = pa[ct];
             reg_dft<T, S::B1>(a);
-            // the twiddles are read from LDS each time (an opaque copy of t keeps
-            // the compiler from holding all of them in registers across the loop);
             // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
-            int tl = t;
-            asm volatile("" : "+v"(tl));
 #pragma unroll
-            for (int k2 = 1; k2 < S::B1; ++k2) a[k2] = cmul(a[k2], tw1[tl * k2]);
+            for (int k2 = 1; k2 < S::B1; ++k2) a[k2] = cmul(a[k2], tw1[t * k2]);
 #pragma unroll
             for (int k2 = 0; k2 < S::B1; ++k2) Xr[k2 * S::A1 + t] = a[k2];
+            // the row's lanes share a wavefront, whose LDS accesses complete in order
             __builtin_amdgcn_wave_barrier();
             cpx<T>* xk = Xk + ((size_t)(j * CT + ct) * N2 + y) * XKP;
-#pragma unroll
-            for (int s2 = 0; s2 < (S::B1 + S::A1 - 1) / S::A1; ++s2) {
-              const int k2 = t + S::A1 * s2;
-              if (k2 < S::B1) {
-                cpx<T> u[S::A1];
-#pragma unroll
-                for (int n = 0; n < S::A1; ++n) u[n] = Xr[k2 * S::A1 + n];
-                reg_dft<T, S::A1>(u);
-#pragma unroll
-                for (int k1 = 0; k1 < S::A1; ++k1) {
-                  const int jk = kept(k2 + S::B1 * k1, N1, gx);
-                  if (jk >= 0) xk[jk] = u[k1];
-                }
-              }
-            }
+            for (int jk = t; jk < ekx; jk += S::L1)
+              xk[jk] = kept_out<T, S::A1, S::B1>(Xr, 1, jk - gx, tw1);
             // the next product's exchange writes follow these reads in order
             __builtin_amdgcn_wave_barrier();
           }
@@ -291,43 +322,32 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH)) k_pair_xy(
       }
     }
     lds_sync();  // every kept x column of the group is in Xk
-    // y transforms of the kept columns (j, ct, jkx)
+    // y transforms of the kept columns (j, ct, jkx): A2 lanes of B2 values per
+    // column, the first factor in registers (written back in place, twiddled),
+    // the second at the kept y frequencies only
     const int pp = tid / S::L2, tt = tid % S::L2;
     const int tot = nb * nvalid * ekx;
     for (int q0 = 0; q0 < tot; q0 += S::NTH / S::L2) {
       const int q = q0 + pp;
-      if (q < tot && tt < S::A2) {
+      if (q < tot) {
         const int jc = q / ekx, jk = q - jc * ekx;
         const int j = jc / nvalid, ct = jc - j * nvalid;
         cpx<T>* col = Xk + (size_t)(j * CT + ct) * N2 * XKP + jk;
-        cpx<T> a[S::B2];
+        if (tt < S::A2) {
+          cpx<T> a[S::B2];
 #pragma unroll
-        for (int m = 0; m < S::B2; ++m) a[m] = col[(tt + S::A2 * m) * XKP];
-        reg_dft<T, S::B2>(a);
-        int tl = tt;
-        asm volatile("" : "+v"(tl));
+          for (int m = 0; m < S::B2; ++m) a[m] = col[(tt + S::A2 * m) * XKP];
+          reg_dft<T, S::B2>(a);
 #pragma unroll
-        for (int k2 = 1; k2 < S::B2; ++k2) a[k2] = cmul(a[k2], tw2[tl * k2]);
+          for (int k2 = 1; k2 < S::B2; ++k2) a[k2] = cmul(a[k2], tw2[tt * k2]);
 #pragma unroll
-        for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + tt) * XKP] = a[k2];
+          for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + tt) * XKP] = a[k2];
+        }
         __builtin_amdgcn_wave_barrier();
         const size_t pl = (size_t)(cg * CT + ct) * nvt + g0 + j;
         cpx<T>* dst = tout + (pl * n3 + z) * (size_t)(ekx * eky) + jk;
-#pragma unroll
-        for (int s2 = 0; s2 < (S::B2 + S::A2 - 1) / S::A2; ++s2) {
-          const int k2 = tt + S::A2 * s2;
-          if (k2 < S::B2) {
-            cpx<T> u[S::A2];
-#pragma unroll
-            for (int n = 0; n < S::A2; ++n) u[n] = col[(k2 * S::A2 + n) * XKP];
-            reg_dft<T, S::A2>(u);
-#pragma unroll
-            for (int k1 = 0; k1 < S::A2; ++k1) {
-              const int jky = kept(k2 + S::B2 * k1, N2, gy);
-              if (jky >= 0) dst[(size_t)jky * ekx] = u[k1];
-            }
-          }
-        }
+        for (int jky = tt; jky < eky; jky += S::L2)
+          dst[(size_t)jky * ekx] = kept_out<T, S::A2, S::B2>(col, XKP, jky - gy, tw2);
       }
     }
     lds_sync();  // Xk consumed before the next group writes it

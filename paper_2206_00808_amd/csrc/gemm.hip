@@ -89,15 +89,31 @@ gw_status chi0_combine_real(gw_ctx* c, int neps, int nfreq, const double* h, dou
 // ---------------------------------------------------------------- single-q contractions
 // Grid (upper-triangle tiles, frequencies, pair ranges). Range 0 adds into chi0;
 // range s >= 1 covers pairs [s pc, (s+1) pc) and stores into partial matrix s-1.
+// The grid is one-dimensional over (frequency, range, tile), renumbered per
+// XCD; the tile order table groups the upper-triangle tiles into 8 x 16 blocks
+// of the tile grid, so that the workgroups one XCD runs at a time share the
+// operand rows of 8 tile rows and 16 tile columns in its L2.
 template <int WM, typename Tin>
 __global__ void __launch_bounds__(64 * WM * WM, sizeof(Tin) == 8 ? 3 : 2) k_chi0_f64(const cpx<Tin>* __restrict__ M, int P,
                                                            int neps, const double* __restrict__ wts,
-                                                           cpx<double>* __restrict__ chi, int nt,
+                                                           cpx<double>* __restrict__ chi,
+                                                           const int2* __restrict__ order,
+                                                           int ntile, int split, int nf,
                                                            int skip_head, int pc,
                                                            cpx<double>* __restrict__ part) {
+  const long long lin = xcd_linear(blockIdx.x, (long long)ntile * split * nf);
+  if (lin < 0) return;
   int ti, tj;
-  tri_tile(blockIdx.x, nt, &ti, &tj);
-  const int f = blockIdx.y, s = blockIdx.z, nf = gridDim.y;
+  if (order) {
+    const int2 tt = order[lin % ntile];
+    ti = tt.x;
+    tj = tt.y;
+  } else {  // row-major over the triangle (callers that keep no table)
+    int nt = 0;
+    while (nt * (nt + 1) / 2 < ntile) ++nt;
+    tri_tile((int)(lin % ntile), nt, &ti, &tj);
+  }
+  const int fs = (int)(lin / ntile), s = fs % split, f = fs / split;
   const int p0 = s * pc, np = min(P, p0 + pc) - p0;
   const size_t nn = (size_t)neps * neps;
   if (s == 0)
@@ -171,6 +187,34 @@ __global__ void __launch_bounds__(64 * WM * WM) k_chi0_bf16s(const unsigned shor
                         skip_head, true);
 }
 
+// The 128 x 128 tiles: grid = the tile order table x ranges x frequencies,
+// renumbered per XCD so that each XCD takes a contiguous run of the order, in
+// which consecutive tiles form 4 x 8 blocks of the tile grid (the concurrent
+// workgroups of an XCD then share the A slabs of 4 tile rows and the B slabs
+// of 8 tile columns in its L2). Range s of frequency f adds into chi0 (s = 0)
+// or stores into part[s - 1][f].
+__global__ void __launch_bounds__(512, 1) k_chi0_bf16w(const unsigned short* __restrict__ X,
+                                                       int Pb, int neps,
+                                                       const int2* __restrict__ order, int ntile,
+                                                       int split, int nf,
+                                                       cpx<double>* __restrict__ chi,
+                                                       int skip_head, int pbc,
+                                                       cpx<double>* __restrict__ part) {
+  const long long lin = xcd_linear(blockIdx.x, (long long)ntile * split * nf);
+  if (lin < 0) return;
+  const int tile = (int)(lin % ntile);
+  const int fs = (int)(lin / ntile), s = fs % split, f = fs / split;
+  const int2 tt = order[tile];
+  const int pb0 = s * pbc, npb = min(Pb, pb0 + pbc) - pb0;
+  const size_t nn = (size_t)neps * neps, osz = (size_t)Pb * 4 * neps * BK;
+  const unsigned short* XB = X + (size_t)(1 + f) * osz;
+  if (s == 0)
+    chi0_bf16s_tile_w(X, XB, pb0, npb, neps, chi + (size_t)f * nn, tt.x, tt.y, skip_head, false);
+  else
+    chi0_bf16s_tile_w(X, XB, pb0, npb, neps, part + ((size_t)(s - 1) * nf + f) * nn, tt.x,
+                      tt.y, skip_head, true);
+}
+
 // chi0 += part[0] + part[1] + ... (fixed order, so the result does not depend on
 // which range finished first)
 __global__ void k_chi0_reduce(cpx<double>* __restrict__ chi, const cpx<double>* __restrict__ part,
@@ -184,14 +228,59 @@ __global__ void k_chi0_reduce(cpx<double>* __restrict__ chi, const cpx<double>* 
 
 constexpr int kChiWM = 2, kChiTM = 32 * kChiWM;
 
+// pairs summed in float by one workgroup of the 128 x 128 split-BF16 tile
+constexpr int kBf16Range = 8192;
+
+// Pair ranges of the 128 x 128 split-BF16 contraction: at least P / 8192 (the
+// float accumulation bound), then the count in the next eight that fills the
+// last round of workgroups (one per CU) best.
+static int chi0_split_w(gw_ctx* c, int P, int neps, int nfreq) {
+  const int nt = (neps + WT - 1) / WT;
+  const long long b1 = (long long)nt * (nt + 1) / 2 * nfreq;
+  const double conc = (double)c->cus;
+  auto fill = [&](long long b) {
+    const double r = (double)b / conc;
+    return r / std::ceil(r);
+  };
+  const int smin = std::max(1, (P + kBf16Range - 1) / kBf16Range);
+  int best = smin;
+  double bf = fill(b1 * smin);
+  for (int s = smin + 1; s <= smin + 8; ++s) {
+    if (P / s < 512) break;  // keep each range long against its epilogue and the extra pass
+    const double f = fill(b1 * s);
+    if (f > bf + 0.05) { best = s; bf = f; }
+  }
+  return best;
+}
+
+// Upper-triangle tiles (ti <= tj) of an nt x nt tile grid in GR x GC blocks,
+// blocks row-major, tiles row-major inside a block; one device table per
+// (nt, GR, GC), kept by the context.
+static gw_status tile_order(gw_ctx* c, int nt, int GR, int GC, const int2** out) {
+  const long long key = ((long long)nt << 16) | (GR << 8) | GC;
+  auto it = c->tile_orders.find(key);
+  if (it != c->tile_orders.end()) { *out = static_cast<const int2*>(it->second); return GW_OK; }
+  std::vector<int2> h;
+  for (int bi = 0; bi < nt; bi += GR)
+    for (int bj = (bi / GC) * GC; bj < nt; bj += GC)
+      for (int i = bi; i < std::min(nt, bi + GR); ++i)
+        for (int j = bj; j < std::min(nt, bj + GC); ++j)
+          if (i <= j) h.push_back(make_int2(i, j));
+  void* d = nullptr;
+  GW_HIP(c, hipMalloc(&d, h.size() * sizeof(int2)));
+  GW_HIP(c, hipMemcpy(d, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
+  c->tile_orders[key] = d;
+  *out = static_cast<const int2*>(d);
+  return GW_OK;
+}
+
 int chi0_split(gw_ctx* c, int P, int neps, int nfreq, gw_prec prec, gw_dtype dt) {
+  if (prec == GW_PREC_SPLITBF16) return chi0_split_w(c, P, neps, nfreq);
   const int nt = (neps + kChiTM - 1) / kChiTM;
   const long long b1 = (long long)nt * (nt + 1) / 2 * nfreq;
   int per_cu = 0;
   hipError_t e;
-  if (prec == GW_PREC_SPLITBF16)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_bf16s<kChiWM>, 64 * kChiWM * kChiWM, 0);
-  else if (dt == GW_C128)
+  if (dt == GW_C128)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_f64<kChiWM, double>, 64 * kChiWM * kChiWM, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chi0_f64<kChiWM, float>, 64 * kChiWM * kChiWM, 0);
@@ -230,24 +319,35 @@ static gw_status chi0_reduce(gw_ctx* c, int neps, int nfreq, double* chi0, int s
 }
 
 gw_status chi0_fp64(gw_ctx* c, int P, int neps, const void* mtxel, gw_dtype dt, int nfreq,
-                    const double* wts, int skip_head, double* chi0, int split, double* part) {
+                    const double* wts, int skip_head, double* chi0, int split, double* part,
+                    bool no_alloc) {
   const int nt = (neps + kChiTM - 1) / kChiTM;
   const int ntri = nt * (nt + 1) / 2;
   const int pc = range_len(P, split);
   if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
     return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
+  // the blocked tile order is a device table built on first use; a caller that
+  // may not allocate takes the row-major order instead
+  const int2* order = nullptr;
+  if (!no_alloc) {
+    gw_status st = tile_order(c, nt, 8, 16, &order);
+    if (st != GW_OK) return st;
+  }
   {
     ProfScope ps(c, "chi0_fp64");
-    const dim3 g(ntri, nfreq, split);
+    const long long tot = (long long)ntri * split * nfreq;
+    const dim3 g((unsigned)(((tot + kXcd - 1) / kXcd) * kXcd));
     auto* pp = reinterpret_cast<cpx<double>*>(part);
     if (dt == GW_C128)
       hipLaunchKernelGGL((k_chi0_f64<kChiWM, double>), g, dim3(64 * kChiWM * kChiWM), 0, c->stream,
                          static_cast<const cpx<double>*>(mtxel), P, neps, wts,
-                         reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc, pp);
+                         reinterpret_cast<cpx<double>*>(chi0), order, ntri, split, nfreq,
+                         skip_head, pc, pp);
     else
       hipLaunchKernelGGL((k_chi0_f64<kChiWM, float>), g, dim3(64 * kChiWM * kChiWM), 0, c->stream,
                          static_cast<const cpx<float>*>(mtxel), P, neps, wts,
-                         reinterpret_cast<cpx<double>*>(chi0), nt, skip_head, pc, pp);
+                         reinterpret_cast<cpx<double>*>(chi0), order, ntri, split, nfreq,
+                         skip_head, pc, pp);
     GW_CHECK_LAUNCH(c, "k_chi0_f64");
   }
   return chi0_reduce(c, neps, nfreq, chi0, split, part);
@@ -274,20 +374,26 @@ gw_status split_bf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq, c
 gw_status chi0_splitbf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq,
                          const double* wts, int skip_head, double* chi0, int split, double* part,
                          void* xsplit) {
-  const int nt = (neps + kChiTM - 1) / kChiTM;
-  const int ntri = nt * (nt + 1) / 2;
+  const int nt = (neps + WT - 1) / WT;
+  const int ntile = nt * (nt + 1) / 2;
   const int pc = range_len(P, split), Pb = (P + BK - 1) / BK;
   if (split > 1 && (!part || (long long)pc * (split - 1) >= P))
     return fail(c, GW_EINVAL, "chi0 pair split %d of %d pairs is invalid", split, P);
-  auto* X = static_cast<unsigned short*>(xsplit);
-  gw_status st = split_bf16(c, P, neps, mtxel, nfreq, wts, xsplit);
+  if (pc > kBf16Range + BK)
+    return fail(c, GW_EINVAL, "chi0 pair range of %d pairs exceeds the float accumulation bound", pc);
+  const int2* order = nullptr;
+  gw_status st = tile_order(c, nt, 4, 8, &order);
   if (st != GW_OK) return st;
+  auto* X = static_cast<unsigned short*>(xsplit);
+  if ((st = split_bf16(c, P, neps, mtxel, nfreq, wts, xsplit)) != GW_OK) return st;
   {
     ProfScope ps(c, "chi0_bf16x3");
-    hipLaunchKernelGGL(k_chi0_bf16s<kChiWM>, dim3(ntri, nfreq, split), dim3(64 * kChiWM * kChiWM),
-                       0, c->stream, X, Pb, neps, reinterpret_cast<cpx<double>*>(chi0), nt,
-                       skip_head, pc / BK, reinterpret_cast<cpx<double>*>(part));
-    GW_CHECK_LAUNCH(c, "k_chi0_bf16s");
+    const long long tot = (long long)ntile * split * nfreq;
+    const unsigned grid = (unsigned)(((tot + kXcd - 1) / kXcd) * kXcd);
+    hipLaunchKernelGGL(k_chi0_bf16w, dim3(grid), dim3(512), 0, c->stream, X, Pb, neps, order,
+                       ntile, split, nfreq, reinterpret_cast<cpx<double>*>(chi0), skip_head,
+                       pc / BK, reinterpret_cast<cpx<double>*>(part));
+    GW_CHECK_LAUNCH(c, "k_chi0_bf16w");
   }
   return chi0_reduce(c, neps, nfreq, chi0, split, part);
 }

@@ -460,6 +460,127 @@ __device__ __forceinline__ void chi0_bf16s_tile_dl(const unsigned short* __restr
       }
 }
 
+// ------------------------------------------------------------------ split-BF16 chi0 tile, 128 x 128
+// The contraction's operand traffic per flop falls with the tile edge: a 64 x 64
+// tile streams 32 KiB of staged operands per 32-pair slab for 3.1 MFLOP, which
+// at the matrix cores' rate needs more operand feed than L2 and the CU's load
+// path give. This tile is 128 x 128 on 8 wavefronts of 64 x 32 (4 x 2 blocks
+// of v_mfma_f32_16x16x32_bf16): per slab 64 KiB in, 12.6 MFLOP, and each
+// wavefront reads 24 fragments of 1 KiB from LDS for 96 MFMAs.
+//   - Slabs go straight into LDS with global_load_lds_dwordx4 (16 rows x 64 B
+//     of one plane per wavefront instruction, 8 per wavefront per slab), into
+//     two slabs kept as separate LDS objects (128 KiB) and alternated, one
+//     barrier per slab; the chunk XOR swizzle is the 64 x 64 tile's.
+//   - The accumulation stays in float over the whole pair range of the
+//     workgroup (the caller bounds it at 8192 pairs, 256 MFMA accumulations);
+//     ranges are added in double.
+constexpr int WT = 128;  // tile edge of chi0_bf16s_tile_w
+__device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restrict__ XA,
+                                                  const unsigned short* __restrict__ XB, int pb0,
+                                                  int npb, int neps, cpx<double>* __restrict__ C,
+                                                  int ti, int tj, int skip_head, bool overwrite) {
+  __shared__ __align__(16) unsigned short As0[4][WT][BK], Bs0[4][WT][BK];
+  __shared__ __align__(16) unsigned short As1[4][WT][BK], Bs1[4][WT][BK];
+  typedef unsigned short (*Slab)[WT][BK];
+  const int i0 = ti * WT, j0 = tj * WT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;  // rows wr*64 .. +63, columns wc*32 .. +31
+  const int l16 = lane & 15, lk = lane >> 4;
+  f4 cr[4][2], ci[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      cr[x][y] = (f4){0, 0, 0, 0};
+      ci[x][y] = (f4){0, 0, 0, 0};
+    }
+  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lrow >> 2) & 3);
+  // the wavefront's 8 of the slab's 64 row blocks (operand, plane, 16-row block)
+  auto issue = [&](Slab A, Slab B, int pb) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = wave * 8 + u, opnd = idx >> 5, q = (idx >> 3) & 3, blk = idx & 7;
+      const size_t plane = ((size_t)pb * 4 + q) * neps;
+      const int r = 16 * blk + lrow;
+      const unsigned short* src =
+          (opnd ? XB + (plane + min(j0 + r, neps - 1)) * BK
+                : XA + (plane + min(i0 + r, neps - 1)) * BK) + lchunk * 8;
+      unsigned short* dst = opnd ? &B[q][16 * blk][0] : &A[q][16 * blk][0];
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)dst, 16, 0, 0);
+    }
+  };
+  const int pch = (lk ^ ((l16 >> 2) & 3)) * 8;
+  auto compute = [&](Slab A, Slab B) {
+    bf8 b[2][4];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        b[y][q] = *reinterpret_cast<const bf8*>(&B[q][wc * 32 + y * 16 + l16][pch]);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      bf8 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[q] = *reinterpret_cast<const bf8*>(&A[q][wr * 64 + x * 16 + l16][pch]);
+      bf8 na[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 t = __builtin_bit_cast(us8, a[2 + q]);
+        t ^= (us8)(0x8000);
+        na[q] = __builtin_bit_cast(bf8, t);
+      }
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+#define GW_MF(ACC, A_, B_) ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_, B_, ACC[x][y], 0, 0, 0);
+        GW_MF(cr, a[0], b[y][0])
+        GW_MF(ci, a[0], b[y][2])
+        GW_MF(cr, a[0], b[y][1])
+        GW_MF(ci, a[0], b[y][3])
+        GW_MF(cr, a[1], b[y][0])
+        GW_MF(ci, a[1], b[y][2])
+        GW_MF(cr, a[2], b[y][2])
+        GW_MF(ci, na[0], b[y][0])
+        GW_MF(cr, a[2], b[y][3])
+        GW_MF(ci, na[0], b[y][1])
+        GW_MF(cr, a[3], b[y][2])
+        GW_MF(ci, na[1], b[y][0])
+#undef GW_MF
+      }
+    }
+  };
+  const int pend = pb0 + npb;
+  auto step = [&](Slab Ac, Slab Bc, Slab An, Slab Bn, int pn) {
+    if (pn < pend) issue(An, Bn, pn);
+    compute(Ac, Bc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  if (npb > 0) {
+    issue(As0, Bs0, pb0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int pb = pb0; pb < pend; pb += 2) {
+      step(As0, Bs0, As1, Bs1, pb + 1);
+      if (pb + 1 < pend) step(As1, Bs1, As0, Bs0, pb + 2);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
+        const int i = i0 + wr * 64 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
+        double im = ci[x][y][r];
+        bool od;
+        if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
+        if (overwrite) herm_store(C, neps, i, j, (double)cr[x][y][r], im, od, skip_head);
+        else herm_add(C, neps, i, j, (double)cr[x][y][r], im, od, skip_head);
+      }
+}
+
 template <int WM>
 __device__ __forceinline__ void chi0_bf16s_tile(const unsigned short* __restrict__ XA,
                                                 const unsigned short* __restrict__ XB, int pb0,
