@@ -199,7 +199,9 @@ gw_status gw_chi0_accumulate_real(gw_ctx* ctx, int nv, int nc, int neps,
  * Hermitian negative semidefinite (the imaginary axis), eps~ = I - V^1/2 chi0
  * V^1/2 is Hermitian positive definite and is inverted by blocked Gauss-Jordan
  * without pivoting, every pivot checked (real part >= 1/2, |imaginary part| <=
- * 1/4 of it).  If a check fails (for example eps from the real axis), the
+ * 1/4 of it), and chi0 checked for Hermiticity as eps~ is formed
+ * (|chi_ij - conj(chi_ji)| <= 1e-12 (|chi_ij| + |chi_ji|)).  If a check fails
+ * (for example eps from the real axis), the
  * Gauss-Jordan result is kept only if max_ij |(eps X - I)_ij| <= 1e-10 / neps
  * (|re| + |im|, every frequency, eps formed again and multiplied on the matrix
  * cores), which bounds the relative error of X in the infinity norm by 1e-10;
@@ -209,8 +211,9 @@ gw_status gw_chi0_accumulate_real(gw_ctx* ctx, int nv, int nc, int neps,
  *   chi0    (device) complex double[nfreq][neps][neps].
  *   vcoul   (device) double[neps], v(q+G) = 4 pi / (Omega |q+G|^2).
  *   epsinv  (device) out complex double[nfreq][neps][neps]; may not alias chi0.
- * Synchronises the context stream to read the flags: GW_ESINGULAR if any pivot
- * of the LU path was exactly zero (epsinv then holds non-finite values).
+ * Synchronises the context stream to read the flags: GW_EINVAL if chi0 holds
+ * a non-finite entry, GW_ESINGULAR if any pivot of the LU path was exactly zero
+ * (epsinv then holds non-finite values).
  */
 gw_status gw_epsinv(gw_ctx* ctx, int neps, int nfreq, const double* chi0,
                     const double* vcoul, double* epsinv);

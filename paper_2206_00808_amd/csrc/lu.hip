@@ -209,6 +209,7 @@ __global__ void k_fill_int(int* p, int n, int v) {
 
 // epst = I - S chi0 S with S = diag(sqrt(v)), one 32x32 tile per workgroup
 // (grid: tiles x tiles x nfreq). flag[1] = 1 if some v <= 0 or non-finite;
+// flag[4] = 1 if some chi0 entry is not finite;
 // flag[3] = 1 if chi0 is not Hermitian: |chi_ij - conj(chi_ji)| above
 // kHermRel (|chi_ij| + |chi_ji|) for some pair, checked against the mirror
 // tile staged through LDS. The Gauss-Jordan pivot test alone cannot tell a
@@ -232,7 +233,7 @@ __global__ void __launch_bounds__(256) k_epst_build(const cpx<double>* __restric
     if (i < N && j < N) mir[c][r] = chi[(size_t)i * N + j];
   }
   __syncthreads();
-  bool bad = false;
+  bool bad = false, nonfinite = false;
   for (int r = r0; r < ET; r += 256 / ET) {
     const int i = ti * ET + r, j = tj * ET + c;
     if (i >= N || j >= N) continue;
@@ -242,12 +243,13 @@ __global__ void __launch_bounds__(256) k_epst_build(const cpx<double>* __restric
     const cpx<double> y = mir[r][c];  // chi[j][i]
     const double dr = x.x - y.x, di = x.y + y.y;
     const double lim = kHermRel * (fabs(x.x) + fabs(x.y) + fabs(y.x) + fabs(y.y));
-    // a non-finite entry also routes the result through the residual check
+    nonfinite = nonfinite || !(fabs(x.x) < INFINITY && fabs(x.y) < INFINITY);
     bad = bad || !(fabs(dr) <= lim && fabs(di) <= lim);
     const double s = sqrt(vi) * sqrt(vj);
     A[(size_t)i * N + j] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
   }
   if (bad) flag[3] = 1;
+  if (nonfinite) flag[4] = 1;
 }
 
 // Inverse of the diagonal block D = A[K][K] (nbk <= GB = 64) by Gauss-Jordan
@@ -774,9 +776,10 @@ gw_status epsinv_run(gw_ctx* c, int N, int nfreq, const double* chi0, const doub
                      double* epsinv) {
   gw_status st = epsinv_gauss_jordan(c, N, nfreq, chi0, vcoul, epsinv);
   if (st != GW_OK) return st;
-  int flags[4] = {0, 0, 0, 0};
+  int flags[5] = {0, 0, 0, 0, 0};
   GW_HIP(c, hipMemcpyAsync(flags, c->d_flag, sizeof flags, hipMemcpyDeviceToHost, c->stream));
   GW_HIP(c, hipStreamSynchronize(c->stream));
+  if (flags[4]) return fail(c, GW_EINVAL, "chi0 holds a non-finite entry");
   // some v <= 0: the symmetric form eps~ does not exist; general LU
   if (flags[1]) return epsinv_pivoted_one(c, N, nfreq, chi0, vcoul, epsinv);
   if (!flags[2] && !flags[3]) return GW_OK;

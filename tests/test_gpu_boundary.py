@@ -96,3 +96,31 @@ def test_non_hermitian_chi_with_passing_pivots_is_verified(P, ctx):
         assert oracle.rel_f(out.cpu().numpy(), want) < 1e-10, name
         # the Hermitian matrix needs no residual check; the other one gets it
         assert ("eps_verify" in tab) == (name == "non_hermitian"), (name, sorted(tab))
+
+
+def test_nan_coefficient_is_reported_by_epsinv(P, ctx):
+    """Error injection: one NaN coefficient in a conduction band spreads through
+    the matrix elements and chi0 (the calls do not read device data back), and
+    gw_epsinv, which reads its flags, reports it as GW_EINVAL."""
+    from paper_2206_00808_amd import pipeline
+    s = synth.build_system(synth.CONFIGS["T1"])
+    bad = dict(s, cc=s["cc"].copy())
+    bad["cc"][3, 1, 7] = np.nan
+    d = pipeline.upload(bad)
+    out = pipeline.alloc_outputs(d)
+    pipeline.run_path(ctx, d, out, stages=("mtxel", "chi0"))
+    torch.cuda.synchronize()
+    m = out["mtxel"].cpu().numpy()
+    assert np.isnan(m[:, 3]).any() and np.isfinite(np.delete(m, 3, axis=1)).all()
+    with pytest.raises(P.GwError) as ei:
+        P.gw_epsinv(ctx, d["neps"], len(d["omega"]), out["chi0"], d["vcoul"], out["epsinv"])
+    assert ei.value.status == P.GW_EINVAL
+    # the context stays usable: the clean system goes through
+    good = pipeline.upload(s)
+    o2 = pipeline.alloc_outputs(good)
+    pipeline.run_path(ctx, good, o2)
+    torch.cuda.synchronize()
+    mref = oracle.mtxel_convolution(s["cv"], s["gv"], s["cc"], s["gc"], s["geps"])
+    x = oracle.chi0(mref, s["ev"], s["ec"], s["omega"])
+    e = oracle.epsilon_inverse(x, s["vcoul"])
+    assert oracle.rel_f(o2["epsinv"].cpu().numpy(), e) < 1e-10
