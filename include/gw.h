@@ -149,6 +149,25 @@ gw_status gw_chi0_accumulate(gw_ctx* ctx, int nv, int nc, int neps,
                              double* chi0);
 
 /*
+ * gw_chi0_accumulate_noalloc -- gw_chi0_accumulate in FP64 (GW_PREC_FP64)
+ * without any allocation, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it.
+ * Same arguments and result as gw_chi0_accumulate with prec = GW_PREC_FP64;
+ * the contraction runs as one pair range (no partial sums), the frequencies
+ * travel by value in the kernel arguments, and the pair weights live in a
+ * fixed 32 MiB device array of the library (one copy on each device, held until
+ * the process ends).  Limits: nfreq <= 64 and nfreq * nv * nc * 8 bytes <= 32
+ * MiB, else GW_EINVAL before anything is enqueued.  Calls that overlap on one
+ * device share that array and race; calls on one stream are ordered.
+ * Asynchronous; calls no allocating routine.
+ */
+gw_status gw_chi0_accumulate_noalloc(gw_ctx* ctx, int nv, int nc, int neps,
+                                     const void* mtxel, gw_dtype dtype, const double* ev,
+                                     const double* ec, int nfreq, const double* omega,
+                                     double prefactor, const double* mhead, int head_index,
+                                     double* chi0);
+
+/*
  * gw_head_dipole -- the q -> 0 head M_vc(q, G=0) from momentum matrix elements at
  * one k-point (Sec. II, optical absorption: the dipole relation with the
  * momentum operator standing in for the velocity), to first order in q:

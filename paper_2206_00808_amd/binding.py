@@ -26,7 +26,8 @@ EXPORTED = [
     "gw_ctx_create", "gw_ctx_destroy", "gw_ctx_set_stream", "gw_last_error", "gw_status_string",
     "gw_ctx_profile", "gw_ctx_profile_only", "gw_ctx_profile_reset", "gw_ctx_profile_count",
     "gw_ctx_profile_entry",
-    "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_epsinv", "gw_chi0_accumulate_real",
+    "gw_mtxel_spinor", "gw_chi0_accumulate", "gw_chi0_accumulate_noalloc", "gw_epsinv",
+    "gw_chi0_accumulate_real",
     "gw_epsinv_lu", "gw_head_dipole", "gw_screened_w", "gw_sigma_sx",
     "gw_unfold_spinor", "gw_gpp_modes", "gw_sigma_gpp", "gw_chi0_symmetrize",
     "gw_bse_kernel", "gw_little_group", "gw_kgrid_orbits", "gw_epsinv_lowrank",
@@ -78,6 +79,8 @@ _SIG = {
                              _vp, _i, _vp]),
     "gw_chi0_accumulate": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _i, _vp, _i,
                                 _vp]),
+    "gw_chi0_accumulate_noalloc": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _vp,
+                                        _i, _vp]),
     "gw_epsinv": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "gw_chi0_accumulate_real": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _d, _d, _i,
                                      _vp]),
@@ -248,6 +251,19 @@ def gw_chi0_accumulate(ctx, nv, nc, neps, mtxel, ev, ec, omega, prefactor, prec,
     s = _lib.gw_chi0_accumulate(ctx.handle, int(nv), int(nc), int(neps), _ptr(mtxel), dt,
                                 _ptr(ev), _ptr(ec), len(om), om.ctypes.data, float(prefactor),
                                 int(prec), _ptr(mhead), int(head_index), _ptr(chi0))
+    return _check(ctx, s)
+
+
+def gw_chi0_accumulate_noalloc(ctx, nv, nc, neps, mtxel, ev, ec, omega, prefactor, chi0,
+                               mhead=None, head_index=-1):
+    """gw_chi0_accumulate in FP64 without any allocation (see include/gw.h)."""
+    ctx.sync_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    dt = _dtype_code(mtxel)
+    s = _lib.gw_chi0_accumulate_noalloc(ctx.handle, int(nv), int(nc), int(neps), _ptr(mtxel), dt,
+                                        _ptr(ev), _ptr(ec), len(om), om.ctypes.data,
+                                        float(prefactor), _ptr(mhead), int(head_index),
+                                        _ptr(chi0))
     return _check(ctx, s)
 
 

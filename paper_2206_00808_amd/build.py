@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libgwspinor.so")
-SOURCES = ["api.hip", "fft.hip", "fft_xy.hip", "gemm.hip", "head.hip", "lu.hip", "closure.hip", "plan.hip", "symm.hip", "gpp.hip", "bse.hip", "lowrank.hip", "probe.hip"]
+SOURCES = ["api.hip", "fft.hip", "fft_xy.hip", "gemm.hip", "head.hip", "lu.hip", "closure.hip", "plan.hip", "symm.hip", "gpp.hip", "bse.hip", "lowrank.hip", "probe.hip", "noalloc.hip"]
 ARCH = os.environ.get("GW_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
