@@ -7,15 +7,18 @@
 // eigenvalues and epst_B(w) = U^H epst(w) U:
 //   epst^-1(w) ~= I + U (epst_B(w)^-1 - I) U^H,   eps^-1 = V^1/2 epst^-1 V^-1/2.
 //
-// The eigenvectors come from a cyclic two-sided Jacobi method on the GPU:
-// each sweep runs N - 1 rounds of N/2 disjoint plane rotations in round-robin
-// order (every pair once per sweep), each round as two kernels (rotation
-// parameters; then one workgroup per pair rewriting its two rows of J^H A J and
-// of the eigenvector rows, see k_jac_round).
-// One sweep is captured into a HIP graph and replayed; sweeps repeat until the
-// off-diagonal Frobenius norm is below 1e-14 of the matrix's.  The projections
-// and the small inverses run on the FP64 GEMM and the library's Hermitian
-// inverse (Gauss-Jordan with its checks).
+// The eigenvectors come from a Jacobi method on the GPU, repeated in sweeps
+// until the off-diagonal Frobenius norm is below 1e-14 of the matrix's, one
+// sweep captured into a HIP graph and replayed:
+//   - N >= 128: block Jacobi. 32 x 32 sub-problems (pairs of 16-row blocks) are
+//     diagonalised in LDS (k_bj_solve), and their unitaries update the block
+//     rows and columns of A and the eigenvector rows on the matrix cores
+//     (k_bj_mix), in round-robin rounds over block pairs;
+//   - N < 128: N - 1 rounds of N/2 disjoint plane rotations, each round one
+//     kernel that forms its rotations and rewrites the two rows of J^H A J and
+//     of the eigenvector rows of every pair in LDS (k_jac_round_pp).
+// The projections and the small inverses run on the FP64 GEMM and the
+// library's Hermitian inverse (Gauss-Jordan with its checks).
 #include <cmath>
 #include <vector>
 
@@ -39,107 +42,6 @@ __global__ void k_lr_epst(const cpx<double>* __restrict__ chi, const double* __r
   const double s = sqrt(v[i]) * sqrt(v[j]);
   const cpx<double> x = chi[(size_t)blockIdx.y * nn + e];
   E[(size_t)blockIdx.y * nn + e] = mk((i == j ? 1.0 : 0.0) - s * x.x, -s * x.y);
-}
-
-// round r of the round-robin schedule over m (even) indices: pair 0 is (r, m-1),
-// pair k > 0 is ((r + k) mod (m-1), (r - k) mod (m-1)); indices >= N are padding
-__global__ void k_jac_params(const cpx<double>* __restrict__ A, int N, int m, int r,
-                             JacRot* __restrict__ rot, int* __restrict__ pairof) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m / 2) return;
-  int p, q;
-  if (k == 0) {
-    p = r;
-    q = m - 1;
-  } else {
-    p = (r + k) % (m - 1);
-    q = (r - k + (m - 1)) % (m - 1);
-  }
-  if (p > q) {
-    const int t = p;
-    p = q;
-    q = t;
-  }
-  JacRot o;
-  o.p = p;
-  o.q = q;
-  o.pad = 0;
-  o.skip = 1;
-  o.c = 1.0;
-  o.s = 0.0;
-  o.er = 1.0;
-  o.ei = 0.0;
-  if (q < N) {
-    const cpx<double> b = A[(size_t)p * N + q];
-    const double ab = hypot(b.x, b.y);
-    if (ab > 0.0) {
-      const double a = A[(size_t)p * N + p].x, d = A[(size_t)q * N + q].x;
-      // real symmetric [[a, |b|], [|b|, d]]: t = tan(theta), the smaller root
-      const double tau = (d - a) / (2.0 * ab);
-      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-      o.c = 1.0 / sqrt(1.0 + t * t);
-      o.s = t * o.c;
-      o.er = b.x / ab;
-      o.ei = b.y / ab;
-      o.skip = 0;
-    }
-  }
-  rot[k] = o;
-  if (p < N) pairof[p] = k;
-  if (q < N) pairof[q] = k;
-}
-
-// One round, one workgroup per pair (p, q): rows p and q of A' = J^H A J.  The
-// row rotation needs only rows p and q of A; the column rotation then mixes,
-// inside each of those rows, the two entries of every pair of the round, so the
-// whole update stays within the two rows (held in LDS).  Vt <- J^T Vt (the
-// eigenvectors as rows) needs the row rotation only.
-__global__ void __launch_bounds__(256) k_jac_round(cpx<double>* __restrict__ A,
-                                                   cpx<double>* __restrict__ Vt, int N,
-                                                   const JacRot* __restrict__ rot,
-                                                   const int* __restrict__ pairof) {
-  extern __shared__ cpx<double> rows[];  // [2][N]
-  cpx<double>* bp = rows;
-  cpx<double>* bq = rows + N;
-  const JacRot o = rot[blockIdx.x];
-  const bool hasq = o.q < N;
-  const cpx<double> e = mk(o.er, o.ei), ec = mk(o.er, -o.ei);
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    const cpx<double> ap = A[(size_t)o.p * N + j];
-    const cpx<double> aq = hasq ? A[(size_t)o.q * N + j] : mk(0.0, 0.0);
-    if (o.skip) {
-      bp[j] = ap;
-      bq[j] = aq;
-    } else {
-      // J^H rows: new p = c ap - s e^{i phi} aq;  new q = s ap + c e^{i phi} aq
-      const cpx<double> eq = cmul(e, aq);
-      bp[j] = scal(ap, o.c) - scal(eq, o.s);
-      bq[j] = scal(ap, o.s) + scal(eq, o.c);
-      // (V J)^T rows: new p = c vp - s e^{-i phi} vq;  new q = s vp + c e^{-i phi} vq
-      const cpx<double> vp = Vt[(size_t)o.p * N + j], vq = Vt[(size_t)o.q * N + j];
-      const cpx<double> ev = cmul(ec, vq);
-      Vt[(size_t)o.p * N + j] = scal(vp, o.c) - scal(ev, o.s);
-      Vt[(size_t)o.q * N + j] = scal(vp, o.s) + scal(ev, o.c);
-    }
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    const JacRot w = rot[pairof[j]];
-    cpx<double> np = bp[j], nq = bq[j];
-    if (!w.skip) {
-      // columns: new col p' = c a_p' - s e^{-i phi} a_q';  new col q' = s a_p' + c e^{-i phi} a_q'
-      const cpx<double> wc = mk(w.er, -w.ei);
-      if (j == w.p) {
-        np = scal(bp[w.p], w.c) - scal(cmul(wc, bp[w.q]), w.s);
-        nq = scal(bq[w.p], w.c) - scal(cmul(wc, bq[w.q]), w.s);
-      } else {
-        np = scal(bp[w.p], w.s) + scal(cmul(wc, bp[w.q]), w.c);
-        nq = scal(bq[w.p], w.s) + scal(cmul(wc, bq[w.q]), w.c);
-      }
-    }
-    A[(size_t)o.p * N + j] = np;
-    if (hasq) A[(size_t)o.q * N + j] = nq;
-  }
 }
 
 // The whole round in one kernel, reading A_in and writing A_out (the two buffers
@@ -496,32 +398,94 @@ __global__ void k_bj_select(const cpx<double>* __restrict__ Vt, int Np, const in
   }
 }
 
-// partial sums of |A_ij|^2 off the diagonal and over all entries, fixed order
+// Frobenius norms as (scale, ssq) with norm = scale * sqrt(ssq), the scaled
+// sum of squares of LAPACK's lassq: no square is formed of an unscaled entry,
+// so entries up to the double range neither overflow nor lose their smallest
+// companions to underflow.
+struct ScaledSsq {
+  double scale, ssq;
+};
+__host__ __device__ __forceinline__ void ssq_add(ScaledSsq& a, double x) {
+  const double ax = fabs(x);
+  if (ax == 0.0) return;
+  if (a.scale < ax) {
+    const double r = a.scale / ax;
+    a.ssq = fma(a.ssq * r, r, 1.0);
+    a.scale = ax;
+  } else {
+    const double r = ax / a.scale;
+    a.ssq = fma(r, r, a.ssq);
+  }
+}
+__host__ __device__ __forceinline__ ScaledSsq ssq_merge(ScaledSsq a, ScaledSsq b) {
+  if (a.scale < b.scale) {
+    const ScaledSsq t = a;
+    a = b;
+    b = t;
+  }
+  if (b.scale == 0.0) return a;
+  const double r = b.scale / a.scale;
+  a.ssq = fma(b.ssq * r, r, a.ssq);
+  return a;
+}
+// Non-finite entries are flagged on their own: a NaN compares false in ssq_add
+// and would drop out of the sums.
+constexpr int kNormParts = 1024;          // blocks of the norm reduction, at most
+constexpr size_t kNormPartBytes = (size_t)kNormParts * 5 * sizeof(double);
+
+// per block: (scale, ssq) off the diagonal and over all entries, and a
+// non-finite flag, in a fixed order
 __global__ void __launch_bounds__(256) k_lr_norms(const cpx<double>* __restrict__ A, int N,
                                                   double* __restrict__ part) {
-  __shared__ double so[256], sa[256];
+  __shared__ ScaledSsq so[256], sa[256];
+  __shared__ int bad[256];
   const size_t nn = (size_t)N * N;
-  double off = 0.0, all = 0.0;
+  ScaledSsq off{0.0, 0.0}, all{0.0, 0.0};
+  int nf = 0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (size_t)gridDim.x * 256) {
     const cpx<double> x = A[e];
-    const double m2 = x.x * x.x + x.y * x.y;
-    all += m2;
-    if (e / N != e % N) off += m2;
+    nf |= !(isfinite(x.x) && isfinite(x.y));
+    ssq_add(all, x.x);
+    ssq_add(all, x.y);
+    if (e / N != e % N) {
+      ssq_add(off, x.x);
+      ssq_add(off, x.y);
+    }
   }
   so[threadIdx.x] = off;
   sa[threadIdx.x] = all;
+  bad[threadIdx.x] = nf;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
-      so[threadIdx.x] += so[threadIdx.x + h];
-      sa[threadIdx.x] += sa[threadIdx.x + h];
+      so[threadIdx.x] = ssq_merge(so[threadIdx.x], so[threadIdx.x + h]);
+      sa[threadIdx.x] = ssq_merge(sa[threadIdx.x], sa[threadIdx.x + h]);
+      bad[threadIdx.x] |= bad[threadIdx.x + h];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = so[0];
-    part[2 * blockIdx.x + 1] = sa[0];
+    double* o = part + 5 * (size_t)blockIdx.x;
+    o[0] = so[0].scale;
+    o[1] = so[0].ssq;
+    o[2] = sa[0].scale;
+    o[3] = sa[0].ssq;
+    o[4] = bad[0] ? 1.0 : 0.0;
   }
+}
+
+// Jacobi convergence from the per-block norms: 1 converged (off-diagonal norm at
+// most 1e-14 of the whole), 0 not yet, -1 a non-finite entry
+static int jacobi_converged(const std::vector<double>& hp, int nblocks) {
+  ScaledSsq so{0.0, 0.0}, sa{0.0, 0.0};
+  for (int b = 0; b < nblocks; ++b) {
+    const double* p = hp.data() + 5 * (size_t)b;
+    if (p[4] != 0.0) return -1;
+    so = ssq_merge(so, ScaledSsq{p[0], p[1]});
+    sa = ssq_merge(sa, ScaledSsq{p[2], p[3]});
+  }
+  if (!std::isfinite(sa.scale) || !std::isfinite(sa.ssq)) return -1;
+  return so.scale * std::sqrt(so.ssq) <= 1e-14 * (sa.scale * std::sqrt(sa.ssq)) ? 1 : 0;
 }
 
 // rank of eigenvalue i in descending order (ties by index); eigenvalues ascending out
@@ -612,7 +576,7 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   const int nblk = Np / kBJ, npairs = nblk / 2;
   const size_t nnp = (size_t)Np * Np;
   const size_t bytes = 2 * align_up(nnp * 16) + align_up((size_t)npairs * kBJ2 * kBJ2 * 16) +
-                       align_up(2 * 1024 * 8) + align_up((size_t)N * 4) + 1024;
+                       align_up(kNormPartBytes) + align_up((size_t)N * 4) + 1024;
   char* base = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
     return fail(c, GW_ENOMEM, "block-Jacobi buffers of %zu bytes", bytes);
@@ -633,7 +597,7 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
   auto* Ap = reinterpret_cast<cpx<double>*>(take(nnp * 16));
   auto* Vp = reinterpret_cast<cpx<double>*>(take(nnp * 16));
   auto* Qt = reinterpret_cast<cpx<double>*>(take((size_t)npairs * kBJ2 * kBJ2 * 16));
-  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* part = reinterpret_cast<double*>(take(kNormPartBytes));
   auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
   const unsigned gnp = (unsigned)((nnp + 255) / 256);
   {
@@ -666,8 +630,8 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
     if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
   }
   GW_HIP(c, hipGraphInstantiate(&sg.exec, sg.g, nullptr, nullptr, 0));
-  const int nrb = (int)std::min<size_t>(1024, (nnp + 255) / 256);
-  std::vector<double> hp(2 * (size_t)nrb);
+  const int nrb = (int)std::min<size_t>(kNormParts, (nnp + 255) / 256);
+  std::vector<double> hp(5 * (size_t)nrb);
   bool done = false;
   for (int sweep = 0; sweep < 40 && !done; ++sweep) {
     {
@@ -678,14 +642,9 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
     GW_CHECK_LAUNCH(c, "k_lr_norms");
     GW_HIP(c, hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     GW_HIP(c, hipStreamSynchronize(c->stream));
-    double so = 0.0, sa = 0.0;
-    for (int b = 0; b < nrb; ++b) {
-      so += hp[2 * b];
-      sa += hp[2 * b + 1];
-    }
-    if (!std::isfinite(so) || !std::isfinite(sa))
-      return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
-    done = so <= 1e-28 * sa;
+    const int cv = jacobi_converged(hp, nrb);
+    if (cv < 0) return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
+    done = cv > 0;
   }
   if (!done) return fail(c, GW_EINVAL, "block-Jacobi eigen-decomposition did not converge");
   ProfScope ps(c, "lowrank_basis");
@@ -698,10 +657,12 @@ static gw_status jacobi_basis_block(gw_ctx* c, int N, int nb, const cpx<double>*
 
 constexpr int kBlockJacobiMin = 128;  // from this N on, block Jacobi
 
+// A2 and Vt (N x N) are used only below kBlockJacobiMin (null otherwise)
 static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<double>* A2,
-                              cpx<double>* Vt, JacRot* rot, int* pairof, double* part, int* rank,
-                              cpx<double>* U, cpx<double>* Uh, double* lam) {
+                              cpx<double>* Vt, double* part, int* rank, cpx<double>* U,
+                              cpx<double>* Uh, double* lam) {
   if (N >= kBlockJacobiMin) return jacobi_basis_block(c, N, nb, A, U, Uh, lam);
+  static_assert(kBlockJacobiMin <= 1024, "the one-kernel rounds keep two rows in LDS");
   const size_t nn = (size_t)N * N;
   const int m = N + (N & 1);
   {
@@ -713,8 +674,8 @@ static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<doub
   }
   // cyclic Jacobi on epst(0): one sweep (2 (m - 1) small launches) is captured
   // once into a graph on a private stream and replayed until converged
-  const int nblk = (int)std::min<size_t>(1024, (nn + 255) / 256);
-  std::vector<double> hp(2 * (size_t)nblk);
+  const int nblk = (int)std::min<size_t>(kNormParts, (nn + 255) / 256);
+  std::vector<double> hp(5 * (size_t)nblk);
   struct SweepGraph {
     hipStream_t cap = nullptr;
     hipGraph_t g = nullptr;
@@ -727,29 +688,19 @@ static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<doub
   } sg;
   GW_HIP(c, hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
   GW_HIP(c, hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
-  // one kernel per round while every pair's rotation and the two rows fit in
-  // 64 KiB of LDS (N up to about 1090): rounds alternate A -> A2 -> A ..., and an
-  // odd number of rounds ends with a copy back.  Larger N: a parameter kernel,
-  // then the two-row update in place.
+  // one kernel per round: every pair's rotation and the two rows fit in LDS
+  // (under 8 KiB below N = 128); rounds alternate A -> A2 -> A ..., and an odd
+  // number of rounds ends with a copy back
   const size_t lds_pp = (size_t)(m / 2) * sizeof(JacRot) + (size_t)((N + 3) & ~3) * 4 +
                         (size_t)2 * N * 16;
-  if (lds_pp <= 65536) {
-    for (int r = 0; r < m - 1; ++r) {
-      const bool even = (r & 1) == 0;
-      hipLaunchKernelGGL(k_jac_round_pp, dim3(m / 2), dim3(256), lds_pp, sg.cap, even ? A : A2,
-                         even ? A2 : A, Vt, N, m, r);
-    }
-    if ((m - 1) & 1)
-      hipLaunchKernelGGL(k_lr_copy, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, sg.cap, A2,
-                         nn, A);
-  } else {
-    const dim3 gp((m / 2 + 127) / 128);
-    for (int r = 0; r < m - 1; ++r) {
-      hipLaunchKernelGGL(k_jac_params, gp, dim3(128), 0, sg.cap, A, N, m, r, rot, pairof);
-      hipLaunchKernelGGL(k_jac_round, dim3(m / 2), dim3(256), (size_t)2 * N * 16, sg.cap, A, Vt,
-                         N, rot, pairof);
-    }
+  for (int r = 0; r < m - 1; ++r) {
+    const bool even = (r & 1) == 0;
+    hipLaunchKernelGGL(k_jac_round_pp, dim3(m / 2), dim3(256), lds_pp, sg.cap, even ? A : A2,
+                       even ? A2 : A, Vt, N, m, r);
   }
+  if ((m - 1) & 1)
+    hipLaunchKernelGGL(k_lr_copy, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, sg.cap, A2,
+                       nn, A);
   {
     const hipError_t le = hipGetLastError();
     const hipError_t ce = hipStreamEndCapture(sg.cap, &sg.g);
@@ -767,14 +718,9 @@ static gw_status jacobi_basis(gw_ctx* c, int N, int nb, cpx<double>* A, cpx<doub
     GW_CHECK_LAUNCH(c, "k_lr_norms");
     GW_HIP(c, hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     GW_HIP(c, hipStreamSynchronize(c->stream));
-    double so = 0.0, sa = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      so += hp[2 * b];
-      sa += hp[2 * b + 1];
-    }
-    if (!std::isfinite(so) || !std::isfinite(sa))
-      return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
-    done = so <= 1e-28 * sa;
+    const int cv = jacobi_converged(hp, nblk);
+    if (cv < 0) return fail(c, GW_EINVAL, "non-finite entries in epst(0)");
+    done = cv > 0;
   }
   if (!done) return fail(c, GW_EINVAL, "Jacobi eigen-decomposition of epst(0) did not converge");
   {
@@ -825,26 +771,24 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
                              const double* vcoul, int nb, double* epsinv, double* lam,
                              char* base) {
   const size_t nn = (size_t)N * N, nub = (size_t)N * nb, bb = (size_t)nb * nb;
-  const int m = N + (N & 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* p = base + off;
     off += align_up(bytes);
     return p;
   };
+  const bool small = N < kBlockJacobiMin;
   auto* E = reinterpret_cast<cpx<double>*>(take(nfreq * nn * 16));
   auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* A2 = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* A2 = small ? reinterpret_cast<cpx<double>*>(take(nn * 16)) : nullptr;
+  auto* Vt = small ? reinterpret_cast<cpx<double>*>(take(nn * 16)) : nullptr;
   auto* U = reinterpret_cast<cpx<double>*>(take(nub * 16));
   auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
   auto* Y = reinterpret_cast<cpx<double>*>(take(nfreq * nub * 16));
   auto* B = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
   auto* Bi = reinterpret_cast<cpx<double>*>(take(nfreq * bb * 16));
-  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
-  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* part = reinterpret_cast<double*>(take(kNormPartBytes));
   auto* rank = reinterpret_cast<int*>(take((size_t)N * 4));
-  auto* pairof = reinterpret_cast<int*>(take((size_t)N * 4));
   auto* ones = reinterpret_cast<double*>(take((size_t)nb * 8));
   const unsigned gnn = (unsigned)((nn + 255) / 256);
   {
@@ -852,13 +796,12 @@ static gw_status lowrank_run(gw_ctx* c, int N, int nfreq, const double* chi0,
     hipLaunchKernelGGL(k_lr_epst, dim3(gnn, nfreq), dim3(256), 0, c->stream,
                        reinterpret_cast<const cpx<double>*>(chi0), vcoul, N, E);
     GW_HIP(c, hipMemcpyAsync(A, E, nn * 16, hipMemcpyDeviceToDevice, c->stream));
-    // Vt = I; also the identity that the final products accumulate onto, and ones
-    hipLaunchKernelGGL(k_lr_fill, dim3(gnn, 1), dim3(256), 0, c->stream, Vt, N, ones, nb);
+    // the identity that the final products accumulate onto, and ones
     hipLaunchKernelGGL(k_lr_fill, dim3(gnn, nfreq), dim3(256), 0, c->stream,
                        reinterpret_cast<cpx<double>*>(epsinv), N, ones, nb);
     GW_CHECK_LAUNCH(c, "low-rank preparation");
   }
-  gw_status st = jacobi_basis(c, N, nb, A, A2, Vt, rot, pairof, part, rank, U, Uh, lam);
+  gw_status st = jacobi_basis(c, N, nb, A, A2, Vt, part, rank, U, Uh, lam);
   if (st != GW_OK) return st;
   const long long snn = (long long)nn, snb = (long long)nub, sbb = (long long)bb;
   // Y_f = E_f U;  B_f = U^H Y_f
@@ -903,11 +846,11 @@ extern "C" gw_status gw_epsinv_lowrank(gw_ctx* c, int neps, int nfreq, const dou
   for (double x : hv)
     if (!(x > 0.0) || !std::isfinite(x)) return fail(c, GW_EINVAL, "vcoul must be positive");
   const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb, bb = (size_t)nb * nb;
-  const int m = neps + (neps & 1);
-  const size_t bytes = align_up(nfreq * nn * 16) + 3 * align_up(nn * 16) + 2 * align_up(nub * 16) +
-                       align_up(nfreq * nub * 16) + 2 * align_up(nfreq * bb * 16) +
-                       align_up((size_t)(m / 2) * 48) + align_up(2 * 1024 * 8) +
-                       2 * align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
+  const int nsq = neps < kBlockJacobiMin ? 3 : 1;  // A, and A2 and Vt for plane rotations
+  const size_t bytes = align_up(nfreq * nn * 16) + nsq * align_up(nn * 16) +
+                       2 * align_up(nub * 16) + align_up(nfreq * nub * 16) +
+                       2 * align_up(nfreq * bb * 16) + align_up(kNormPartBytes) +
+                       align_up((size_t)neps * 4) + align_up((size_t)nb * 8) + 4096;
   // its own buffers: the small inverse below uses the context workspace
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, bytes);
@@ -942,9 +885,9 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
   gw_status st = check_v_positive(c, vcoul, neps);
   if (st != GW_OK) return st;
   const size_t nn = (size_t)neps * neps, nub = (size_t)neps * nb;
-  const int m = neps + (neps & 1);
-  const size_t bytes = 3 * align_up(nn * 16) + align_up(nub * 16) + align_up((size_t)(m / 2) * 48) +
-                       align_up(2 * 1024 * 8) + 2 * align_up((size_t)neps * 4) + 4096;
+  const bool small = neps < kBlockJacobiMin;
+  const size_t bytes = (small ? 3 : 1) * align_up(nn * 16) + align_up(nub * 16) +
+                       align_up(kNormPartBytes) + align_up((size_t)neps * 4) + 4096;
   char* base = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess)
     return fail(c, GW_ENOMEM, "basis buffers of %zu bytes", bytes);
@@ -955,13 +898,11 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
     return p;
   };
   auto* A = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* A2 = reinterpret_cast<cpx<double>*>(take(nn * 16));
-  auto* Vt = reinterpret_cast<cpx<double>*>(take(nn * 16));
+  auto* A2 = small ? reinterpret_cast<cpx<double>*>(take(nn * 16)) : nullptr;
+  auto* Vt = small ? reinterpret_cast<cpx<double>*>(take(nn * 16)) : nullptr;
   auto* Uh = reinterpret_cast<cpx<double>*>(take(nub * 16));
-  auto* rot = reinterpret_cast<JacRot*>(take((size_t)(m / 2) * sizeof(JacRot)));
-  auto* part = reinterpret_cast<double*>(take(2 * 1024 * 8));
+  auto* part = reinterpret_cast<double*>(take(kNormPartBytes));
   auto* rank = reinterpret_cast<int*>(take((size_t)neps * 4));
-  auto* pairof = reinterpret_cast<int*>(take((size_t)neps * 4));
   {
     ProfScope ps(c, "lowrank_prep");
     hipLaunchKernelGGL(k_lr_epst, dim3((unsigned)((nn + 255) / 256), 1), dim3(256), 0, c->stream,
@@ -969,7 +910,7 @@ extern "C" gw_status gw_lowrank_basis(gw_ctx* c, int neps, const double* chi0_st
     st = hipGetLastError() == hipSuccess ? GW_OK : GW_EDEVICE;
   }
   if (st == GW_OK)
-    st = jacobi_basis(c, neps, nb, A, A2, Vt, rot, pairof, part, rank,
+    st = jacobi_basis(c, neps, nb, A, A2, Vt, part, rank,
                       reinterpret_cast<cpx<double>*>(basis), Uh, eigenvalues);
   const hipError_t e2 = hipStreamSynchronize(c->stream);
   (void)hipFree(base);

@@ -108,7 +108,7 @@ def test_sigma_gpp_full_size_sampled_states(P, ctx, c2):
 
 
 def test_lowrank_full_size(P, ctx, c2):
-    """N_eps = 1000 (one Jacobi kernel per round), 100 eigenvectors, 3 frequencies:
+    """N_eps = 1000 (block Jacobi), 100 eigenvectors, 3 frequencies:
     V^1/2 chi0(w) V^1/2 = -Q diag(l_i / (1 + a_i w)) Q^H with a random unitary Q, 100
     modes l in [1, 5] and 900 in [0, 0.1] (a clear gap, so the basis is unique),
     the same input on both sides."""

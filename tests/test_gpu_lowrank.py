@@ -48,8 +48,9 @@ def _run(P, ctx, chi, v, nb, lam=False):
 @pytest.mark.parametrize("n,nf,rank,nb", [(40, 3, 10, 10), (37, 2, 37, 37), (130, 4, 25, 25),
                                           (64, 1, 64, 64), (1, 1, 1, 1), (1201, 1, 30, 30)])
 def test_lowrank_matches_oracle(P, ctx, n, nf, rank, nb):
-    """Up to N ~ 1090 each Jacobi round is one kernel; N = 1201 (odd) takes the
-    two-kernel rounds."""
+    """N < 128 takes plane-rotation Jacobi (one kernel per round); N >= 128 block
+    Jacobi on 32 x 32 sub-problems, with N = 130 and the odd N = 1201 padded to
+    a multiple of 32."""
     chi, v = _chi(n + rank, n, nf, rank)
     got, lam = _run(P, ctx, chi, v, nb, lam=True)
     want, wlam = oracle.epsinv_lowrank(chi, v, nb)
@@ -117,3 +118,52 @@ def test_projected_route_matches_oracle(P, ctx, case):
         ex = oracle.epsilon_inverse(chi, v)
         for f in range(len(om)):
             assert oracle.rel_f(got[f], ex[f]) < 1e-10
+
+
+def _projector(u):
+    return u @ u.conj().T
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e160])
+def test_block_basis_wide_range(P, ctx, scale):
+    """Block Jacobi (N = 150) on chi0 scaled by up to 1e160: off-diagonal
+    entries beyond 1e150 take the rotation's overflow-free route and the
+    convergence test uses scaled sums of squares, so the eigenvalues and the
+    span of the leading eigenvectors match numpy's eigh at any scale."""
+    n, rank = 150, 12
+    chi, v = _chi(77, n, 1, rank)
+    chi = chi * scale
+    u = torch.empty((n, rank), dtype=torch.complex128, device="cuda:0")
+    ev = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    P.gw_lowrank_basis(ctx, n, _dev(chi[0]), _dev(v), rank, u, ev)
+    torch.cuda.synchronize()
+    sv = np.sqrt(v)
+    epst = np.eye(n) - sv[:, None] * chi[0] * sv[None, :]
+    wlam, wvec = np.linalg.eigh(epst)
+    lam = ev.cpu().numpy()
+    assert np.all(np.isfinite(lam))
+    assert np.abs(lam - wlam).max() < 1e-12 * np.abs(wlam).max()
+    got = u.cpu().numpy()
+    assert np.abs(got.conj().T @ got - np.eye(rank)).max() < 1e-12
+    assert np.linalg.norm(_projector(got) - _projector(wvec[:, n - rank:])) < 1e-10
+
+
+def test_block_basis_diagonal(P, ctx):
+    """A diagonal chi0 (N = 140): every off-diagonal entry is zero, so every
+    rotation is skipped and the basis is the unit vectors of the largest
+    eigenvalues, each up to a phase."""
+    n, nb = 140, 9
+    rng = np.random.default_rng(3)
+    d = -rng.uniform(0.1, 4.0, n)
+    v = rng.uniform(0.2, 3.0, n)
+    chi = np.diag(d).astype(np.complex128)
+    u = torch.empty((n, nb), dtype=torch.complex128, device="cuda:0")
+    ev = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    P.gw_lowrank_basis(ctx, n, _dev(chi), _dev(v), nb, u, ev)
+    torch.cuda.synchronize()
+    lam0 = 1.0 - v * d
+    assert np.abs(ev.cpu().numpy() - np.sort(lam0)).max() < 1e-14 * np.abs(lam0).max()
+    top = np.argsort(-lam0, kind="stable")[:nb]
+    want = np.zeros((n, nb))
+    want[top, np.arange(nb)] = 1.0
+    assert np.abs(np.abs(u.cpu().numpy()) - want).max() < 1e-14
