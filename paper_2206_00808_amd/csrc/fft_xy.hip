@@ -71,6 +71,55 @@ __device__ __forceinline__ cpx<T> kept_out(const cpx<T>* line, int es, int f,
   return x;
 }
 
+// kept_out split into the per-lane part that does not change from pencil to
+// pencil (the first-factor column and the roots) and the sum itself. For A a
+// multiple of 3 the sum runs as three interleaved Horner chains in w^3 over
+// t = r (mod 3), joined by two steps in w:
+//   X = sum_r w^r sum_b (w^3)^b line[(r + 3 b) es],
+// the same number of complex multiply-adds as one chain but a third of its
+// dependent length, so the LDS reads of one chain overlap the others' FMAs.
+template <typename T>
+struct KeptPlan {
+  cpx<T> w, w3;
+  int off;  // k2 A: first entry of the column in the line, in entries
+};
+template <typename T, int A, int B>
+__device__ __forceinline__ KeptPlan<T> kept_plan(int f, const cpx<T>* twN) {
+  constexpr int N = A * B;
+  const int k = f < 0 ? f + N : f;
+  const int k1 = k / B;
+  KeptPlan<T> pl;
+  pl.off = (k % B) * A;
+  pl.w = twN[(B * k1) % N];
+  pl.w3 = twN[(3 * B * k1) % N];
+  return pl;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> horner_step(cpx<T> x, cpx<T> w, cpx<T> q) {
+  return mk(fma(x.x, w.x, fma(-x.y, w.y, q.x)), fma(x.x, w.y, fma(x.y, w.x, q.y)));
+}
+template <typename T, int A>
+__device__ __forceinline__ cpx<T> kept_eval(const cpx<T>* line, int es, const KeptPlan<T>& pl) {
+  const cpx<T>* p = line + pl.off * es;
+  if constexpr (A % 3 == 0 && A > 3) {
+    constexpr int L = A / 3;
+    cpx<T> x0 = p[(3 * (L - 1)) * es], x1 = p[(3 * (L - 1) + 1) * es],
+           x2 = p[(3 * (L - 1) + 2) * es];
+#pragma unroll
+    for (int b = L - 2; b >= 0; --b) {
+      x0 = horner_step(x0, pl.w3, p[(3 * b) * es]);
+      x1 = horner_step(x1, pl.w3, p[(3 * b + 1) * es]);
+      x2 = horner_step(x2, pl.w3, p[(3 * b + 2) * es]);
+    }
+    return horner_step(horner_step(x2, pl.w, x1), pl.w, x0);
+  } else {
+    cpx<T> x = p[(A - 1) * es];
+#pragma unroll
+    for (int t = A - 2; t >= 0; --t) x = horner_step(x, pl.w, p[t * es]);
+    return x;
+  }
+}
+
 // sum_s conj(v_s) c_s over NS spinor components, as fused multiply-adds
 template <typename T, int NS>
 __device__ __forceinline__ cpx<T> spin_dot(const cpx<T> (&v)[NS], const cpx<T> (&c)[NS]) {
@@ -211,7 +260,9 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
   cpx<T>* tw2 = tw1 + N1;
   cpx<T>* Xr0 = tw2 + N2;              // N2 exchange rows of pitch XP
   cpx<T>* R = Xr0 + N2 * S::XP;        // build: Q, Yw; valence loop: Xk
+  static_assert(XyTile<T>::CT <= 2, "the y pass splits columns over at most two planes");
   const int ekx = 2 * gx + 1, eky = 2 * gy + 1, XKP = ekx | 1;
+  const unsigned ekx_magic = ekx > 1 ? 0xffffffffu / (unsigned)ekx + 1u : 0u;
   const int ncg = (nct + CT - 1) / CT;
   const long long lin = xcd_linear(blockIdx.x, (long long)n3 * ncg);
   if (lin < 0) return;
@@ -277,6 +328,10 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
   const cpx<T>* pv0 = uvz + (size_t)z * NP + (size_t)(act ? y : 0) * N1 + (act ? t : 0);
   // one row-slice buffer: each band's slice is consumed by the products before
   // the next band's loads are issued into the same registers
+  // the lane's first kept x and y frequencies (more only when an eps sphere is
+  // wider than a lane group: 2 g + 1 > 16)
+  const KeptPlan<T> xplan = kept_plan<T, S::A1, S::B1>(t - gx, tw1);
+  const int tt = tid % S::L2;
   cpx<T> vn[S::B1][NS];
   auto fetch = [&](int vl) {
     const cpx<T>* pv = pv0 + (size_t)(v0 + vl) * NS * vstride;
@@ -297,9 +352,22 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
 #pragma unroll
           for (int m = 0; m < S::B1; ++m) pa[ct][m] = spin_dot<T, NS>(vn[m], cr[ct][m]);
         // the last band fetches itself again (unconditional loads keep the
-        // buffer in one set of registers)
+        // buffer in one set of registers). The empty asm statements pin the
+        // products ahead of the loads: the loads then reuse the registers the
+        // products just consumed, instead of a second set that is copied back
+        // (and waited for) at the end of every iteration
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int m = 0; m < S::B1; ++m) asm volatile("" ::"v"(pa[ct][m].x), "v"(pa[ct][m].y));
+        asm volatile("" ::: "memory");
         fetch(min(g0 + j + 1, nvt - 1));
-        // x transforms, kept outputs to Xk
+        // x transforms, kept outputs to Xk. The lane index is made opaque
+        // here so that the twiddle addresses t k2 are recomputed (one integer
+        // multiply each) rather than held across the loop, where they would be
+        // spilled and their reloads would wait on the prefetch just issued
+        int tq = t;
+        asm volatile("" : "+v"(tq));
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
           if (ct < nvalid) {
@@ -307,13 +375,14 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
             reg_dft<T, S::B1>(a);
             // tw[0] = 1 exactly, so lane 0 multiplies by one without rounding
 #pragma unroll
-            for (int k2 = 1; k2 < S::B1; ++k2) a[k2] = cmul(a[k2], tw1[t * k2]);
+            for (int k2 = 1; k2 < S::B1; ++k2) a[k2] = cmul(a[k2], tw1[tq * k2]);
 #pragma unroll
             for (int k2 = 0; k2 < S::B1; ++k2) Xr[k2 * S::A1 + t] = a[k2];
             // the row's lanes share a wavefront, whose LDS accesses complete in order
             __builtin_amdgcn_wave_barrier();
             cpx<T>* xk = Xk + ((size_t)(j * CT + ct) * N2 + y) * XKP;
-            for (int jk = t; jk < ekx; jk += S::L1)
+            if (t < ekx) xk[t] = kept_eval<T, S::A1>(Xr, 1, xplan);
+            for (int jk = t + S::L1; jk < ekx; jk += S::L1)
               xk[jk] = kept_out<T, S::A1, S::B1>(Xr, 1, jk - gx, tw1);
             // the next product's exchange writes follow these reads in order
             __builtin_amdgcn_wave_barrier();
@@ -325,13 +394,16 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
     // y transforms of the kept columns (j, ct, jkx): A2 lanes of B2 values per
     // column, the first factor in registers (written back in place, twiddled),
     // the second at the kept y frequencies only
-    const int pp = tid / S::L2, tt = tid % S::L2;
+    const int pp = tid / S::L2;
+    const KeptPlan<T> yplan = kept_plan<T, S::A2, S::B2>(tt - gy, tw2);
     const int tot = nb * nvalid * ekx;
     for (int q0 = 0; q0 < tot; q0 += S::NTH / S::L2) {
       const int q = q0 + pp;
       if (q < tot) {
-        const int jc = q / ekx, jk = q - jc * ekx;
-        const int j = jc / nvalid, ct = jc - j * nvalid;
+        // q / ekx by multiply-high (exact for q ekx < 2^32; the magic number
+        // of ekx = 1 would be 2^32)
+        const int jc = ekx == 1 ? q : (int)__umulhi((unsigned)q, ekx_magic), jk = q - jc * ekx;
+        const int j = nvalid == 1 ? jc : jc >> 1, ct = jc - j * nvalid;
         cpx<T>* col = Xk + (size_t)(j * CT + ct) * N2 * XKP + jk;
         if (tt < S::A2) {
           cpx<T> a[S::B2];
@@ -346,7 +418,8 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
         __builtin_amdgcn_wave_barrier();
         const size_t pl = (size_t)(cg * CT + ct) * nvt + g0 + j;
         cpx<T>* dst = tout + (pl * n3 + z) * (size_t)(ekx * eky) + jk;
-        for (int jky = tt; jky < eky; jky += S::L2)
+        if (tt < eky) dst[(size_t)tt * ekx] = kept_eval<T, S::A2>(col, XKP, yplan);
+        for (int jky = tt + S::L2; jky < eky; jky += S::L2)
           dst[(size_t)jky * ekx] = kept_out<T, S::A2, S::B2>(col, XKP, jky - gy, tw2);
       }
     }
