@@ -486,13 +486,16 @@ __device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 2, wc = wave & 3;  // rows wr*64 .. +63, columns wc*32 .. +31
   const int l16 = lane & 15, lk = lane >> 4;
-  f4 cr[4][2], ci[4][2];
+  // imaginary part = cp - cn: the conjugated operand's minus sign is taken
+  // at the end instead of negating fragments in the loop
+  f4 cr[4][2], cp[4][2], cn[4][2];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       cr[x][y] = (f4){0, 0, 0, 0};
-      ci[x][y] = (f4){0, 0, 0, 0};
+      cp[x][y] = (f4){0, 0, 0, 0};
+      cn[x][y] = (f4){0, 0, 0, 0};
     }
   const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lrow >> 2) & 3);
   // the wavefront's 8 of the slab's 64 row blocks (operand, plane, 16-row block)
@@ -523,31 +526,25 @@ __device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restri
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         a[q] = *reinterpret_cast<const bf8*>(&A[q][wr * 64 + x * 16 + l16][pch]);
-      bf8 na[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-        us8 t = __builtin_bit_cast(us8, a[2 + q]);
-        t ^= (us8)(0x8000);
-        na[q] = __builtin_bit_cast(bf8, t);
-      }
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-#define GW_MF(ACC, A_, B_) ACC[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_, B_, ACC[x][y], 0, 0, 0);
-        GW_MF(cr, a[0], b[y][0])
-        GW_MF(ci, a[0], b[y][2])
-        GW_MF(cr, a[0], b[y][1])
-        GW_MF(ci, a[0], b[y][3])
-        GW_MF(cr, a[1], b[y][0])
-        GW_MF(ci, a[1], b[y][2])
-        GW_MF(cr, a[2], b[y][2])
-        GW_MF(ci, na[0], b[y][0])
-        GW_MF(cr, a[2], b[y][3])
-        GW_MF(ci, na[0], b[y][1])
-        GW_MF(cr, a[3], b[y][2])
-        GW_MF(ci, na[1], b[y][0])
+      // the two column blocks interleaved, and the six real-part products
+      // spread between the others, so that no accumulator is updated by
+      // consecutive instructions
+#define GW_MF(ACC, A_, Q)                                                                         \
+  ACC[x][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_, b[0][Q], ACC[x][0], 0, 0, 0);           \
+  ACC[x][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_, b[1][Q], ACC[x][1], 0, 0, 0);
+      GW_MF(cr, a[0], 0)
+      GW_MF(cp, a[0], 2)
+      GW_MF(cr, a[0], 1)
+      GW_MF(cn, a[2], 0)
+      GW_MF(cr, a[1], 0)
+      GW_MF(cp, a[0], 3)
+      GW_MF(cr, a[2], 2)
+      GW_MF(cn, a[2], 1)
+      GW_MF(cr, a[2], 3)
+      GW_MF(cp, a[1], 2)
+      GW_MF(cr, a[3], 2)
+      GW_MF(cn, a[3], 0)
 #undef GW_MF
-      }
     }
   };
   const int pend = pb0 + npb;
@@ -573,7 +570,7 @@ __device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restri
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // f32 16x16x32 D layout: row 4*lk + r, column l16
         const int i = i0 + wr * 64 + x * 16 + lk * 4 + r, j = j0 + wc * 32 + y * 16 + l16;
-        double im = ci[x][y][r];
+        double im = (double)cp[x][y][r] - (double)cn[x][y][r];
         bool od;
         if (!herm_keep(ti == tj, i, j, &im, &od)) continue;
         if (overwrite) herm_store(C, neps, i, j, (double)cr[x][y][r], im, od, skip_head);
