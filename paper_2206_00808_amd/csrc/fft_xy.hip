@@ -42,7 +42,10 @@ template <typename T, int N1, int N2>
 struct XyShape {
   static constexpr int A1 = xy_split(N1), B1 = N1 / A1, L1 = pow2_at_least(A1);
   static constexpr int NTH = ((N2 * L1 + 63) / 64) * 64;  // one lane group per row y
-  static constexpr int XP = N1 + 1;                        // exchange row pitch
+  // exchange row pitch: in double, rows 4 (mod 16) entries apart put the 16
+  // (row, column) chunks that a wavefront's Horner reads touch at once on
+  // distinct LDS banks (columns are A1 entries apart)
+  static constexpr int XP = sizeof(T) == 8 ? ((N1 + 1 + 11) / 16) * 16 + 4 : N1 + 1;
   static constexpr int A2 = xy_split(N2), B2 = N2 / A2, L2 = pow2_at_least(A2);
   static_assert(64 % L1 == 0 && 64 % L2 == 0, "a pencil must sit in one wavefront");
   static_assert(NTH <= 1024, "block too large");
