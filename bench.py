@@ -206,6 +206,26 @@ def roofline_of(kernel, launches, ms, d, config, path):
     return r
 
 
+EPSINV_STAGES = ("eps_build", "flags_clear", "gj_diag", "gj_small", "gj_update", "gj_step",
+                 "eps_unscale")
+
+
+def epsinv_roofline(stage, d):
+    """eps^-1 by Gauss-Jordan: 8 N^3 flops per frequency (N^3 complex multiply-adds
+    of the in-place inverse) over the summed time of the eps build, the
+    diagonal-block inverses, the rank updates and the unscaling, against the FP64
+    matrix-core peak that the rank updates run on."""
+    ms = sum(stage[k][1] for k in EPSINV_STAGES if k in stage)
+    if ms <= 0:
+        return None
+    n, nf = d["neps"], len(d["omega"])
+    flops = 8.0 * n ** 3 * nf
+    return {"kernel": "epsinv (Gauss-Jordan, all stages)", "ms_per_step": ms, "bound": "mfma",
+            "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "note": "8 N^3 n_omega flops over the summed stage times"}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -809,6 +829,7 @@ def main():
     for k in ("chi0_fp64", "pair_plane", "pair_xpass"):
         if k in st64 and k != rk64:
             others[k] = roofline_of(k, st64[k][0], st64[k][1], d64, args.config, "fp64")
+    others["epsinv"] = epsinv_roofline(st64, d64)
     result["other_rooflines"] = others
     fft_keys = ("band_xpass", "band_plane", "band_zc", "band_zyx", "pair_plane", "pair_xpass")
     fft_ms = sum(st64.get(k, (0, 0))[1] for k in fft_keys)
@@ -867,6 +888,7 @@ def main():
             "pairs_per_s": pairs / (ms32 * 1e-3), "ms_per_step": ms32,
             "chi0_tflops": flops / (chi_ms32 * 1e-3) / 1e12,
             "chi0_roofline": bf,
+            "epsinv_roofline": epsinv_roofline(st32, d32),
             "roofline": roofline_of(rk32, rl32, rms32, d32, args.config, "mixed"),
             "epsinv_rel_err_vs_fp64": e_inv, "epsinv_max_err_vs_fp64": e_inv_max,
             "chi0_rel_err_vs_fp64": e_chi, "chi0_max_err_vs_fp64": e_chi_max,

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libgwspinor.so")
-SOURCES = ["api.hip", "fft.hip", "fft_xy.hip", "gemm.hip", "head.hip", "lu.hip", "closure.hip", "plan.hip", "symm.hip", "gpp.hip", "bse.hip", "lowrank.hip", "probe.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "fft.hip", "fft_xy.hip", "gemm.hip", "head.hip", "lu.hip", "closure.hip", "plan.hip", "symm.hip", "gpp.hip", "bse.hip", "lowrank.hip", "probe.hip", "noalloc.hip",
+           "symm_host.cpp"]
 ARCH = os.environ.get("GW_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -18,6 +19,9 @@ FLAGS = [
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+
+
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 
 def _hipcc():
@@ -36,9 +40,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if src.endswith(".cpp"):  # host-only C++ (no device code)
+            cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o",
+                   obj]
+        else:
+            cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
