@@ -292,14 +292,21 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
       }
       lds_sync();  // Q in place (and the twiddles, the first time)
       if (cl < nct) {
-        for (int o = tid; o < N2 * exw; o += S::NTH) {
-          const int yy = o / exw, jx = o - yy * exw;
-          cpx<T> acc = mk<T>(0, 0);
-          for (int jy = 0; jy < eyw; ++jy) {
-            const cpx<T> w = tw2[mod_pos((jy - gyw) * yy, N2)];
-            acc = acc + cmul(Q[jy * exw + jx], w);
+        // y transform of the slab's columns, split as n2 = A2 B2 like the
+        // pencils: for output y = t + A2 m, b_r = sum_{g_y = r mod B2} Q(g_y)
+        // W_n2^(g_y t) and one B2-point DFT gives the B2 outputs of item (jx, t)
+        for (int o = tid; o < exw * S::A2; o += S::NTH) {
+          const int jx = o / S::A2, t2 = o - jx * S::A2;
+          cpx<T> b[S::B2];
+#pragma unroll
+          for (int r = 0; r < S::B2; ++r) {
+            b[r] = mk<T>(0, 0);
+            for (int g = -gyw + mod_pos(r + gyw, S::B2); g <= gyw; g += S::B2)
+              b[r] = b[r] + cmul(Q[(g + gyw) * exw + jx], tw2[mod_pos(g * t2, N2)]);
           }
-          Yw[yy * YP + jx] = acc;
+          reg_dft<T, S::B2>(b);
+#pragma unroll
+          for (int m = 0; m < S::B2; ++m) Yw[(t2 + S::A2 * m) * YP + jx] = b[m];
         }
       }
       lds_sync();  // Yw complete
