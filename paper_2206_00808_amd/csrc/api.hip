@@ -142,6 +142,23 @@ gw_status sphere_map(gw_ctx* c, const int32_t* g, int n, const int box[3], Spher
   }
   GW_HIP(c, hipMalloc(&sm.d_cube, ncube * sizeof(int)));
   GW_HIP(c, hipMemcpy(sm.d_cube, cube.data(), ncube * sizeof(int), hipMemcpyHostToDevice));
+  // columns (jx, jy) with at least one sphere point, y-major
+  const int nxy = sm.ext[0] * sm.ext[1];
+  std::vector<int> disk(nxy, -1), cols;
+  for (int jy = 0; jy < sm.ext[1]; ++jy)
+    for (int jx = 0; jx < sm.ext[0]; ++jx) {
+      bool any = false;
+      for (int jz = 0; jz < sm.ext[2] && !any; ++jz)
+        any = cube[((size_t)jx * sm.ext[1] + jy) * sm.ext[2] + jz] >= 0;
+      if (any) {
+        disk[jy * sm.ext[0] + jx] = (int)cols.size();
+        cols.push_back(jy * sm.ext[0] + jx);
+      }
+    }
+  sm.ndisk = (int)cols.size();
+  disk.insert(disk.end(), cols.begin(), cols.end());
+  GW_HIP(c, hipMalloc(&sm.d_disk, disk.size() * sizeof(int)));
+  GW_HIP(c, hipMemcpy(sm.d_disk, disk.data(), disk.size() * sizeof(int), hipMemcpyHostToDevice));
   auto res = c->spheres.emplace(key, sm);
   *out = &res.first->second;
   return GW_OK;
@@ -325,7 +342,10 @@ gw_status gw_ctx_destroy(gw_ctx* c) {
   for (gw_plan* p : std::vector<gw_plan*>(c->plans.begin(), c->plans.end())) plan_free(p);
   for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
-  for (auto& kv : c->spheres) (void)hipFree(kv.second.d_cube);
+  for (auto& kv : c->spheres) {
+    (void)hipFree(kv.second.d_cube);
+    (void)hipFree(kv.second.d_disk);
+  }
   for (auto& kv : c->twiddles) (void)hipFree(kv.second);
   for (auto& kv : c->tile_orders) (void)hipFree(kv.second);
   if (c->ws) (void)hipFree(c->ws);

@@ -66,6 +66,11 @@ struct SphereMap {
   int ext[3];            // 2*gmax+1
   int* d_cube = nullptr; // device int32[ext0*ext1*ext2]
   int n = 0;             // sphere size
+  // the (x, y) columns of the compact cube that hold a sphere point: d_disk
+  // [ext1*ext0] maps jy*ext0 + jx to the column's index (or -1), followed by
+  // [ndisk] entries giving each column's jy*ext0 + jx (device, one allocation)
+  int ndisk = 0;
+  int* d_disk = nullptr;
 };
 
 struct ProfRec {

@@ -15,7 +15,8 @@
 //     L2 (3.2 MB in float, 6.4 MB in double for 56 bands);
 //   - the spin-summed product, the x transform (keeping |g_x| <= g_eps,x) and
 //     the y transform (keeping |g_y| <= g_eps,y) leave (2 g_x + 1)(2 g_y + 1)
-//     values per pair and z, written to T[pair][z][jy][jx];
+//     values per pair and z, of which those in the (x, y) columns that hold
+//     eps-sphere points are written to T[pair][z][column];
 //   - k_pair_zp transforms T along z, keeps |g_z| <= g_eps,z, scales by 1/N
 //     and scatters onto the eps sphere.
 // The yz-plane of such a box (9,600 points) would not fit on chip beside a
@@ -254,7 +255,8 @@ template <typename T, int NS, int N1, int N2>
 __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
     const cpx<T>* __restrict__ uvz, const cpx<T>* __restrict__ tcz, int exw, int eyw, int gxw,
     int gyw, int v0, int nvt, int c0, int nct, int n3, int gx, int gy,
-    const cpx<T>* __restrict__ twx, const cpx<T>* __restrict__ twy, cpx<T>* __restrict__ tout) {
+    const cpx<T>* __restrict__ twx, const cpx<T>* __restrict__ twy,
+    const int* __restrict__ disk, int ndisk, cpx<T>* __restrict__ tout) {
   using S = XyShape<T, N1, N2>;
   constexpr int CT = XyTile<T>::CT, VB = XyTile<T>::VB;
   constexpr int NP = N1 * N2;
@@ -426,11 +428,19 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
           for (int k2 = 0; k2 < S::B2; ++k2) col[(k2 * S::A2 + tt) * XKP] = a[k2];
         }
         __builtin_amdgcn_wave_barrier();
+        // only the (x, y) columns that hold eps-sphere points are kept
         const size_t pl = (size_t)(cg * CT + ct) * nvt + g0 + j;
-        cpx<T>* dst = tout + (pl * n3 + z) * (size_t)(ekx * eky) + jk;
-        if (tt < eky) dst[(size_t)tt * ekx] = kept_eval<T, S::A2>(col, XKP, yplan);
-        for (int jky = tt + S::L2; jky < eky; jky += S::L2)
-          dst[(size_t)jky * ekx] = kept_out<T, S::A2, S::B2>(col, XKP, jky - gy, tw2);
+        cpx<T>* dst = tout + (pl * n3 + z) * (size_t)ndisk;
+        if (tt < eky) {
+          const cpx<T> val = kept_eval<T, S::A2>(col, XKP, yplan);
+          const int d = disk[tt * ekx + jk];
+          if (d >= 0) dst[d] = val;
+        }
+        for (int jky = tt + S::L2; jky < eky; jky += S::L2) {
+          const cpx<T> val = kept_out<T, S::A2, S::B2>(col, XKP, jky - gy, tw2);
+          const int d = disk[jky * ekx + jk];
+          if (d >= 0) dst[d] = val;
+        }
       }
     }
     lds_sync();  // Xk consumed before the next group writes it
@@ -438,21 +448,23 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
 }
 
 // ---------------------------------------------------------------- z pass
-// For each pair and kept (jkx, jky) column of T, the z transform with A lanes
+// For each pair and (jkx, jky) column of T (those holding eps-sphere points,
+// listed after the column map in disk), the z transform with A lanes
 // of B values, keeping |g_z| <= gz, scaled by 1/N and scattered onto the eps
 // sphere through its compact cube map emap[jx][jy][jz].
 template <typename T, int N3>
 __global__ void __launch_bounds__(kZThreads) k_pair_zp(
     const cpx<T>* __restrict__ tin, int ekx, int eky, int ekz, int gz,
-    const int* __restrict__ emap, const cpx<T>* __restrict__ twz, T invN, int v0, int nvt,
-    int c0, int nc_total, int neps, cpx<T>* __restrict__ M) {
+    const int* __restrict__ emap, const int* __restrict__ disk, int ndisk,
+    const cpx<T>* __restrict__ twz, T invN, int v0, int nvt, int c0, int nc_total, int neps,
+    cpx<T>* __restrict__ M) {
   constexpr int A = split_n1(N3), B = N3 / A, L = pow2_at_least(A), CPB = kZThreads / L;
   __shared__ cpx<T> X[CPB][N3 + 1];
   __shared__ cpx<T> tw[N3];
   const int pr = blockIdx.y, tid = threadIdx.x;
   for (int i = tid; i < N3; i += kZThreads) tw[i] = twz[i];
   __syncthreads();
-  const int ncol = ekx * eky;
+  const int ncol = ndisk;
   const int cq = tid / L, t = tid % L;
   const int col = blockIdx.x * CPB + cq;
   if (col >= ncol || t >= A) return;
@@ -469,7 +481,8 @@ __global__ void __launch_bounds__(kZThreads) k_pair_zp(
   __builtin_amdgcn_wave_barrier();
   const int v = v0 + pr % nvt, c = c0 + pr / nvt;
   cpx<T>* dst = M + ((size_t)v * nc_total + c) * neps;
-  const int jky = col / ekx, jkx = col - jky * ekx;
+  const int cxy = disk[ekx * eky + col];  // jky * ekx + jkx of this column
+  const int jky = cxy / ekx, jkx = cxy - jky * ekx;
   const int* em = emap + ((size_t)jkx * eky + jky) * ekz;
 #pragma unroll
   for (int s = 0; s < (B + A - 1) / A; ++s) {
@@ -512,7 +525,7 @@ size_t band_zc_bytes(const int box[3], const SphereMap* sm, int nbs, size_t elem
 }
 
 size_t pair_xy_scratch_bytes(const int box[3], const SphereMap* em, int npairs, size_t elem) {
-  return (size_t)npairs * box[2] * em->ext[0] * em->ext[1] * elem;
+  return (size_t)npairs * box[2] * em->ndisk * elem;
 }
 
 template <typename K>
@@ -603,14 +616,14 @@ gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* u
                          static_cast<const cpx<T>*>(uvz), static_cast<const cpx<T>*>(tcz),       \
                          sc->ext[0], sc->ext[1], sc->gmax[0], sc->gmax[1], v0, nvt, c0, nct, n3, \
                          gx, gy, static_cast<const cpx<T>*>(twx),                               \
-                         static_cast<const cpx<T>*>(twy), tbuf);                                 \
+                         static_cast<const cpx<T>*>(twy), em->d_disk, em->ndisk, tbuf);          \
     } else {                                                                                    \
       if (!c->capturing) GW_HIP(c, allow_lds_xy(k_pair_xy<T, 1, A, B>, lds));                   \
       hipLaunchKernelGGL((k_pair_xy<T, 1, A, B>), dim3(grid), dim3(S::NTH), lds, c->stream,     \
                          static_cast<const cpx<T>*>(uvz), static_cast<const cpx<T>*>(tcz),       \
                          sc->ext[0], sc->ext[1], sc->gmax[0], sc->gmax[1], v0, nvt, c0, nct, n3, \
                          gx, gy, static_cast<const cpx<T>*>(twx),                               \
-                         static_cast<const cpx<T>*>(twy), tbuf);                                 \
+                         static_cast<const cpx<T>*>(twy), em->d_disk, em->ndisk, tbuf);          \
     }                                                                                           \
   }
     GW_XY_SHAPES(X)
@@ -627,10 +640,10 @@ gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* u
   if (!done && n3 == N) {                                                                      \
     done = true;                                                                               \
     constexpr int CPB = kZThreads / pow2_at_least(split_n1(N));                                \
-    hipLaunchKernelGGL((k_pair_zp<T, N>), dim3((ekx * eky + CPB - 1) / CPB, npairs),           \
+    hipLaunchKernelGGL((k_pair_zp<T, N>), dim3((em->ndisk + CPB - 1) / CPB, npairs),           \
                        dim3(kZThreads), 0, c->stream, tbuf, ekx, eky, em->ext[2], em->gmax[2], \
-                       em->d_cube, static_cast<const cpx<T>*>(twz), invN, v0, nvt, c0,         \
-                       nc_total, em->n, static_cast<cpx<T>*>(mtxel));                          \
+                       em->d_cube, em->d_disk, em->ndisk, static_cast<const cpx<T>*>(twz),     \
+                       invN, v0, nvt, c0, nc_total, em->n, static_cast<cpx<T>*>(mtxel));       \
   }
     GW_XY_ZLEN(X)
 #undef X
