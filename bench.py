@@ -89,9 +89,10 @@ def pair_work(d):
     e = 2 * g + 1
     f = lambda n: 5.0 * n * np.log2(n)  # noqa: E731
     prod = (8 * ns - 2) * nbox
-    if (n1, n2) in XY_PLANES:    # x on every row, y on kept x, z last on kept (x, y)
-        plane = prod + f(n1) * n2 * n3 + f(n2) * e[0] * n3
-        last = f(n3) * e[0] * e[1]
+    if (n1, n2) in XY_PLANES:    # x on every row, y on kept x, z last on the (x, y)
+        plane = prod + f(n1) * n2 * n3 + f(n2) * e[0] * n3   # columns holding sphere points
+        cols = {(int(a), int(b)) for a, b in np.asarray(d["geps"])[:, :2]}
+        last = f(n3) * len(cols)
     else:                        # z on every row, y on kept z, x last on kept (y, z)
         plane = prod + f(n3) * n1 * n2 + f(n2) * e[2] * n1
         last = f(n1) * e[1] * e[2]

@@ -127,44 +127,47 @@ __global__ void __launch_bounds__(64 * WM * WM, sizeof(Tin) == 8 ? 3 : 2) k_chi0
 // Split the contraction operands once: X_0 = M and X_{1+f} = w_f * M (the
 // product taken in float), each component x as hi = bf16_rn(x) and
 // lo = bf16_rn(x - hi). Output layout X_o[pb][q][G][32] (see chi0_bf16s_tile),
-// zero past P. A block takes 32 pairs x 64 columns of one output through LDS,
-// so that both the reads of M and the writes are contiguous; each thread forms
-// 8 values of one column and writes all four planes of them.
+// zero past P. A block stages 32 pairs x 64 columns of M through LDS, so that
+// both the reads of M and the writes are contiguous, and forms every output
+// from that one tile (M is read from HBM once); each thread forms 8 values of
+// one column per output and writes all four planes of them.
 __global__ void __launch_bounds__(256) k_bf16_split(const cpx<float>* __restrict__ M, int P,
-                                                    int neps, const double* __restrict__ wts,
+                                                    int neps, int nout,
+                                                    const double* __restrict__ wts,
                                                     unsigned short* __restrict__ X) {
   __shared__ cpx<float> Ms[BK][64 + 1];
-  __shared__ float Wsh[BK];
   typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-  const int pb = blockIdx.x, Pb = gridDim.x, g0 = blockIdx.y * 64, o = blockIdx.z;
+  const int pb = blockIdx.x, Pb = gridDim.x, g0 = blockIdx.y * 64;
   const int tid = threadIdx.x;
   for (int e = tid; e < BK * 64; e += 256) {
     const int k = e / 64, g = e % 64, p = pb * BK + k;
     Ms[k][g] = (p < P && g0 + g < neps) ? M[(size_t)p * neps + g0 + g] : mk(0.f, 0.f);
   }
-  if (tid < BK) {
-    const int p = pb * BK + tid;
-    Wsh[tid] = (o == 0) ? 1.f : (p < P ? (float)wts[(size_t)(o - 1) * P + p] : 0.f);
-  }
   __syncthreads();
   const int row = tid / 4, kc = tid % 4, g = g0 + row;
   if (g >= neps) return;
-  us8 v[4];
+  cpx<float> m[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int k = kc * 8 + t;
-    const cpx<float> m = Ms[k][row];
-    const float xr = Wsh[k] * m.x, xi = Wsh[k] * m.y;
-    const unsigned short hr = bf16_rn_bits(xr), hi = bf16_rn_bits(xi);
-    v[0][t] = hr;
-    v[1][t] = bf16_rn_bits(xr - bf16_to_f(hr));
-    v[2][t] = hi;
-    v[3][t] = bf16_rn_bits(xi - bf16_to_f(hi));
+  for (int t = 0; t < 8; ++t) m[t] = Ms[kc * 8 + t][row];
+  // every output from the one staged tile: M is read once for all of them
+  for (int o = 0; o < nout; ++o) {
+    us8 v[4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int p = pb * BK + kc * 8 + t;
+      const float wk = (o == 0) ? 1.f : (p < P ? (float)wts[(size_t)(o - 1) * P + p] : 0.f);
+      const float xr = wk * m[t].x, xi = wk * m[t].y;
+      const unsigned short hr = bf16_rn_bits(xr), hi = bf16_rn_bits(xi);
+      v[0][t] = hr;
+      v[1][t] = bf16_rn_bits(xr - bf16_to_f(hr));
+      v[2][t] = hi;
+      v[3][t] = bf16_rn_bits(xi - bf16_to_f(hi));
+    }
+    unsigned short* Xo = X + (size_t)o * Pb * 4 * neps * BK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<us8*>(Xo + (((size_t)pb * 4 + q) * neps + g) * BK + kc * 8) = v[q];
   }
-  unsigned short* Xo = X + (size_t)o * Pb * 4 * neps * BK;
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    *reinterpret_cast<us8*>(Xo + (((size_t)pb * 4 + q) * neps + g) * BK + kc * 8) = v[q];
 }
 
 // Range s of the pair blocks of frequency f, from the pre-split operands.
@@ -364,8 +367,8 @@ gw_status split_bf16(gw_ctx* c, int P, int neps, const void* mtxel, int nfreq, c
   if (P <= 0 || neps <= 0) return GW_OK;
   const int Pb = (P + BK - 1) / BK;
   ProfScope ps(c, "bf16_split");
-  hipLaunchKernelGGL(k_bf16_split, dim3(Pb, (neps + 63) / 64, 1 + nfreq), dim3(256), 0,
-                     c->stream, static_cast<const cpx<float>*>(mtxel), P, neps, wts,
+  hipLaunchKernelGGL(k_bf16_split, dim3(Pb, (neps + 63) / 64), dim3(256), 0, c->stream,
+                     static_cast<const cpx<float>*>(mtxel), P, neps, 1 + nfreq, wts,
                      static_cast<unsigned short*>(xsplit));
   GW_CHECK_LAUNCH(c, "k_bf16_split");
   return GW_OK;
