@@ -1045,15 +1045,20 @@ template <typename T, int N1>
 __global__ void __launch_bounds__(kThreads) k_pair_x_rf(
     const cpx<T>* __restrict__ t2, int ncol, int ey, int ez, int gx,
     const int* __restrict__ emap, const cpx<T>* __restrict__ twx, T invN, int v0, int nvt,
-    int c0, int nct_total, int neps, cpx<T>* __restrict__ M) {
+    int c0, int nct_total, int neps, int npairs, cpx<T>* __restrict__ M) {
   using S = XpShape<T, N1>;
   __shared__ cpx<T> X[S::CPB][N1 + 1];
   __shared__ cpx<T> tw[N1];
-  const int pr = blockIdx.y, tid = threadIdx.x;
+  // all column blocks of a pair on one XCD: its scattered stores into the
+  // pair's row of M then fill whole lines in that XCD's L2 before write-back
+  const int nbx = (ncol + S::CPB - 1) / S::CPB;
+  const long long lin = xcd_linear(blockIdx.x, (long long)nbx * npairs);
+  if (lin < 0) return;
+  const int pr = (int)(lin / nbx), bx = (int)(lin - (long long)pr * nbx), tid = threadIdx.x;
   for (int i = tid; i < N1; i += kThreads) tw[i] = twx[i];
   __syncthreads();
   const int cq = tid / S::L, t = tid % S::L;
-  const int col = blockIdx.x * S::CPB + cq;
+  const int col = bx * S::CPB + cq;
   if (col >= ncol || t >= S::A) return;
   const cpx<T>* src = t2 + (size_t)pr * N1 * ncol + col;
   cpx<T> a[S::B];
@@ -1388,11 +1393,13 @@ gw_status pair_to_eps(gw_ctx* c, const int box[3], int nspinor, const void* uv, 
 #define X(N)                                                                                   \
   if (!done && n1 == N) {                                                                      \
     done = true;                                                                               \
-    dim3 g((ncol + XpShape<T, N>::CPB - 1) / XpShape<T, N>::CPB, npairs);                      \
-    hipLaunchKernelGGL((k_pair_x_rf<T, N>), g, dim3(kThreads), 0, c->stream, t2, ncol,         \
-                       em->ext[1], em->ext[2], em->gmax[0], em->d_cube,                        \
+    const long long tot =                                                                      \
+        (long long)((ncol + XpShape<T, N>::CPB - 1) / XpShape<T, N>::CPB) * npairs;            \
+    const unsigned grid = (unsigned)(((tot + kXcd - 1) / kXcd) * kXcd);                        \
+    hipLaunchKernelGGL((k_pair_x_rf<T, N>), dim3(grid), dim3(kThreads), 0, c->stream, t2,      \
+                       ncol, em->ext[1], em->ext[2], em->gmax[0], em->d_cube,                  \
                        static_cast<const cpx<T>*>(twx), invN, v0, nvt, c0, nc_total, em->n,    \
-                       static_cast<cpx<T>*>(mtxel));                                           \
+                       npairs, static_cast<cpx<T>*>(mtxel));                                   \
   }
     GW_X_LENGTHS(X)
 #undef X

@@ -457,16 +457,20 @@ __global__ void __launch_bounds__(kZThreads) k_pair_zp(
     const cpx<T>* __restrict__ tin, int ekx, int eky, int ekz, int gz,
     const int* __restrict__ emap, const int* __restrict__ disk, int ndisk,
     const cpx<T>* __restrict__ twz, T invN, int v0, int nvt, int c0, int nc_total, int neps,
-    cpx<T>* __restrict__ M) {
+    int npairs, cpx<T>* __restrict__ M) {
   constexpr int A = split_n1(N3), B = N3 / A, L = pow2_at_least(A), CPB = kZThreads / L;
   __shared__ cpx<T> X[CPB][N3 + 1];
   __shared__ cpx<T> tw[N3];
-  const int pr = blockIdx.y, tid = threadIdx.x;
+  // all column blocks of a pair on one XCD: its scattered stores into the
+  // pair's row of M then fill whole lines in that XCD's L2 before write-back
+  const int ncol = ndisk, nbx = (ncol + CPB - 1) / CPB;
+  const long long lin = xcd_linear(blockIdx.x, (long long)nbx * npairs);
+  if (lin < 0) return;
+  const int pr = (int)(lin / nbx), bx = (int)(lin - (long long)pr * nbx), tid = threadIdx.x;
   for (int i = tid; i < N3; i += kZThreads) tw[i] = twz[i];
   __syncthreads();
-  const int ncol = ndisk;
   const int cq = tid / L, t = tid % L;
-  const int col = blockIdx.x * CPB + cq;
+  const int col = bx * CPB + cq;
   if (col >= ncol || t >= A) return;
   const cpx<T>* src = tin + (size_t)pr * N3 * ncol + col;
   cpx<T> a[B];
@@ -640,10 +644,12 @@ gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* u
   if (!done && n3 == N) {                                                                      \
     done = true;                                                                               \
     constexpr int CPB = kZThreads / pow2_at_least(split_n1(N));                                \
-    hipLaunchKernelGGL((k_pair_zp<T, N>), dim3((em->ndisk + CPB - 1) / CPB, npairs),           \
-                       dim3(kZThreads), 0, c->stream, tbuf, ekx, eky, em->ext[2], em->gmax[2], \
-                       em->d_cube, em->d_disk, em->ndisk, static_cast<const cpx<T>*>(twz),     \
-                       invN, v0, nvt, c0, nc_total, em->n, static_cast<cpx<T>*>(mtxel));       \
+    const long long tot = (long long)((em->ndisk + CPB - 1) / CPB) * npairs;                   \
+    const unsigned grid = (unsigned)(((tot + kXcd - 1) / kXcd) * kXcd);                        \
+    hipLaunchKernelGGL((k_pair_zp<T, N>), dim3(grid), dim3(kZThreads), 0, c->stream, tbuf,     \
+                       ekx, eky, em->ext[2], em->gmax[2], em->d_cube, em->d_disk, em->ndisk,    \
+                       static_cast<const cpx<T>*>(twz), invN, v0, nvt, c0, nc_total, em->n,    \
+                       npairs, static_cast<cpx<T>*>(mtxel));                                   \
   }
     GW_XY_ZLEN(X)
 #undef X
