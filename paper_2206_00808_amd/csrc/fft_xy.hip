@@ -278,6 +278,16 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
   for (int i = tid; i < N1; i += S::NTH) tw1[i] = twx[i];
   for (int i = tid; i < N2; i += S::NTH) tw2[i] = twy[i];
   const int ncw = exw * eyw, YP = exw | 1;
+  // FP32: the column table of T in LDS after R (build: ncw + N2 (exw | 1)
+  // entries; valence loop: VB CT N2 XKP), read once per kept output of the y
+  // pass (1% of the C3 plane pass). FP64 reads it from global memory: the LDS
+  // copy's pointer costs the 128-register kernel two more spilled registers,
+  // which cost more than the loads save.
+  constexpr bool kDkLds = sizeof(T) == 4;
+  const int rlen = max(ncw + N2 * YP, VB * CT * N2 * XKP);
+  int* Dk = reinterpret_cast<int*>(R + rlen);
+  if constexpr (kDkLds)
+    for (int i = tid; i < ekx * eky; i += S::NTH) Dk[i] = disk[i];
   cpx<T>* Q = R;
   cpx<T>* Yw = R + ncw;
 
@@ -433,12 +443,12 @@ __global__ void __launch_bounds__((XyShape<T, N1, N2>::NTH), 1) k_pair_xy(
         cpx<T>* dst = tout + (pl * n3 + z) * (size_t)ndisk;
         if (tt < eky) {
           const cpx<T> val = kept_eval<T, S::A2>(col, XKP, yplan);
-          const int d = disk[tt * ekx + jk];
+          const int d = kDkLds ? Dk[tt * ekx + jk] : disk[tt * ekx + jk];
           if (d >= 0) dst[d] = val;
         }
         for (int jky = tt + S::L2; jky < eky; jky += S::L2) {
           const cpx<T> val = kept_out<T, S::A2, S::B2>(col, XKP, jky - gy, tw2);
-          const int d = disk[jky * ekx + jk];
+          const int d = kDkLds ? Dk[jky * ekx + jk] : disk[jky * ekx + jk];
           if (d >= 0) dst[d] = val;
         }
       }
@@ -610,7 +620,8 @@ gw_status pair_to_eps_xy(gw_ctx* c, const int box[3], int nspinor, const void* u
     const int ncw = sc->ext[0] * sc->ext[1];                                                    \
     const size_t build = (size_t)ncw + (size_t)B * (sc->ext[0] | 1);                            \
     const size_t xk = (size_t)VB * CT * B * (ekx | 1);                                          \
-    const size_t lds = ((size_t)A + B + (size_t)B * S::XP + std::max(build, xk)) * sizeof(cpx<T>); \
+    const size_t lds = ((size_t)A + B + (size_t)B * S::XP + std::max(build, xk)) * sizeof(cpx<T>) + \
+                       (size_t)ekx * eky * sizeof(int);                                           \
     const int ncg = (nct + CT - 1) / CT;                                                        \
     const long long tot = (long long)n3 * ncg;                                                  \
     const unsigned grid = (unsigned)(((tot + kXcd - 1) / kXcd) * kXcd);                         \
