@@ -347,7 +347,9 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
 //     Cb (N x GB) and R (GB x N), which stay in L2; the next four K are loaded
 //     while the current ones feed the matrix cores. C is read in the epilogue;
 //     three workgroups per CU cover that latency with the other wavefronts'
-//     products. Tiles of 64x64 are numbered frequency, row band, column band
+//     products.
+//     From N = 2048 the operands pass through LDS instead
+//     (gj_update_tile_lds), which loads each fragment once per workgroup. Tiles of 64x64 are numbered frequency, row band, column band
 //     and renumbered per XCD, so one XCD's L2 holds the panels of its tiles.
 //   - Look-ahead (nb2 > 0): the first nfreq workgroups each form the next
 //     diagonal block Dn = A[K'][K'] - Cb[K'] R[:, K'] with the same tile code,
@@ -358,6 +360,142 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
 //     R and Dinv), so no workgroup writes what another reads.
 constexpr int UT = 64;  // workgroup tile (2x2 wavefronts of 32x32)
 
+// A -= product on a wavefront's 32x32 block at (ia, ja): Re = t1 - t2, Im = t3 -
+// t1 - t2 (f64 16x16x4 D layout: row lk + 4r, column l16). The 8 entries of
+// each row block are loaded (at clamped, always valid addresses) before any is
+// stored, so the loads are in flight together: with a load, a wait and a store
+// per entry, each of the 16 entries cost a full memory round trip.
+__device__ __forceinline__ void gj_epilogue(const d4 (&t1)[2][2], const d4 (&t2)[2][2],
+                                            const d4 (&t3)[2][2], cpx<double>* A, int N, int ia,
+                                            int ja) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    cpx<double> v[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = min(ia + a * 16 + lk + 4 * r, N - 1), j = min(ja + b * 16 + l16, N - 1);
+        v[b][r] = A[(size_t)i * N + j];
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ia + a * 16 + lk + 4 * r, j = ja + b * 16 + l16;
+        if (i < N && j < N)
+          A[(size_t)i * N + j] = mk(v[b][r].x - (t1[a][b][r] - t2[a][b][r]),
+                                    v[b][r].y - ((t3[a][b][r] - t1[a][b][r]) - t2[a][b][r]));
+      }
+  }
+}
+
+// A -= Cb R on the 64x64 tile at (i0, j0) (rows and columns below N) with the
+// operands staged in LDS: Cb[i0 .. i0 + 63][K] and R[K][j0 .. j0 + 63] pass in
+// chunks of 8 K through two 16 KiB buffers, loaded by global_load_lds, so each
+// fragment comes from L2 once per workgroup, where the 2x2 wavefronts loading
+// their fragments directly fetch each twice.
+//   - Cb chunk [64 rows][8 k of 16 B]: k stored at slot k ^ f(row), f(row) =
+//     (row & 7) ^ ((row >> 3) & 1), so a fragment read (16 rows, one k per
+//     group of 16 lanes) meets 16 distinct groups of four banks and any 8
+//     consecutive rows 8 distinct groups. R chunk [8 k][64 columns]: a
+//     fragment read is 256 contiguous bytes per k.
+//   - K past kdim is read clamped and zeroed at the fragment (stale panel
+//     entries may hold anything); rows and columns past N are clamped and
+//     feed outputs that are not stored.
+//   - Products as in gj_update_tile: 2x2 v_mfma_f64_16x16x4_f64 blocks per
+//     wavefront, three real products per complex one, A read in the epilogue.
+__device__ __forceinline__ void gj_update_tile_lds(const cpx<double>* __restrict__ Cb,
+                                                   const cpx<double>* __restrict__ R,
+                                                   cpx<double>* A, int N, int kdim, int i0,
+                                                   int j0) {
+  __shared__ __align__(16) cpx<double> Cs0[UT * 8], Rs0[8 * UT], Cs1[UT * 8], Rs1[8 * UT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  d4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
+    }
+  // chunk at K offset kc: 16 row blocks of 1 KiB (8 of Cb, 8 rows each; 8 of
+  // R, one k each), 4 per wavefront
+  auto issue = [&](cpx<double>* Cs, cpx<double>* Rs, int kc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = wave * 4 + u;
+      const int row = (idx & 7) * 8 + (lane >> 3);
+      const int kb = (lane & 7) ^ (lane >> 3) ^ (idx & 1);
+      const cpx<double>* sa = Cb + (size_t)min(i0 + row, N - 1) * GB + min(kc + kb, kdim - 1);
+      const cpx<double>* sr = R + (size_t)min(kc + (idx & 7), kdim - 1) * N + min(j0 + lane, N - 1);
+      if (idx < 8)
+        __builtin_amdgcn_global_load_lds((const void*)sa, (lds_void*)(Cs + idx * 64), 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((const void*)sr, (lds_void*)(Rs + (idx - 8) * 64), 16,
+                                         0, 0);
+    }
+  };
+  auto compute = [&](const cpx<double>* Cs, const cpx<double>* Rs, int kc) {
+#pragma unroll
+    for (int kk = 0; kk < 8; kk += 4) {
+      const int k = kk + lk;
+      const bool ok = kc + k < kdim;
+      cpx<double> fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int row = wi + a * 16 + l16;
+        const cpx<double> v = Cs[row * 8 + (k ^ ((l16 & 7) ^ ((l16 >> 3) & 1)))];
+        fa[a] = ok ? v : mk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const cpx<double> v = Rs[k * UT + wj + b * 16 + l16];
+        fb[b] = ok ? v : mk(0.0, 0.0);
+      }
+      double sa[2], sb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) sa[a] = fa[a].x + fa[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, t1[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].y, t2[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
+    }
+  };
+  const int nch = (kdim + 7) / 8;
+  issue(Cs0, Rs0, 0);
+  __syncthreads();  // (its fence waits for the loads)
+  for (int c = 0; c < nch; c += 2) {
+    if (c + 1 < nch) issue(Cs1, Rs1, (c + 1) * 8);
+    compute(Cs0, Rs0, c * 8);
+    __syncthreads();
+    if (c + 1 < nch) {
+      if (c + 2 < nch) issue(Cs0, Rs0, (c + 2) * 8);
+      compute(Cs1, Rs1, (c + 1) * 8);
+      __syncthreads();
+    }
+  }
+  gj_epilogue(t1, t2, t3, A, N, i0 + wi, j0 + wj);
+}
+
+template <bool kLds>
 __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ A, int N,
                                                       int kdim, const cpx<double>* __restrict__ Cb,
                                                       const cpx<double>* __restrict__ R,
@@ -405,8 +543,12 @@ __global__ void __launch_bounds__(256, 3) k_gj_update(cpx<double>* __restrict__ 
   const int ti = rem / nt, tj = rem % nt;
   if (nb2 > 0 && ti == k2 / UT && tj == k2 / UT) return;
   A += (size_t)f * N * N;
-  gj_update_tile(Cb + (size_t)f * N * GB, GB, R + (size_t)f * GB * N, A, N, kdim,
-                 ti * UT + (wave >> 1) * 32, tj * UT + (wave & 1) * 32, N, A, N, 0);
+  if constexpr (kLds)
+    gj_update_tile_lds(Cb + (size_t)f * N * GB, R + (size_t)f * GB * N, A, N, kdim, ti * UT,
+                       tj * UT);
+  else
+    gj_update_tile(Cb + (size_t)f * N * GB, GB, R + (size_t)f * GB * N, A, N, kdim,
+                   ti * UT + (wave >> 1) * 32, tj * UT + (wave & 1) * 32, N, A, N, 0);
 }
 
 // ---------------------------------------------------------------- consumers of eps^-1
@@ -686,8 +828,14 @@ static gw_status epsinv_gauss_jordan(gw_ctx* c, int N, int nfreq, const double* 
       const int nt = (N + UT - 1) / UT;
       const long long tiles = (long long)nt * nt * nfreq;
       const long long grid = (nb2 > 0 ? nfreq : 0) + ((tiles + kXcd - 1) / kXcd) * kXcd;
-      hipLaunchKernelGGL(k_gj_update, dim3((unsigned)grid), dim3(256), 0, c->stream, A, N, nbk,
-                         Cb, R, nfreq, k2, nb2, Dn, Dw[(s + 1) & 1], c->d_flag);
+      // operands staged in LDS from N = 2048 (C3, N = 4000: 8.8 vs 9.7 ms per step);
+      // below, fragments straight from L2 (C2, N = 1000: 1.68 vs 1.84 ms)
+      if (N >= 2048)
+        hipLaunchKernelGGL(k_gj_update<true>, dim3((unsigned)grid), dim3(256), 0, c->stream, A,
+                           N, nbk, Cb, R, nfreq, k2, nb2, Dn, Dw[(s + 1) & 1], c->d_flag);
+      else
+        hipLaunchKernelGGL(k_gj_update<false>, dim3((unsigned)grid), dim3(256), 0, c->stream, A,
+                           N, nbk, Cb, R, nfreq, k2, nb2, Dn, Dw[(s + 1) & 1], c->d_flag);
       GW_CHECK_LAUNCH(c, "k_gj_update");
     }
     kp = k;
