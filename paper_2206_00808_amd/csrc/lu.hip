@@ -347,10 +347,10 @@ __global__ void k_gj_fix(cpx<double>* __restrict__ A, int N, int k, int nbk,
 //     Cb (N x GB) and R (GB x N), which stay in L2; the next four K are loaded
 //     while the current ones feed the matrix cores. C is read in the epilogue;
 //     three workgroups per CU cover that latency with the other wavefronts'
-//     products.
-//     From N = 2048 the operands pass through LDS instead
-//     (gj_update_tile_lds), which loads each fragment once per workgroup. Tiles of 64x64 are numbered frequency, row band, column band
-//     and renumbered per XCD, so one XCD's L2 holds the panels of its tiles.
+//     products. From N = 2048 the operands pass through LDS instead
+//     (gj_update_tile_lds), which loads each fragment once per workgroup.
+//     Tiles of 64x64 are numbered frequency, row band, column band and
+//     renumbered per XCD, so one XCD's L2 holds the panels of its tiles.
 //   - Look-ahead (nb2 > 0): the first nfreq workgroups each form the next
 //     diagonal block Dn = A[K'][K'] - Cb[K'] R[:, K'] with the same tile code,
 //     invert it in registers (gj_invert_64, 16x16 threads holding 4x4 entries)
