@@ -409,12 +409,13 @@ def test_alias_box_rejected(P, ctx):
     assert ei.value.status == P.GW_EINVAL
 
 
-@pytest.mark.parametrize("n,kind", [(n, "definite") for n in (1, 63, 64, 65, 129, 200)]
+@pytest.mark.parametrize("n,kind", [(n, "definite") for n in (1, 63, 64, 65, 129, 200, 2048, 2113)]
                          + [(n, "indefinite") for n in (65, 129)])
 def test_epsinv_block_counts_match_oracle(P, ctx, n, kind):
     """eps^-1 at sizes around the 64-wide Gauss-Jordan blocks (one block, a ragged
     last block, the look-ahead block skipped by the rank update), three
-    frequencies at once. 'definite' is chi0 <= 0 (the Gauss-Jordan path); in
+    frequencies at once; from N = 2048 (whole blocks, and a last block of one
+    column) the rank update stages its panels in LDS. 'definite' is chi0 <= 0 (the Gauss-Jordan path); in
     'indefinite' one frequency has chi0 with eigenvalues above 1/v, so eps~ is not
     positive definite and the call must take the pivoted LU path."""
     rng = np.random.default_rng(7 * n + (kind == "indefinite"))
