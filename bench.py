@@ -63,9 +63,9 @@ XY_PLANES = {(60, 60), (16, 16)}
 
 
 def fft_stage_bytes(d, elem):
-    """The survey's algorithmic HBM bytes of the FFT stage (band + pair transforms)
-    per q: every band field written and read back, and both spinor planes of
-    the conduction band per pair."""
+    """Algorithmic HBM bytes of the FFT stage (band + pair transforms) per q in
+    the full-field accounting: every band field written and read back, and both
+    spinor planes of the conduction band per pair."""
     nbox = int(np.prod(d["box"]))
     nv, nc, neps = d["nv"], d["nc"], d["neps"]
     ngv, ngc = d["gv"].shape[0], d["gc"].shape[0]
@@ -841,10 +841,10 @@ def main():
         "pair_flop_equivalents": sum(work.values()),
         "alu_TFLOP_per_s": sum(work.values()) / (fft_ms * 1e-3) / 1e12,
         "frac_of_alu_peak": sum(work.values()) / (fft_ms * 1e-3) / 1e12 / VECTOR_PEAK_TFLOPS["f64"],
-        "survey_unit_GB": (bb + pb) / 1e9,
+        "full_field_unit_GB": (bb + pb) / 1e9,
         "note": "bound by the vector ALU: the product and pruned transforms of every pair "
                 "(5 n log2 n flop-equivalents per transform) over the band and pair kernels' "
-                "time; the survey's byte unit counts conduction planes the kernels never "
+                "time; the full-field byte unit counts conduction planes the kernels never "
                 "move, so it is given for reference only; measured HBM traffic per kernel "
                 "is in the rooflines when a counter record exists"}
     epsinv64 = o64["epsinv"]
