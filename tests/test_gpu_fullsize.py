@@ -76,8 +76,12 @@ def layered(P, ctx):
     picks = [(0, 0), (nv - 1, nc - 1)] + [(int(rng.integers(nv)), int(rng.integers(nc)))
                                           for _ in range(6)]
     out["m_pairs"] = [(v, c, o["mtxel"][v, c].cpu().numpy()) for v, c in picks]
-    # every pair's elements at G indices on both sides of 64-wide tile edges
-    sel = np.array([0, 1, 62, 63, 64, 65, 127, 128, 2047, 2048, 3967, 3968, 3999])
+    # every pair's elements at G indices on both sides of 64-wide tile edges, and
+    # at the sphere's extreme g_x, g_y and g_z (the outermost kept columns of the
+    # xy-plane pass and the last kept z frequencies)
+    ge = np.asarray(s["geps"])
+    ext = [int(np.argmax(ge[:, a])) for a in range(3)] + [int(np.argmin(ge[:, a])) for a in range(3)]
+    sel = np.unique(np.array([0, 1, 62, 63, 64, 65, 127, 128, 2047, 2048, 3967, 3968, 3999] + ext))
     out["sel"] = sel
     out["m_sel"] = o["mtxel"][:, :, sel].cpu().numpy()
     del o, d
