@@ -13,6 +13,7 @@ from .generate import (  # noqa: F401
     build_system,
     g_sphere,
     config_by_name,
+    config_digest,
     batch_systems,
     closure_systems,
     EV_PER_HA,

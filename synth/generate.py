@@ -24,6 +24,8 @@ Draw order per system (numpy default_rng(seed)):
 from __future__ import annotations
 
 import dataclasses
+import hashlib
+import json
 import math
 from dataclasses import dataclass, field
 
@@ -82,6 +84,13 @@ CONFIGS = {
 
 def config_by_name(name: str) -> SystemConfig:
     return CONFIGS[name]
+
+
+def config_digest(cfg: SystemConfig) -> str:
+    """First 12 hex digits of the SHA-256 of the workload's parameters (sorted
+    JSON): the key of a stored reference computed for that workload."""
+    text = json.dumps(dataclasses.asdict(cfg), sort_keys=True)
+    return hashlib.sha256(text.encode()).hexdigest()[:12]
 
 
 def _cart(cell, kred, g):
