@@ -123,6 +123,8 @@ def test_chi0_and_epsinv_fp64(P, ctx, name):
     for f in range(len(s["omega"])):
         assert oracle.rel_f(out["chi0"][f], x[f]) < 1e-10
         assert oracle.rel_f(out["epsinv"][f], e[f]) < 1e-10
+        assert _max_rel(out["chi0"][f], x[f]) < 1e-10
+        assert _max_rel(out["epsinv"][f], e[f]) < 1e-10
     # Hermitian by construction (mirrored tiles)
     c = out["chi0"]
     assert np.abs(c - np.conj(np.transpose(c, (0, 2, 1)))).max() <= 1e-15 * np.abs(c).max()
@@ -368,6 +370,8 @@ def test_mixed_path_within_1e4(P, ctx, name):
     for f in range(len(s["omega"])):
         assert oracle.rel_f(out["chi0"][f], x[f]) < 1e-4
         assert oracle.rel_f(out["epsinv"][f], e[f]) < 1e-4
+        assert _max_rel(out["chi0"][f], x[f]) < 1e-4
+        assert _max_rel(out["epsinv"][f], e[f]) < 1e-4
 
 
 def test_mixed_head_wings_in_fp64(P, ctx):
