@@ -396,11 +396,11 @@ __device__ __forceinline__ void gj_epilogue(const d4 (&t1)[2][2], const d4 (&t2)
 // chunks of 8 K through two 16 KiB buffers, loaded by global_load_lds, so each
 // fragment comes from L2 once per workgroup, where the 2x2 wavefronts loading
 // their fragments directly fetch each twice.
-//   - Cb chunk [64 rows][8 k of 16 B]: k stored at slot k ^ f(row), f(row) =
-//     (row & 7) ^ ((row >> 3) & 1), so a fragment read (16 rows, one k per
-//     group of 16 lanes) meets 16 distinct groups of four banks and any 8
-//     consecutive rows 8 distinct groups. R chunk [8 k][64 columns]: a
-//     fragment read is 256 contiguous bytes per k.
+//   - Cb chunk [64 rows][8 k of 16 B]: k stored at slot k ^ (row & 7). A
+//     fragment read (16 rows, one k per group of 16 lanes) then takes as many
+//     LDS cycles as a contiguous 1 KiB read, by the bank-conflict counter;
+//     (row & 7) ^ ((row >> 3) & 1) took twice as many. R chunk [8 k][64
+//     columns]: a fragment read is 256 contiguous bytes per k.
 //   - K past kdim is read clamped and zeroed at the fragment (stale panel
 //     entries may hold anything); rows and columns past N are clamped and
 //     feed outputs that are not stored.
@@ -430,7 +430,7 @@ __device__ __forceinline__ void gj_update_tile_lds(const cpx<double>* __restrict
     for (int u = 0; u < 4; ++u) {
       const int idx = wave * 4 + u;
       const int row = (idx & 7) * 8 + (lane >> 3);
-      const int kb = (lane & 7) ^ (lane >> 3) ^ (idx & 1);
+      const int kb = (lane & 7) ^ (lane >> 3);  // row & 7 = lane >> 3
       const cpx<double>* sa = Cb + (size_t)min(i0 + row, N - 1) * GB + min(kc + kb, kdim - 1);
       const cpx<double>* sr = R + (size_t)min(kc + (idx & 7), kdim - 1) * N + min(j0 + lane, N - 1);
       if (idx < 8)
@@ -449,7 +449,7 @@ __device__ __forceinline__ void gj_update_tile_lds(const cpx<double>* __restrict
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int row = wi + a * 16 + l16;
-        const cpx<double> v = Cs[row * 8 + (k ^ ((l16 & 7) ^ ((l16 >> 3) & 1)))];
+        const cpx<double> v = Cs[row * 8 + (k ^ (l16 & 7))];
         fa[a] = ok ? v : mk(0.0, 0.0);
       }
 #pragma unroll

@@ -331,11 +331,11 @@ __device__ __forceinline__ void chi0_f64_tile(const cpx<Tin>* __restrict__ M, in
 // global_load_lds_dwordx4 (one wavefront instruction = 16 rows x 64 bytes of
 // one plane), into two slabs kept as separate LDS objects and alternated, one
 // barrier per slab. Rows are stored unpadded; the four 16-byte chunks of row r
-// are permuted by XOR with ((r >> 1) ^ (r >> 3)) & 3 on the way in and on the
-// way out, so that a fragment read (16 rows, one chunk each) is free of bank
-// conflicts whether the LDS serves it 8 lanes at a time over 32 banks or 16
-// lanes at a time over 64: rows 8 apart, and the even (odd) rows of each 8,
-// get distinct chunks.
+// are permuted by XOR with (r >> 1) & 3 on the way in and on the way out. With
+// that permutation a fragment read (16 rows of 64 bytes, one chunk each) takes
+// as many LDS cycles as a contiguous 1 KiB read, by the bank-conflict counter;
+// ((r >> 1) ^ (r >> 3)) & 3, (r & 3), (r >> 2) & 3 and no permutation all take
+// twice as many.
 __device__ __forceinline__ void chi0_bf16s_tile_dl(const unsigned short* __restrict__ XA,
                                                    const unsigned short* __restrict__ XB, int pb0,
                                                    int npb, int neps, cpx<double>* __restrict__ C,
@@ -360,7 +360,7 @@ __device__ __forceinline__ void chi0_bf16s_tile_dl(const unsigned short* __restr
       for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
     }
   // this lane's row within a 16-row block and the logical chunk it carries
-  const int lrow = lane >> 2, lchunk = (lane & 3) ^ (((lrow >> 1) ^ (lrow >> 3)) & 3);
+  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lrow >> 1) & 3);
   const int ra = min(i0 + lrow, neps - 1), rb = min(j0 + lrow, neps - 1);
   // the wavefront's 8 of the slab's 32 row blocks (operand, plane, 16-row block)
   auto issue = [&](Slab A, Slab B, int pb) {
@@ -376,7 +376,7 @@ __device__ __forceinline__ void chi0_bf16s_tile_dl(const unsigned short* __restr
     }
   };
   // physical chunk of logical chunk lk in this lane's fragment rows
-  const int pch = (lk ^ (((l16 >> 1) ^ (l16 >> 3)) & 3)) * 8;
+  const int pch = (lk ^ ((l16 >> 1) & 3)) * 8;
   int since_flush = 0;
   auto compute = [&](Slab A, Slab B, bool last) {
     bf8 a[2][4], b[2][4];
@@ -500,7 +500,7 @@ __device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restri
       cp[x][y] = (f4){0, 0, 0, 0};
       cn[x][y] = (f4){0, 0, 0, 0};
     }
-  const int lrow = lane >> 2, lchunk = (lane & 3) ^ (((lrow >> 1) ^ (lrow >> 3)) & 3);
+  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lrow >> 1) & 3);
   // the wavefront's 8 of the slab's 64 row blocks (operand, plane, 16-row block)
   auto issue = [&](Slab A, Slab B, int pb) {
 #pragma unroll
@@ -515,7 +515,7 @@ __device__ __forceinline__ void chi0_bf16s_tile_w(const unsigned short* __restri
       __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)dst, 16, 0, 0);
     }
   };
-  const int pch = (lk ^ (((l16 >> 1) ^ (l16 >> 3)) & 3)) * 8;
+  const int pch = (lk ^ ((l16 >> 1) & 3)) * 8;
   auto compute = [&](Slab A, Slab B) {
     bf8 b[2][4];
 #pragma unroll
